@@ -1,0 +1,150 @@
+"""Seeded synthetic inputs for the particle-particle-ladder (PPL) response path.
+
+This module only draws random numbers.  It holds none of the method's
+arithmetic: no integrals, no right-hand sides, no denominators.  Both the
+FP64 CPU oracle and the GPU library are fed from here, so the two sides see
+bit-identical inputs.
+
+Recipe (stand-in for the paper's molecular workloads, whose integrals are not
+available; shapes follow the systems of the paper's efficiency section and
+its retained-virtual range of about 50--300 spinors):
+
+* Cholesky vectors ``L[P, a, c]`` (complex, vv block):
+  ``L^P = gamma * (G^P + G^P^H) / 2 * exp(-P / 16)`` with ``G ~ CN(0, 1)``.
+  Each ``L^P`` is Hermitian in its pair index, which is what real
+  Cholesky vectors of a Hermitian two-electron matrix look like in a Kramers-
+  unrestricted spinor basis.
+* Occupied spinor energies ``U(-2, -0.5)`` Eh, virtual ``U(0.1, 5)`` Eh.
+* Dipole ov block ``mu[x, i, a] ~ CN(0, 0.1^2)``.
+* A complex normal ``CN(0, s^2)`` draw is ``s * (x + i y) / sqrt(2)`` with
+  ``x, y ~ N(0, 1)``, so ``E|z|^2 = s^2``.
+* Draw order from ``numpy.random.default_rng(seed)``: G real part, G
+  imaginary part (each ``[nchol, v, v]``), occupied energies, virtual
+  energies, then per dipole component its real and imaginary part.
+
+Packed doubles for sigma-only runs are drawn directly in packed form
+(``[nrhs, o(o-1)/2, v(v-1)/2]``, ``CN(0, 1)``); they stand for an amplitude
+vector that is antisymmetric in ij and in ab, which the packed form encodes.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "CONFIGS",
+    "Config",
+    "cn",
+    "make_L",
+    "make_instance",
+    "make_packed",
+    "npair",
+    "solve_gamma",
+]
+
+
+def npair(n: int) -> int:
+    """Number of strictly ordered pairs p<q among n indices."""
+    return n * (n - 1) // 2
+
+
+def cn(rng: np.random.Generator, shape, scale: float = 1.0) -> np.ndarray:
+    """Complex normal CN(0, scale^2): real part drawn first, then imaginary."""
+    re = rng.standard_normal(shape)
+    im = rng.standard_normal(shape)
+    return (scale / math.sqrt(2.0)) * (re + 1j * im)
+
+
+def make_L(rng: np.random.Generator, nchol: int, v: int, gamma: float = 1.0,
+           hermitian: bool = True) -> np.ndarray:
+    """Cholesky vectors ``[nchol, v, v]`` complex128, decaying as exp(-P/16).
+
+    With ``hermitian=False`` the symmetrisation is skipped (general complex
+    vectors, used for adjoint tests where L has no structure).
+    """
+    g = cn(rng, (nchol, v, v))
+    if hermitian:
+        g = 0.5 * (g + np.conj(np.swapaxes(g, 1, 2)))
+    decay = np.exp(-np.arange(nchol, dtype=np.float64) / 16.0)
+    return (gamma * decay)[:, None, None] * g
+
+
+def make_packed(rng: np.random.Generator, nrhs: int, o: int, v: int,
+                scale: float = 1.0) -> np.ndarray:
+    """Packed doubles ``[nrhs, o(o-1)/2, v(v-1)/2]`` complex128, CN(0, scale^2)."""
+    return cn(rng, (nrhs, npair(o), npair(v)), scale)
+
+
+def solve_gamma(v: int) -> float:
+    """Scale applied to L for response solves: 1 / (3 sqrt(v)).
+
+    The raw generator gives a ladder operator whose norm grows like 5v Eh,
+    far above the smallest orbital-energy gap (about 1.2 Eh), which makes the
+    model Jacobian indefinite.  With this scale the ladder part stays below
+    the smallest gap and the shifted Jacobian is positive definite for the
+    frequencies used here.
+    """
+    return 1.0 / (3.0 * math.sqrt(v))
+
+
+@dataclass
+class Instance:
+    o: int
+    v: int
+    nchol: int
+    L: np.ndarray      # [nchol, v, v] complex128
+    eps: np.ndarray    # [o + v] float64, occupied first
+    mu: np.ndarray     # [ncomp, o, v] complex128
+    gamma: float
+
+
+def make_instance(o: int, v: int, nchol: int, ncomp: int = 3, seed: int = 0,
+                  gamma: float = 1.0, hermitian: bool = True) -> Instance:
+    """One synthetic LR instance, drawn in the documented order."""
+    rng = np.random.default_rng(seed)
+    L = make_L(rng, nchol, v, gamma, hermitian)
+    e_occ = rng.uniform(-2.0, -0.5, size=o)
+    e_vir = rng.uniform(0.1, 5.0, size=v)
+    mu = np.stack([cn(rng, (o, v), 0.1) for _ in range(ncomp)]) if ncomp else \
+        np.zeros((0, o, v), np.complex128)
+    return Instance(o, v, nchol, L, np.concatenate([e_occ, e_vir]), mu, gamma)
+
+
+@dataclass
+class Config:
+    name: str
+    o: int
+    v: int
+    nchol: int
+    ncomp: int
+    omegas: tuple
+    seed: int = 0
+    note: str = ""
+    instances: list = field(default_factory=list)  # batched workload only
+
+    @property
+    def nrhs(self) -> int:
+        return self.ncomp * len(self.omegas)
+
+
+# The five workloads: a tiny oracle case, the FP64 baseline, the precision
+# study, the uneven batch, and the large differentiation/scale case.
+CONFIGS = {
+    "tiny": Config("tiny", 4, 24, 64, 1, (0.0,), 0,
+                   "o=4 v=24 Nchol=64, z only, omega=0"),
+    "baseline": Config("baseline", 16, 160, 640, 3, (0.0, 0.0656), 0,
+                       "o=16 v=160 Nchol=640, 3 components x 2 frequencies"),
+    "precision": Config("precision", 24, 256, 1024, 1,
+                        (0.0, 0.0428, 0.0656, 0.0856), 0,
+                        "o=24 v=256 Nchol=1024, z x 4 frequencies"),
+    "batch": Config("batch", 0, 0, 0, 3, (0.0, 0.0428, 0.0656, 0.0856), 0,
+                    "8 instances o in {8..32}, v=10o, Nchol=4v, seeds 0..7",
+                    instances=[(o, 10 * o, 40 * o, s) for s, o in
+                               enumerate((8, 12, 16, 20, 24, 28, 32, 32))]),
+    "scale": Config("scale", 40, 480, 2400, 1, (0.0,), 0,
+                    "o=40 v=480 Nchol=2400, one RHS"),
+    "gradcheck": Config("gradcheck", 6, 36, 144, 1, (0.0,), 0,
+                        "o=6 v=36 Nchol=144 (Nchol = 4v)"),
+}

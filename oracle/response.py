@@ -1,0 +1,190 @@
+"""Model linear-response problem driven by the PPL product (FP64, CPU).
+
+Paper, Sec. 2.2: the first-order right-hand amplitudes solve
+X(omega) = (-A + omega I)^{-1} xi(omega), i.e. (A - omega) X = -xi, with A
+the CC Jacobian.  Here A is the doubles-doubles block at T = 0 restricted
+to the Fock diagonal plus the particle-particle ladder:
+
+    (A X)_ij^ab = D_ij^ab X_ij^ab + sigma_ij^ab,
+    D_ij^ab = e_a + e_b - e_i - e_j,
+
+the same orbital-energy difference that forms the diagonal-Jacobian
+denominators of the perturbation-sensitive amplitudes (Sec. 2.4).
+
+Right-hand side (a reading; the paper defines xi only as the projection of
+the similarity-transformed perturbation on the excited determinants): the
+antisymmetric doubles image of the dipole ov block,
+
+    xi_ij^ab = mu_ia mu_jb - mu_ib mu_ja.
+
+Response function (Sec. 2.2, last equation, reduced to the right-hand
+amplitudes of this model): alpha_xy(omega) = -<xi_x | X_y(omega)> with
+<u|w> = sum over packed (r, i<j, a<b) of conj(u) w.
+
+Three solves:
+  solve_iterative -- Jacobi + DIIS on the packed vector, one subspace per RHS
+  solve_dense     -- per occupied pair ij, an LU solve of the packed
+                     (A_ij - omega) system (A is block diagonal in ij here)
+  solve_sos       -- eigen-decomposition H = U diag(lam) U^H of the ladder
+                     plus virtual energies, giving the sum-over-states form
+                     of Eq. (sos) exactly (Hermitian L only)
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import ppl
+
+
+def rhs(mu: np.ndarray, o: int, v: int) -> np.ndarray:
+    """xi[x, ij, ab] = mu_ia mu_jb - mu_ib mu_ja on packed pairs."""
+    pi, pj = ppl.pairs(o)
+    pa, pb = ppl.pairs(v)
+    ncomp = mu.shape[0]
+    xi = np.zeros((ncomp, len(pi), len(pa)), dtype=np.complex128)
+    for x in range(ncomp):
+        m = mu[x]
+        xi[x] = (m[pi][:, pa] * m[pj][:, pb]) - (m[pi][:, pb] * m[pj][:, pa])
+    return xi
+
+
+def denominators(eps: np.ndarray, o: int, v: int) -> np.ndarray:
+    """D[ij, ab] = e_a + e_b - e_i - e_j on packed pairs."""
+    pi, pj = ppl.pairs(o)
+    pa, pb = ppl.pairs(v)
+    eo, ev = eps[:o], eps[o:o + v]
+    return (ev[pa] + ev[pb])[None, :] - (eo[pi] + eo[pj])[:, None]
+
+
+def apply_jacobian(L, X, eps, o, v):
+    """(A X) = D o X + sigma(X)."""
+    return denominators(eps, o, v)[None] * X + ppl.sigma(L, X, o, v)
+
+
+def _diis_coefficients(errs):
+    """Pulay DIIS: minimise |sum c_k e_k| subject to sum c_k = 1.
+
+    Solves the bordered system [[B, 1], [1^T, 0]] [c; l] = [0; 1] with
+    B_kl = <e_k|e_l> divided by its largest diagonal entry (a common scale,
+    which leaves c unchanged).  Returns None when B is numerically singular:
+    condition number of the unit-diagonal form D^-1/2 B D^-1/2 above 1e14.
+    """
+    m = len(errs)
+    B = np.array([[np.vdot(errs[k], errs[l]) for l in range(m)]
+                  for k in range(m)])
+    d = np.sqrt(np.real(np.diag(B)))
+    if m > 1 and np.linalg.cond(B / np.outer(d, d)) > 1e14:
+        return None
+    A = np.zeros((m + 1, m + 1), dtype=np.complex128)
+    A[:m, :m] = B / np.max(d) ** 2
+    A[:m, m] = 1.0
+    A[m, :m] = 1.0
+    rhs_ = np.zeros(m + 1, dtype=np.complex128)
+    rhs_[m] = 1.0
+    return np.linalg.solve(A, rhs_)[:m]
+
+
+def solve_iterative(L, eps, mu, omegas, o, v, tol=1e-8, max_iter=200,
+                    diis_dim=8, sigma_fn=None):
+    """Jacobi + DIIS for every (omega, component) right-hand side.
+
+    X0 = -xi / (D - omega).  Each iteration: R = -xi - (D - omega) X - sigma(X);
+    stop when |R|_2 / |xi|_2 < tol; otherwise X~ = X + R / (D - omega),
+    e = X~ - X, and X = sum_k c_k X~_k over the last ``diis_dim`` pairs.  If
+    the DIIS matrix is singular, take the plain Jacobi step and restart the
+    subspace.  All active right-hand sides share one sigma call per iteration.
+
+    Returns dict(alpha [nomega, ncomp, ncomp], X [nomega, ncomp, npo, npv],
+    iters [nomega, ncomp], relres [nomega, ncomp], n_sigma).
+    """
+    sigma_fn = sigma_fn or (lambda X: ppl.sigma(L, X, o, v))
+    xi = rhs(mu, o, v)
+    D = denominators(eps, o, v)
+    ncomp = xi.shape[0]
+    nom = len(omegas)
+    rhs_list = [(w, x) for w in range(nom) for x in range(ncomp)]
+    n = len(rhs_list)
+    b = np.stack([-xi[x] for (_, x) in rhs_list])
+    Dw = np.stack([D - omegas[w] for (w, _) in rhs_list])
+    bnorm = np.array([np.linalg.norm(xi[x]) for (_, x) in rhs_list])
+    X = b / Dw
+    hist = [[] for _ in range(n)]
+    iters = np.zeros(n, dtype=int)
+    relres = np.full(n, np.inf)
+    active = np.ones(n, dtype=bool)
+    n_sigma = 0
+    for it in range(max_iter + 1):
+        idx = np.nonzero(active)[0]
+        if len(idx) == 0:
+            break
+        S = sigma_fn(X[idx])
+        n_sigma += 1
+        for k, r in enumerate(idx):
+            R = b[r] - Dw[r] * X[r] - S[k]
+            relres[r] = np.linalg.norm(R) / bnorm[r]
+            if relres[r] < tol or it == max_iter:
+                active[r] = False
+                continue
+            Xt = X[r] + R / Dw[r]
+            hist[r].append((Xt, Xt - X[r]))
+            if len(hist[r]) > diis_dim:
+                hist[r].pop(0)
+            c = _diis_coefficients([e for (_, e) in hist[r]])
+            if c is None:
+                X[r] = Xt
+                hist[r] = [hist[r][-1]]
+            else:
+                X[r] = sum(ck * Xk for ck, (Xk, _) in zip(c, hist[r]))
+            iters[r] = it + 1
+    Xs = X.reshape(nom, ncomp, *X.shape[1:])
+    alpha = np.zeros((nom, ncomp, ncomp), dtype=np.complex128)
+    for w in range(nom):
+        for x in range(ncomp):
+            for y in range(ncomp):
+                alpha[w, x, y] = -np.vdot(xi[x], Xs[w, y])
+    return dict(alpha=alpha, X=Xs, iters=iters.reshape(nom, ncomp),
+                relres=relres.reshape(nom, ncomp), n_sigma=n_sigma)
+
+
+def solve_dense(L, eps, mu, omegas, o, v):
+    """Exact solve: per occupied pair ij, LU of (diag(D_ij) + K - omega).
+
+    K = 2 <ab||cd> on packed pairs (the ladder acting on one ij block).
+    Returns dict(alpha, X) with the same shapes as ``solve_iterative``.
+    """
+    xi = rhs(mu, o, v)
+    D = denominators(eps, o, v)
+    K = ppl.ladder_matrix(L, v)
+    ncomp, npo, npv = xi.shape
+    X = np.zeros((len(omegas), ncomp, npo, npv), dtype=np.complex128)
+    for w, om in enumerate(omegas):
+        for ij in range(npo):
+            Aij = K + np.diag(D[ij] - om)
+            X[w, :, ij, :] = np.linalg.solve(Aij, -xi[:, ij, :].T).T
+    alpha = -np.einsum("xpq,wypq->wxy", np.conj(xi), X)
+    return dict(alpha=alpha, X=X)
+
+
+def solve_sos(L, eps, mu, omegas, o, v):
+    """Sum-over-states form (Eq. sos) of the same model, Hermitian L only.
+
+    H = diag(e_a + e_b) + K = U diag(lam) U^H on packed virtual pairs; with
+    s_ij = e_i + e_j the pair block of A - omega has eigenvalues
+    lam_k - s_ij - omega, so
+    alpha_xy(omega) = sum_ij sum_k conj(U^H xi_x,ij)_k (U^H xi_y,ij)_k
+                                      / (lam_k - s_ij - omega).
+    """
+    xi = rhs(mu, o, v)
+    pa, pb = ppl.pairs(v)
+    pi, pj = ppl.pairs(o)
+    eo, ev = eps[:o], eps[o:o + v]
+    H = ppl.ladder_matrix(L, v) + np.diag(ev[pa] + ev[pb])
+    lam, U = np.linalg.eigh(H)
+    s = eo[pi] + eo[pj]
+    proj = np.einsum("ka,xpa->xpk", np.conj(U.T), xi)   # (U^H xi)[x, ij, k]
+    alpha = np.zeros((len(omegas), xi.shape[0], xi.shape[0]),
+                     dtype=np.complex128)
+    for w, om in enumerate(omegas):
+        den = lam[None, :] - s[:, None] - om              # [ij, k]
+        alpha[w] = np.einsum("xpk,ypk,pk->xy", np.conj(proj), proj, 1.0 / den)
+    return dict(alpha=alpha, eigenvalues=lam)
