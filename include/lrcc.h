@@ -1,0 +1,174 @@
+/*
+ * lrcc.h -- C ABI of the MI355X (gfx950) particle-particle-ladder library.
+ *
+ * The library computes the particle-particle-ladder (PPL) part of the
+ * Cholesky-decomposed relativistic LR-CCSD Jacobian product and the model
+ * response solve built on it (paper: Sec. 2.2 response equations and
+ * Jacobian; Sec. 3, integrals with more than two particle indices rebuilt on
+ * the fly from Cholesky vectors):
+ *
+ *   <ab|cd>      = sum_P L^P_ac L^P_bd           (never stored)
+ *   <ab||cd>     = <ab|cd> - <ab|dc>
+ *   sigma_ij^ab  = sum_{c,d} <ab||cd> X_ij^cd     (unrestricted c,d sum)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array pointers are DEVICE pointers unless marked (host).  Buffers are
+ *   contiguous, row-major, complex values interleaved (re, im), and at least
+ *   8-byte aligned (16-byte for complex128).  The caller owns every buffer;
+ *   the library never frees caller memory.
+ * - Cholesky vectors: L[P][a][c] = L^P_ac, shape [nchol][v][v].
+ * - Doubles (X, sigma, gradients): packed [nrhs][o(o-1)/2][v(v-1)/2]; the pair
+ *   index of p<q among n is p(2n-p-1)/2 + (q-p-1) (row-major upper
+ *   triangle), the same formula for (i,j) with n=o and (a,b) with n=v.
+ * - Every function returns an lrcc_status.  Nothing throws or aborts across
+ *   the ABI.  Argument errors are found before any launch and leave every
+ *   output untouched; lrcc_last_error() then names the argument.
+ * - lrcc_ppl_sigma and lrcc_ppl_sigma_adjoint are stream-ordered and
+ *   asynchronous on the handle's stream.  lrcc_solve and lrcc_solve_batched
+ *   are synchronous and return alpha on the host.
+ * - A handle owns a grow-only device workspace and is not thread-safe;
+ *   separate handles are independent.
+ */
+#ifndef LRCC_H
+#define LRCC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LRCC_OK = 0,
+  LRCC_ERR_ARG = 1,            /* null pointer, bad enum, negative size       */
+  LRCC_ERR_SHAPE = 2,          /* sizes inconsistent or beyond the limits     */
+  LRCC_ERR_DTYPE = 3,          /* dtype/precision combination not offered     */
+  LRCC_ERR_DEVICE = 4,         /* no gfx950 device, or a HIP runtime failure  */
+  LRCC_ERR_NOMEM = 5,          /* workspace allocation failed                 */
+  LRCC_ERR_NOT_CONVERGED = 6,  /* solve hit max_iter; info is still filled    */
+  LRCC_ERR_NONFINITE = 7,      /* NaN/Inf met in a residual or norm           */
+  LRCC_ERR_UNSUPPORTED = 8     /* valid request the library does not offer    */
+} lrcc_status;
+
+typedef enum { LRCC_C128 = 0, LRCC_C64 = 1 } lrcc_dtype;  /* storage of L, X, sigma */
+typedef enum { LRCC_FP64 = 0, LRCC_FP32 = 1, LRCC_BF16X3 = 2 } lrcc_prec; /* PPL arithmetic */
+typedef enum { LRCC_CMUL_4M = 0, LRCC_CMUL_3M = 1 } lrcc_cmul;  /* complex product form */
+
+typedef struct lrcc_handle_s* lrcc_handle;
+
+/* Create a handle on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Fails with LRCC_ERR_DEVICE when
+ * the device is not gfx950. */
+lrcc_status lrcc_create(lrcc_handle* h, int device, void* hip_stream);
+/* Free the handle and its workspace (waits for its stream first). */
+lrcc_status lrcc_destroy(lrcc_handle h);
+/* Change the stream later calls are issued on. */
+lrcc_status lrcc_set_stream(lrcc_handle h, void* hip_stream);
+
+/* sigma = PPL(L, X).
+ * o, v     occupied / virtual counts (o>=0, v>=0; pairs need o,v>=2, else the
+ *          packed extent is 0 and the call returns LRCC_OK doing nothing).
+ * nchol    number of Cholesky vectors (0 gives sigma = 0).
+ * nrhs     number of independent doubles vectors.
+ * L        [nchol][v][v] complex in `dt`.
+ * X        [nrhs][o(o-1)/2][v(v-1)/2] complex in `dt`.
+ * sigma    same shape and dtype as X; overwritten, never accumulated.  May not
+ *          alias X or L.
+ * prec     arithmetic of the ladder GEMMs: FP64, FP32 (FP32 MFMA with FP32
+ *          accumulation inside a tile) or BF16X3 (split hi/lo bf16 MFMA, FP32
+ *          accumulation).  Sums across tiles are kept in FP64 for C128 output.
+ * cmul     4M (four real products per complex product) or 3M (three).
+ * Limits: v <= 4096, nchol <= 65536, nrhs*o(o-1)/2 <= 2^24. */
+lrcc_status lrcc_ppl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs,
+                           const void* L, const void* X, void* sigma,
+                           lrcc_dtype dt, lrcc_prec prec, lrcc_cmul cmul);
+
+/* Vector-Jacobian products of sigma = PPL(L, X) for a real loss with
+ * upstream gradient G = dloss/dsigma (PyTorch's complex convention:
+ * dloss = Re sum conj(grad) d(input)).
+ *   dX = sigma(L^H, G)                  (the adjoint ladder; (L^H)^P = (L^P)^H)
+ *   dL^P = 2 sum_m G_m conj(L^P) X_m^H  (G_m, X_m full antisymmetric v x v)
+ * Either output may be NULL to skip it.  dX has the shape of X, dL of L; both
+ * are overwritten.  The ladder tiles are recomputed, never stored. */
+lrcc_status lrcc_ppl_sigma_adjoint(lrcc_handle h, int o, int v, int nchol, int nrhs,
+                                   const void* L, const void* X, const void* G,
+                                   void* dX, void* dL,
+                                   lrcc_dtype dt, lrcc_prec prec, lrcc_cmul cmul);
+
+/* Options of the response solve.  Zero-initialised fields take defaults. */
+typedef struct {
+  double tol;        /* relative residual |R|/|xi| (default 1e-8)            */
+  int max_iter;      /* FP64 iterations, or inner iterations per refinement
+                        sweep for reduced precision (default 100)            */
+  int diis_dim;      /* DIIS subspace size, 1 = plain Jacobi (default 8)     */
+  lrcc_prec prec;    /* ladder arithmetic of the inner iterations            */
+  lrcc_cmul cmul;
+  double inner_tol;  /* reduced precision: inner relative tolerance (1e-5)   */
+  int max_outer;     /* reduced precision: refinement sweeps (default 6)     */
+  int deterministic; /* reserved; must be 0                                  */
+} lrcc_solve_opts;
+
+typedef struct {
+  int iters_max;        /* most iterations any right-hand side took          */
+  int n_sigma_fp64;     /* FP64 ladder applications                          */
+  int n_sigma_lowp;     /* reduced-precision ladder applications             */
+  double final_relres;  /* largest final relative residual (FP64 residual)   */
+  double seconds;       /* wall time of the call                             */
+} lrcc_solve_info;
+
+/* Model response solve (paper Sec. 2.2): for every dipole component x and
+ * frequency w, solve (A - w) X = -xi_x with (A X) = D o X + sigma(X),
+ * D_ij^ab = e_a + e_b - e_i - e_j, xi_ij^ab = mu_ia mu_jb - mu_ib mu_ja, by
+ * Jacobi + DIIS (reduced precision: iterative refinement around it), then
+ * alpha_xy(w) = -<xi_x | X_y(w)>.
+ * eps    [o+v] float64, occupied first (device).
+ * L      [nchol][v][v] complex128 (device).
+ * mu     [ncomp][o][v] complex128 dipole ov block (device).
+ * omegas (host) [nomega] float64.
+ * alpha  (host) [nomega][ncomp][ncomp] complex128 interleaved.
+ * info   (host) nullable.
+ * Returns LRCC_ERR_NOT_CONVERGED if any RHS misses tol (alpha still written). */
+lrcc_status lrcc_solve(lrcc_handle h, int o, int v, int nchol,
+                       const double* eps, const void* L,
+                       int ncomp, const void* mu,
+                       int nomega, const double* omegas,
+                       const lrcc_solve_opts* opts,
+                       double* alpha, lrcc_solve_info* info);
+
+/* One instance of a batched solve; all pointers as in lrcc_solve. */
+typedef struct {
+  int o, v, nchol;
+  const double* eps;   /* device */
+  const void* L;       /* device, complex128 */
+  int ncomp;
+  const void* mu;      /* device, complex128 */
+  int nomega;
+  const double* omegas;/* host */
+  double* alpha;       /* host, [nomega][ncomp][ncomp] complex128 */
+} lrcc_instance;
+
+/* Solve several uneven instances together: every ladder application of
+ * every instance, component and frequency goes into one persistent launch
+ * per iteration (a work queue ordered longest tile first). */
+lrcc_status lrcc_solve_batched(lrcc_handle h, int ninst, const lrcc_instance* inst,
+                               const lrcc_solve_opts* opts, lrcc_solve_info* info);
+
+/* Host-only argument check of lrcc_ppl_sigma: runs the same validation and
+ * launches nothing (usable without a GPU; h may be NULL). */
+lrcc_status lrcc_check_sigma_args(int o, int v, int nchol, int nrhs,
+                                  const void* L, const void* X, const void* sigma,
+                                  lrcc_dtype dt, lrcc_prec prec, lrcc_cmul cmul);
+
+/* Static text for a status code. */
+const char* lrcc_status_str(lrcc_status s);
+/* Message of the last failed call on this handle ("" if none; h may be NULL
+ * for the last failure of a call made without a handle). */
+const char* lrcc_last_error(lrcc_handle h);
+/* Library version string. */
+const char* lrcc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRCC_H */

@@ -1,0 +1,291 @@
+"""Python binding of liblrcc, the MI355X particle-particle-ladder library.
+
+Argument marshalling only: every step of the ladder product, its adjoint and
+the response solve runs in the library's HIP kernels.  PyTorch provides the
+device memory and the stream.  There is no CPU fallback: if liblrcc.so is
+missing or no gfx950 device is present, the calls raise.
+
+    import paper_2604_12914_amd as lrcc
+    sigma = lrcc.ppl_sigma(L, X)                 # torch complex tensors on cuda
+    dX, dL = lrcc.ppl_sigma_adjoint(L, X, G)
+    alpha, info = lrcc.solve(eps, L, mu, omegas)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB_PATH = os.path.join(HERE, "liblrcc.so")
+HEADER = os.path.join(ROOT, "include", "lrcc.h")
+
+# enums of include/lrcc.h
+STATUS = {0: "LRCC_OK", 1: "LRCC_ERR_ARG", 2: "LRCC_ERR_SHAPE", 3: "LRCC_ERR_DTYPE",
+          4: "LRCC_ERR_DEVICE", 5: "LRCC_ERR_NOMEM", 6: "LRCC_ERR_NOT_CONVERGED",
+          7: "LRCC_ERR_NONFINITE", 8: "LRCC_ERR_UNSUPPORTED"}
+OK, ERR_ARG, ERR_SHAPE, ERR_DTYPE, ERR_DEVICE, ERR_NOMEM, ERR_NOT_CONVERGED, \
+    ERR_NONFINITE, ERR_UNSUPPORTED = range(9)
+C128, C64 = 0, 1
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+CMUL = {"4m": 0, "3m": 1}
+
+
+class LrccError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("diis_dim", ctypes.c_int), ("prec", ctypes.c_int),
+                ("cmul", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int), ("deterministic", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters_max", ctypes.c_int), ("n_sigma_fp64", ctypes.c_int),
+                ("n_sigma_lowp", ctypes.c_int), ("final_relres", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("o", ctypes.c_int), ("v", ctypes.c_int), ("nchol", ctypes.c_int),
+                ("eps", ctypes.c_void_p), ("L", ctypes.c_void_p), ("ncomp", ctypes.c_int),
+                ("mu", ctypes.c_void_p), ("nomega", ctypes.c_int),
+                ("omegas", ctypes.c_void_p), ("alpha", ctypes.c_void_p)]
+
+
+_lib = None
+_lock = threading.Lock()
+_handles = {}
+
+
+def header_symbols():
+    """Names of the functions include/lrcc.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:lrcc_status|const char\*)\s+(lrcc_\w+)\s*\(",
+                                 text, re.M)))
+
+
+def lib() -> ctypes.CDLL:
+    """Load liblrcc.so (built by paper_2604_12914_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run "
+                               "'python -m paper_2604_12914_amd.build'")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        sig = {
+            "lrcc_create": [ctypes.POINTER(vp), i, vp],
+            "lrcc_destroy": [vp],
+            "lrcc_set_stream": [vp, vp],
+            "lrcc_ppl_sigma": [vp, i, i, i, i, vp, vp, vp, i, i, i],
+            "lrcc_ppl_sigma_adjoint": [vp, i, i, i, i, vp, vp, vp, vp, vp, i, i, i],
+            "lrcc_solve": [vp, i, i, i, vp, vp, i, vp, i, vp,
+                           ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)],
+            "lrcc_solve_batched": [vp, i, ctypes.POINTER(Instance),
+                                   ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)],
+            "lrcc_check_sigma_args": [i, i, i, i, vp, vp, vp, i, i, i],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        for name in ("lrcc_status_str",):
+            getattr(L, name).argtypes = [ctypes.c_int]
+            getattr(L, name).restype = ctypes.c_char_p
+        L.lrcc_last_error.argtypes = [vp]
+        L.lrcc_last_error.restype = ctypes.c_char_p
+        L.lrcc_version.argtypes = []
+        L.lrcc_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int, h=None):
+    if status != OK:
+        msg = lib().lrcc_last_error(h).decode()
+        raise LrccError(status, msg)
+
+
+def handle(device: int):
+    """Per-device library handle (created once, bound to torch's stream)."""
+    import torch
+    with _lock:
+        h = _handles.get(device)
+        if h is None:
+            hp = ctypes.c_void_p()
+            _check(lib().lrcc_create(ctypes.byref(hp), device, None))
+            h = hp.value
+            _handles[device] = h
+    stream = torch.cuda.current_stream(device).cuda_stream
+    _check(lib().lrcc_set_stream(h, ctypes.c_void_p(stream)), h)
+    return h
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.complex128:
+        return C128
+    if t.dtype == torch.complex64:
+        return C64
+    raise TypeError(f"expected complex64 or complex128, got {t.dtype}")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
+
+
+def _o_from_npo(npo: int) -> int:
+    o = int(round((1 + math.sqrt(1 + 8 * npo)) / 2)) if npo else 0
+    if o * (o - 1) // 2 != npo:
+        raise ValueError(f"{npo} is not a pair count o(o-1)/2")
+    return o
+
+
+def _geometry(L, X, o):
+    if L.dim() != 3 or L.shape[1] != L.shape[2]:
+        raise ValueError("L must be [nchol, v, v]")
+    if X.dim() != 3:
+        raise ValueError("X must be [nrhs, o(o-1)/2, v(v-1)/2]")
+    nchol, v = L.shape[0], L.shape[1]
+    if X.shape[2] != v * (v - 1) // 2:
+        raise ValueError("X's last extent must be v(v-1)/2")
+    o = _o_from_npo(X.shape[1]) if o is None else o
+    if X.shape[1] != o * (o - 1) // 2:
+        raise ValueError("X's middle extent must be o(o-1)/2")
+    if not (L.is_cuda and X.is_cuda and L.device == X.device):
+        raise ValueError("L and X must be on the same GPU")
+    if L.dtype != X.dtype:
+        raise TypeError("L and X must have the same dtype")
+    return nchol, v, o, X.shape[0], X.device.index
+
+
+def ppl_sigma(L, X, o=None, prec="fp64", cmul="4m", out=None):
+    """sigma = PPL(L, X) on the GPU; returns a new tensor (or fills ``out``)."""
+    import torch
+    L, X = L.contiguous(), X.contiguous()
+    nchol, v, o, nrhs, dev = _geometry(L, X, o)
+    out = torch.empty_like(X) if out is None else out
+    h = handle(dev)
+    _check(lib().lrcc_ppl_sigma(h, o, v, nchol, nrhs, _ptr(L), _ptr(X), _ptr(out),
+                                _dtype_code(X), PREC[prec], CMUL[cmul]), h)
+    return out
+
+
+def ppl_sigma_adjoint(L, X, G, o=None, want_dX=True, want_dL=True, prec="fp64", cmul="4m"):
+    """(dX, dL) for upstream gradient G of sigma = PPL(L, X)."""
+    import torch
+    L, X, G = L.contiguous(), X.contiguous(), G.contiguous()
+    nchol, v, o, nrhs, dev = _geometry(L, X, o)
+    if G.shape != X.shape or G.dtype != X.dtype:
+        raise ValueError("G must match X")
+    dX = torch.empty_like(X) if want_dX else None
+    dL = torch.empty_like(L) if want_dL else None
+    h = handle(dev)
+    _check(lib().lrcc_ppl_sigma_adjoint(h, o, v, nchol, nrhs, _ptr(L), _ptr(X), _ptr(G),
+                                        _ptr(dX), _ptr(dL), _dtype_code(X), PREC[prec],
+                                        CMUL[cmul]), h)
+    return dX, dL
+
+
+def _autograd_function():
+    import torch
+
+    class PPLSigma(torch.autograd.Function):
+        """sigma = PPL(L, X) with a hand-written backward (adjoint ladder and
+        dL kernels; integral tiles recomputed, never stored)."""
+
+        @staticmethod
+        def forward(ctx, L, X, prec="fp64", cmul="4m"):
+            ctx.save_for_backward(L, X)
+            ctx.prec, ctx.cmul = prec, cmul
+            return ppl_sigma(L, X, prec=prec, cmul=cmul)
+
+        @staticmethod
+        def backward(ctx, G):
+            L, X = ctx.saved_tensors
+            dX, dL = ppl_sigma_adjoint(L, X, G, want_dX=ctx.needs_input_grad[1],
+                                       want_dL=ctx.needs_input_grad[0],
+                                       prec=ctx.prec, cmul=ctx.cmul)
+            return dL, dX, None, None
+
+    return PPLSigma
+
+
+_PPLSigma = None
+
+
+def PPLSigma():
+    """The torch.autograd.Function class (created on first use)."""
+    global _PPLSigma
+    if _PPLSigma is None:
+        _PPLSigma = _autograd_function()
+    return _PPLSigma
+
+
+def ppl(L, X, prec="fp64", cmul="4m"):
+    """Differentiable sigma = PPL(L, X)."""
+    return PPLSigma().apply(L, X, prec, cmul)
+
+
+def solve(eps, L, mu, omegas, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64",
+          cmul="4m", inner_tol=1e-5, max_outer=6, check=True):
+    """Model response solve; returns (alpha [nomega, ncomp, ncomp] complex128 numpy,
+    info dict)."""
+    import numpy as np
+    import torch
+    L, mu, eps = L.contiguous(), mu.contiguous(), eps.contiguous()
+    if L.dtype != torch.complex128 or mu.dtype != torch.complex128 or eps.dtype != torch.float64:
+        raise TypeError("solve takes complex128 L and mu and float64 eps")
+    nchol, v = L.shape[0], L.shape[1]
+    ncomp, o = mu.shape[0], mu.shape[1]
+    om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+    alpha = np.zeros((len(om), ncomp, ncomp), dtype=np.complex128)
+    opts = SolveOpts(tol, max_iter, diis_dim, PREC[prec], CMUL[cmul], inner_tol, max_outer, 0)
+    info = SolveInfo()
+    h = handle(L.device.index)
+    st = lib().lrcc_solve(h, o, v, nchol, _ptr(eps), _ptr(L), ncomp, _ptr(mu), len(om),
+                          om.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts),
+                          alpha.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info))
+    if st != OK and (check or st != ERR_NOT_CONVERGED):
+        _check(st, h)
+    return alpha, dict(info.as_dict(), status=STATUS[st])
+
+
+def solve_batched(instances, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64", cmul="4m",
+                  inner_tol=1e-5, max_outer=6, check=True):
+    """Batched solve of several instances: each a dict(eps, L, mu, omegas)."""
+    import numpy as np
+    import torch
+    keep, arr = [], (Instance * len(instances))()
+    alphas = []
+    dev = None
+    for k, inst in enumerate(instances):
+        L, mu, eps = (inst["L"].contiguous(), inst["mu"].contiguous(),
+                      inst["eps"].contiguous())
+        if L.dtype != torch.complex128 or mu.dtype != torch.complex128:
+            raise TypeError("solve_batched takes complex128 L and mu")
+        om = np.ascontiguousarray(np.asarray(inst["omegas"], dtype=np.float64))
+        al = np.zeros((len(om), mu.shape[0], mu.shape[0]), dtype=np.complex128)
+        keep += [L, mu, eps, om]
+        alphas.append(al)
+        dev = L.device.index
+        arr[k] = Instance(mu.shape[1], L.shape[1], L.shape[0], eps.data_ptr(), L.data_ptr(),
+                          mu.shape[0], mu.data_ptr(), len(om), om.ctypes.data, al.ctypes.data)
+    opts = SolveOpts(tol, max_iter, diis_dim, PREC[prec], CMUL[cmul], inner_tol, max_outer, 0)
+    info = SolveInfo()
+    h = handle(dev)
+    st = lib().lrcc_solve_batched(h, len(instances), arr, ctypes.byref(opts), ctypes.byref(info))
+    if st != OK and (check or st != ERR_NOT_CONVERGED):
+        _check(st, h)
+    return alphas, dict(info.as_dict(), status=STATUS[st])

@@ -1,0 +1,287 @@
+// C ABI entry points of the ladder library: handles, validation, sigma.
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace lrcc {
+
+namespace {
+thread_local std::string g_last_error;
+
+// Makes the handle's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+}  // namespace
+
+lrcc_status fail(lrcc_handle h, lrcc_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  g_last_error = msg;
+  return s;
+}
+
+lrcc_status hip_fail(lrcc_handle h, hipError_t e, const char* what) {
+  std::string m = std::string("HIP error in ") + what + ": " + hipGetErrorString(e);
+  return fail(h, e == hipErrorOutOfMemory ? LRCC_ERR_NOMEM : LRCC_ERR_DEVICE, m);
+}
+
+Geom make_geom(int o, int v, int nchol, int nrhs, int kc) {
+  Geom g;
+  g.o = o;
+  g.v = v;
+  g.nchol = nchol;
+  g.nrhs = nrhs;
+  g.npo = npair(o);
+  g.npv = npair(v);
+  g.M = (long)nrhs * g.npo;
+  g.Mp = roundup(g.M, 16);
+  g.nbv = (v + TB - 1) / TB;
+  g.nbp = g.nbv * (g.nbv + 1) / 2;
+  g.ncp = (int)roundup(nchol, kc);
+  return g;
+}
+
+hipError_t Buf::ensure(size_t bytes) {
+  bytes = (size_t)roundup((long)(bytes ? bytes : 16), 256);
+  if (bytes <= n) return hipSuccess;
+  release();
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    n = 0;
+    (void)hipGetLastError();
+    return e;
+  }
+  n = bytes;
+  return hipSuccess;
+}
+
+void Buf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  n = 0;
+}
+
+lrcc_status ensure_tab(lrcc_handle h, int nbv) {
+  if (h->tab_nbv == nbv) return LRCC_OK;
+  const int nbp = nbv * (nbv + 1) / 2;
+  std::vector<int> t(nbp > 0 ? nbp : 1);
+  int k = 0;
+  for (int A = 0; A < nbv; ++A)
+    for (int B = A; B < nbv; ++B) t[k++] = (A << 16) | B;
+  LRCC_HIP(h, h->tab.ensure(t.size() * sizeof(int)));
+  LRCC_HIP(h, hipMemcpyAsync(h->tab.p, t.data(), t.size() * sizeof(int), hipMemcpyHostToDevice,
+                             h->stream));
+  LRCC_HIP(h, hipStreamSynchronize(h->stream));
+  h->tab_nbv = nbv;
+  return LRCC_OK;
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+static lrcc_status check_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* L,
+                               const void* X, const void* S, lrcc_dtype dt, lrcc_prec prec,
+                               lrcc_cmul cmul, const char* sname) {
+  if (o < 0 || v < 0 || nchol < 0 || nrhs < 0)
+    return fail(h, LRCC_ERR_ARG, "o, v, nchol and nrhs must be non-negative");
+  if (dt != LRCC_C128 && dt != LRCC_C64) return fail(h, LRCC_ERR_ARG, "unknown dtype");
+  if (prec != LRCC_FP64 && prec != LRCC_FP32 && prec != LRCC_BF16X3)
+    return fail(h, LRCC_ERR_ARG, "unknown precision");
+  if (cmul != LRCC_CMUL_4M && cmul != LRCC_CMUL_3M)
+    return fail(h, LRCC_ERR_ARG, "unknown complex-multiply form");
+  if (v > 4096) return fail(h, LRCC_ERR_SHAPE, "v exceeds 4096");
+  if (nchol > 65536) return fail(h, LRCC_ERR_SHAPE, "nchol exceeds 65536");
+  const long M = (long)nrhs * npair(o);
+  if (M > (1L << 24)) return fail(h, LRCC_ERR_SHAPE, "nrhs*o(o-1)/2 exceeds 2^24");
+  const size_t es = dt == LRCC_C128 ? 16 : 8;
+  const size_t nx = (size_t)M * npair(v) * es;
+  const size_t nl = (size_t)nchol * v * v * es;
+  if (nx > 0) {
+    if (!X) return fail(h, LRCC_ERR_ARG, "X is NULL");
+    if (!S) return fail(h, LRCC_ERR_ARG, std::string(sname) + " is NULL");
+    if ((uintptr_t)X % es || (uintptr_t)S % es)
+      return fail(h, LRCC_ERR_ARG, "X/sigma not aligned to the element size");
+    if (overlaps(X, nx, S, nx)) return fail(h, LRCC_ERR_ARG, "sigma overlaps X");
+    if (nl > 0) {
+      if (!L) return fail(h, LRCC_ERR_ARG, "L is NULL");
+      if ((uintptr_t)L % es) return fail(h, LRCC_ERR_ARG, "L not aligned to the element size");
+      if (overlaps(L, nl, S, nx)) return fail(h, LRCC_ERR_ARG, "sigma overlaps L");
+    }
+  }
+  return LRCC_OK;
+}
+
+lrcc_status sigma_packed(lrcc_handle h, const Geom& g, const void* L, bool conj_t,
+                         const void* X, void* S, lrcc_dtype dt, lrcc_prec prec,
+                         lrcc_cmul cmul) {
+  const size_t es = dt == LRCC_C128 ? 16 : 8;
+  const size_t nx = (size_t)g.M * g.npv * es;
+  if (nx == 0) return LRCC_OK;
+  if (prec == LRCC_BF16X3 || cmul == LRCC_CMUL_3M)
+    return fail(h, LRCC_ERR_UNSUPPORTED, "this precision / complex form is not built yet");
+  lrcc_status st = ensure_tab(h, g.nbv);
+  if (st != LRCC_OK) return st;
+  const int* tab = h->tab.as<int>();
+  const bool acc64 = dt == LRCC_C128 || prec == LRCC_FP64;
+  LRCC_HIP(h, h->ls.ensure(ppl_ls_bytes(prec, cmul, g)));
+  LRCC_HIP(h, h->xb.ensure(ppl_xb_bytes(prec, g)));
+  const size_t sbytes = (size_t)2 * g.xb_plane() * (acc64 ? 8 : 4);
+  LRCC_HIP(h, h->sb.ensure(sbytes));
+  LRCC_HIP(h, fill_zero(h->sb.p, sbytes, h->stream));
+  if (g.nchol > 0) {
+    const int np = ppl_planes(prec, cmul);
+    if (prec == LRCC_FP64) {
+      LRCC_HIP(h, stage_L<double>(L, dt, g, np, conj_t, h->ls.as<double>(), h->stream));
+      LRCC_HIP(h, pack_to_block<double>(X, dt, g, tab, h->xb.as<double>(), h->stream));
+    } else {
+      LRCC_HIP(h, stage_L<float>(L, dt, g, np, conj_t, h->ls.as<float>(), h->stream));
+      LRCC_HIP(h, pack_to_block<float>(X, dt, g, tab, h->xb.as<float>(), h->stream));
+    }
+    LRCC_HIP(h, ppl_launch(prec, cmul, acc64, g, h->ls.p, h->xb.p, h->sb.p, tab, h->stream));
+  }
+  if (acc64)
+    LRCC_HIP(h, block_to_pack<double>(h->sb.as<double>(), g, tab, S, dt, h->stream));
+  else
+    LRCC_HIP(h, block_to_pack<float>(h->sb.as<float>(), g, tab, S, dt, h->stream));
+  return LRCC_OK;
+}
+
+}  // namespace lrcc
+
+using namespace lrcc;
+
+extern "C" {
+
+lrcc_status lrcc_create(lrcc_handle* out, int device, void* stream) {
+  if (!out) return fail(nullptr, LRCC_ERR_ARG, "handle pointer is NULL");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+    (void)hipGetLastError();
+    return fail(nullptr, LRCC_ERR_DEVICE, "no HIP device");
+  }
+  if (device < 0 || device >= ndev) return fail(nullptr, LRCC_ERR_ARG, "device out of range");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+    return fail(nullptr, LRCC_ERR_DEVICE, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, LRCC_ERR_DEVICE,
+                std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+  lrcc_handle h = new (std::nothrow) lrcc_handle_s();
+  if (!h) return fail(nullptr, LRCC_ERR_NOMEM, "out of host memory");
+  h->device = device;
+  h->stream = static_cast<hipStream_t>(stream);
+  h->ncu = prop.multiProcessorCount;
+  *out = h;
+  return LRCC_OK;
+}
+
+lrcc_status lrcc_destroy(lrcc_handle h) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  {
+    DeviceGuard dg(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    h->ls.release();
+    h->ls2.release();
+    h->xb.release();
+    h->sb.release();
+    h->gb.release();
+    h->tab.release();
+    for (auto& b : h->sv) b.release();
+  }
+  delete h;
+  return LRCC_OK;
+}
+
+lrcc_status lrcc_set_stream(lrcc_handle h, void* stream) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  h->stream = static_cast<hipStream_t>(stream);
+  return LRCC_OK;
+}
+
+lrcc_status lrcc_check_sigma_args(int o, int v, int nchol, int nrhs, const void* L, const void* X,
+                                  const void* sigma, lrcc_dtype dt, lrcc_prec prec,
+                                  lrcc_cmul cmul) {
+  return check_sigma(nullptr, o, v, nchol, nrhs, L, X, sigma, dt, prec, cmul, "sigma");
+}
+
+lrcc_status lrcc_ppl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* L,
+                           const void* X, void* sigma, lrcc_dtype dt, lrcc_prec prec,
+                           lrcc_cmul cmul) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  lrcc_status st = check_sigma(h, o, v, nchol, nrhs, L, X, sigma, dt, prec, cmul, "sigma");
+  if (st != LRCC_OK) return st;
+  DeviceGuard dg(h->device);
+  h->err.clear();
+  Geom g = make_geom(o, v, nchol, nrhs, ppl_chunk(prec, cmul));
+  return sigma_packed(h, g, L, false, X, sigma, dt, prec, cmul);
+}
+
+lrcc_status lrcc_ppl_sigma_adjoint(lrcc_handle h, int o, int v, int nchol, int nrhs,
+                                   const void* L, const void* X, const void* G, void* dX,
+                                   void* dL, lrcc_dtype dt, lrcc_prec prec, lrcc_cmul cmul) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  lrcc_status st = check_sigma(h, o, v, nchol, nrhs, L, G, dX ? dX : (void*)1, dt, prec, cmul,
+                               "dX");
+  if (st != LRCC_OK) return st;
+  if (dL) return fail(h, LRCC_ERR_UNSUPPORTED, "dL is not built yet");
+  (void)X;
+  DeviceGuard dg(h->device);
+  h->err.clear();
+  Geom g = make_geom(o, v, nchol, nrhs, ppl_chunk(prec, cmul));
+  if (dX) {
+    // the adjoint ladder: sigma with (L^P)^H, applied to G
+    st = sigma_packed(h, g, L, true, G, dX, dt, prec, cmul);
+    if (st != LRCC_OK) return st;
+  }
+  return LRCC_OK;
+}
+
+lrcc_status lrcc_solve(lrcc_handle h, int, int, int, const double*, const void*, int,
+                       const void*, int, const double*, const lrcc_solve_opts*, double*,
+                       lrcc_solve_info*) {
+  return fail(h, LRCC_ERR_UNSUPPORTED, "solve is not built yet");
+}
+
+lrcc_status lrcc_solve_batched(lrcc_handle h, int, const lrcc_instance*, const lrcc_solve_opts*,
+                               lrcc_solve_info*) {
+  return fail(h, LRCC_ERR_UNSUPPORTED, "batched solve is not built yet");
+}
+
+const char* lrcc_status_str(lrcc_status s) {
+  switch (s) {
+    case LRCC_OK: return "ok";
+    case LRCC_ERR_ARG: return "invalid argument";
+    case LRCC_ERR_SHAPE: return "invalid shape";
+    case LRCC_ERR_DTYPE: return "unsupported dtype";
+    case LRCC_ERR_DEVICE: return "device error";
+    case LRCC_ERR_NOMEM: return "out of memory";
+    case LRCC_ERR_NOT_CONVERGED: return "not converged";
+    case LRCC_ERR_NONFINITE: return "non-finite value";
+    case LRCC_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* lrcc_last_error(lrcc_handle h) {
+  return h ? h->err.c_str() : g_last_error.c_str();
+}
+
+const char* lrcc_version(void) { return "lrcc 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Internal declarations of the lrcc library (not part of the ABI).
+//
+// Block-pair layout used by every kernel
+// --------------------------------------
+// Virtual indices are grouped in blocks of TB = 8; nbv = ceil(v / 8).  An
+// ordered block pair (A, B) with A <= B has index
+//   bp(A, B) = A * nbv - A * (A - 1) / 2 + (B - A),   nbp = nbv (nbv + 1) / 2,
+// and holds NS = 64 slots s = a_l * 8 + b_l for a = 8A + a_l, b = 8B + b_l.
+// A slot is live when a < b < v; dead slots hold zeros.
+//
+// Doubles (X, sigma, G) live on the device as planar arrays
+//   buf[plane][bp][m][64],   m = r * o(o-1)/2 + ij,  m < Mp = roundup(M, 16)
+// so the 64 slots of one block pair and all rows m form one contiguous run.
+//
+// Cholesky vectors are staged (once per call) as
+//   Ls[A][C][P][plane][64],  64 = a_l * 8 + c_l,  P < ncp = roundup(nchol, KC)
+// so one 8 x 8 block of every L^P is a contiguous 64-element run per plane.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/lrcc.h"
+
+namespace lrcc {
+
+constexpr int TB = 8;    // virtual indices per block
+constexpr int NS = 64;   // slots per block pair
+constexpr int WG = 256;  // threads per workgroup of the ladder kernels
+
+inline long npair(long n) { return n * (n - 1) / 2; }
+inline long roundup(long x, long m) { return (x + m - 1) / m * m; }
+
+struct Geom {
+  int o = 0, v = 0, nchol = 0, nrhs = 0;
+  long npo = 0, npv = 0;  // occupied / virtual pair counts
+  long M = 0, Mp = 0;     // rows (nrhs * npo) and rows padded to 16
+  int nbv = 0, nbp = 0;   // virtual blocks, block pairs
+  int ncp = 0;            // nchol padded to the chunk length
+  long xb_plane() const { return (long)nbp * Mp * NS; }  // elements per plane
+};
+
+Geom make_geom(int o, int v, int nchol, int nrhs, int kc);
+
+// Grow-only device buffer.
+struct Buf {
+  void* p = nullptr;
+  size_t n = 0;
+  hipError_t ensure(size_t bytes);
+  void release();
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace lrcc
+
+struct lrcc_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int ncu = 0;
+  // ladder workspace
+  lrcc::Buf ls, ls2;      // staged Cholesky vectors (ls2: second operand set)
+  lrcc::Buf xb, sb, gb;   // block-layout doubles: input, accumulator, gradient
+  lrcc::Buf tab;          // block-pair table
+  int tab_nbv = -1;
+  // solver workspace
+  lrcc::Buf sv[12];
+};
+
+namespace lrcc {
+
+// Status helpers -------------------------------------------------------------
+lrcc_status fail(lrcc_handle h, lrcc_status s, const std::string& msg);
+lrcc_status hip_fail(lrcc_handle h, hipError_t e, const char* what);
+
+#define LRCC_HIP(h, call)                                   \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return ::lrcc::hip_fail(h, e_, #call); \
+  } while (0)
+
+// Staging / layout launchers (layout.hip) ----------------------------------
+// Stage L (complex, dtype dt) into planar blocks of type T with nplanes = 2
+// (re, im) or 3 (re, im, re+im).  conj_t: stage (L^P)^H instead of L^P.
+template <typename T>
+hipError_t stage_L(const void* L, lrcc_dtype dt, const Geom& g, int nplanes,
+                   bool conj_t, T* Ls, hipStream_t st);
+// Packed doubles -> planar block layout (2 planes of T); dead slots and pad
+// rows are written as zero.
+template <typename T>
+hipError_t pack_to_block(const void* X, lrcc_dtype dt, const Geom& g,
+                         const int* tab, T* Xb, hipStream_t st);
+// Planar block layout (2 planes of T) -> packed doubles in dtype dt.
+template <typename T>
+hipError_t block_to_pack(const T* Sb, const Geom& g, const int* tab, void* S,
+                         lrcc_dtype dt, hipStream_t st);
+hipError_t fill_zero(void* p, size_t bytes, hipStream_t st);
+
+// Ladder launchers (ppl_mfma.hip) -------------------------------------------
+// Sb (2 planes, accumulated with atomics) += PPL of Xb for all tile pairs.
+// Sb must be zeroed by the caller.
+hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
+                      const void* Ls, const void* Xb, void* Sb, const int* tab,
+                      hipStream_t st);
+int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul);   // KC of the staged layout
+int ppl_planes(lrcc_prec prec, lrcc_cmul cmul);  // planes of the staged L
+size_t ppl_ls_bytes(lrcc_prec prec, lrcc_cmul cmul, const Geom& g);
+size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g);
+
+// Block-pair table: tab[bp] = (A << 16) | B.
+lrcc_status ensure_tab(lrcc_handle h, int nbv);
+
+// Full sigma on device pointers in the packed layout (used by the API and
+// the solver).  X, S packed in dtype dt.
+lrcc_status sigma_packed(lrcc_handle h, const Geom& g, const void* L, bool conj_t,
+                         const void* X, void* S, lrcc_dtype dt, lrcc_prec prec,
+                         lrcc_cmul cmul);
+
+}  // namespace lrcc

@@ -1,0 +1,305 @@
+// Fused particle-particle-ladder kernel for gfx950 (FP64 and FP32 MFMA).
+//
+// One workgroup (4 waves) owns one tile pair (AB, CD) of virtual block pairs
+// and does, without leaving the CU:
+//   1. build   W1[(a,c),(b,d)] = sum_P L^P_ac L^P_bd   (a in A, c in C, b in B, d in D)
+//              W2[(a,d),(b,c)] = sum_P L^P_ad L^P_bc
+//      as two 64 x 64 complex GEMMs over the Cholesky index on the matrix
+//      cores (16x16x4 MFMA, complex product in 4M form), operands streamed
+//      through LDS in chunks of KC vectors;
+//   2. antisymmetrise in LDS: V[(ab),(cd)] = 2 (W1 - W2) = 2 <ab||cd>, dead
+//      slots zeroed (the 2 turns the unrestricted c,d sum into the packed
+//      c<d sum);
+//   3. contract   sigma[m, ab] += sum_cd X[m, cd] V[ab, cd] for every row m,
+//      on the matrix cores, and add the 64-slot partial sums to the block-
+//      layout accumulator with device-scope atomics.
+// The integral tile never reaches HBM.
+#include "internal.hpp"
+
+namespace lrcc {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef d4 t; };
+template <> struct Acc<float> { typedef f4 t; };
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Output row of accumulator item r in lane group lk (column = lane % 16).
+// The f64 16x16x4 MFMA interleaves rows across lane groups (row lk + 4r);
+// the f32 one keeps them together (row 4 lk + r).  Inputs: A[i][k] and
+// B[k][j] come from lane i + 16 k and j + 16 k for both.
+template <typename T> __device__ __forceinline__ int out_row(int lk, int r);
+template <> __device__ __forceinline__ int out_row<double>(int lk, int r) { return lk + 4 * r; }
+template <> __device__ __forceinline__ int out_row<float>(int lk, int r) { return 4 * lk + r; }
+
+template <typename T> struct Vec16;
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+template <> struct Vec16<double> { typedef dv2 t; static constexpr int n = 2; };
+template <> struct Vec16<float> { typedef fv4 t; static constexpr int n = 4; };
+
+__device__ __forceinline__ void atomic_add(double* p, double x) { unsafeAtomicAdd(p, x); }
+__device__ __forceinline__ void atomic_add(float* p, float x) { unsafeAtomicAdd(p, x); }
+
+// LDS bytes: 4 blocks x KC vectors x 2 planes x 64 of T; the 64 x 64 complex
+// V tile (2 planes x 4096 of T) reuses the same space after the build.
+template <typename T, int KC>
+struct Smem {
+  static constexpr int chunk = 2 * NS * KC;        // elements of one block's chunk
+  static constexpr int build = 4 * chunk;
+  static constexpr int vtile = 2 * NS * NS;
+  static constexpr int elems = build > vtile ? build : vtile;
+};
+
+template <typename T, typename TA, int KC>
+__global__ __launch_bounds__(WG, 1) void k_ppl_4m(const T* __restrict__ Ls,
+                                                  const T* __restrict__ Xb,
+                                                  TA* __restrict__ Sb,
+                                                  const int* __restrict__ tab, int nbv,
+                                                  int nbp, int ncp, int Mp, int v) {
+  typedef typename Acc<T>::t acc_t;
+  typedef typename Vec16<T>::t vec_t;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int CH = Smem<T, KC>::chunk;
+  __shared__ __attribute__((aligned(16))) T lds[Smem<T, KC>::elems];
+
+  const int tile = blockIdx.x;
+  const int ab = tile / nbp, cd = tile - ab * nbp;
+  const int pAB = tab[ab], pCD = tab[cd];
+  const int A = pAB >> 16, B = pAB & 0xffff, C = pCD >> 16, D = pCD & 0xffff;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+
+  // ---- 1. build W1 (rows (a,c) of this wave, all columns (b,d)) and W2 ----
+  const size_t bstride = (size_t)ncp * 2 * NS;
+  const T* const gblk[4] = {Ls + (size_t)(A * nbv + C) * bstride,
+                            Ls + (size_t)(B * nbv + D) * bstride,
+                            Ls + (size_t)(A * nbv + D) * bstride,
+                            Ls + (size_t)(B * nbv + C) * bstride};
+
+  acc_t w1r[4], w1i[4], w2r[4], w2i[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    w1r[j] = acc_t{0, 0, 0, 0};
+    w1i[j] = w1r[j];
+    w2r[j] = w1r[j];
+    w2i[j] = w1r[j];
+  }
+
+  // chunk of KC vectors of the four blocks: contiguous runs of CH elements,
+  // prefetched into registers one chunk ahead of the MFMA work
+  constexpr int nvec = 4 * CH / VN;
+  constexpr int NPF = nvec / WG;        // vectors per thread per chunk
+  constexpr int KPB = CH / VN / WG;     // of which per block
+  static_assert(NPF == 4 * KPB, "chunk must split evenly over the workgroup");
+  vec_t pf[NPF];
+  auto fetch = [&](int p0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const vec_t* src = reinterpret_cast<const vec_t*>(gblk[q] + (size_t)p0 * 2 * NS);
+#pragma unroll
+      for (int k = 0; k < KPB; ++k) pf[q * KPB + k] = src[k * WG + threadIdx.x];
+    }
+  };
+  fetch(0);
+  for (int p0 = 0; p0 < ncp; p0 += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int k = 0; k < KPB; ++k)
+        reinterpret_cast<vec_t*>(lds + q * CH)[k * WG + threadIdx.x] = pf[q * KPB + k];
+    }
+    __syncthreads();
+    if (p0 + KC < ncp) fetch(p0 + KC);
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int p = 4 * ks + lk;  // vector within the chunk used by this lane
+      const T* lac = lds + 0 * CH + p * 2 * NS;
+      const T* lbd = lds + 1 * CH + p * 2 * NS;
+      const T* lad = lds + 2 * CH + p * 2 * NS;
+      const T* lbc = lds + 3 * CH + p * 2 * NS;
+      const T acr = lac[16 * wave + li], aci = lac[NS + 16 * wave + li];
+      const T adr = lad[16 * wave + li], adi = lad[NS + 16 * wave + li];
+      T bdr[4], bdi[4], bcr[4], bci[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        bdr[j] = lbd[16 * j + li];
+        bdi[j] = lbd[NS + 16 * j + li];
+        bcr[j] = lbc[16 * j + li];
+        bci[j] = lbc[NS + 16 * j + li];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        w1r[j] = mfma(acr, bdr[j], w1r[j]);
+        w1i[j] = mfma(acr, bdi[j], w1i[j]);
+        w2r[j] = mfma(adr, bcr[j], w2r[j]);
+        w2i[j] = mfma(adr, bci[j], w2i[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        w1r[j] = mfma(-aci, bdi[j], w1r[j]);
+        w1i[j] = mfma(aci, bdr[j], w1i[j]);
+        w2r[j] = mfma(-adi, bci[j], w2r[j]);
+        w2i[j] = mfma(adi, bcr[j], w2i[j]);
+      }
+    }
+  }
+  __syncthreads();  // every wave is done with the chunk buffers
+
+  // ---- 2. antisymmetrise into V[cd][ab] (planar) in LDS --------------------
+  T* Vr = lds;
+  T* Vi = lds + NS * NS;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * wave + out_row<T>(lk, r), jj = 16 * j + li;
+      // W1 element: i = (a_l, c_l), jj = (b_l, d_l)
+      const int idx = ((i & 7) * TB + (jj & 7)) * NS + (i >> 3) * TB + (jj >> 3);
+      Vr[idx] = (T)2 * w1r[j][r];
+      Vi[idx] = (T)2 * w1i[j][r];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * wave + out_row<T>(lk, r), jj = 16 * j + li;
+      // W2 element: i = (a_l, d_l), jj = (b_l, c_l)
+      const int al = i >> 3, dl = i & 7, bl = jj >> 3, cl = jj & 7;
+      const int idx = (cl * TB + dl) * NS + al * TB + bl;
+      const bool live = (A < B || al < bl) && (B * TB + bl < v) && (C < D || cl < dl) &&
+                        (D * TB + dl < v);
+      Vr[idx] = live ? Vr[idx] - (T)2 * w2r[j][r] : (T)0;
+      Vi[idx] = live ? Vi[idx] - (T)2 * w2i[j][r] : (T)0;
+    }
+  }
+  __syncthreads();
+
+  // ---- 3. contract against X[:, CD] and accumulate into sigma[:, AB] ------
+  const size_t plane = (size_t)nbp * Mp * NS;
+  const T* xr_g = Xb + (size_t)cd * Mp * NS;
+  const T* xi_g = xr_g + plane;
+  TA* sr_g = Sb + (size_t)ab * Mp * NS;
+  TA* si_g = sr_g + plane;
+  // lane (row li, group lk) holds X[m0+li][16 lk .. 16 lk + 15]; the rows of
+  // the next m-chunk are fetched while this one is contracted
+  constexpr int NX = 16 / VN;
+  vec_t xpr[NX], xpi[NX];
+  auto fetch_x = [&](int m0) {
+    const vec_t* pr = reinterpret_cast<const vec_t*>(xr_g + (size_t)(m0 + li) * NS + 16 * lk);
+    const vec_t* pi = reinterpret_cast<const vec_t*>(xi_g + (size_t)(m0 + li) * NS + 16 * lk);
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      xpr[k] = pr[k];
+      xpi[k] = pi[k];
+    }
+  };
+  if (wave < Mp / 16) fetch_x(wave * 16);
+  for (int mc = wave; mc < Mp / 16; mc += 4) {
+    const int m0 = mc * 16;
+    T xr[16], xi[16];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+#pragma unroll
+      for (int t = 0; t < VN; ++t) {
+        xr[k * VN + t] = xpr[k][t];
+        xi[k * VN + t] = xpi[k][t];
+      }
+    }
+    if (mc + 4 < Mp / 16) fetch_x(m0 + 64);
+    acc_t sr[4], si[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      sr[n] = acc_t{0, 0, 0, 0};
+      si[n] = sr[n];
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = 16 * lk + s;  // cd slot fed by this lane at step s
+      T vr[4], vi[4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        vr[n] = Vr[k * NS + 16 * n + li];
+        vi[n] = Vi[k * NS + 16 * n + li];
+      }
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        sr[n] = mfma(xr[s], vr[n], sr[n]);
+        si[n] = mfma(xr[s], vi[n], si[n]);
+      }
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        sr[n] = mfma(-xi[s], vi[n], sr[n]);
+        si[n] = mfma(xi[s], vr[n], si[n]);
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const size_t o = (size_t)(m0 + out_row<T>(lk, r)) * NS + 16 * n + li;
+        atomic_add(sr_g + o, (TA)sr[n][r]);
+        atomic_add(si_g + o, (TA)si[n][r]);
+      }
+    }
+  }
+}
+
+constexpr int KC64 = 16;
+constexpr int KC32 = 32;
+
+}  // namespace
+
+int ppl_chunk(lrcc_prec prec, lrcc_cmul) { return prec == LRCC_FP64 ? KC64 : KC32; }
+int ppl_planes(lrcc_prec, lrcc_cmul cmul) { return cmul == LRCC_CMUL_3M ? 3 : 2; }
+
+size_t ppl_ls_bytes(lrcc_prec prec, lrcc_cmul cmul, const Geom& g) {
+  const size_t es = prec == LRCC_FP64 ? 8 : 4;
+  return (size_t)g.nbv * g.nbv * g.ncp * ppl_planes(prec, cmul) * NS * es;
+}
+size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g) {
+  return (size_t)2 * g.xb_plane() * (prec == LRCC_FP64 ? 8 : 4);
+}
+
+hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
+                      const void* Ls, const void* Xb, void* Sb, const int* tab,
+                      hipStream_t st) {
+  if (cmul != LRCC_CMUL_4M) return hipErrorNotSupported;
+  const long ntile = (long)g.nbp * g.nbp;
+  if (ntile == 0 || g.Mp == 0) return hipSuccess;
+  if (ntile > 0x7fffffffL) return hipErrorInvalidValue;
+  dim3 grid((unsigned)ntile), block(WG);
+  if (prec == LRCC_FP64) {
+    hipLaunchKernelGGL((k_ppl_4m<double, double, KC64>), grid, block, 0, st,
+                       static_cast<const double*>(Ls), static_cast<const double*>(Xb),
+                       static_cast<double*>(Sb), tab, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v);
+  } else if (prec == LRCC_FP32) {
+    if (acc64)
+      hipLaunchKernelGGL((k_ppl_4m<float, double, KC32>), grid, block, 0, st,
+                         static_cast<const float*>(Ls), static_cast<const float*>(Xb),
+                         static_cast<double*>(Sb), tab, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v);
+    else
+      hipLaunchKernelGGL((k_ppl_4m<float, float, KC32>), grid, block, 0, st,
+                         static_cast<const float*>(Ls), static_cast<const float*>(Xb),
+                         static_cast<float*>(Sb), tab, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v);
+  } else {
+    return hipErrorNotSupported;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lrcc

@@ -1,0 +1,141 @@
+"""GPU parity of the fused ladder kernel against the FP64 oracle, through the
+C ABI (python binding -> liblrcc.so -> HIP kernels)."""
+import numpy as np
+import pytest
+
+import lrcc_synth as S
+from oracle import grads, ppl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def lrcc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_12914_amd as m
+    return m
+
+
+def dev(x, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda").to(dtype)
+
+
+def run(lrcc, L, X, prec="fp64", cmul="4m", dtype=torch.complex128):
+    s = lrcc.ppl_sigma(dev(L, dtype), dev(X, dtype), prec=prec, cmul=cmul)
+    torch.cuda.synchronize()
+    return s.cpu().numpy().astype(np.complex128)
+
+
+# (o, v, nchol, nrhs, hermitian): several tiles, ragged virtual blocks
+# (v not a multiple of 8), nchol not a multiple of the chunk, several RHS.
+CASES = [
+    (4, 24, 64, 1, True),      # tiny workload
+    (5, 44, 100, 3, False),    # ragged v, general complex L
+    (3, 37, 7, 2, False),      # short Cholesky index, odd v
+    (6, 16, 33, 1, True),
+    (2, 9, 16, 1, False),      # one full block plus a 1-wide tail
+    (7, 2, 5, 2, False),       # a single virtual pair
+]
+
+
+@pytest.mark.parametrize("o,v,nchol,nrhs,herm", CASES)
+def test_fp64_matches_oracle(lrcc, o, v, nchol, nrhs, herm):
+    print(f"fp64 parity o={o} v={v} nchol={nchol} nrhs={nrhs}", flush=True)
+    rng = np.random.default_rng(100 + v)
+    L = S.make_L(rng, nchol, v, hermitian=herm)
+    X = S.make_packed(rng, nrhs, o, v)
+    got = run(lrcc, L, X)
+    ref = ppl.sigma(L, X, o, v)
+    assert rel(got, ref) < 1e-10
+
+
+def test_fp64_complex64_storage(lrcc):
+    rng = np.random.default_rng(7)
+    o, v, nchol = 4, 30, 40
+    L = S.make_L(rng, nchol, v).astype(np.complex64)
+    X = S.make_packed(rng, 2, o, v).astype(np.complex64)
+    got = run(lrcc, L, X, dtype=torch.complex64)
+    ref = ppl.sigma(L.astype(np.complex128), X.astype(np.complex128), o, v)
+    assert rel(got, ref) < 1e-6       # only the final rounding to complex64
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_fp32_matches_oracle(lrcc, dtype):
+    rng = np.random.default_rng(8)
+    o, v, nchol = 5, 40, 160
+    L = S.make_L(rng, nchol, v)
+    X = S.make_packed(rng, 2, o, v)
+    got = run(lrcc, L, X, prec="fp32", dtype=dtype)
+    ref = ppl.sigma(L.astype(np.complex64).astype(np.complex128),
+                    X.astype(np.complex64).astype(np.complex128), o, v)
+    # FP32 products and sums over K = nchol and 64-slot tiles: ~ sqrt(K) * 2^-24
+    assert rel(got, ref) < 2e-6
+
+
+def test_empty_and_degenerate(lrcc):
+    rng = np.random.default_rng(9)
+    # nchol = 0: sigma is zero
+    X = S.make_packed(rng, 2, 4, 12)
+    L0 = np.zeros((0, 12, 12), np.complex128)
+    s = lrcc.ppl_sigma(dev(L0), dev(X))
+    assert float(torch.abs(s).max()) == 0.0
+    # no occupied pairs / no virtual pairs / no rhs: empty outputs, no error
+    for (o, v, nrhs) in [(1, 12, 2), (4, 1, 2), (4, 12, 0)]:
+        L = S.make_L(rng, 5, v)
+        X = np.zeros((nrhs, o * (o - 1) // 2, v * (v - 1) // 2), np.complex128)
+        s = lrcc.ppl_sigma(dev(L), dev(X), o=o)
+        assert s.shape == X.shape
+    # rank-one Hermitian vectors cancel exactly in <ab||cd>
+    v = 20
+    L = np.stack([np.outer(u, np.conj(u)) for u in S.cn(rng, (3, v))])
+    X = S.make_packed(rng, 1, 3, v)
+    got = run(lrcc, L, X)
+    assert np.linalg.norm(got) < 1e-13 * np.linalg.norm(L) ** 2 * np.linalg.norm(X)
+
+
+def test_argument_errors_raise(lrcc):
+    L = dev(S.make_L(np.random.default_rng(1), 4, 10))
+    X = dev(S.make_packed(np.random.default_rng(2), 1, 3, 10))
+    with pytest.raises(lrcc.LrccError) as e:
+        lrcc.lib().lrcc_ppl_sigma  # noqa: B018
+        lrcc._check(lrcc.lib().lrcc_ppl_sigma(lrcc.handle(0), 3, 10, 4, 1, lrcc._ptr(L),
+                                              lrcc._ptr(X), lrcc._ptr(X), 0, 0, 0),
+                    lrcc.handle(0))
+    assert e.value.status == lrcc.ERR_ARG
+
+
+def test_adjoint_dX_matches_oracle(lrcc):
+    rng = np.random.default_rng(10)
+    o, v, nchol = 4, 26, 48
+    L = S.make_L(rng, nchol, v, hermitian=False)
+    X, G = S.make_packed(rng, 2, o, v), S.make_packed(rng, 2, o, v)
+    dX, _ = lrcc.ppl_sigma_adjoint(dev(L), dev(X), dev(G), want_dL=False)
+    torch.cuda.synchronize()
+    assert rel(dX.cpu().numpy(), grads.vjp_X(L, G, o, v)) < 1e-10
+
+
+def test_baseline_size_sampled_entries(lrcc):
+    # the FP64 baseline workload (o=16, v=160, Nchol=640, 6 RHS), checked on
+    # sampled entries that the oracle computes one by one
+    o, v, nchol, nrhs = 16, 160, 640, 6
+    print(f"fp64 sampled parity o={o} v={v} nchol={nchol} nrhs={nrhs}", flush=True)
+    rng = np.random.default_rng(0)
+    L = S.make_L(rng, nchol, v)
+    X = S.make_packed(rng, nrhs, o, v)
+    got = run(lrcc, L, X).reshape(-1, X.shape[-1])
+    pa, pb = ppl.pairs(v)
+    srng = np.random.default_rng(1)
+    ks = np.concatenate([[0, 1, len(pa) - 1], srng.choice(len(pa), 29, replace=False)])
+    rows = np.concatenate([[0, got.shape[0] - 1], srng.choice(got.shape[0], 14, replace=False)])
+    ref = ppl.sigma_entries(L, X, v, rows, [(pa[k], pb[k]) for k in ks])
+    assert rel(got[np.ix_(rows, ks)], ref) < 1e-10
+    # invariants at full size: linearity in X and homogeneity in L
+    got2 = run(lrcc, 2.0 * L, X).reshape(got.shape)
+    assert rel(got2, 4.0 * got) < 1e-13
