@@ -252,10 +252,29 @@ lrcc_status lrcc_ppl_sigma_adjoint(lrcc_handle h, int o, int v, int nchol, int n
   return LRCC_OK;
 }
 
-lrcc_status lrcc_solve(lrcc_handle h, int, int, int, const double*, const void*, int,
-                       const void*, int, const double*, const lrcc_solve_opts*, double*,
-                       lrcc_solve_info*) {
-  return fail(h, LRCC_ERR_UNSUPPORTED, "solve is not built yet");
+lrcc_status lrcc_solve(lrcc_handle h, int o, int v, int nchol, const double* eps, const void* L,
+                       int ncomp, const void* mu, int nomega, const double* omegas,
+                       const lrcc_solve_opts* opts, double* alpha, lrcc_solve_info* info) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  if (o < 0 || v < 0 || nchol < 0 || ncomp < 0 || nomega < 0)
+    return fail(h, LRCC_ERR_ARG, "sizes must be non-negative");
+  if (v > 4096) return fail(h, LRCC_ERR_SHAPE, "v exceeds 4096");
+  if (nchol > 65536) return fail(h, LRCC_ERR_SHAPE, "nchol exceeds 65536");
+  if ((long)nomega * ncomp * npair(o) > (1L << 24))
+    return fail(h, LRCC_ERR_SHAPE, "nomega*ncomp*o(o-1)/2 exceeds 2^24");
+  if ((long)nomega * ncomp > 4096) return fail(h, LRCC_ERR_SHAPE, "more than 4096 right-hand sides");
+  if (nomega * ncomp > 0) {
+    if (!alpha) return fail(h, LRCC_ERR_ARG, "alpha is NULL");
+    if (!omegas) return fail(h, LRCC_ERR_ARG, "omegas is NULL");
+    if (o + v > 0 && !eps) return fail(h, LRCC_ERR_ARG, "eps is NULL");
+    if (o > 0 && v > 0 && !mu) return fail(h, LRCC_ERR_ARG, "mu is NULL");
+    if (nchol > 0 && v > 0 && !L) return fail(h, LRCC_ERR_ARG, "L is NULL");
+    if ((uintptr_t)L % 16 || (uintptr_t)mu % 16 || (uintptr_t)eps % 8)
+      return fail(h, LRCC_ERR_ARG, "L/mu must be 16-byte and eps 8-byte aligned");
+  }
+  DeviceGuard dg(h->device);
+  h->err.clear();
+  return solve_impl(h, o, v, nchol, eps, L, ncomp, mu, nomega, omegas, opts, alpha, info);
 }
 
 lrcc_status lrcc_solve_batched(lrcc_handle h, int, const lrcc_instance*, const lrcc_solve_opts*,

@@ -119,4 +119,9 @@ lrcc_status sigma_packed(lrcc_handle h, const Geom& g, const void* L, bool conj_
                          const void* X, void* S, lrcc_dtype dt, lrcc_prec prec,
                          lrcc_cmul cmul);
 
+// Response solve (solver.hip); arguments already validated.
+lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps, const void* L,
+                       int ncomp, const void* mu, int nomega, const double* omegas,
+                       const lrcc_solve_opts* opts, double* alpha, lrcc_solve_info* info);
+
 }  // namespace lrcc

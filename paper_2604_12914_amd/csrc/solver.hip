@@ -1,0 +1,774 @@
+// Model LR-CCSD response solve on the device (paper Sec. 2.2):
+//   (A - w) X = -xi,  (A X) = D o X + sigma(X),  D_ij^ab = e_a + e_b - e_i - e_j,
+//   xi_ij^ab = mu_ia mu_jb - mu_ib mu_ja,  alpha_xy(w) = -<xi_x | X_y(w)>.
+//
+// Everything between the ladder launches stays on the device in FP64 and in
+// the block-pair layout of the ladder kernel (no packing per iteration):
+//   k_resid   one streaming pass per iteration: R = b - (D - w) X - sigma,
+//             e = R / (D - w) (denominators rebuilt from the orbital
+//             energies, never stored), X~ = X + e into the DIIS ring, and per
+//             right-hand side the partial sums |R|^2, |b|^2 and <e_j|e>;
+//   k_diis    one workgroup per right-hand side: fixed-order reduction of the
+//             partials, convergence test, DIIS matrix update, bordered solve;
+//   k_extrap  X = sum_k c_k X~_k.
+// The host reads back only the per-RHS active flags and residuals.
+//
+// Reduced precision (FP32 / BF16X3 ladder): iterative refinement.  The outer
+// residual r = -xi - (A - w) x uses the FP64 ladder; the correction solves
+// (A - w) d = r with the reduced-precision ladder by the same Jacobi + DIIS
+// to a loose relative tolerance; x += d.
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace lrcc {
+
+namespace {
+
+constexpr int MAXD = 12;  // largest DIIS subspace
+constexpr int RB = 256;   // threads of the streaming kernels
+
+struct Dims {
+  long Mp, npo, plane;  // padded rows, occupied pairs, elements per plane
+  int nbp, v, o;
+  long per_rhs;         // elements of one RHS over all block pairs: nbp*npo*64
+};
+
+// Element f of right-hand side r -> global index in the block layout; also
+// its virtual pair (a, b) and occupied pair (i, j).
+struct Elem {
+  long g;
+  int a, b, i, j;
+  bool live;
+};
+
+__device__ __forceinline__ Elem locate(const Dims& d, int r, long f, const int* tab,
+                                       const int* otab) {
+  Elem e;
+  const int s = f & 63;
+  const long ml = (f >> 6) % d.npo;
+  const int bp = (int)((f >> 6) / d.npo);
+  e.g = (((long)bp * d.Mp) + (long)r * d.npo + ml) * 64 + s;
+  const int AB = tab[bp], IJ = otab[ml];
+  e.a = (AB >> 16) * TB + (s >> 3);
+  e.b = (AB & 0xffff) * TB + (s & 7);
+  e.i = IJ >> 16;
+  e.j = IJ & 0xffff;
+  e.live = e.a < e.b && e.b < d.v;
+  return e;
+}
+
+template <int NT>
+__device__ __forceinline__ double2 block_sum(double2 x, double2* sh) {
+  const int t = threadIdx.x;
+  sh[t] = x;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      sh[t].x += sh[t + s].x;
+      sh[t].y += sh[t + s].y;
+    }
+    __syncthreads();
+  }
+  double2 r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// xi in block layout for every RHS r = w * ncomp + x.
+__global__ void k_xi(Dims d, int ncomp, const double2* __restrict__ mu, const int* tab,
+                     const int* otab, double* __restrict__ xi) {
+  const int r = blockIdx.y;
+  const double2* m = mu + (size_t)(r % ncomp) * d.o * d.v;
+  for (long f = blockIdx.x * (long)RB + threadIdx.x; f < d.per_rhs; f += (long)gridDim.x * RB) {
+    Elem e = locate(d, r, f, tab, otab);
+    double re = 0, im = 0;
+    if (e.live) {
+      const double2 ia = m[e.i * d.v + e.a], jb = m[e.j * d.v + e.b];
+      const double2 ib = m[e.i * d.v + e.b], ja = m[e.j * d.v + e.a];
+      re = (ia.x * jb.x - ia.y * jb.y) - (ib.x * ja.x - ib.y * ja.y);
+      im = (ia.x * jb.y + ia.y * jb.x) - (ib.x * ja.y + ib.y * ja.x);
+    }
+    xi[e.g] = re;
+    xi[e.g + d.plane] = im;
+  }
+}
+
+__device__ __forceinline__ double denom(const Dims& d, const Elem& e, const double* eps, double w) {
+  return (eps[d.o + e.a] + eps[d.o + e.b]) - (eps[e.i] + eps[e.j]) - w;
+}
+
+// x = b / (D - w), or x = 0 when zero_start.
+__global__ void k_start(Dims d, const double* __restrict__ eps, const double* __restrict__ omega,
+                        const int* tab, const int* otab, const int* __restrict__ active,
+                        const double* __restrict__ b, double* __restrict__ x) {
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  const double w = omega[r];
+  for (long f = blockIdx.x * (long)RB + threadIdx.x; f < d.per_rhs; f += (long)gridDim.x * RB) {
+    Elem e = locate(d, r, f, tab, otab);
+    double re = 0, im = 0;
+    if (e.live) {
+      const double D = denom(d, e, eps, w);
+      re = b[e.g] / D;
+      im = b[e.g + d.plane] / D;
+    }
+    x[e.g] = re;
+    x[e.g + d.plane] = im;
+  }
+}
+
+// One Jacobi + DIIS residual pass.  part layout: [r][q][chunk] double2 with
+// q = 0: (|R|^2, |b|^2), q = 1 + j: <e_j | e_new> for ring slot j.
+__global__ __launch_bounds__(RB) void k_resid(Dims d, const double* __restrict__ eps,
+                                              const double* __restrict__ omega, const int* tab,
+                                              const int* otab, const int* __restrict__ active,
+                                              const unsigned* __restrict__ valid, int slot,
+                                              int mdim, const double* __restrict__ b,
+                                              const double* __restrict__ x,
+                                              const double* __restrict__ s,
+                                              double* __restrict__ xt, double* __restrict__ ev,
+                                              double2* __restrict__ part) {
+  __shared__ double2 sh[RB];
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  const double w = omega[r];
+  const unsigned vmask = valid[r] | (1u << slot);
+  const size_t hs = (size_t)2 * d.plane;  // stride between ring slots
+  double rr = 0, bb = 0;
+  double2 dots[MAXD];
+#pragma unroll
+  for (int j = 0; j < MAXD; ++j) dots[j] = make_double2(0, 0);
+  for (long f = blockIdx.x * (long)RB + threadIdx.x; f < d.per_rhs; f += (long)gridDim.x * RB) {
+    Elem e = locate(d, r, f, tab, otab);
+    if (!e.live) continue;
+    const double D = denom(d, e, eps, w);
+    const double br = b[e.g], bi = b[e.g + d.plane];
+    const double xr = x[e.g], xi = x[e.g + d.plane];
+    const double Rr = br - D * xr - s[e.g], Ri = bi - D * xi - s[e.g + d.plane];
+    const double er = Rr / D, ei = Ri / D;
+    xt[slot * hs + e.g] = xr + er;
+    xt[slot * hs + e.g + d.plane] = xi + ei;
+    ev[slot * hs + e.g] = er;
+    ev[slot * hs + e.g + d.plane] = ei;
+    rr += Rr * Rr + Ri * Ri;
+    bb += br * br + bi * bi;
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j) {
+      if (j >= mdim || !((vmask >> j) & 1u)) continue;
+      double ur = er, ui = ei;
+      if (j != slot) {
+        ur = ev[j * hs + e.g];
+        ui = ev[j * hs + e.g + d.plane];
+      }
+      // conj(e_j) * e_new
+      dots[j].x += ur * er + ui * ei;
+      dots[j].y += ur * ei - ui * er;
+    }
+  }
+  const int nq = mdim + 1;
+  double2* pr = part + ((size_t)r * nq) * gridDim.x;
+  double2 t = block_sum<RB>(make_double2(rr, bb), sh);
+  if (threadIdx.x == 0) pr[blockIdx.x] = t;
+  for (int j = 0; j < mdim; ++j) {
+    if (!((vmask >> j) & 1u)) continue;
+    t = block_sum<RB>(dots[j], sh);
+    if (threadIdx.x == 0) pr[(size_t)(1 + j) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cdiv(double2 a, double2 b) {
+  const double den = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+
+// Per RHS: reduce partials, test convergence, update the DIIS matrix and
+// solve for the extrapolation coefficients.  Bmat: [r][MAXD][MAXD] double2.
+__global__ void k_diis(int nchunk, int mdim, int slot, int it, int max_iter, double tol,
+                       const double2* __restrict__ part, int* __restrict__ active,
+                       unsigned* __restrict__ valid, double2* __restrict__ Bmat,
+                       double2* __restrict__ coef, double* __restrict__ relres) {
+  __shared__ double2 sh[64];
+  __shared__ double2 q[MAXD + 1];
+  const int r = blockIdx.x;
+  if (!active[r]) return;
+  const int nq = mdim + 1;
+  const unsigned vmask = valid[r] | (1u << slot);
+  for (int k = 0; k < nq; ++k) {
+    if (k > 0 && !((vmask >> (k - 1)) & 1u)) continue;  // uniform over the block
+    double2 acc = make_double2(0, 0);
+    const double2* p = part + ((size_t)r * nq + k) * nchunk;
+    for (int c = threadIdx.x; c < nchunk; c += 64) {
+      acc.x += p[c].x;
+      acc.y += p[c].y;
+    }
+    acc = block_sum<64>(acc, sh);
+    if (threadIdx.x == 0) q[k] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double rel = sqrt(q[0].x / q[0].y);
+  relres[r] = rel;
+  if (rel < tol || it >= max_iter || !isfinite(rel)) {
+    active[r] = 0;
+    return;
+  }
+  double2* B = Bmat + (size_t)r * MAXD * MAXD;
+  for (int j = 0; j < mdim; ++j) {
+    if (!((vmask >> j) & 1u)) continue;
+    B[slot * MAXD + j] = make_double2(q[1 + j].x, -q[1 + j].y);  // <e_new|e_j>
+    B[j * MAXD + slot] = q[1 + j];                                // <e_j|e_new>
+  }
+  int idx[MAXD], k = 0;
+  for (int j = 0; j < mdim; ++j)
+    if ((vmask >> j) & 1u) idx[k++] = j;
+  double2* c = coef + (size_t)r * MAXD;
+  for (int j = 0; j < MAXD; ++j) c[j] = make_double2(0, 0);
+  bool singular = false;
+  double2 sol[MAXD + 1];
+  if (k > 1) {
+    // singularity test: Cholesky of the unit-diagonal form of B
+    double dg[MAXD], G[MAXD][MAXD][2];
+    double dmax = 0;
+    for (int u = 0; u < k; ++u) {
+      dg[u] = sqrt(B[idx[u] * MAXD + idx[u]].x);
+      dmax = fmax(dmax, dg[u]);
+    }
+    for (int u = 0; u < k; ++u)
+      for (int t = 0; t < k; ++t) {
+        const double2 z = B[idx[u] * MAXD + idx[t]];
+        G[u][t][0] = z.x / (dg[u] * dg[t]);
+        G[u][t][1] = z.y / (dg[u] * dg[t]);
+      }
+    for (int u = 0; u < k && !singular; ++u) {
+      double piv = G[u][u][0];
+      for (int t = 0; t < u; ++t) piv -= G[u][t][0] * G[u][t][0] + G[u][t][1] * G[u][t][1];
+      if (!(piv > 1e-14)) {
+        singular = true;
+        break;
+      }
+      const double l = sqrt(piv);
+      G[u][u][0] = l;
+      G[u][u][1] = 0;
+      for (int t = u + 1; t < k; ++t) {
+        // L[t][u] = (G[t][u] - sum_s L[t][s] conj(L[u][s])) / l
+        double zr = G[t][u][0], zi = G[t][u][1];
+        for (int s2 = 0; s2 < u; ++s2) {
+          zr -= G[t][s2][0] * G[u][s2][0] + G[t][s2][1] * G[u][s2][1];
+          zi -= G[t][s2][1] * G[u][s2][0] - G[t][s2][0] * G[u][s2][1];
+        }
+        G[t][u][0] = zr / l;
+        G[t][u][1] = zi / l;
+      }
+    }
+    if (!singular) {
+      // bordered system [[B / dmax^2, 1], [1^T, 0]] [c; l] = [0; 1],
+      // Gaussian elimination with partial pivoting
+      const int n = k + 1;
+      double2 Aa[MAXD + 1][MAXD + 2];
+      for (int u = 0; u < n; ++u)
+        for (int t = 0; t <= n; ++t) Aa[u][t] = make_double2(0, 0);
+      for (int u = 0; u < k; ++u) {
+        for (int t = 0; t < k; ++t) {
+          const double2 z = B[idx[u] * MAXD + idx[t]];
+          Aa[u][t] = make_double2(z.x / (dmax * dmax), z.y / (dmax * dmax));
+        }
+        Aa[u][k] = make_double2(1, 0);
+        Aa[k][u] = make_double2(1, 0);
+      }
+      Aa[k][n] = make_double2(1, 0);
+      for (int col = 0; col < n; ++col) {
+        int p = col;
+        double best = hypot(Aa[col][col].x, Aa[col][col].y);
+        for (int u = col + 1; u < n; ++u) {
+          const double m2 = hypot(Aa[u][col].x, Aa[u][col].y);
+          if (m2 > best) {
+            best = m2;
+            p = u;
+          }
+        }
+        if (!(best > 0)) {
+          singular = true;
+          break;
+        }
+        if (p != col)
+          for (int t = 0; t <= n; ++t) {
+            double2 tmp = Aa[col][t];
+            Aa[col][t] = Aa[p][t];
+            Aa[p][t] = tmp;
+          }
+        for (int u = col + 1; u < n; ++u) {
+          const double2 f = cdiv(Aa[u][col], Aa[col][col]);
+          for (int t = col; t <= n; ++t) {
+            const double2 z = cmul(f, Aa[col][t]);
+            Aa[u][t].x -= z.x;
+            Aa[u][t].y -= z.y;
+          }
+        }
+      }
+      if (!singular) {
+        for (int u = n - 1; u >= 0; --u) {
+          double2 z = Aa[u][n];
+          for (int t = u + 1; t < n; ++t) {
+            const double2 y = cmul(Aa[u][t], sol[t]);
+            z.x -= y.x;
+            z.y -= y.y;
+          }
+          sol[u] = cdiv(z, Aa[u][u]);
+        }
+      }
+    }
+  }
+  if (k <= 1 || singular) {
+    c[slot] = make_double2(1, 0);
+    valid[r] = 1u << slot;
+  } else {
+    for (int u = 0; u < k; ++u) c[idx[u]] = sol[u];
+    valid[r] = vmask;
+  }
+}
+
+__global__ void k_extrap(Dims d, int mdim, const int* __restrict__ active,
+                         const unsigned* __restrict__ valid, const double2* __restrict__ coef,
+                         const double* __restrict__ xt, double* __restrict__ x) {
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  const unsigned vm = valid[r];
+  const double2* c = coef + (size_t)r * MAXD;
+  const size_t hs = (size_t)2 * d.plane;
+  for (long f = blockIdx.x * (long)RB + threadIdx.x; f < d.per_rhs; f += (long)gridDim.x * RB) {
+    const int s = f & 63;
+    const long ml = (f >> 6) % d.npo;
+    const int bp = (int)((f >> 6) / d.npo);
+    const long g = (((long)bp * d.Mp) + (long)r * d.npo + ml) * 64 + s;
+    double re = 0, im = 0;
+    for (int j = 0; j < mdim; ++j) {
+      if (!((vm >> j) & 1u)) continue;
+      const double ar = xt[j * hs + g], ai = xt[j * hs + g + d.plane];
+      re += c[j].x * ar - c[j].y * ai;
+      im += c[j].x * ai + c[j].y * ar;
+    }
+    x[g] = re;
+    x[g + d.plane] = im;
+  }
+}
+
+// Outer residual of the refinement: r = b0 - (D - w) x - s, and per RHS
+// partial (|r|^2, |b0|^2).  x += d beforehand when add_d.
+__global__ __launch_bounds__(RB) void k_outer(Dims d, const double* __restrict__ eps,
+                                              const double* __restrict__ omega, const int* tab,
+                                              const int* otab, const int* __restrict__ active,
+                                              const double* __restrict__ b0,
+                                              const double* __restrict__ x,
+                                              const double* __restrict__ s,
+                                              double* __restrict__ rk, double2* __restrict__ part) {
+  __shared__ double2 sh[RB];
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  const double w = omega[r];
+  double rr = 0, bb = 0;
+  for (long f = blockIdx.x * (long)RB + threadIdx.x; f < d.per_rhs; f += (long)gridDim.x * RB) {
+    Elem e = locate(d, r, f, tab, otab);
+    double Rr = 0, Ri = 0;
+    if (e.live) {
+      const double D = denom(d, e, eps, w);
+      const double br = b0[e.g], bi = b0[e.g + d.plane];
+      Rr = br - D * x[e.g] - s[e.g];
+      Ri = bi - D * x[e.g + d.plane] - s[e.g + d.plane];
+      rr += Rr * Rr + Ri * Ri;
+      bb += br * br + bi * bi;
+    }
+    rk[e.g] = Rr;
+    rk[e.g + d.plane] = Ri;
+  }
+  double2 t = block_sum<RB>(make_double2(rr, bb), sh);
+  if (threadIdx.x == 0) part[(size_t)r * gridDim.x + blockIdx.x] = t;
+}
+
+// x += d for the active right-hand sides.
+__global__ void k_add(Dims d, const int* __restrict__ active, const double* __restrict__ dlt,
+                      double* __restrict__ x) {
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  for (long f = blockIdx.x * (long)RB + threadIdx.x; f < d.per_rhs; f += (long)gridDim.x * RB) {
+    const int s = f & 63;
+    const long ml = (f >> 6) % d.npo;
+    const int bp = (int)((f >> 6) / d.npo);
+    const long g = (((long)bp * d.Mp) + (long)r * d.npo + ml) * 64 + s;
+    x[g] += dlt[g];
+    x[g + d.plane] += dlt[g + d.plane];
+  }
+}
+
+// Partial sums of <u_r1 | w_r2> for the pairs (r1, r2) = (xi of (w, x), X of (w, y)).
+__global__ __launch_bounds__(RB) void k_alpha(Dims d, int ncomp, const double* __restrict__ xi,
+                                              const double* __restrict__ x,
+                                              double2* __restrict__ part) {
+  __shared__ double2 sh[RB];
+  const int p = blockIdx.y;  // (w, xc, yc)
+  const int yc = p % ncomp, xc = (p / ncomp) % ncomp, w = p / (ncomp * ncomp);
+  const int r1 = w * ncomp + xc, r2 = w * ncomp + yc;
+  double2 acc = make_double2(0, 0);
+  for (long f = blockIdx.x * (long)RB + threadIdx.x; f < d.per_rhs; f += (long)gridDim.x * RB) {
+    const int s = f & 63;
+    const long ml = (f >> 6) % d.npo;
+    const int bp = (int)((f >> 6) / d.npo);
+    const long base = ((long)bp * d.Mp + ml) * 64 + s;
+    const long g1 = base + (long)r1 * d.npo * 64, g2 = base + (long)r2 * d.npo * 64;
+    const double ur = xi[g1], ui = xi[g1 + d.plane];
+    const double wr = x[g2], wi = x[g2 + d.plane];
+    acc.x += ur * wr + ui * wi;
+    acc.y += ur * wi - ui * wr;
+  }
+  double2 t = block_sum<RB>(acc, sh);
+  if (threadIdx.x == 0) part[(size_t)p * gridDim.x + blockIdx.x] = t;
+}
+
+// b = -a elementwise.
+__global__ void k_neg(long n, const double* __restrict__ a, double* __restrict__ b) {
+  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) b[i] = -a[i];
+}
+
+// Convert the two FP64 planes of the doubles to float for the reduced-
+// precision ladder.
+__global__ void k_to_f32(long n, const double* __restrict__ a, float* __restrict__ b) {
+  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB)
+    b[i] = (float)a[i];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host driver
+
+namespace {
+
+struct Solver {
+  lrcc_handle h;
+  Geom g;
+  Dims d;
+  int n, ncomp, nomega, mdim, nchunk;
+  // device buffers
+  double *xi = nullptr, *x = nullptr, *s = nullptr, *xt = nullptr, *ev = nullptr, *b = nullptr;
+  double *omega = nullptr, *eps = nullptr, *x2 = nullptr, *rk = nullptr;
+  float* x32 = nullptr;
+  int *otab = nullptr, *active = nullptr;
+  unsigned* valid = nullptr;
+  double2 *Bm = nullptr, *coef = nullptr, *part = nullptr;
+  double* relres = nullptr;
+  // host mirrors (pinned)
+  int* h_active = nullptr;
+  double* h_relres = nullptr;
+  double2* h_part = nullptr;
+  int n_sigma64 = 0, n_sigma_lp = 0, iters_max = 0;
+  const void* Lstaged64 = nullptr;
+  const void* Lstaged32 = nullptr;
+};
+
+lrcc_status stage_for(Solver& S, const void* L, lrcc_prec prec, lrcc_cmul cmul) {
+  lrcc_handle h = S.h;
+  Geom g = S.g;
+  g.ncp = (int)roundup(g.nchol, ppl_chunk(prec, cmul));
+  Buf& dst = prec == LRCC_FP64 ? h->ls : h->ls2;
+  LRCC_HIP(h, dst.ensure(ppl_ls_bytes(prec, cmul, g)));
+  if (g.nchol > 0) {
+    if (prec == LRCC_FP64)
+      LRCC_HIP(h, stage_L<double>(L, LRCC_C128, g, ppl_planes(prec, cmul), false,
+                                  dst.as<double>(), h->stream));
+    else
+      LRCC_HIP(h, stage_L<float>(L, LRCC_C128, g, ppl_planes(prec, cmul), false,
+                                 dst.as<float>(), h->stream));
+  }
+  return LRCC_OK;
+}
+
+// s = ladder(xin) for all rows (block layout, FP64 accumulation).
+lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul cmul) {
+  lrcc_handle h = S.h;
+  Geom g = S.g;
+  g.ncp = (int)roundup(g.nchol, ppl_chunk(prec, cmul));
+  LRCC_HIP(h, fill_zero(S.s, (size_t)2 * S.d.plane * 8, h->stream));
+  if (g.nchol == 0) return LRCC_OK;
+  const void* xb = xin;
+  if (prec != LRCC_FP64) {
+    const long n = 2 * S.d.plane;
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)std::min<long>((n + RB - 1) / RB, 8192)),
+                       dim3(RB), 0, h->stream, n, xin, S.x32);
+    LRCC_HIP(h, hipGetLastError());
+    xb = S.x32;
+  }
+  const void* ls = prec == LRCC_FP64 ? h->ls.p : h->ls2.p;
+  LRCC_HIP(h, ppl_launch(prec, cmul, true, g, ls, xb, S.s, h->tab.as<int>(), h->stream));
+  if (prec == LRCC_FP64) ++S.n_sigma64;
+  else ++S.n_sigma_lp;
+  return LRCC_OK;
+}
+
+dim3 grid_rhs(const Solver& S, int nr) { return dim3(S.nchunk, nr); }
+
+// Jacobi + DIIS for (A - w) x = b on the RHS whose active flag is set on
+// entry.  x receives the solution.  Returns LRCC_ERR_NOT_CONVERGED if any
+// RHS stopped at max_iter, LRCC_ERR_NONFINITE on NaN/Inf.
+lrcc_status jacobi_diis(Solver& S, const double* b, double* x, lrcc_prec prec, lrcc_cmul cmul,
+                        double tol, int max_iter, int* h_active_in) {
+  lrcc_handle h = S.h;
+  const int n = S.n;
+  LRCC_HIP(h, hipMemcpyAsync(S.active, h_active_in, n * sizeof(int), hipMemcpyHostToDevice,
+                             h->stream));
+  LRCC_HIP(h, fill_zero(S.valid, roundup((long)n * 4, 16), h->stream));
+  hipLaunchKernelGGL(k_start, grid_rhs(S, n), dim3(RB), 0, h->stream, S.d, S.eps, S.omega,
+                     h->tab.as<int>(), S.otab, S.active, b, x);
+  LRCC_HIP(h, hipGetLastError());
+  std::vector<int> act(h_active_in, h_active_in + n);
+  lrcc_status result = LRCC_OK;
+  for (int it = 0;; ++it) {
+    lrcc_status st = apply_sigma(S, x, prec, cmul);
+    if (st != LRCC_OK) return st;
+    const int slot = it % S.mdim;
+    hipLaunchKernelGGL(k_resid, grid_rhs(S, n), dim3(RB), 0, h->stream, S.d, S.eps, S.omega,
+                       h->tab.as<int>(), S.otab, S.active, S.valid, slot, S.mdim, b, x, S.s,
+                       S.xt, S.ev, S.part);
+    LRCC_HIP(h, hipGetLastError());
+    hipLaunchKernelGGL(k_diis, dim3(n), dim3(64), 0, h->stream, S.nchunk, S.mdim, slot, it,
+                       max_iter, tol, S.part, S.active, S.valid, S.Bm, S.coef, S.relres);
+    LRCC_HIP(h, hipGetLastError());
+    hipLaunchKernelGGL(k_extrap, grid_rhs(S, n), dim3(RB), 0, h->stream, S.d, S.mdim, S.active,
+                       S.valid, S.coef, S.xt, x);
+    LRCC_HIP(h, hipGetLastError());
+    LRCC_HIP(h, hipMemcpyAsync(S.h_active, S.active, n * sizeof(int), hipMemcpyDeviceToHost,
+                               h->stream));
+    LRCC_HIP(h, hipMemcpyAsync(S.h_relres, S.relres, n * sizeof(double), hipMemcpyDeviceToHost,
+                               h->stream));
+    LRCC_HIP(h, hipStreamSynchronize(h->stream));
+    int nact = 0;
+    for (int r = 0; r < n; ++r) {
+      if (!act[r]) continue;
+      if (!std::isfinite(S.h_relres[r])) result = LRCC_ERR_NONFINITE;
+      if (S.h_active[r]) {
+        ++nact;
+      } else {
+        act[r] = 0;
+        if (S.h_relres[r] >= tol && result == LRCC_OK) result = LRCC_ERR_NOT_CONVERGED;
+      }
+    }
+    S.iters_max = std::max(S.iters_max, it);
+    if (nact == 0 || result == LRCC_ERR_NONFINITE) break;
+  }
+  return result;
+}
+
+lrcc_status finish_alpha(Solver& S, const double* x, double* alpha) {
+  lrcc_handle h = S.h;
+  const int np = S.nomega * S.ncomp * S.ncomp;
+  hipLaunchKernelGGL(k_alpha, dim3(S.nchunk, np), dim3(RB), 0, h->stream, S.d, S.ncomp, S.xi, x,
+                     S.part);
+  LRCC_HIP(h, hipGetLastError());
+  LRCC_HIP(h, hipMemcpyAsync(S.h_part, S.part, (size_t)np * S.nchunk * sizeof(double2),
+                             hipMemcpyDeviceToHost, h->stream));
+  LRCC_HIP(h, hipStreamSynchronize(h->stream));
+  for (int p = 0; p < np; ++p) {
+    double re = 0, im = 0;
+    for (int c = 0; c < S.nchunk; ++c) {
+      re += S.h_part[(size_t)p * S.nchunk + c].x;
+      im += S.h_part[(size_t)p * S.nchunk + c].y;
+    }
+    alpha[2 * p] = -re;  // alpha_xy = -<xi_x | X_y>
+    alpha[2 * p + 1] = -im;
+  }
+  return LRCC_OK;
+}
+
+}  // namespace
+
+lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps, const void* L,
+                       int ncomp, const void* mu, int nomega, const double* omegas,
+                       const lrcc_solve_opts* opts_in, double* alpha, lrcc_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  lrcc_solve_opts op{};
+  if (opts_in) op = *opts_in;
+  const double tol = op.tol > 0 ? op.tol : 1e-8;
+  const int max_iter = op.max_iter > 0 ? op.max_iter : 100;
+  const int mdim = op.diis_dim > 0 ? op.diis_dim : 8;
+  const double inner_tol = op.inner_tol > 0 ? op.inner_tol : 1e-5;
+  const int max_outer = op.max_outer > 0 ? op.max_outer : 6;
+  if (mdim > MAXD) return fail(h, LRCC_ERR_ARG, "diis_dim exceeds 12");
+  if (op.prec != LRCC_FP64 && op.prec != LRCC_FP32 && op.prec != LRCC_BF16X3)
+    return fail(h, LRCC_ERR_ARG, "unknown precision");
+  if (op.cmul != LRCC_CMUL_4M && op.cmul != LRCC_CMUL_3M)
+    return fail(h, LRCC_ERR_ARG, "unknown complex-multiply form");
+  if (op.deterministic) return fail(h, LRCC_ERR_UNSUPPORTED, "deterministic mode is reserved");
+
+  Solver S;
+  S.h = h;
+  S.n = nomega * ncomp;
+  S.ncomp = ncomp;
+  S.nomega = nomega;
+  S.mdim = mdim;
+  S.g = make_geom(o, v, nchol, S.n, 1);
+  const Geom& g = S.g;
+  if (g.M == 0 || g.npv == 0) {
+    for (int p = 0; p < 2 * nomega * ncomp * ncomp; ++p) alpha[p] = 0;
+    if (info) *info = lrcc_solve_info{0, 0, 0, 0.0, 0.0};
+    return LRCC_OK;
+  }
+  lrcc_status st = ensure_tab(h, g.nbv);
+  if (st != LRCC_OK) return st;
+  S.d = Dims{g.Mp, g.npo, g.xb_plane(), g.nbp, v, o, (long)g.nbp * g.npo * 64};
+  S.nchunk = (int)std::max<long>(1, std::min<long>(256, (S.d.per_rhs + 4 * RB - 1) / (4 * RB)));
+
+  // workspace: 0 xi, 1 x, 2 s, 3 ring X~, 4 ring e, 5 b, 6 x2 (outer x), 7 rk,
+  // 8 small device state, 9 partials, 10 x32
+  const size_t vb = (size_t)2 * S.d.plane * 8;
+  const bool ir = op.prec != LRCC_FP64;
+  size_t need[11] = {vb, vb, vb, vb * mdim, vb * mdim, vb, ir ? vb : 16, ir ? vb : 16, 0, 0,
+                     ir ? vb / 2 : 16};
+  const size_t np_alpha = (size_t)nomega * ncomp * ncomp;
+  const size_t npart = std::max((size_t)S.n * (mdim + 1), np_alpha) * S.nchunk;
+  need[9] = npart * sizeof(double2);
+  // small state: omega[n], eps[o+v], otab[npo], active[n], valid[n], relres[n], B, coef
+  const size_t off_om = 0, off_eps = off_om + roundup(S.n * 8, 256),
+               off_ot = off_eps + roundup((o + v) * 8, 256),
+               off_act = off_ot + roundup(g.npo * 4, 256), off_val = off_act + roundup(S.n * 4, 256),
+               off_rel = off_val + roundup(S.n * 4, 256), off_B = off_rel + roundup(S.n * 8, 256),
+               off_c = off_B + roundup((long)S.n * MAXD * MAXD * 16, 256),
+               end = off_c + roundup((long)S.n * MAXD * 16, 256);
+  need[8] = end;
+  for (int k = 0; k < 11; ++k) LRCC_HIP(h, h->sv[k].ensure(need[k]));
+  S.xi = h->sv[0].as<double>();
+  S.x = h->sv[1].as<double>();
+  S.s = h->sv[2].as<double>();
+  S.xt = h->sv[3].as<double>();
+  S.ev = h->sv[4].as<double>();
+  S.b = h->sv[5].as<double>();
+  S.x2 = h->sv[6].as<double>();
+  S.rk = h->sv[7].as<double>();
+  char* sm = h->sv[8].as<char>();
+  S.omega = reinterpret_cast<double*>(sm + off_om);
+  S.eps = reinterpret_cast<double*>(sm + off_eps);
+  S.otab = reinterpret_cast<int*>(sm + off_ot);
+  S.active = reinterpret_cast<int*>(sm + off_act);
+  S.valid = reinterpret_cast<unsigned*>(sm + off_val);
+  S.relres = reinterpret_cast<double*>(sm + off_rel);
+  S.Bm = reinterpret_cast<double2*>(sm + off_B);
+  S.coef = reinterpret_cast<double2*>(sm + off_c);
+  S.part = h->sv[9].as<double2>();
+  S.x32 = h->sv[10].as<float>();
+
+  // host-side small state (pinned)
+  std::vector<double> om(S.n);
+  for (int w = 0; w < nomega; ++w)
+    for (int x = 0; x < ncomp; ++x) om[w * ncomp + x] = omegas[w];
+  std::vector<int> ot(g.npo);
+  for (int i = 0, k = 0; i < o; ++i)
+    for (int j = i + 1; j < o; ++j) ot[k++] = (i << 16) | j;
+  LRCC_HIP(h, hipHostMalloc((void**)&S.h_active, S.n * sizeof(int), hipHostMallocDefault));
+  struct Pinned {
+    Solver* s;
+    ~Pinned() {
+      if (s->h_active) (void)hipHostFree(s->h_active);
+      if (s->h_relres) (void)hipHostFree(s->h_relres);
+      if (s->h_part) (void)hipHostFree(s->h_part);
+    }
+  } pinned{&S};
+  LRCC_HIP(h, hipHostMalloc((void**)&S.h_relres, S.n * sizeof(double), hipHostMallocDefault));
+  LRCC_HIP(h, hipHostMalloc((void**)&S.h_part, np_alpha * S.nchunk * sizeof(double2),
+                            hipHostMallocDefault));
+  LRCC_HIP(h, hipMemcpyAsync(S.omega, om.data(), S.n * 8, hipMemcpyHostToDevice, h->stream));
+  LRCC_HIP(h, hipMemcpyAsync(S.eps, eps, (o + v) * 8, hipMemcpyDeviceToDevice, h->stream));
+  LRCC_HIP(h, hipMemcpyAsync(S.otab, ot.data(), g.npo * 4, hipMemcpyHostToDevice, h->stream));
+  LRCC_HIP(h, hipStreamSynchronize(h->stream));  // host vectors go out of scope below
+
+  // right-hand sides and staged Cholesky vectors
+  hipLaunchKernelGGL(k_xi, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, ncomp,
+                     static_cast<const double2*>(mu), h->tab.as<int>(), S.otab, S.xi);
+  LRCC_HIP(h, hipGetLastError());
+  // zero the iterates and the DIIS ring once so dead slots and pad rows hold
+  // zeros (the ladder kernel reads whole block-pair rows)
+  LRCC_HIP(h, fill_zero(S.x, vb, h->stream));
+  LRCC_HIP(h, fill_zero(S.xt, vb * mdim, h->stream));
+  LRCC_HIP(h, fill_zero(S.ev, vb * mdim, h->stream));
+  hipLaunchKernelGGL(k_neg, dim3((unsigned)std::min<long>((2 * S.d.plane + RB - 1) / RB, 8192)),
+                     dim3(RB), 0, h->stream, 2 * S.d.plane, (const double*)S.xi, S.b);
+  LRCC_HIP(h, hipGetLastError());
+  std::vector<int> all(S.n, 1);
+  st = stage_for(S, L, LRCC_FP64, LRCC_CMUL_4M);
+  if (st != LRCC_OK) return st;
+  if (ir) {
+    st = stage_for(S, L, op.prec, op.cmul);
+    if (st != LRCC_OK) return st;
+  }
+
+  lrcc_status result = LRCC_OK;
+  double final_rel = 0;
+  if (!ir) {
+    result = jacobi_diis(S, S.b, S.x, LRCC_FP64, LRCC_CMUL_4M, tol, max_iter, all.data());
+    for (int r = 0; r < S.n; ++r) final_rel = std::max(final_rel, S.h_relres[r]);
+    if (result == LRCC_ERR_NONFINITE) return fail(h, result, "non-finite residual");
+    st = finish_alpha(S, S.x, alpha);
+    if (st != LRCC_OK) return st;
+  } else {
+    // iterative refinement: x2 = 0, rk = b
+    LRCC_HIP(h, fill_zero(S.x2, vb, h->stream));
+    LRCC_HIP(h, hipMemcpyAsync(S.rk, S.b, vb, hipMemcpyDeviceToDevice, h->stream));
+    std::vector<int> act(S.n, 1);
+    std::vector<double> rel(S.n, 1.0);
+    result = LRCC_ERR_NOT_CONVERGED;
+    for (int outer = 0; outer < max_outer; ++outer) {
+      lrcc_status is = jacobi_diis(S, S.rk, S.x, op.prec, op.cmul, inner_tol, max_iter,
+                                   act.data());
+      if (is == LRCC_ERR_NONFINITE) return fail(h, is, "non-finite residual");
+      // x2 += d; rk = b - (D - w) x2 - sigma64(x2)
+      LRCC_HIP(h, hipMemcpyAsync(S.active, act.data(), S.n * sizeof(int), hipMemcpyHostToDevice,
+                                 h->stream));
+      hipLaunchKernelGGL(k_add, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.active, S.x,
+                         S.x2);
+      LRCC_HIP(h, hipGetLastError());
+      st = apply_sigma(S, S.x2, LRCC_FP64, LRCC_CMUL_4M);
+      if (st != LRCC_OK) return st;
+      hipLaunchKernelGGL(k_outer, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.eps, S.omega,
+                         h->tab.as<int>(), S.otab, S.active, S.b, S.x2, S.s, S.rk, S.part);
+      LRCC_HIP(h, hipGetLastError());
+      LRCC_HIP(h, hipMemcpyAsync(S.h_part, S.part, (size_t)S.n * S.nchunk * sizeof(double2),
+                                 hipMemcpyDeviceToHost, h->stream));
+      LRCC_HIP(h, hipStreamSynchronize(h->stream));
+      int nact = 0;
+      for (int r = 0; r < S.n; ++r) {
+        if (!act[r]) continue;
+        double rr = 0, bb = 0;
+        for (int c = 0; c < S.nchunk; ++c) {
+          rr += S.h_part[(size_t)r * S.nchunk + c].x;
+          bb += S.h_part[(size_t)r * S.nchunk + c].y;
+        }
+        rel[r] = std::sqrt(rr / bb);
+        if (!std::isfinite(rel[r])) return fail(h, LRCC_ERR_NONFINITE, "non-finite residual");
+        if (rel[r] < tol) act[r] = 0;
+        else ++nact;
+      }
+      if (nact == 0) {
+        result = LRCC_OK;
+        break;
+      }
+    }
+    for (int r = 0; r < S.n; ++r) final_rel = std::max(final_rel, rel[r]);
+    st = finish_alpha(S, S.x2, alpha);
+    if (st != LRCC_OK) return st;
+  }
+  if (info) {
+    info->iters_max = S.iters_max;
+    info->n_sigma_fp64 = S.n_sigma64;
+    info->n_sigma_lowp = S.n_sigma_lp;
+    info->final_relres = final_rel;
+    info->seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (result == LRCC_ERR_NOT_CONVERGED) return fail(h, result, "tolerance not reached");
+  return result;
+}
+
+}  // namespace lrcc
