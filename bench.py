@@ -1,0 +1,214 @@
+"""Benchmark of the PPL response path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: o=16 occupied, v=160 virtual spinors, Nchol=640 complex Cholesky
+vectors, 3 dipole components x 2 frequencies (0, 0.0656 Eh) = 6 right-hand
+sides, FP64 complex (seeded synthetic inputs, see lrcc_synth).
+
+One step = one full FP64 response solve: staging of the Cholesky vectors,
+right-hand sides, every Jacobi + DIIS iteration (fused ladder kernel,
+residual / preconditioner / norms pass, DIIS solve, extrapolation) and alpha.
+value = algorithmic ladder flops of all ladder applications in the step
+(F = 8 (2 npv^2 Nchol + nrhs npo npv^2) per application, 4M form, no
+symmetry savings) / wall time, in TFLOP/s.
+
+Also reported: ladder-only rates per precision, the split-precision solve
+(time and |d alpha| against the FP64 solve), the roofline of the fused
+ladder kernel (HIP-event kernel time inside the timed region) and the FP64
+CPU oracle timed on a bounded share of one ladder application.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.0 / 3.0}   # TFLOP/s, dense MFMA
+HBM_GBS = 8000.0
+
+
+def flops_per_sigma(o, v, nchol, nrhs):
+    npo, npv = o * (o - 1) // 2, v * (v - 1) // 2
+    return 8.0 * (2.0 * npv * npv * nchol + nrhs * npo * npv * npv)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the per-precision extras")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the ladder path is single-GPU; multi-GPU sharding is a design note)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import lrcc_synth as S
+    import paper_2604_12914_amd as lrcc
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    lrcc.lib()  # fails loudly if liblrcc.so is missing
+
+    cfg = S.CONFIGS["baseline"]
+    o, v, nchol = cfg.o, cfg.v, cfg.nchol
+    omegas = list(cfg.omegas)
+    nrhs = cfg.nrhs
+    inst = S.make_instance(o, v, nchol, ncomp=cfg.ncomp, seed=cfg.seed,
+                           gamma=S.solve_gamma(v))
+    eps = torch.from_numpy(inst.eps).cuda()
+    L = torch.from_numpy(inst.L).cuda()
+    mu = torch.from_numpy(inst.mu).cuda()
+    F = flops_per_sigma(o, v, nchol, nrhs)
+
+    # ---- timed region: K full FP64 solves ---------------------------------
+    for _ in range(args.warmup):
+        alpha64, info = lrcc.solve(eps, L, mu, omegas, tol=1e-8)
+    torch.cuda.synchronize()
+    lrcc.set_timing(True)
+    n_sigma = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        alpha64, info = lrcc.solve(eps, L, mu, omegas, tol=1e-8)
+        n_sigma += info["n_sigma_fp64"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, nlaunch = lrcc.get_timing()
+    lrcc.set_timing(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = n_sigma * F / (t1 - t0) / 1e12
+    k_avg = kms / max(nlaunch, 1)
+    achieved = F / (k_avg * 1e-3) / 1e12
+
+    out = {
+        "metric": "PPL A*X TFLOP/s FP64 vs split-prec; LR solve time at |d alpha|<1e-5 a.u.",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "FP64 LR solve, o=16 v=160 Nchol=640, 3 dipole components x "
+                        "omega {0, 0.0656} = 6 RHS, Jacobi+DIIS to relative residual 1e-8",
+            "o": o, "v": v, "nchol": nchol, "nrhs": nrhs,
+            "sigma_per_step": n_sigma / args.steps,
+            "flop_per_sigma": F,
+        },
+        "roofline": {
+            "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"],
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4), "traffic": None,
+            "kernel": "k_ppl_4m<double> (fused build + antisymmetrise + contract)",
+            "kernel_ms_avg": round(k_avg, 4), "launches": nlaunch,
+        },
+    }
+
+    # ---- extras: ladder-only rates, split-precision solve ------------------
+    if not args.no_extra:
+        extra = {}
+        X = torch.from_numpy(S.make_packed(np.random.default_rng(3), nrhs, o, v)).cuda()
+        Lraw = torch.from_numpy(S.make_L(np.random.default_rng(4), nchol, v)).cuda()
+        for prec in ("fp64", "fp32"):
+            try:
+                s = lrcc.ppl_sigma(Lraw, X, prec=prec)
+                torch.cuda.synchronize()
+                lrcc.set_timing(True)
+                ts = []
+                for _ in range(3):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    lrcc.ppl_sigma(Lraw, X, prec=prec, out=s)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ts.append(e0.elapsed_time(e1))
+                km, kn = lrcc.get_timing()
+                lrcc.set_timing(False)
+                extra[f"sigma_{prec}"] = {
+                    "call_ms": round(min(ts), 3),
+                    "kernel_ms": round(km / kn, 3),
+                    "tflops_call": round(F / (min(ts) * 1e-3) / 1e12, 2),
+                    "tflops_kernel": round(F / (km / kn * 1e-3) / 1e12, 2),
+                    "frac_peak": round(F / (km / kn * 1e-3) / 1e12 / PEAK[prec], 4),
+                }
+            except lrcc.LrccError as e:
+                extra[f"sigma_{prec}"] = {"error": str(e)}
+        for prec in ("fp32",):
+            try:
+                lrcc.solve(eps, L, mu, omegas, prec=prec, tol=1e-8)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                a_lp, inf_lp = lrcc.solve(eps, L, mu, omegas, prec=prec, tol=1e-8)
+                t1 = time.perf_counter()
+                extra[f"solve_{prec}_ir"] = {
+                    "ms": round((t1 - t0) * 1e3, 3),
+                    "speedup_vs_fp64": round(ms_step / ((t1 - t0) * 1e3), 3),
+                    "max_abs_dalpha": float(np.abs(a_lp - alpha64).max()),
+                    "n_sigma_fp64": inf_lp["n_sigma_fp64"],
+                    "n_sigma_lowp": inf_lp["n_sigma_lowp"],
+                }
+            except lrcc.LrccError as e:
+                extra[f"solve_{prec}_ir"] = {"error": str(e)}
+        extra["solve_fp64"] = {"ms": round(ms_step, 3), "iters_max": info["iters_max"],
+                               "alpha_zz": [float(alpha64[w, 2, 2].real)
+                                            for w in range(len(omegas))]}
+        out["extra"] = extra
+
+    # ---- CPU oracle on a bounded share of one ladder application ----------
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(inst.L, o, v, nchol, nrhs, F)
+
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(L, o, v, nchol, nrhs, F, budget_s=12.0):
+    """Time the FP64 oracle's definition-route sigma on rows a = 0, 1, ...
+    until ~budget_s has passed, and scale to the whole ladder application by
+    the work share of those rows (each row a costs in proportion to v-a-1)."""
+    import numpy as np
+
+    import lrcc_synth as S
+    from oracle import ppl
+
+    X = S.make_packed(np.random.default_rng(3), nrhs, o, v)
+    npv = v * (v - 1) // 2
+    t0 = time.perf_counter()
+    a = 0
+    while a < v - 1 and time.perf_counter() - t0 < budget_s:
+        ppl.sigma(L, X, o, v, a_range=(a, a + 1))
+        a += 1
+    dt = time.perf_counter() - t0
+    share = sum(v - r - 1 for r in range(a)) / npv
+    t_full = dt / share
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": round(F / t_full / 1e12, 5), "unit": "TFLOP/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"rows a=0..{a - 1} of one FP64 ladder application at o={o} v={v} "
+                      f"Nchol={nchol} nrhs={nrhs} ({100 * share:.1f}% of its work, "
+                      f"{dt:.1f} s), scaled by work share to {t_full:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

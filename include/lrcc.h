@@ -154,6 +154,15 @@ typedef struct {
 lrcc_status lrcc_solve_batched(lrcc_handle h, int ninst, const lrcc_instance* inst,
                                const lrcc_solve_opts* opts, lrcc_solve_info* info);
 
+/* Kernel timing: while enabled, HIP events are recorded on the handle's
+ * stream around every ladder-kernel launch (the fused build/antisymmetrise/
+ * contract kernel only, not staging or layout kernels).  lrcc_set_timing
+ * with enable != 0 clears the totals and starts recording; 0 stops.
+ * lrcc_get_timing synchronises the stream and returns the summed kernel
+ * milliseconds and the number of launches since timing was enabled. */
+lrcc_status lrcc_set_timing(lrcc_handle h, int enable);
+lrcc_status lrcc_get_timing(lrcc_handle h, double* ms, long* launches);
+
 /* Host-only argument check of lrcc_ppl_sigma: runs the same validation and
  * launches nothing (usable without a GPU; h may be NULL). */
 lrcc_status lrcc_check_sigma_args(int o, int v, int nchol, int nrhs,

@@ -57,19 +57,22 @@ def coulomb_ab(L: np.ndarray, a: int) -> np.ndarray:
     return np.transpose(g, (1, 0, 2))
 
 
-def sigma(L: np.ndarray, X: np.ndarray, o: int, v: int) -> np.ndarray:
+def sigma(L: np.ndarray, X: np.ndarray, o: int, v: int, a_range=None) -> np.ndarray:
     """Definition route.  L ``[nchol, v, v]``, X packed -> sigma packed.
 
     For each virtual a: build <ab|cd> for all b, c, d from the Cholesky
     vectors, antisymmetrise in (c, d), and contract the full c, d sum
     against the unpacked X.  Only b > a is kept (packed output).
+    ``a_range=(a0, a1)`` evaluates only the rows a0 <= a < a1 (the others
+    stay zero); used to time a bounded share of the work.
     """
     nrhs, npo, npv = X.shape
     M = nrhs * npo
     Xf = unpack(X.reshape(M, npv), v).reshape(M, v * v)     # X^{cd}, all c, d
     pa, pb = pairs(v)
     out = np.zeros((M, npv), dtype=np.complex128)
-    for a in range(v - 1):
+    a0, a1 = a_range if a_range is not None else (0, v - 1)
+    for a in range(a0, min(a1, v - 1)):
         g = coulomb_ab(L, a)                     # <ab|cd>  [b, c, d]
         g_as = g - np.transpose(g, (0, 2, 1))   # <ab||cd> = <ab|cd> - <ab|dc>
         s_ab = Xf @ g_as.reshape(v, v * v).T     # sum_{c,d} <ab||cd> X^cd  [M, b]

@@ -95,6 +95,8 @@ def lib() -> ctypes.CDLL:
             "lrcc_solve_batched": [vp, i, ctypes.POINTER(Instance),
                                    ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)],
             "lrcc_check_sigma_args": [i, i, i, i, vp, vp, vp, i, i, i],
+            "lrcc_set_timing": [vp, i],
+            "lrcc_get_timing": [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_long)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -196,6 +198,20 @@ def ppl_sigma_adjoint(L, X, G, o=None, want_dX=True, want_dL=True, prec="fp64", 
                                         _ptr(dX), _ptr(dL), _dtype_code(X), PREC[prec],
                                         CMUL[cmul]), h)
     return dX, dL
+
+
+def set_timing(enable: bool, device: int = 0):
+    """Start (clearing totals) or stop HIP-event timing of ladder kernels."""
+    h = handle(device)
+    _check(lib().lrcc_set_timing(h, 1 if enable else 0), h)
+
+
+def get_timing(device: int = 0):
+    """(summed ladder-kernel milliseconds, launches) since timing was enabled."""
+    h = handle(device)
+    ms, n = ctypes.c_double(), ctypes.c_long()
+    _check(lib().lrcc_get_timing(h, ctypes.byref(ms), ctypes.byref(n)), h)
+    return ms.value, n.value
 
 
 def _autograd_function():

@@ -89,6 +89,29 @@ lrcc_status ensure_tab(lrcc_handle h, int nbv) {
   return LRCC_OK;
 }
 
+lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
+                    const void* Ls, const void* Xb, void* Sb) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->timing) {
+    if (h->tev.size() < 2 * (h->tev_used + 1)) {
+      for (int k = 0; k < 2; ++k) {
+        hipEvent_t e;
+        LRCC_HIP(h, hipEventCreate(&e));
+        h->tev.push_back(e);
+      }
+    }
+    e0 = h->tev[2 * h->tev_used];
+    e1 = h->tev[2 * h->tev_used + 1];
+    LRCC_HIP(h, hipEventRecord(e0, h->stream));
+  }
+  LRCC_HIP(h, ppl_launch(prec, cmul, acc64, g, Ls, Xb, Sb, h->tab.as<int>(), h->stream));
+  if (h->timing) {
+    LRCC_HIP(h, hipEventRecord(e1, h->stream));
+    ++h->tev_used;
+  }
+  return LRCC_OK;
+}
+
 static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = static_cast<const char*>(a);
   const char* pb = static_cast<const char*>(b);
@@ -153,7 +176,8 @@ lrcc_status sigma_packed(lrcc_handle h, const Geom& g, const void* L, bool conj_
       LRCC_HIP(h, stage_L<float>(L, dt, g, np, conj_t, h->ls.as<float>(), h->stream));
       LRCC_HIP(h, pack_to_block<float>(X, dt, g, tab, h->xb.as<float>(), h->stream));
     }
-    LRCC_HIP(h, ppl_launch(prec, cmul, acc64, g, h->ls.p, h->xb.p, h->sb.p, tab, h->stream));
+    st = ppl_run(h, prec, cmul, acc64, g, h->ls.p, h->xb.p, h->sb.p);
+    if (st != LRCC_OK) return st;
   }
   if (acc64)
     LRCC_HIP(h, block_to_pack<double>(h->sb.as<double>(), g, tab, S, dt, h->stream));
@@ -203,6 +227,7 @@ lrcc_status lrcc_destroy(lrcc_handle h) {
     h->gb.release();
     h->tab.release();
     for (auto& b : h->sv) b.release();
+    for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
   }
   delete h;
   return LRCC_OK;
@@ -211,6 +236,28 @@ lrcc_status lrcc_destroy(lrcc_handle h) {
 lrcc_status lrcc_set_stream(lrcc_handle h, void* stream) {
   if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
   h->stream = static_cast<hipStream_t>(stream);
+  return LRCC_OK;
+}
+
+lrcc_status lrcc_set_timing(lrcc_handle h, int enable) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  h->timing = enable != 0;
+  h->tev_used = 0;
+  return LRCC_OK;
+}
+
+lrcc_status lrcc_get_timing(lrcc_handle h, double* ms, long* launches) {
+  if (!h || !ms || !launches) return fail(h, LRCC_ERR_ARG, "NULL argument");
+  DeviceGuard dg(h->device);
+  LRCC_HIP(h, hipStreamSynchronize(h->stream));
+  double total = 0;
+  for (size_t k = 0; k < h->tev_used; ++k) {
+    float t = 0;
+    LRCC_HIP(h, hipEventElapsedTime(&t, h->tev[2 * k], h->tev[2 * k + 1]));
+    total += t;
+  }
+  *ms = total;
+  *launches = (long)h->tev_used;
   return LRCC_OK;
 }
 

@@ -22,6 +22,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/lrcc.h"
 
@@ -68,6 +69,10 @@ struct lrcc_handle_s {
   int tab_nbv = -1;
   // solver workspace
   lrcc::Buf sv[12];
+  // ladder-kernel timing (lrcc_set_timing)
+  bool timing = false;
+  std::vector<hipEvent_t> tev;  // start/stop pairs
+  size_t tev_used = 0;          // pairs recorded since enabling
 };
 
 namespace lrcc {
@@ -109,6 +114,11 @@ int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul);   // KC of the staged layout
 int ppl_planes(lrcc_prec prec, lrcc_cmul cmul);  // planes of the staged L
 size_t ppl_ls_bytes(lrcc_prec prec, lrcc_cmul cmul, const Geom& g);
 size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g);
+
+// ppl_launch on the handle's stream, bracketed by timing events when the
+// handle has timing enabled.
+lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
+                    const void* Ls, const void* Xb, void* Sb);
 
 // Block-pair table: tab[bp] = (A << 16) | B.
 lrcc_status ensure_tab(lrcc_handle h, int nbv);

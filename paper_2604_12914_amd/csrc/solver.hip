@@ -504,7 +504,8 @@ lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul 
     xb = S.x32;
   }
   const void* ls = prec == LRCC_FP64 ? h->ls.p : h->ls2.p;
-  LRCC_HIP(h, ppl_launch(prec, cmul, true, g, ls, xb, S.s, h->tab.as<int>(), h->stream));
+  lrcc_status st = ppl_run(h, prec, cmul, true, g, ls, xb, S.s);
+  if (st != LRCC_OK) return st;
   if (prec == LRCC_FP64) ++S.n_sigma64;
   else ++S.n_sigma_lp;
   return LRCC_OK;
