@@ -1,5 +1,7 @@
 // C ABI entry points of the ladder library: handles, validation, sigma.
+#include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -112,6 +114,37 @@ lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, c
   return LRCC_OK;
 }
 
+lrcc_status bf16x3_apply(lrcc_handle h, const Geom& g, const void* Ls, const void* Xb, void* Sb,
+                         bool acc64) {
+  if (h->panel_cap == 0) {
+    size_t freeb = 0, totalb = 0;
+    LRCC_HIP(h, hipMemGetInfo(&freeb, &totalb));
+    size_t cap = (size_t)16 << 30;
+    if (const char* e = getenv("LRCC_PANEL_MB")) cap = (size_t)atol(e) << 20;
+    h->panel_cap = std::max<size_t>(std::min(cap, freeb / 2), (size_t)64 << 20);
+  }
+  const size_t per_ab = bf16x3_panel_bytes(g, 1);
+  int panel = (int)std::min<size_t>((size_t)g.nbp, std::max<size_t>(1, h->panel_cap / per_ab));
+  LRCC_HIP(h, h->vws.ensure(bf16x3_panel_bytes(g, panel)));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->timing) {
+    while (h->tev.size() < 2 * (h->tev_used + 1)) {
+      hipEvent_t e;
+      LRCC_HIP(h, hipEventCreate(&e));
+      h->tev.push_back(e);
+    }
+    e0 = h->tev[2 * h->tev_used];
+    e1 = h->tev[2 * h->tev_used + 1];
+    LRCC_HIP(h, hipEventRecord(e0, h->stream));
+  }
+  LRCC_HIP(h, bf16x3_run(g, Ls, Xb, Sb, acc64, h->vws.p, panel, h->tab.as<int>(), h->stream));
+  if (h->timing) {
+    LRCC_HIP(h, hipEventRecord(e1, h->stream));
+    ++h->tev_used;
+  }
+  return LRCC_OK;
+}
+
 static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = static_cast<const char*>(a);
   const char* pb = static_cast<const char*>(b);
@@ -156,12 +189,34 @@ lrcc_status sigma_packed(lrcc_handle h, const Geom& g, const void* L, bool conj_
   const size_t es = dt == LRCC_C128 ? 16 : 8;
   const size_t nx = (size_t)g.M * g.npv * es;
   if (nx == 0) return LRCC_OK;
-  if (prec == LRCC_BF16X3 || cmul == LRCC_CMUL_3M)
-    return fail(h, LRCC_ERR_UNSUPPORTED, "this precision / complex form is not built yet");
+  if (cmul == LRCC_CMUL_3M && prec == LRCC_BF16X3)
+    return fail(h, LRCC_ERR_UNSUPPORTED, "bf16x3 uses the 4M complex form only");
+  if (cmul == LRCC_CMUL_3M)
+    return fail(h, LRCC_ERR_UNSUPPORTED, "this complex form is not built yet");
   lrcc_status st = ensure_tab(h, g.nbv);
   if (st != LRCC_OK) return st;
   const int* tab = h->tab.as<int>();
   const bool acc64 = dt == LRCC_C128 || prec == LRCC_FP64;
+  if (prec == LRCC_BF16X3) {
+    Geom gb = g;
+    gb.ncp = (int)roundup(g.nchol, bf16x3_chunk());
+    const size_t sbytes = (size_t)2 * g.xb_plane() * (acc64 ? 8 : 4);
+    LRCC_HIP(h, h->sb.ensure(sbytes));
+    LRCC_HIP(h, fill_zero(h->sb.p, sbytes, h->stream));
+    if (g.nchol > 0) {
+      LRCC_HIP(h, h->ls.ensure(bf16x3_ls_bytes(gb)));
+      LRCC_HIP(h, h->xb.ensure(bf16x3_xb_bytes(gb)));
+      LRCC_HIP(h, bf16x3_stage_L(L, dt, gb, conj_t, h->ls.p, h->stream));
+      LRCC_HIP(h, bf16x3_pack_x(X, dt, gb, tab, h->xb.p, h->stream));
+      st = bf16x3_apply(h, gb, h->ls.p, h->xb.p, h->sb.p, acc64);
+      if (st != LRCC_OK) return st;
+    }
+    if (acc64)
+      LRCC_HIP(h, block_to_pack<double>(h->sb.as<double>(), g, tab, S, dt, h->stream));
+    else
+      LRCC_HIP(h, block_to_pack<float>(h->sb.as<float>(), g, tab, S, dt, h->stream));
+    return LRCC_OK;
+  }
   LRCC_HIP(h, h->ls.ensure(ppl_ls_bytes(prec, cmul, g)));
   LRCC_HIP(h, h->xb.ensure(ppl_xb_bytes(prec, g)));
   const size_t sbytes = (size_t)2 * g.xb_plane() * (acc64 ? 8 : 4);
@@ -226,6 +281,7 @@ lrcc_status lrcc_destroy(lrcc_handle h) {
     h->sb.release();
     h->gb.release();
     h->tab.release();
+    h->vws.release();
     for (auto& b : h->sv) b.release();
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
   }

@@ -66,6 +66,8 @@ struct lrcc_handle_s {
   lrcc::Buf ls, ls2;      // staged Cholesky vectors (ls2: second operand set)
   lrcc::Buf xb, sb, gb;   // block-layout doubles: input, accumulator, gradient
   lrcc::Buf tab;          // block-pair table
+  lrcc::Buf vws;          // bf16x3: one panel of antisymmetrised integral tiles
+  size_t panel_cap = 0;   // bytes allowed for vws (0 = not yet chosen)
   int tab_nbv = -1;
   // solver workspace
   lrcc::Buf sv[12];
@@ -119,6 +121,22 @@ size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g);
 // handle has timing enabled.
 lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
                     const void* Ls, const void* Xb, void* Sb);
+
+// bf16x3 ladder (ppl_bf16x3.hip): staged layouts and the panel driver.
+int bf16x3_chunk();
+size_t bf16x3_ls_bytes(const Geom& g);
+size_t bf16x3_xb_bytes(const Geom& g);
+size_t bf16x3_panel_bytes(const Geom& g, int panel_ab);
+hipError_t bf16x3_stage_L(const void* L, lrcc_dtype dt, const Geom& g, bool conj_t, void* Ls,
+                          hipStream_t st);
+hipError_t bf16x3_pack_x(const void* X, lrcc_dtype dt, const Geom& g, const int* tab, void* Xb,
+                         hipStream_t st);
+hipError_t bf16x3_split_x(const double* x, const Geom& g, void* Xb, hipStream_t st);
+hipError_t bf16x3_run(const Geom& g, const void* Ls, const void* Xb, void* Sb, bool acc64,
+                      void* Vws, int panel_ab, const int* tab, hipStream_t st);
+// Run the bf16x3 ladder with the handle's panel workspace (sized here).
+lrcc_status bf16x3_apply(lrcc_handle h, const Geom& g, const void* Ls, const void* Xb, void* Sb,
+                         bool acc64);
 
 // Block-pair table: tab[bp] = (A << 16) | B.
 lrcc_status ensure_tab(lrcc_handle h, int nbv);

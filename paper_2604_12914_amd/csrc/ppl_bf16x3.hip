@@ -1,0 +1,438 @@
+// Split-BF16 (bf16x3) ladder for gfx950.
+//
+// Every real operand x is split as x = hi + lo with hi = bf16(x) and
+// lo = bf16(x - hi) (round to nearest even), and a real product is taken as
+// hi*hi + hi*lo + lo*hi (the lo*lo term is dropped), all on the bf16 matrix
+// cores (16x16x32 MFMA) with FP32 accumulation.  Complex products use the
+// 4M form, so one complex multiply-accumulate costs 12 bf16 MFMA products.
+//
+// The ladder is evaluated in panels of virtual block pairs AB:
+//   k_vbuild   one workgroup per tile (AB, CD): W1 = sum_P L_AC (x) L_BD and
+//              W2 = sum_P L_AD (x) L_BC on the matrix cores, antisymmetrised
+//              in LDS to V = 2 <ab||cd>, split to hi/lo and written to the
+//              panel workspace (32 KB per tile);
+//   k_contract sigma[m, AB] = sum_CD X[m, CD] V[AB, CD]^T, a bf16x3 GEMM in
+//              which each workgroup owns its output tile (128 rows x 64
+//              slots) and loops over all CD: no atomics, every sigma entry
+//              written once.
+// The integral panel is transient: at most one panel of AB rows exists.
+// The reason for the split: the fused kernel's atomic accumulation of sigma
+// across CD tiles runs at the device's atomic throughput, which caps the fast
+// bf16 arithmetic; a panel costs one extra write and read of V per apply.
+#include <hip/hip_bf16.h>
+
+#include "internal.hpp"
+
+namespace lrcc {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+
+constexpr int KB = 32;                 // Cholesky vectors per chunk (MFMA k)
+constexpr int NPL = 4;                 // planes: re_hi, re_lo, im_hi, im_lo
+constexpr int CHUNK = NPL * NS * KB;   // bf16 per block per chunk (16 KB)
+constexpr int VT = NPL * NS * NS;      // bf16 per V tile (32 KB)
+
+__device__ __forceinline__ f4 mfma(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Output row of accumulator item r in lane group lk (column = lane % 16).
+__device__ __forceinline__ int out_row(int lk, int r) { return 4 * lk + r; }
+
+__device__ __forceinline__ bf8 neg(bf8 x) {
+  u4 u = __builtin_bit_cast(u4, x);
+  u ^= (u4){0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  return __builtin_bit_cast(bf8, u);
+}
+
+__device__ __forceinline__ void split(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+// acc += x * y for real operands given as (hi, lo): hi*hi + hi*lo + lo*hi
+__device__ __forceinline__ f4 mac3(bf8 xh, bf8 xl, bf8 yh, bf8 yl, f4 acc) {
+  acc = mfma(xh, yh, acc);
+  acc = mfma(xh, yl, acc);
+  acc = mfma(xl, yh, acc);
+  return acc;
+}
+
+__device__ inline double2 load_c(const void* p, lrcc_dtype dt, size_t i) {
+  if (dt == LRCC_C128) return static_cast<const double2*>(p)[i];
+  float2 f = static_cast<const float2*>(p)[i];
+  return make_double2(f.x, f.y);
+}
+
+__device__ inline long pidx(long p, long q, long n) { return p * (2 * n - p - 1) / 2 + (q - p - 1); }
+
+// L -> Ls16[A][C][chunk][plane][64 (a,c)][32 P]
+__global__ void k_stage_L16(const void* __restrict__ L, lrcc_dtype dt, int v, int nchol, int nbv,
+                            int ncp, int conj_t, __bf16* __restrict__ Ls) {
+  const long total = (long)nbv * nbv * ncp * NS;  // (block, P, slot)
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int p = e % KB;
+    const int s = (e / KB) % NS;
+    const long rest = e / (KB * NS);  // (block, chunk)
+    const int pc = rest % (ncp / KB);
+    const long blk = rest / (ncp / KB);
+    const int C = blk % nbv, A = blk / nbv;
+    const int a = A * TB + s / TB, c = C * TB + s % TB, P = pc * KB + p;
+    float re = 0.f, im = 0.f;
+    if (a < v && c < v && P < nchol) {
+      const size_t src = conj_t ? ((size_t)P * v + c) * v + a : ((size_t)P * v + a) * v + c;
+      double2 z = load_c(L, dt, src);
+      re = (float)z.x;
+      im = (float)(conj_t ? -z.y : z.y);
+    }
+    __bf16* dst = Ls + (size_t)rest * CHUNK + s * KB + p;
+    split(re, dst[0], dst[NS * KB]);
+    split(im, dst[2 * NS * KB], dst[3 * NS * KB]);
+  }
+}
+
+// Packed doubles -> Xb16[plane][bp][m][64] (hi/lo split, zeros in dead slots)
+__global__ void k_pack_x16(const void* __restrict__ X, lrcc_dtype dt, int v, long npv, long M,
+                           long Mp, int nbp, const int* __restrict__ tab, __bf16* __restrict__ Xb) {
+  const long plane = (long)nbp * Mp * NS;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < plane;
+       e += (long)gridDim.x * blockDim.x) {
+    const int s = e % NS;
+    const long m = (e / NS) % Mp;
+    const int bp = e / (NS * Mp);
+    const int AB = tab[bp];
+    const int a = (AB >> 16) * TB + s / TB, b = (AB & 0xffff) * TB + s % TB;
+    float re = 0.f, im = 0.f;
+    if (a < b && b < v && m < M) {
+      double2 z = load_c(X, dt, (size_t)m * npv + pidx(a, b, v));
+      re = (float)z.x;
+      im = (float)z.y;
+    }
+    split(re, Xb[e], Xb[e + plane]);
+    split(im, Xb[e + 2 * plane], Xb[e + 3 * plane]);
+  }
+}
+
+// FP64 block planes -> bf16 hi/lo planes (same layout)
+__global__ void k_split_x16(long plane, const double* __restrict__ x, __bf16* __restrict__ Xb) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < plane;
+       e += (long)gridDim.x * blockDim.x) {
+    split((float)x[e], Xb[e], Xb[e + plane]);
+    split((float)x[e + plane], Xb[e + 2 * plane], Xb[e + 3 * plane]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// V panel build.  Waves 0,1 build W1 rows (a,c) 0-31 / 32-63 x all (b,d);
+// waves 2,3 build W2 rows (a,d) likewise x all (b,c).
+__global__ __launch_bounds__(WG, 1) void k_vbuild(const __bf16* __restrict__ Ls,
+                                                  const int* __restrict__ tab, int nbv, int nbp,
+                                                  int ncp, int v, int ab0,
+                                                  __bf16* __restrict__ Vws) {
+  __shared__ __attribute__((aligned(16))) __bf16 lds[4 * CHUNK];  // 64 KB
+  const int tile = blockIdx.x;
+  const int abl = tile / nbp, cd = tile - abl * nbp;
+  const int pAB = tab[ab0 + abl], pCD = tab[cd];
+  const int A = pAB >> 16, B = pAB & 0xffff, C = pCD >> 16, D = pCD & 0xffff;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wsel = wave >> 1, rb0 = (wave & 1) * 2;
+  const int nch = ncp / KB;
+  const __bf16* gblk[4] = {Ls + (size_t)(A * nbv + C) * nch * CHUNK,
+                           Ls + (size_t)(B * nbv + D) * nch * CHUNK,
+                           Ls + (size_t)(A * nbv + D) * nch * CHUNK,
+                           Ls + (size_t)(B * nbv + C) * nch * CHUNK};
+  const int qa = wsel ? 2 : 0, qb = wsel ? 3 : 1;
+
+  f4 wr[2][4], wi[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      wr[i][j] = (f4){0, 0, 0, 0};
+      wi[i][j] = wr[i][j];
+    }
+
+  constexpr int V16 = CHUNK / 8;        // 16-byte vectors per block chunk (2048)
+  constexpr int KPB = V16 / WG;         // per thread per block (8)
+  u4 pf[4 * KPB];
+  auto fetch = [&](int pc) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u4* src = reinterpret_cast<const u4*>(gblk[q] + (size_t)pc * CHUNK);
+#pragma unroll
+      for (int k = 0; k < KPB; ++k) pf[q * KPB + k] = src[k * WG + threadIdx.x];
+    }
+  };
+  fetch(0);
+  for (int pc = 0; pc < nch; ++pc) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < KPB; ++k)
+        reinterpret_cast<u4*>(lds + q * CHUNK)[k * WG + threadIdx.x] = pf[q * KPB + k];
+    __syncthreads();
+    if (pc + 1 < nch) fetch(pc + 1);
+    // operands: [plane][row][32 P], lane reads 8 consecutive P at 8*lk
+    const __bf16* la = lds + qa * CHUNK + 8 * lk;
+    const __bf16* lb = lds + qb * CHUNK + 8 * lk;
+    bf8 a[2][4], b[4][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        a[i][p] = *reinterpret_cast<const bf8*>(la + p * NS * KB + (16 * (rb0 + i) + li) * KB);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        b[j][p] = *reinterpret_cast<const bf8*>(lb + p * NS * KB + (16 * j + li) * KB);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bf8 nih = neg(a[i][2]), nil = neg(a[i][3]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        wr[i][j] = mac3(a[i][0], a[i][1], b[j][0], b[j][1], wr[i][j]);  // Ar Br
+        wi[i][j] = mac3(a[i][0], a[i][1], b[j][2], b[j][3], wi[i][j]);  // Ar Bi
+        wr[i][j] = mac3(nih, nil, b[j][2], b[j][3], wr[i][j]);          // -Ai Bi
+        wi[i][j] = mac3(a[i][2], a[i][3], b[j][0], b[j][1], wi[i][j]);  // Ai Br
+      }
+    }
+  }
+  __syncthreads();
+
+  // antisymmetrise into V32[plane][ab][cd] (f32, 32 KB) in the chunk space
+  float* Vr = reinterpret_cast<float*>(lds);
+  float* Vi = Vr + NS * NS;
+  if (wsel == 0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ii = 16 * (rb0 + i) + out_row(lk, r), jj = 16 * j + li;  // (a,c), (b,d)
+          const int idx = ((ii >> 3) * TB + (jj >> 3)) * NS + (ii & 7) * TB + (jj & 7);
+          Vr[idx] = 2.f * wr[i][j][r];
+          Vi[idx] = 2.f * wi[i][j][r];
+        }
+  }
+  __syncthreads();
+  if (wsel == 1) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ii = 16 * (rb0 + i) + out_row(lk, r), jj = 16 * j + li;  // (a,d), (b,c)
+          const int al = ii >> 3, dl = ii & 7, bl = jj >> 3, cl = jj & 7;
+          const int idx = (al * TB + bl) * NS + cl * TB + dl;
+          const bool live = (A < B || al < bl) && (B * TB + bl < v) && (C < D || cl < dl) &&
+                            (D * TB + dl < v);
+          Vr[idx] = live ? Vr[idx] - 2.f * wr[i][j][r] : 0.f;
+          Vi[idx] = live ? Vi[idx] - 2.f * wi[i][j][r] : 0.f;
+        }
+  }
+  __syncthreads();
+  // split and write the tile: Vws[abl][cd][plane][ab][cd_slot]
+  __bf16* dst = Vws + ((size_t)abl * nbp + cd) * VT;
+  for (int w = threadIdx.x; w < NS * (NS / 8); w += WG) {
+    const int ab = w >> 3, q = (w & 7) * 8;
+    bf8 rh, rl, ih, il;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      __bf16 h, l;
+      split(Vr[ab * NS + q + t], h, l);
+      rh[t] = h;
+      rl[t] = l;
+      split(Vi[ab * NS + q + t], h, l);
+      ih[t] = h;
+      il[t] = l;
+    }
+    *reinterpret_cast<bf8*>(dst + 0 * NS * NS + ab * NS + q) = rh;
+    *reinterpret_cast<bf8*>(dst + 1 * NS * NS + ab * NS + q) = rl;
+    *reinterpret_cast<bf8*>(dst + 2 * NS * NS + ab * NS + q) = ih;
+    *reinterpret_cast<bf8*>(dst + 3 * NS * NS + ab * NS + q) = il;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Contraction of one panel: workgroup (m-block of 128 rows, AB); wave w owns
+// rows 32w .. 32w+31 of the block and all 64 ab slots.
+template <typename TA>
+__global__ __launch_bounds__(WG, 1) void k_contract(const __bf16* __restrict__ Xb,
+                                                    const __bf16* __restrict__ Vws, int nbp,
+                                                    int Mp, int nmb, int ab0,
+                                                    TA* __restrict__ Sb) {
+  __shared__ __attribute__((aligned(16))) __bf16 vt[VT];  // 32 KB
+  const int mb = blockIdx.x % nmb, abl = blockIdx.x / nmb;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const size_t plane = (size_t)nbp * Mp * NS;
+  int mrow[2];
+  bool mok[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    mrow[i] = mb * 128 + 32 * wave + 16 * i;
+    mok[i] = mrow[i] < Mp;
+  }
+  f4 sr[2][4], si[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      sr[i][j] = (f4){0, 0, 0, 0};
+      si[i][j] = sr[i][j];
+    }
+  // X operands of one CD: [mblk][k-step][plane], 8 consecutive cd per lane
+  bf8 xa[2][2][4], xn[2][2][4];
+  auto fetch_x = [&](int cd, bf8 (&dst)[2][2][4]) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          bf8 z = {};
+          if (mok[i])
+            z = *reinterpret_cast<const bf8*>(
+                Xb + p * plane + ((size_t)cd * Mp + mrow[i] + li) * NS + 32 * ks + 8 * lk);
+          dst[i][ks][p] = z;
+        }
+  };
+  constexpr int VV = VT / 8 / WG;  // 16-byte vectors per thread per V tile (8)
+  u4 vp[VV];
+  const __bf16* vsrc = Vws + (size_t)abl * nbp * VT;
+  auto fetch_v = [&](int cd) {
+#pragma unroll
+    for (int k = 0; k < VV; ++k)
+      vp[k] = reinterpret_cast<const u4*>(vsrc + (size_t)cd * VT)[k * WG + threadIdx.x];
+  };
+  fetch_v(0);
+  fetch_x(0, xn);
+  for (int cd = 0; cd < nbp; ++cd) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < VV; ++k) reinterpret_cast<u4*>(vt)[k * WG + threadIdx.x] = vp[k];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) xa[i][ks][p] = xn[i][ks][p];
+    __syncthreads();
+    if (cd + 1 < nbp) {
+      fetch_v(cd + 1);
+      fetch_x(cd + 1, xn);
+    }
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      bf8 b[4][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          b[j][p] = *reinterpret_cast<const bf8*>(vt + p * NS * NS + (16 * j + li) * NS +
+                                                  32 * ks + 8 * lk);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const bf8 nih = neg(xa[i][ks][2]), nil = neg(xa[i][ks][3]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          sr[i][j] = mac3(xa[i][ks][0], xa[i][ks][1], b[j][0], b[j][1], sr[i][j]);
+          si[i][j] = mac3(xa[i][ks][0], xa[i][ks][1], b[j][2], b[j][3], si[i][j]);
+          sr[i][j] = mac3(nih, nil, b[j][2], b[j][3], sr[i][j]);
+          si[i][j] = mac3(xa[i][ks][2], xa[i][ks][3], b[j][0], b[j][1], si[i][j]);
+        }
+      }
+    }
+  }
+  // sole writer of sigma[rows, AB]
+  const int ab = ab0 + abl;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (!mok[i]) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const size_t o = ((size_t)ab * Mp + mrow[i] + out_row(lk, r)) * NS + 16 * j + li;
+        Sb[o] = (TA)sr[i][j][r];
+        Sb[o + plane] = (TA)si[i][j][r];
+      }
+  }
+}
+
+inline int grid_for(long n) {
+  long g = (n + 255) / 256;
+  return (int)(g < 65536 ? (g < 1 ? 1 : g) : 65536);
+}
+
+}  // namespace
+
+int bf16x3_chunk() { return KB; }
+size_t bf16x3_ls_bytes(const Geom& g) { return (size_t)g.nbv * g.nbv * g.ncp * NS * NPL * 2; }
+size_t bf16x3_xb_bytes(const Geom& g) { return (size_t)NPL * g.xb_plane() * 2; }
+
+hipError_t bf16x3_stage_L(const void* L, lrcc_dtype dt, const Geom& g, bool conj_t, void* Ls,
+                          hipStream_t st) {
+  const long total = (long)g.nbv * g.nbv * g.ncp * NS;
+  hipLaunchKernelGGL(k_stage_L16, dim3(grid_for(total)), dim3(256), 0, st, L, dt, g.v, g.nchol,
+                     g.nbv, g.ncp, (int)conj_t, static_cast<__bf16*>(Ls));
+  return hipGetLastError();
+}
+
+hipError_t bf16x3_pack_x(const void* X, lrcc_dtype dt, const Geom& g, const int* tab, void* Xb,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_x16, dim3(grid_for(g.xb_plane())), dim3(256), 0, st, X, dt, g.v,
+                     g.npv, g.M, g.Mp, g.nbp, tab, static_cast<__bf16*>(Xb));
+  return hipGetLastError();
+}
+
+hipError_t bf16x3_split_x(const double* x, const Geom& g, void* Xb, hipStream_t st) {
+  hipLaunchKernelGGL(k_split_x16, dim3(grid_for(g.xb_plane())), dim3(256), 0, st, g.xb_plane(),
+                     x, static_cast<__bf16*>(Xb));
+  return hipGetLastError();
+}
+
+size_t bf16x3_panel_bytes(const Geom& g, int panel_ab) {
+  return (size_t)panel_ab * g.nbp * VT * sizeof(__bf16);
+}
+
+// Panels of `panel_ab` AB block pairs: build, then contract.  Sb receives
+// every live sigma entry exactly once (FP64 or FP32 planes).
+hipError_t bf16x3_run(const Geom& g, const void* Ls, const void* Xb, void* Sb, bool acc64,
+                      void* Vws, int panel_ab, const int* tab, hipStream_t st) {
+  if (g.nbp == 0 || g.Mp == 0) return hipSuccess;
+  const int nmb = (int)((g.Mp + 127) / 128);
+  for (int ab0 = 0; ab0 < g.nbp; ab0 += panel_ab) {
+    const int n = std::min(panel_ab, g.nbp - ab0);
+    const long nb = (long)n * g.nbp;
+    if (nb > 0x7fffffffL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_vbuild, dim3((unsigned)nb), dim3(WG), 0, st,
+                       static_cast<const __bf16*>(Ls), tab, g.nbv, g.nbp, g.ncp, g.v, ab0,
+                       static_cast<__bf16*>(Vws));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (acc64)
+      hipLaunchKernelGGL(k_contract<double>, dim3((unsigned)(nmb * n)), dim3(WG), 0, st,
+                         static_cast<const __bf16*>(Xb), static_cast<const __bf16*>(Vws), g.nbp,
+                         (int)g.Mp, nmb, ab0, static_cast<double*>(Sb));
+    else
+      hipLaunchKernelGGL(k_contract<float>, dim3((unsigned)(nmb * n)), dim3(WG), 0, st,
+                         static_cast<const __bf16*>(Xb), static_cast<const __bf16*>(Vws), g.nbp,
+                         (int)g.Mp, nmb, ab0, static_cast<float*>(Sb));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace lrcc

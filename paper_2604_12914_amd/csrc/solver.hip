@@ -474,6 +474,12 @@ struct Solver {
 lrcc_status stage_for(Solver& S, const void* L, lrcc_prec prec, lrcc_cmul cmul) {
   lrcc_handle h = S.h;
   Geom g = S.g;
+  if (prec == LRCC_BF16X3) {
+    g.ncp = (int)roundup(g.nchol, bf16x3_chunk());
+    LRCC_HIP(h, h->ls2.ensure(bf16x3_ls_bytes(g)));
+    if (g.nchol > 0) LRCC_HIP(h, bf16x3_stage_L(L, LRCC_C128, g, false, h->ls2.p, h->stream));
+    return LRCC_OK;
+  }
   g.ncp = (int)roundup(g.nchol, ppl_chunk(prec, cmul));
   Buf& dst = prec == LRCC_FP64 ? h->ls : h->ls2;
   LRCC_HIP(h, dst.ensure(ppl_ls_bytes(prec, cmul, g)));
@@ -495,6 +501,14 @@ lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul 
   g.ncp = (int)roundup(g.nchol, ppl_chunk(prec, cmul));
   LRCC_HIP(h, fill_zero(S.s, (size_t)2 * S.d.plane * 8, h->stream));
   if (g.nchol == 0) return LRCC_OK;
+  if (prec == LRCC_BF16X3) {
+    g.ncp = (int)roundup(g.nchol, bf16x3_chunk());
+    LRCC_HIP(h, bf16x3_split_x(xin, g, S.x32, h->stream));
+    lrcc_status st = bf16x3_apply(h, g, h->ls2.p, S.x32, S.s, true);
+    if (st != LRCC_OK) return st;
+    ++S.n_sigma_lp;
+    return LRCC_OK;
+  }
   const void* xb = xin;
   if (prec != LRCC_FP64) {
     const long n = 2 * S.d.plane;
@@ -628,7 +642,7 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
   const size_t vb = (size_t)2 * S.d.plane * 8;
   const bool ir = op.prec != LRCC_FP64;
   size_t need[11] = {vb, vb, vb, vb * mdim, vb * mdim, vb, ir ? vb : 16, ir ? vb : 16, 0, 0,
-                     ir ? vb / 2 : 16};
+                     ir ? vb / 2 : 16};  // f32 planes, or 4 bf16 planes: same bytes
   const size_t np_alpha = (size_t)nomega * ncomp * ncomp;
   const size_t npart = std::max((size_t)S.n * (mdim + 1), np_alpha) * S.nchunk;
   need[9] = npart * sizeof(double2);

@@ -79,6 +79,25 @@ def test_fp32_matches_oracle(lrcc, dtype):
     assert rel(got, ref) < 2e-6
 
 
+@pytest.mark.parametrize("o,v,nchol,nrhs,dtype", [(5, 44, 100, 3, torch.complex128),
+                                                  (4, 24, 64, 1, torch.complex128),
+                                                  (3, 37, 7, 2, torch.complex64),
+                                                  (6, 96, 200, 2, torch.complex128)])
+def test_bf16x3_matches_oracle(lrcc, o, v, nchol, nrhs, dtype):
+    print(f"bf16x3 parity o={o} v={v} nchol={nchol} nrhs={nrhs}", flush=True)
+    rng = np.random.default_rng(200 + v)
+    L = S.make_L(rng, nchol, v, hermitian=False)
+    X = S.make_packed(rng, nrhs, o, v)
+    got = run(lrcc, L, X, prec="bf16x3", dtype=dtype)
+    ref = ppl.sigma(L, X, o, v)
+    # each real product keeps hi*hi + hi*lo + lo*hi of the bf16 split
+    # (relative error about 2^-17 per product), sums in FP32; two chained
+    # products (integral build, contraction): bound 2^-14 relative
+    err = rel(got, ref)
+    print(f"bf16x3 relative error {err:.2e}", flush=True)
+    assert err < 6e-5
+
+
 def test_empty_and_degenerate(lrcc):
     rng = np.random.default_rng(9)
     # nchol = 0: sigma is zero

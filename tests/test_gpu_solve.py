@@ -79,7 +79,7 @@ def test_jacobi_only(lrcc):
     assert info["iters_max"] == int(ref["iters"].max())
 
 
-@pytest.mark.parametrize("prec", ["fp32"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_refinement_reaches_fp64_answer(lrcc, prec):
     o, v, nchol = 5, 44, 100
     inst = S.make_instance(o, v, nchol, ncomp=3, seed=2, gamma=S.solve_gamma(v))
