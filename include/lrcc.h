@@ -107,6 +107,10 @@ typedef struct {
   double inner_tol;  /* reduced precision: inner relative tolerance (1e-5)   */
   int max_outer;     /* reduced precision: refinement sweeps (default 6)     */
   int deterministic; /* reserved; must be 0                                  */
+  int resid_fp64_every; /* reduced precision: 0 (default) = FP64 ladder of the
+                        iterate in the first sweep only, later sweeps update it
+                        by the reduced-precision ladder of the correction
+                        (the ladder is linear); 1 = FP64 ladder every sweep   */
 } lrcc_solve_opts;
 
 typedef struct {

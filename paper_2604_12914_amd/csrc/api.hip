@@ -7,6 +7,8 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "internal.hpp"
 
 namespace lrcc {
@@ -153,7 +155,7 @@ static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 static lrcc_status check_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* L,
                                const void* X, const void* S, lrcc_dtype dt, lrcc_prec prec,
-                               lrcc_cmul cmul, const char* sname) {
+                               lrcc_cmul cmul, const char* sname, bool out_optional = false) {
   if (o < 0 || v < 0 || nchol < 0 || nrhs < 0)
     return fail(h, LRCC_ERR_ARG, "o, v, nchol and nrhs must be non-negative");
   if (dt != LRCC_C128 && dt != LRCC_C64) return fail(h, LRCC_ERR_ARG, "unknown dtype");
@@ -170,14 +172,14 @@ static lrcc_status check_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs,
   const size_t nl = (size_t)nchol * v * v * es;
   if (nx > 0) {
     if (!X) return fail(h, LRCC_ERR_ARG, "X is NULL");
-    if (!S) return fail(h, LRCC_ERR_ARG, std::string(sname) + " is NULL");
+    if (!S && !out_optional) return fail(h, LRCC_ERR_ARG, std::string(sname) + " is NULL");
     if ((uintptr_t)X % es || (uintptr_t)S % es)
       return fail(h, LRCC_ERR_ARG, "X/sigma not aligned to the element size");
-    if (overlaps(X, nx, S, nx)) return fail(h, LRCC_ERR_ARG, "sigma overlaps X");
+    if (S && overlaps(X, nx, S, nx)) return fail(h, LRCC_ERR_ARG, "sigma overlaps X");
     if (nl > 0) {
       if (!L) return fail(h, LRCC_ERR_ARG, "L is NULL");
       if ((uintptr_t)L % es) return fail(h, LRCC_ERR_ARG, "L not aligned to the element size");
-      if (overlaps(L, nl, S, nx)) return fail(h, LRCC_ERR_ARG, "sigma overlaps L");
+      if (S && overlaps(L, nl, S, nx)) return fail(h, LRCC_ERR_ARG, "sigma overlaps L");
     }
   }
   return LRCC_OK;
@@ -284,6 +286,7 @@ lrcc_status lrcc_destroy(lrcc_handle h) {
     h->vws.release();
     for (auto& b : h->sv) b.release();
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
+    if (h->rb) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(h->rb));
   }
   delete h;
   return LRCC_OK;
@@ -339,17 +342,27 @@ lrcc_status lrcc_ppl_sigma_adjoint(lrcc_handle h, int o, int v, int nchol, int n
                                    const void* L, const void* X, const void* G, void* dX,
                                    void* dL, lrcc_dtype dt, lrcc_prec prec, lrcc_cmul cmul) {
   if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
-  lrcc_status st = check_sigma(h, o, v, nchol, nrhs, L, G, dX ? dX : (void*)1, dt, prec, cmul,
-                               "dX");
+  lrcc_status st = check_sigma(h, o, v, nchol, nrhs, L, G, dX, dt, prec, cmul, "dX", true);
   if (st != LRCC_OK) return st;
-  if (dL) return fail(h, LRCC_ERR_UNSUPPORTED, "dL is not built yet");
-  (void)X;
+  if (dL) {
+    const size_t es = dt == LRCC_C128 ? 16 : 8;
+    const size_t nl = (size_t)nchol * v * v * es;
+    const size_t nx = (size_t)nrhs * npair(o) * npair(v) * es;
+    if (nl > 0 && ((uintptr_t)dL % es || overlaps(dL, nl, L, nl) ||
+                   (nx > 0 && (overlaps(dL, nl, X, nx) || overlaps(dL, nl, G, nx)))))
+      return fail(h, LRCC_ERR_ARG, "dL misaligned or overlapping an input");
+    if (nx > 0 && !X) return fail(h, LRCC_ERR_ARG, "X is NULL");
+  }
   DeviceGuard dg(h->device);
   h->err.clear();
   Geom g = make_geom(o, v, nchol, nrhs, ppl_chunk(prec, cmul));
   if (dX) {
     // the adjoint ladder: sigma with (L^P)^H, applied to G
     st = sigma_packed(h, g, L, true, G, dX, dt, prec, cmul);
+    if (st != LRCC_OK) return st;
+  }
+  if (dL) {
+    st = grad_L(h, g, L, X, G, dL, dt);
     if (st != LRCC_OK) return st;
   }
   return LRCC_OK;

@@ -71,6 +71,7 @@ struct lrcc_handle_s {
   int tab_nbv = -1;
   // solver workspace
   lrcc::Buf sv[12];
+  void* rb = nullptr;     // rocBLAS handle (gradient GEMMs), created on first use
   // ladder-kernel timing (lrcc_set_timing)
   bool timing = false;
   std::vector<hipEvent_t> tev;  // start/stop pairs
@@ -137,6 +138,10 @@ hipError_t bf16x3_run(const Geom& g, const void* Ls, const void* Xb, void* Sb, b
 // Run the bf16x3 ladder with the handle's panel workspace (sized here).
 lrcc_status bf16x3_apply(lrcc_handle h, const Geom& g, const void* Ls, const void* Xb, void* Sb,
                          bool acc64);
+
+// dL = gradient of sigma with respect to L (ppl_grad.hip); packed X, G.
+lrcc_status grad_L(lrcc_handle h, const Geom& g, const void* L, const void* X, const void* G,
+                   void* dL, lrcc_dtype dt);
 
 // Block-pair table: tab[bp] = (A << 16) | B.
 lrcc_status ensure_tab(lrcc_handle h, int nbv);

@@ -430,6 +430,22 @@ __global__ __launch_bounds__(RB) void k_alpha(Dims d, int ncomp, const double* _
   if (threadIdx.x == 0) part[(size_t)p * gridDim.x + blockIdx.x] = t;
 }
 
+// acc += s for the active right-hand sides (the reduced-precision ladder of
+// a refinement correction added to the ladder of the iterate).
+__global__ void k_acc(Dims d, const int* __restrict__ active, const double* __restrict__ s,
+                      double* __restrict__ acc) {
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  for (long f = blockIdx.x * (long)RB + threadIdx.x; f < d.per_rhs; f += (long)gridDim.x * RB) {
+    const int sl = f & 63;
+    const long ml = (f >> 6) % d.npo;
+    const int bp = (int)((f >> 6) / d.npo);
+    const long g = (((long)bp * d.Mp) + (long)r * d.npo + ml) * 64 + sl;
+    acc[g] += s[g];
+    acc[g + d.plane] += s[g + d.plane];
+  }
+}
+
 // b = -a elementwise.
 __global__ void k_neg(long n, const double* __restrict__ a, double* __restrict__ b) {
   for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) b[i] = -a[i];
@@ -456,7 +472,7 @@ struct Solver {
   int n, ncomp, nomega, mdim, nchunk;
   // device buffers
   double *xi = nullptr, *x = nullptr, *s = nullptr, *xt = nullptr, *ev = nullptr, *b = nullptr;
-  double *omega = nullptr, *eps = nullptr, *x2 = nullptr, *rk = nullptr;
+  double *omega = nullptr, *eps = nullptr, *x2 = nullptr, *rk = nullptr, *sx = nullptr;
   float* x32 = nullptr;
   int *otab = nullptr, *active = nullptr;
   unsigned* valid = nullptr;
@@ -638,11 +654,12 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
   S.nchunk = (int)std::max<long>(1, std::min<long>(256, (S.d.per_rhs + 4 * RB - 1) / (4 * RB)));
 
   // workspace: 0 xi, 1 x, 2 s, 3 ring X~, 4 ring e, 5 b, 6 x2 (outer x), 7 rk,
-  // 8 small device state, 9 partials, 10 x32
+  // 8 small device state, 9 partials, 10 x32, 11 sx (ladder of the refined iterate)
   const size_t vb = (size_t)2 * S.d.plane * 8;
   const bool ir = op.prec != LRCC_FP64;
-  size_t need[11] = {vb, vb, vb, vb * mdim, vb * mdim, vb, ir ? vb : 16, ir ? vb : 16, 0, 0,
-                     ir ? vb / 2 : 16};  // f32 planes, or 4 bf16 planes: same bytes
+  size_t need[12] = {vb, vb, vb, vb * mdim, vb * mdim, vb, ir ? vb : 16, ir ? vb : 16, 0, 0,
+                     ir ? vb / 2 : 16,  // f32 planes, or 4 bf16 planes: same bytes
+                     ir ? vb : 16};
   const size_t np_alpha = (size_t)nomega * ncomp * ncomp;
   const size_t npart = std::max((size_t)S.n * (mdim + 1), np_alpha) * S.nchunk;
   need[9] = npart * sizeof(double2);
@@ -654,7 +671,7 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
                off_c = off_B + roundup((long)S.n * MAXD * MAXD * 16, 256),
                end = off_c + roundup((long)S.n * MAXD * 16, 256);
   need[8] = end;
-  for (int k = 0; k < 11; ++k) LRCC_HIP(h, h->sv[k].ensure(need[k]));
+  for (int k = 0; k < 12; ++k) LRCC_HIP(h, h->sv[k].ensure(need[k]));
   S.xi = h->sv[0].as<double>();
   S.x = h->sv[1].as<double>();
   S.s = h->sv[2].as<double>();
@@ -674,6 +691,7 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
   S.coef = reinterpret_cast<double2*>(sm + off_c);
   S.part = h->sv[9].as<double2>();
   S.x32 = h->sv[10].as<float>();
+  S.sx = h->sv[11].as<double>();
 
   // host-side small state (pinned)
   std::vector<double> om(S.n);
@@ -738,16 +756,27 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
       lrcc_status is = jacobi_diis(S, S.rk, S.x, op.prec, op.cmul, inner_tol, max_iter,
                                    act.data());
       if (is == LRCC_ERR_NONFINITE) return fail(h, is, "non-finite residual");
-      // x2 += d; rk = b - (D - w) x2 - sigma64(x2)
+      // x2 += d; sx = ladder(x2): FP64 ladder of the whole iterate in the
+      // first sweep (or every sweep), else sx += reduced-precision ladder of
+      // the correction d; then rk = b - (D - w) x2 - sx
       LRCC_HIP(h, hipMemcpyAsync(S.active, act.data(), S.n * sizeof(int), hipMemcpyHostToDevice,
                                  h->stream));
       hipLaunchKernelGGL(k_add, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.active, S.x,
                          S.x2);
       LRCC_HIP(h, hipGetLastError());
-      st = apply_sigma(S, S.x2, LRCC_FP64, LRCC_CMUL_4M);
-      if (st != LRCC_OK) return st;
+      if (outer == 0 || op.resid_fp64_every) {
+        st = apply_sigma(S, S.x2, LRCC_FP64, LRCC_CMUL_4M);
+        if (st != LRCC_OK) return st;
+        LRCC_HIP(h, hipMemcpyAsync(S.sx, S.s, vb, hipMemcpyDeviceToDevice, h->stream));
+      } else {
+        st = apply_sigma(S, S.x, op.prec, op.cmul);
+        if (st != LRCC_OK) return st;
+        hipLaunchKernelGGL(k_acc, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.active, S.s,
+                           S.sx);
+        LRCC_HIP(h, hipGetLastError());
+      }
       hipLaunchKernelGGL(k_outer, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.eps, S.omega,
-                         h->tab.as<int>(), S.otab, S.active, S.b, S.x2, S.s, S.rk, S.part);
+                         h->tab.as<int>(), S.otab, S.active, S.b, S.x2, S.sx, S.rk, S.part);
       LRCC_HIP(h, hipGetLastError());
       LRCC_HIP(h, hipMemcpyAsync(S.h_part, S.part, (size_t)S.n * S.nchunk * sizeof(double2),
                                  hipMemcpyDeviceToHost, h->stream));

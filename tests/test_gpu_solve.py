@@ -79,13 +79,18 @@ def test_jacobi_only(lrcc):
     assert info["iters_max"] == int(ref["iters"].max())
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_refinement_reaches_fp64_answer(lrcc, prec):
+@pytest.mark.parametrize("prec,every", [("fp32", 0), ("bf16x3", 0), ("bf16x3", 1)])
+def test_refinement_reaches_fp64_answer(lrcc, prec, every):
     o, v, nchol = 5, 44, 100
     inst = S.make_instance(o, v, nchol, ncomp=3, seed=2, gamma=S.solve_gamma(v))
     om = OMEGAS
-    alpha, info = lrcc.solve(*to_dev(inst), om, prec=prec, tol=1e-8, inner_tol=1e-5)
+    alpha, info = lrcc.solve(*to_dev(inst), om, prec=prec, tol=1e-8, inner_tol=1e-5,
+                             resid_fp64_every=every)
     dense = response.solve_dense(inst.L, inst.eps, inst.mu, om, o, v)["alpha"]
     assert info["final_relres"] < 1e-8
     assert rel(alpha, dense) < 1e-7
-    assert info["n_sigma_fp64"] <= 3 and info["n_sigma_lowp"] > 0
+    assert info["n_sigma_lowp"] > 0
+    if every:
+        assert info["n_sigma_fp64"] <= 3
+    else:
+        assert info["n_sigma_fp64"] == 1
