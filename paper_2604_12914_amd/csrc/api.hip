@@ -193,8 +193,6 @@ lrcc_status sigma_packed(lrcc_handle h, const Geom& g, const void* L, bool conj_
   if (nx == 0) return LRCC_OK;
   if (cmul == LRCC_CMUL_3M && prec == LRCC_BF16X3)
     return fail(h, LRCC_ERR_UNSUPPORTED, "bf16x3 uses the 4M complex form only");
-  if (cmul == LRCC_CMUL_3M)
-    return fail(h, LRCC_ERR_UNSUPPORTED, "this complex form is not built yet");
   lrcc_status st = ensure_tab(h, g.nbv);
   if (st != LRCC_OK) return st;
   const int* tab = h->tab.as<int>();

@@ -259,12 +259,194 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_4m(const T* __restrict__ Ls,
   }
 }
 
+// 3M form of the integral build: with planes (re, im, re+im) of the staged
+// Cholesky blocks, T1 = sum ar br, T2 = sum ai bi, T3 = sum (ar+ai)(br+bi)
+// give re = T1 - T2 and im = T3 - T1 - T2: three real MFMA products per
+// complex product instead of four.  The contraction keeps the 4M form.
+template <typename T, typename TA, int KC>
+__global__ __launch_bounds__(WG, 1) void k_ppl_3m(const T* __restrict__ Ls,
+                                                  const T* __restrict__ Xb,
+                                                  TA* __restrict__ Sb,
+                                                  const int* __restrict__ tab, int nbv,
+                                                  int nbp, int ncp, int Mp, int v) {
+  typedef typename Acc<T>::t acc_t;
+  typedef typename Vec16<T>::t vec_t;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int CH = 3 * NS * KC;  // one block's chunk: KC vectors x 3 planes x 64
+  constexpr int ELEMS = 4 * CH > 2 * NS * NS ? 4 * CH : 2 * NS * NS;
+  __shared__ __attribute__((aligned(16))) T lds[ELEMS];
+
+  const int tile = blockIdx.x;
+  const int ab = tile / nbp, cd = tile - ab * nbp;
+  const int pAB = tab[ab], pCD = tab[cd];
+  const int A = pAB >> 16, B = pAB & 0xffff, C = pCD >> 16, D = pCD & 0xffff;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+
+  const size_t bstride = (size_t)ncp * 3 * NS;
+  const T* const gblk[4] = {Ls + (size_t)(A * nbv + C) * bstride,
+                            Ls + (size_t)(B * nbv + D) * bstride,
+                            Ls + (size_t)(A * nbv + D) * bstride,
+                            Ls + (size_t)(B * nbv + C) * bstride};
+  acc_t t1[2][4], t2[2][4], t3[2][4];  // [W1 / W2][column block]
+#pragma unroll
+  for (int w = 0; w < 2; ++w)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      t1[w][j] = acc_t{0, 0, 0, 0};
+      t2[w][j] = t1[w][j];
+      t3[w][j] = t1[w][j];
+    }
+  constexpr int KPB = CH / VN / WG;
+  static_assert(KPB * VN * WG == CH, "chunk must split evenly over the workgroup");
+  vec_t pf[4 * KPB];
+  auto fetch = [&](int p0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const vec_t* src = reinterpret_cast<const vec_t*>(gblk[q] + (size_t)p0 * 3 * NS);
+#pragma unroll
+      for (int k = 0; k < KPB; ++k) pf[q * KPB + k] = src[k * WG + threadIdx.x];
+    }
+  };
+  fetch(0);
+  for (int p0 = 0; p0 < ncp; p0 += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < KPB; ++k)
+        reinterpret_cast<vec_t*>(lds + q * CH)[k * WG + threadIdx.x] = pf[q * KPB + k];
+    __syncthreads();
+    if (p0 + KC < ncp) fetch(p0 + KC);
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int p = 4 * ks + lk;
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        // W1: rows from L_AC (block 0), columns from L_BD (block 1);
+        // W2: rows from L_AD (block 2), columns from L_BC (block 3)
+        const T* la = lds + (2 * w) * CH + p * 3 * NS + 16 * wave + li;
+        const T* lb = lds + (2 * w + 1) * CH + p * 3 * NS + li;
+        const T a0 = la[0], a1 = la[NS], a2 = la[2 * NS];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          t1[w][j] = mfma(a0, lb[16 * j], t1[w][j]);
+          t2[w][j] = mfma(a1, lb[NS + 16 * j], t2[w][j]);
+          t3[w][j] = mfma(a2, lb[2 * NS + 16 * j], t3[w][j]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- 2. antisymmetrise into V[cd][ab] (planar re, im) in LDS -----------
+  T* Vr = lds;
+  T* Vi = lds + NS * NS;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * wave + out_row<T>(lk, r), jj = 16 * j + li;  // (a,c), (b,d)
+      const int idx = ((i & 7) * TB + (jj & 7)) * NS + (i >> 3) * TB + (jj >> 3);
+      Vr[idx] = (T)2 * (t1[0][j][r] - t2[0][j][r]);
+      Vi[idx] = (T)2 * (t3[0][j][r] - t1[0][j][r] - t2[0][j][r]);
+    }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * wave + out_row<T>(lk, r), jj = 16 * j + li;  // (a,d), (b,c)
+      const int al = i >> 3, dl = i & 7, bl = jj >> 3, cl = jj & 7;
+      const int idx = (cl * TB + dl) * NS + al * TB + bl;
+      const bool live = (A < B || al < bl) && (B * TB + bl < v) && (C < D || cl < dl) &&
+                        (D * TB + dl < v);
+      const T re = t1[1][j][r] - t2[1][j][r], im = t3[1][j][r] - t1[1][j][r] - t2[1][j][r];
+      Vr[idx] = live ? Vr[idx] - (T)2 * re : (T)0;
+      Vi[idx] = live ? Vi[idx] - (T)2 * im : (T)0;
+    }
+  __syncthreads();
+
+  // ---- 3. contract against X[:, CD] and accumulate into sigma[:, AB] ------
+  const size_t plane = (size_t)nbp * Mp * NS;
+  const T* xr_g = Xb + (size_t)cd * Mp * NS;
+  const T* xi_g = xr_g + plane;
+  TA* sr_g = Sb + (size_t)ab * Mp * NS;
+  TA* si_g = sr_g + plane;
+  // lane (row li, group lk) holds X[m0+li][16 lk .. 16 lk + 15]; the rows of
+  // the next m-chunk are fetched while this one is contracted
+  constexpr int NX = 16 / VN;
+  vec_t xpr[NX], xpi[NX];
+  auto fetch_x = [&](int m0) {
+    const vec_t* pr = reinterpret_cast<const vec_t*>(xr_g + (size_t)(m0 + li) * NS + 16 * lk);
+    const vec_t* pi = reinterpret_cast<const vec_t*>(xi_g + (size_t)(m0 + li) * NS + 16 * lk);
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      xpr[k] = pr[k];
+      xpi[k] = pi[k];
+    }
+  };
+  if (wave < Mp / 16) fetch_x(wave * 16);
+  for (int mc = wave; mc < Mp / 16; mc += 4) {
+    const int m0 = mc * 16;
+    T xr[16], xi[16];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+#pragma unroll
+      for (int t = 0; t < VN; ++t) {
+        xr[k * VN + t] = xpr[k][t];
+        xi[k * VN + t] = xpi[k][t];
+      }
+    }
+    if (mc + 4 < Mp / 16) fetch_x(m0 + 64);
+    acc_t sr[4], si[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      sr[n] = acc_t{0, 0, 0, 0};
+      si[n] = sr[n];
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = 16 * lk + s;  // cd slot fed by this lane at step s
+      T vr[4], vi[4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        vr[n] = Vr[k * NS + 16 * n + li];
+        vi[n] = Vi[k * NS + 16 * n + li];
+      }
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        sr[n] = mfma(xr[s], vr[n], sr[n]);
+        si[n] = mfma(xr[s], vi[n], si[n]);
+      }
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        sr[n] = mfma(-xi[s], vi[n], sr[n]);
+        si[n] = mfma(xi[s], vr[n], si[n]);
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const size_t o = (size_t)(m0 + out_row<T>(lk, r)) * NS + 16 * n + li;
+        atomic_add(sr_g + o, (TA)sr[n][r]);
+        atomic_add(si_g + o, (TA)si[n][r]);
+      }
+    }
+  }
+}
+
+
 constexpr int KC64 = 16;
 constexpr int KC32 = 32;
 
 }  // namespace
 
-int ppl_chunk(lrcc_prec prec, lrcc_cmul) { return prec == LRCC_FP64 ? KC64 : KC32; }
+int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul) {
+  if (cmul == LRCC_CMUL_3M) return prec == LRCC_FP64 ? 8 : 16;
+  return prec == LRCC_FP64 ? KC64 : KC32;
+}
 int ppl_planes(lrcc_prec, lrcc_cmul cmul) { return cmul == LRCC_CMUL_3M ? 3 : 2; }
 
 size_t ppl_ls_bytes(lrcc_prec prec, lrcc_cmul cmul, const Geom& g) {
@@ -278,11 +460,22 @@ size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g) {
 hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
                       const void* Ls, const void* Xb, void* Sb, const int* tab,
                       hipStream_t st) {
-  if (cmul != LRCC_CMUL_4M) return hipErrorNotSupported;
   const long ntile = (long)g.nbp * g.nbp;
   if (ntile == 0 || g.Mp == 0) return hipSuccess;
   if (ntile > 0x7fffffffL) return hipErrorInvalidValue;
   dim3 grid((unsigned)ntile), block(WG);
+  if (cmul == LRCC_CMUL_3M) {
+#define LRCC_L3(T, TA, KC)                                                                      \
+  hipLaunchKernelGGL((k_ppl_3m<T, TA, KC>), grid, block, 0, st, static_cast<const T*>(Ls),     \
+                     static_cast<const T*>(Xb), static_cast<TA*>(Sb), tab, g.nbv, g.nbp, g.ncp, \
+                     (int)g.Mp, g.v)
+    if (prec == LRCC_FP64) LRCC_L3(double, double, 8);
+    else if (prec == LRCC_FP32 && acc64) LRCC_L3(float, double, 16);
+    else if (prec == LRCC_FP32) LRCC_L3(float, float, 16);
+    else return hipErrorNotSupported;
+#undef LRCC_L3
+    return hipGetLastError();
+  }
   if (prec == LRCC_FP64) {
     hipLaunchKernelGGL((k_ppl_4m<double, double, KC64>), grid, block, 0, st,
                        static_cast<const double*>(Ls), static_cast<const double*>(Xb),

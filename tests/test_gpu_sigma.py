@@ -56,6 +56,19 @@ def test_fp64_matches_oracle(lrcc, o, v, nchol, nrhs, herm):
     assert rel(got, ref) < 1e-10
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-6)])
+@pytest.mark.parametrize("o,v,nchol,nrhs", [(5, 44, 100, 3), (3, 37, 7, 2), (4, 24, 64, 1)])
+def test_3m_matches_oracle(lrcc, prec, tol, o, v, nchol, nrhs):
+    print(f"3M {prec} parity o={o} v={v} nchol={nchol} nrhs={nrhs}", flush=True)
+    rng = np.random.default_rng(400 + v)
+    L = S.make_L(rng, nchol, v, hermitian=False)
+    X = S.make_packed(rng, nrhs, o, v)
+    got = run(lrcc, L, X, prec=prec, cmul="3m")
+    if prec == "fp32":
+        L, X = L.astype(np.complex64).astype(complex), X.astype(np.complex64).astype(complex)
+    assert rel(got, ppl.sigma(L, X, o, v)) < tol
+
+
 def test_fp64_complex64_storage(lrcc):
     rng = np.random.default_rng(7)
     o, v, nchol = 4, 30, 40
