@@ -80,17 +80,83 @@ void Buf::release() {
 
 lrcc_status ensure_tab(lrcc_handle h, int nbv) {
   if (h->tab_nbv == nbv) return LRCC_OK;
-  const int nbp = nbv * (nbv + 1) / 2;
-  std::vector<int> t(nbp > 0 ? nbp : 1);
-  int k = 0;
-  for (int A = 0; A < nbv; ++A)
-    for (int B = A; B < nbv; ++B) t[k++] = (A << 16) | B;
+  std::vector<int> t;
+  block_pair_table(nbv, &t);
   LRCC_HIP(h, h->tab.ensure(t.size() * sizeof(int)));
   LRCC_HIP(h, hipMemcpyAsync(h->tab.p, t.data(), t.size() * sizeof(int), hipMemcpyHostToDevice,
                              h->stream));
   LRCC_HIP(h, hipStreamSynchronize(h->stream));
   h->tab_nbv = nbv;
   return LRCC_OK;
+}
+
+void block_pair_table(int nbv, std::vector<int>* tab) {
+  tab->clear();
+  for (int A = 0; A < nbv; ++A)
+    for (int B = A; B < nbv; ++B) tab->push_back((A << 16) | B);
+  if (tab->empty()) tab->push_back(0);
+}
+
+void supertile_order(const Geom& g, int ab0, int ab1, int sw, int nx, std::vector<int>* ord) {
+  const int nbv = g.nbv, nbp = g.nbp;
+  std::vector<int> A(nbp), B(nbp);
+  for (int a = 0, k = 0; a < nbv; ++a)
+    for (int b = a; b < nbv; ++b, ++k) {
+      A[k] = a;
+      B[k] = b;
+    }
+  const int ng = (nbv + sw - 1) / sw;
+  // groups of block pairs by (A / sw, B / sw)
+  std::vector<std::vector<int>> gab((size_t)ng * ng), gcd((size_t)ng * ng);
+  for (int bp = 0; bp < nbp; ++bp) {
+    const size_t gk = (size_t)(A[bp] / sw) * ng + B[bp] / sw;
+    gcd[gk].push_back(bp);
+    if (bp >= ab0 && bp < ab1) gab[gk].push_back(bp);
+  }
+  const long total = (long)(ab1 - ab0) * nbp;
+  std::vector<int> all;
+  all.reserve(total);
+  for (const auto& ga : gab) {
+    if (ga.empty()) continue;
+    for (const auto& gc : gcd) {
+      if (gc.empty()) continue;
+      for (int ab : ga)
+        for (int cd : gc) all.push_back((ab - ab0) * nbp + cd);
+    }
+  }
+  // contiguous share per XCD; workgroup w runs on XCD w % nx, as the j-th
+  // (j = w / nx) of that XCD's workgroups
+  const long q = total / nx, r = total % nx;
+  ord->assign(total, 0);
+  for (long w = 0; w < total; ++w) {
+    const long x = w % nx, j = w / nx;
+    (*ord)[w] = all[x * q + std::min<long>(x, r) + j];
+  }
+}
+
+const int* tile_order(lrcc_handle h, const Geom& g, int ab0, int ab1, lrcc_status* st) {
+  const int sw = h->order_s > 0 ? h->order_s : 4;
+  const long key[5] = {g.nbv, ab0, ab1, sw, h->ncu};
+  bool same = true;
+  for (int k = 0; k < 5; ++k) same = same && key[k] == h->order_key[k];
+  if (same) {
+    *st = LRCC_OK;
+    return h->order.as<int>();
+  }
+  std::vector<int> ord;
+  supertile_order(g, ab0, ab1, sw, std::max(1, h->ncu / 32), &ord);
+  hipError_t e = h->order.ensure(ord.size() * sizeof(int));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->order.p, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice,
+                       h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    *st = hip_fail(h, e, "tile order upload");
+    return nullptr;
+  }
+  for (int k = 0; k < 5; ++k) h->order_key[k] = key[k];
+  *st = LRCC_OK;
+  return h->order.as<int>();
 }
 
 lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
@@ -108,7 +174,10 @@ lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, c
     e1 = h->tev[2 * h->tev_used + 1];
     LRCC_HIP(h, hipEventRecord(e0, h->stream));
   }
-  LRCC_HIP(h, ppl_launch(prec, cmul, acc64, g, Ls, Xb, Sb, h->tab.as<int>(), h->stream));
+  lrcc_status ost;
+  const int* ord = tile_order(h, g, 0, g.nbp, &ost);
+  if (ost != LRCC_OK) return ost;
+  LRCC_HIP(h, ppl_launch(prec, cmul, acc64, g, Ls, Xb, Sb, h->tab.as<int>(), ord, h->stream));
   if (h->timing) {
     LRCC_HIP(h, hipEventRecord(e1, h->stream));
     ++h->tev_used;
@@ -139,7 +208,7 @@ lrcc_status bf16x3_apply(lrcc_handle h, const Geom& g, const void* Ls, const voi
     e1 = h->tev[2 * h->tev_used + 1];
     LRCC_HIP(h, hipEventRecord(e0, h->stream));
   }
-  LRCC_HIP(h, bf16x3_run(g, Ls, Xb, Sb, acc64, h->vws.p, panel, h->tab.as<int>(), h->stream));
+  LRCC_HIP(h, bf16x3_run(h, g, Ls, Xb, Sb, acc64, h->vws.p, panel, h->tab.as<int>(), h->stream));
   if (h->timing) {
     LRCC_HIP(h, hipEventRecord(e1, h->stream));
     ++h->tev_used;
@@ -391,9 +460,30 @@ lrcc_status lrcc_solve(lrcc_handle h, int o, int v, int nchol, const double* eps
   return solve_impl(h, o, v, nchol, eps, L, ncomp, mu, nomega, omegas, opts, alpha, info);
 }
 
-lrcc_status lrcc_solve_batched(lrcc_handle h, int, const lrcc_instance*, const lrcc_solve_opts*,
-                               lrcc_solve_info*) {
-  return fail(h, LRCC_ERR_UNSUPPORTED, "batched solve is not built yet");
+lrcc_status lrcc_solve_batched(lrcc_handle h, int ninst, const lrcc_instance* inst,
+                               const lrcc_solve_opts* opts, lrcc_solve_info* info) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  if (ninst < 0 || (ninst > 0 && !inst)) return fail(h, LRCC_ERR_ARG, "bad instance list");
+  for (int i = 0; i < ninst; ++i) {
+    const lrcc_instance& I = inst[i];
+    const std::string w = "instance " + std::to_string(i) + ": ";
+    if (I.o < 0 || I.v < 0 || I.nchol < 0 || I.ncomp < 0 || I.nomega < 0)
+      return fail(h, LRCC_ERR_ARG, w + "sizes must be non-negative");
+    if (I.v > 4096 || I.nchol > 65536) return fail(h, LRCC_ERR_SHAPE, w + "v or nchol too large");
+    if ((long)I.nomega * I.ncomp * npair(I.o) > (1L << 24) || (long)I.nomega * I.ncomp > 4096)
+      return fail(h, LRCC_ERR_SHAPE, w + "too many right-hand sides");
+    if (I.nomega * I.ncomp > 0) {
+      if (!I.alpha || !I.omegas) return fail(h, LRCC_ERR_ARG, w + "alpha or omegas is NULL");
+      if (I.o + I.v > 0 && !I.eps) return fail(h, LRCC_ERR_ARG, w + "eps is NULL");
+      if (I.o > 0 && I.v > 0 && !I.mu) return fail(h, LRCC_ERR_ARG, w + "mu is NULL");
+      if (I.nchol > 0 && I.v > 0 && !I.L) return fail(h, LRCC_ERR_ARG, w + "L is NULL");
+      if ((uintptr_t)I.L % 16 || (uintptr_t)I.mu % 16 || (uintptr_t)I.eps % 8)
+        return fail(h, LRCC_ERR_ARG, w + "misaligned L, mu or eps");
+    }
+  }
+  DeviceGuard dg(h->device);
+  h->err.clear();
+  return solve_batched_impl(h, ninst, inst, opts, info);
 }
 
 const char* lrcc_status_str(lrcc_status s) {

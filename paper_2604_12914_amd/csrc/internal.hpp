@@ -66,6 +66,9 @@ struct lrcc_handle_s {
   lrcc::Buf ls, ls2;      // staged Cholesky vectors (ls2: second operand set)
   lrcc::Buf xb, sb, gb;   // block-layout doubles: input, accumulator, gradient
   lrcc::Buf tab;          // block-pair table
+  lrcc::Buf order;        // tile order (XCD-aware super-tiles), see tile_order()
+  long order_key[5] = {-1, -1, -1, -1, -1};
+  int order_s = 0;        // super-tile width in virtual blocks (0 = default)
   lrcc::Buf vws;          // bf16x3: one panel of antisymmetrised integral tiles
   size_t panel_cap = 0;   // bytes allowed for vws (0 = not yet chosen)
   int tab_nbv = -1;
@@ -112,8 +115,24 @@ hipError_t fill_zero(void* p, size_t bytes, hipStream_t st);
 // Sb must be zeroed by the caller.
 hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
                       const void* Ls, const void* Xb, void* Sb, const int* tab,
-                      hipStream_t st);
+                      const int* order, hipStream_t st);
+// One instance of the persistent FP64 ladder (k_ppl_queue): its staged
+// vectors, block-layout doubles and accumulator, geometry, tile order and
+// the first queue item that belongs to it.
+struct BatchInst {
+  const double* Ls;
+  const double* Xb;
+  double* Sb;
+  const int* tab;
+  const int* order;
+  int nbv, nbp, ncp, Mp, v;
+  long start;
+};
+hipError_t ppl_queue_launch(const BatchInst* inst, int ninst, long total, unsigned* counter,
+                            int nwg, hipStream_t st);
 int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul);   // KC of the staged layout
+int ppl_variant_occ(lrcc_prec prec);             // 4M launch variant (1 or 2 WG/CU)
+void ppl_set_variant_occ(lrcc_prec prec, int occ);
 int ppl_planes(lrcc_prec prec, lrcc_cmul cmul);  // planes of the staged L
 size_t ppl_ls_bytes(lrcc_prec prec, lrcc_cmul cmul, const Geom& g);
 size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g);
@@ -133,8 +152,8 @@ hipError_t bf16x3_stage_L(const void* L, lrcc_dtype dt, const Geom& g, bool conj
 hipError_t bf16x3_pack_x(const void* X, lrcc_dtype dt, const Geom& g, const int* tab, void* Xb,
                          hipStream_t st);
 hipError_t bf16x3_split_x(const double* x, const Geom& g, void* Xb, hipStream_t st);
-hipError_t bf16x3_run(const Geom& g, const void* Ls, const void* Xb, void* Sb, bool acc64,
-                      void* Vws, int panel_ab, const int* tab, hipStream_t st);
+hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* Xb, void* Sb,
+                      bool acc64, void* Vws, int panel_ab, const int* tab, hipStream_t st);
 // Run the bf16x3 ladder with the handle's panel workspace (sized here).
 lrcc_status bf16x3_apply(lrcc_handle h, const Geom& g, const void* Ls, const void* Xb, void* Sb,
                          bool acc64);
@@ -142,6 +161,23 @@ lrcc_status bf16x3_apply(lrcc_handle h, const Geom& g, const void* Ls, const voi
 // dL = gradient of sigma with respect to L (ppl_grad.hip); packed X, G.
 lrcc_status grad_L(lrcc_handle h, const Geom& g, const void* L, const void* X, const void* G,
                    void* dL, lrcc_dtype dt);
+
+// Tile order for a launch over AB block pairs [ab0, ab1) x all CD: entry w
+// is the tile (ab - ab0) * nbp + cd run by workgroup w.  Tiles are grouped
+// into super-tiles whose AB and CD pairs come from s-wide ranges of virtual
+// blocks (so the four Cholesky blocks a tile reads fall in s x s sets), and
+// each XCD receives a contiguous run of super-tiles (workgroups go to XCDs
+// round-robin).  Returns a device pointer owned by the handle.
+const int* tile_order(lrcc_handle h, const Geom& g, int ab0, int ab1, lrcc_status* st);
+
+// Host-side builders of the block-pair table and of the super-tile order
+// (nx = number of XCDs to split the order over; 1 = plain super-tile order).
+void block_pair_table(int nbv, std::vector<int>* tab);
+void supertile_order(const Geom& g, int ab0, int ab1, int sw, int nx, std::vector<int>* ord);
+
+// Batched solve (solver.hip); arguments already validated.
+lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* inst,
+                               const lrcc_solve_opts* opts, lrcc_solve_info* info);
 
 // Block-pair table: tab[bp] = (A << 16) | B.
 lrcc_status ensure_tab(lrcc_handle h, int nbv);

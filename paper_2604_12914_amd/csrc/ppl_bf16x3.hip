@@ -131,11 +131,12 @@ __global__ void k_split_x16(long plane, const double* __restrict__ x, __bf16* __
 // V panel build.  Waves 0,1 build W1 rows (a,c) 0-31 / 32-63 x all (b,d);
 // waves 2,3 build W2 rows (a,d) likewise x all (b,c).
 __global__ __launch_bounds__(WG, 1) void k_vbuild(const __bf16* __restrict__ Ls,
-                                                  const int* __restrict__ tab, int nbv, int nbp,
+                                                  const int* __restrict__ tab,
+                                                  const int* __restrict__ order, int nbv, int nbp,
                                                   int ncp, int v, int ab0,
                                                   __bf16* __restrict__ Vws) {
   __shared__ __attribute__((aligned(16))) __bf16 lds[4 * CHUNK];  // 64 KB
-  const int tile = blockIdx.x;
+  const int tile = order[blockIdx.x];
   const int abl = tile / nbp, cd = tile - abl * nbp;
   const int pAB = tab[ab0 + abl], pCD = tab[cd];
   const int A = pAB >> 16, B = pAB & 0xffff, C = pCD >> 16, D = pCD & 0xffff;
@@ -158,8 +159,8 @@ __global__ __launch_bounds__(WG, 1) void k_vbuild(const __bf16* __restrict__ Ls,
       wi[i][j] = wr[i][j];
     }
 
-  constexpr int V16 = CHUNK / 8;        // 16-byte vectors per block chunk (2048)
-  constexpr int KPB = V16 / WG;         // per thread per block (8)
+  constexpr int V16 = CHUNK / 8;        // 16-byte vectors per block chunk (1024)
+  constexpr int KPB = V16 / WG;         // per thread per block (4)
   u4 pf[4 * KPB];
   auto fetch = [&](int pc) {
 #pragma unroll
@@ -408,16 +409,19 @@ size_t bf16x3_panel_bytes(const Geom& g, int panel_ab) {
 
 // Panels of `panel_ab` AB block pairs: build, then contract.  Sb receives
 // every live sigma entry exactly once (FP64 or FP32 planes).
-hipError_t bf16x3_run(const Geom& g, const void* Ls, const void* Xb, void* Sb, bool acc64,
-                      void* Vws, int panel_ab, const int* tab, hipStream_t st) {
+hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* Xb, void* Sb,
+                      bool acc64, void* Vws, int panel_ab, const int* tab, hipStream_t st) {
   if (g.nbp == 0 || g.Mp == 0) return hipSuccess;
   const int nmb = (int)((g.Mp + 127) / 128);
   for (int ab0 = 0; ab0 < g.nbp; ab0 += panel_ab) {
     const int n = std::min(panel_ab, g.nbp - ab0);
     const long nb = (long)n * g.nbp;
     if (nb > 0x7fffffffL) return hipErrorInvalidValue;
+    lrcc_status ost;
+    const int* ord = tile_order(h, g, ab0, ab0 + n, &ost);
+    if (ost != LRCC_OK) return hipErrorUnknown;
     hipLaunchKernelGGL(k_vbuild, dim3((unsigned)nb), dim3(WG), 0, st,
-                       static_cast<const __bf16*>(Ls), tab, g.nbv, g.nbp, g.ncp, g.v, ab0,
+                       static_cast<const __bf16*>(Ls), tab, ord, g.nbv, g.nbp, g.ncp, g.v, ab0,
                        static_cast<__bf16*>(Vws));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -14,6 +14,8 @@
 //      on the matrix cores, and add the 64-slot partial sums to the block-
 //      layout accumulator with device-scope atomics.
 // The integral tile never reaches HBM.
+#include <cstdlib>
+
 #include "internal.hpp"
 
 namespace lrcc {
@@ -61,20 +63,16 @@ struct Smem {
   static constexpr int elems = build > vtile ? build : vtile;
 };
 
-template <typename T, typename TA, int KC>
-__global__ __launch_bounds__(WG, 1) void k_ppl_4m(const T* __restrict__ Ls,
-                                                  const T* __restrict__ Xb,
-                                                  TA* __restrict__ Sb,
-                                                  const int* __restrict__ tab, int nbv,
-                                                  int nbp, int ncp, int Mp, int v) {
+// One tile pair (ab, cd) of the fused ladder, run by one 4-wave workgroup.
+template <typename T, typename TA, int KC, int OCC>
+__device__ __forceinline__ void ppl_tile_4m(const T* __restrict__ Ls, const T* __restrict__ Xb,
+                                            TA* __restrict__ Sb, const int* __restrict__ tab,
+                                            int nbv, int nbp, int ncp, int Mp, int v, int ab,
+                                            int cd, T* lds) {
   typedef typename Acc<T>::t acc_t;
   typedef typename Vec16<T>::t vec_t;
   constexpr int VN = Vec16<T>::n;
   constexpr int CH = Smem<T, KC>::chunk;
-  __shared__ __attribute__((aligned(16))) T lds[Smem<T, KC>::elems];
-
-  const int tile = blockIdx.x;
-  const int ab = tile / nbp, cd = tile - ab * nbp;
   const int pAB = tab[ab], pCD = tab[cd];
   const int A = pAB >> 16, B = pAB & 0xffff, C = pCD >> 16, D = pCD & 0xffff;
 
@@ -208,9 +206,12 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_4m(const T* __restrict__ Ls,
       xpi[k] = pi[k];
     }
   };
-  if (wave < Mp / 16) fetch_x(wave * 16);
+  // with one workgroup per CU the next rows are prefetched; with two, the
+  // other workgroup covers the load latency and the registers are scarce
+  if (OCC == 1 && wave < Mp / 16) fetch_x(wave * 16);
   for (int mc = wave; mc < Mp / 16; mc += 4) {
     const int m0 = mc * 16;
+    if (OCC > 1) fetch_x(m0);
     T xr[16], xi[16];
 #pragma unroll
     for (int k = 0; k < NX; ++k) {
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_4m(const T* __restrict__ Ls,
         xi[k * VN + t] = xpi[k][t];
       }
     }
-    if (mc + 4 < Mp / 16) fetch_x(m0 + 64);
+    if (OCC == 1 && mc + 4 < Mp / 16) fetch_x(m0 + 64);
     acc_t sr[4], si[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
@@ -259,6 +260,44 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_4m(const T* __restrict__ Ls,
   }
 }
 
+template <typename T, typename TA, int KC, int OCC>
+__global__ __launch_bounds__(WG, OCC) void k_ppl_4m(const T* __restrict__ Ls,
+                                                    const T* __restrict__ Xb,
+                                                    TA* __restrict__ Sb,
+                                                    const int* __restrict__ tab,
+                                                    const int* __restrict__ order, int nbv,
+                                                    int nbp, int ncp, int Mp, int v) {
+  __shared__ __attribute__((aligned(16))) T lds[Smem<T, KC>::elems];
+  const int tile = order[blockIdx.x];
+  const int ab = tile / nbp;
+  ppl_tile_4m<T, TA, KC, OCC>(Ls, Xb, Sb, tab, nbv, nbp, ncp, Mp, v, ab, tile - ab * nbp, lds);
+}
+
+// Persistent ladder over several instances: every workgroup takes the next
+// item of one shared queue (items ordered longest tile first) until the
+// queue is exhausted, so uneven instances share one launch without a tail.
+__global__ __launch_bounds__(WG, 1) void k_ppl_queue(const BatchInst* __restrict__ inst,
+                                                     int ninst, long total,
+                                                     unsigned* __restrict__ counter) {
+  __shared__ __attribute__((aligned(16))) double lds[Smem<double, 16>::elems];
+  __shared__ long item;
+  for (;;) {
+    __syncthreads();  // every wave is done with the previous item and its LDS
+    if (threadIdx.x == 0) item = (long)atomicAdd(counter, 1u);
+    __syncthreads();
+    const long t = item;
+    if (t >= total) break;
+    int i = 0;
+    while (i + 1 < ninst && t >= inst[i + 1].start) ++i;
+    const BatchInst& I = inst[i];
+    const long local = t - I.start;
+    const int tile = I.order[local];
+    const int ab = tile / I.nbp;
+    ppl_tile_4m<double, double, 16, 1>(I.Ls, I.Xb, I.Sb, I.tab, I.nbv, I.nbp, I.ncp, I.Mp, I.v,
+                                       ab, tile - ab * I.nbp, lds);
+  }
+}
+
 // 3M form of the integral build: with planes (re, im, re+im) of the staged
 // Cholesky blocks, T1 = sum ar br, T2 = sum ai bi, T3 = sum (ar+ai)(br+bi)
 // give re = T1 - T2 and im = T3 - T1 - T2: three real MFMA products per
@@ -267,7 +306,8 @@ template <typename T, typename TA, int KC>
 __global__ __launch_bounds__(WG, 1) void k_ppl_3m(const T* __restrict__ Ls,
                                                   const T* __restrict__ Xb,
                                                   TA* __restrict__ Sb,
-                                                  const int* __restrict__ tab, int nbv,
+                                                  const int* __restrict__ tab,
+                                                  const int* __restrict__ order, int nbv,
                                                   int nbp, int ncp, int Mp, int v) {
   typedef typename Acc<T>::t acc_t;
   typedef typename Vec16<T>::t vec_t;
@@ -276,7 +316,7 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_3m(const T* __restrict__ Ls,
   constexpr int ELEMS = 4 * CH > 2 * NS * NS ? 4 * CH : 2 * NS * NS;
   __shared__ __attribute__((aligned(16))) T lds[ELEMS];
 
-  const int tile = blockIdx.x;
+  const int tile = order[blockIdx.x];
   const int ab = tile / nbp, cd = tile - ab * nbp;
   const int pAB = tab[ab], pCD = tab[cd];
   const int A = pAB >> 16, B = pAB & 0xffff, C = pCD >> 16, D = pCD & 0xffff;
@@ -443,8 +483,24 @@ constexpr int KC32 = 32;
 
 }  // namespace
 
+// Launch variant of the 4M kernel: 1 = one workgroup per CU (chunk 16/32,
+// prefetch of the next rows), 2 = two workgroups per CU (chunk 8/16).  Set by
+// the tuner (lrcc_autotune) or the environment variable LRCC_OCC.
+static int g_occ[3] = {0, 0, 0};
+int ppl_variant_occ(lrcc_prec prec) {
+  int o = g_occ[prec];
+  if (o == 0) {
+    const char* e = getenv("LRCC_OCC");
+    o = (e && atoi(e) == 2) ? 2 : 1;
+  }
+  return o;
+}
+void ppl_set_variant_occ(lrcc_prec prec, int occ) { g_occ[prec] = occ; }
+
 int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul) {
   if (cmul == LRCC_CMUL_3M) return prec == LRCC_FP64 ? 8 : 16;
+  // the chunk of the occupancy-2 variant divides that of occupancy 1, so one
+  // staged layout (padded to the larger chunk) serves both
   return prec == LRCC_FP64 ? KC64 : KC32;
 }
 int ppl_planes(lrcc_prec, lrcc_cmul cmul) { return cmul == LRCC_CMUL_3M ? 3 : 2; }
@@ -459,7 +515,7 @@ size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g) {
 
 hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
                       const void* Ls, const void* Xb, void* Sb, const int* tab,
-                      hipStream_t st) {
+                      const int* order, hipStream_t st) {
   const long ntile = (long)g.nbp * g.nbp;
   if (ntile == 0 || g.Mp == 0) return hipSuccess;
   if (ntile > 0x7fffffffL) return hipErrorInvalidValue;
@@ -467,7 +523,8 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
   if (cmul == LRCC_CMUL_3M) {
 #define LRCC_L3(T, TA, KC)                                                                      \
   hipLaunchKernelGGL((k_ppl_3m<T, TA, KC>), grid, block, 0, st, static_cast<const T*>(Ls),     \
-                     static_cast<const T*>(Xb), static_cast<TA*>(Sb), tab, g.nbv, g.nbp, g.ncp, \
+                     static_cast<const T*>(Xb), static_cast<TA*>(Sb), tab, order, g.nbv, g.nbp, \
+                     g.ncp,                                                                     \
                      (int)g.Mp, g.v)
     if (prec == LRCC_FP64) LRCC_L3(double, double, 8);
     else if (prec == LRCC_FP32 && acc64) LRCC_L3(float, double, 16);
@@ -476,22 +533,33 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
 #undef LRCC_L3
     return hipGetLastError();
   }
+#define LRCC_L4(T, TA, KC, OCC)                                                             \
+  hipLaunchKernelGGL((k_ppl_4m<T, TA, KC, OCC>), grid, block, 0, st,                         \
+                     static_cast<const T*>(Ls), static_cast<const T*>(Xb), static_cast<TA*>(Sb), \
+                     tab, order, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v)
+  const int occ = ppl_variant_occ(prec);
   if (prec == LRCC_FP64) {
-    hipLaunchKernelGGL((k_ppl_4m<double, double, KC64>), grid, block, 0, st,
-                       static_cast<const double*>(Ls), static_cast<const double*>(Xb),
-                       static_cast<double*>(Sb), tab, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v);
+    if (occ == 2) LRCC_L4(double, double, 8, 2);
+    else LRCC_L4(double, double, KC64, 1);
   } else if (prec == LRCC_FP32) {
-    if (acc64)
-      hipLaunchKernelGGL((k_ppl_4m<float, double, KC32>), grid, block, 0, st,
-                         static_cast<const float*>(Ls), static_cast<const float*>(Xb),
-                         static_cast<double*>(Sb), tab, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v);
-    else
-      hipLaunchKernelGGL((k_ppl_4m<float, float, KC32>), grid, block, 0, st,
-                         static_cast<const float*>(Ls), static_cast<const float*>(Xb),
-                         static_cast<float*>(Sb), tab, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v);
+    if (acc64) {
+      if (occ == 2) LRCC_L4(float, double, 16, 2);
+      else LRCC_L4(float, double, KC32, 1);
+    } else {
+      if (occ == 2) LRCC_L4(float, float, 16, 2);
+      else LRCC_L4(float, float, KC32, 1);
+    }
   } else {
     return hipErrorNotSupported;
   }
+#undef LRCC_L4
+  return hipGetLastError();
+}
+
+hipError_t ppl_queue_launch(const BatchInst* inst, int ninst, long total, unsigned* counter,
+                            int nwg, hipStream_t st) {
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ppl_queue, dim3(nwg), dim3(WG), 0, st, inst, ninst, total, counter);
   return hipGetLastError();
 }
 

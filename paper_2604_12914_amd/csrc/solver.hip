@@ -17,8 +17,10 @@
 // residual r = -xi - (A - w) x uses the FP64 ladder; the correction solves
 // (A - w) d = r with the reduced-precision ladder by the same Jacobi + DIIS
 // to a loose relative tolerance; x += d.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <memory>
 #include <vector>
 
 #include "internal.hpp"
@@ -126,8 +128,9 @@ __global__ void k_start(Dims d, const double* __restrict__ eps, const double* __
 __global__ __launch_bounds__(RB) void k_resid(Dims d, const double* __restrict__ eps,
                                               const double* __restrict__ omega, const int* tab,
                                               const int* otab, const int* __restrict__ active,
-                                              const unsigned* __restrict__ valid, int slot,
-                                              int mdim, const double* __restrict__ b,
+                                              const unsigned* __restrict__ valid,
+                                              const int* __restrict__ itp, int mdim,
+                                              const double* __restrict__ b,
                                               const double* __restrict__ x,
                                               const double* __restrict__ s,
                                               double* __restrict__ xt, double* __restrict__ ev,
@@ -136,6 +139,7 @@ __global__ __launch_bounds__(RB) void k_resid(Dims d, const double* __restrict__
   const int r = blockIdx.y;
   if (!active[r]) return;
   const double w = omega[r];
+  const int slot = *itp % mdim;
   const unsigned vmask = valid[r] | (1u << slot);
   const size_t hs = (size_t)2 * d.plane;  // stride between ring slots
   double rr = 0, bb = 0;
@@ -190,7 +194,7 @@ __device__ inline double2 cdiv(double2 a, double2 b) {
 
 // Per RHS: reduce partials, test convergence, update the DIIS matrix and
 // solve for the extrapolation coefficients.  Bmat: [r][MAXD][MAXD] double2.
-__global__ void k_diis(int nchunk, int mdim, int slot, int it, int max_iter, double tol,
+__global__ void k_diis(int nchunk, int mdim, const int* __restrict__ itp, int max_iter, double tol,
                        const double2* __restrict__ part, int* __restrict__ active,
                        unsigned* __restrict__ valid, double2* __restrict__ Bmat,
                        double2* __restrict__ coef, double* __restrict__ relres) {
@@ -198,6 +202,7 @@ __global__ void k_diis(int nchunk, int mdim, int slot, int it, int max_iter, dou
   __shared__ double2 q[MAXD + 1];
   const int r = blockIdx.x;
   if (!active[r]) return;
+  const int it = *itp, slot = it % mdim;
   const int nq = mdim + 1;
   const unsigned vmask = valid[r] | (1u << slot);
   for (int k = 0; k < nq; ++k) {
@@ -446,6 +451,11 @@ __global__ void k_acc(Dims d, const int* __restrict__ active, const double* __re
   }
 }
 
+// Advance the device-resident iteration counter (one thread).
+__global__ void k_inc(int* itp) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *itp += 1;
+}
+
 // b = -a elementwise.
 __global__ void k_neg(long n, const double* __restrict__ a, double* __restrict__ b) {
   for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) b[i] = -a[i];
@@ -465,16 +475,24 @@ __global__ void k_to_f32(long n, const double* __restrict__ a, float* __restrict
 
 namespace {
 
+// Workspace slots of one solve: 0 xi, 1 x, 2 s, 3 ring X~, 4 ring e, 5 b,
+// 6 x2 (refined iterate), 7 rk, 8 small device state, 9 partials, 10 x32,
+// 11 sx (ladder of the refined iterate), 12 staged FP64 vectors, 13 block-pair
+// table, 14 tile order (the last three only for batched instances).
+constexpr int NBUF = 15;
+
 struct Solver {
-  lrcc_handle h;
+  lrcc_handle h = nullptr;
+  Buf* buf[NBUF] = {};
   Geom g;
   Dims d;
-  int n, ncomp, nomega, mdim, nchunk;
+  int n = 0, ncomp = 0, nomega = 0, mdim = 0, nchunk = 0;
+  const int* tab = nullptr;
   // device buffers
   double *xi = nullptr, *x = nullptr, *s = nullptr, *xt = nullptr, *ev = nullptr, *b = nullptr;
   double *omega = nullptr, *eps = nullptr, *x2 = nullptr, *rk = nullptr, *sx = nullptr;
   float* x32 = nullptr;
-  int *otab = nullptr, *active = nullptr;
+  int *otab = nullptr, *active = nullptr, *itp = nullptr;
   unsigned* valid = nullptr;
   double2 *Bm = nullptr, *coef = nullptr, *part = nullptr;
   double* relres = nullptr;
@@ -483,9 +501,99 @@ struct Solver {
   double* h_relres = nullptr;
   double2* h_part = nullptr;
   int n_sigma64 = 0, n_sigma_lp = 0, iters_max = 0;
-  const void* Lstaged64 = nullptr;
-  const void* Lstaged32 = nullptr;
+  std::vector<int> act;  // host view of the active flags
+  ~Solver() {
+    if (h_active) (void)hipHostFree(h_active);
+    if (h_relres) (void)hipHostFree(h_relres);
+    if (h_part) (void)hipHostFree(h_part);
+  }
 };
+
+dim3 grid_rhs(const Solver& S, int nr) { return dim3(S.nchunk, nr); }
+
+// Geometry, workspace, right-hand sides and zeroed iterates of one solve.
+// tab: the block-pair table for this nbv (device).  `ir`: reduced precision.
+lrcc_status setup(Solver& S, lrcc_handle h, int o, int v, int nchol, const double* eps,
+                  int ncomp, const void* mu, int nomega, const double* omegas, int mdim,
+                  bool ir, const int* tab, hipStream_t st) {
+  S.h = h;
+  S.n = nomega * ncomp;
+  S.ncomp = ncomp;
+  S.nomega = nomega;
+  S.mdim = mdim;
+  S.tab = tab;
+  S.g = make_geom(o, v, nchol, S.n, 1);
+  const Geom& g = S.g;
+  S.d = Dims{g.Mp, g.npo, g.xb_plane(), g.nbp, v, o, (long)g.nbp * g.npo * 64};
+  S.nchunk = (int)std::max<long>(1, std::min<long>(256, (S.d.per_rhs + 4 * RB - 1) / (4 * RB)));
+  const size_t vb = (size_t)2 * S.d.plane * 8;
+  size_t need[12] = {vb, vb, vb, vb * mdim, vb * mdim, vb, ir ? vb : 16, ir ? vb : 16, 0, 0,
+                     ir ? vb / 2 : 16,  // f32 planes, or 4 bf16 planes: same bytes
+                     ir ? vb : 16};
+  const size_t np_alpha = (size_t)nomega * ncomp * ncomp;
+  const size_t npart = std::max((size_t)S.n * (mdim + 1), np_alpha) * S.nchunk;
+  need[9] = npart * sizeof(double2);
+  // small state: omega[n], eps[o+v], otab[npo], active[n], valid[n], relres[n],
+  // B, coef, iteration counter
+  const size_t off_om = 0, off_eps = off_om + roundup(S.n * 8, 256),
+               off_ot = off_eps + roundup((o + v) * 8, 256),
+               off_act = off_ot + roundup(g.npo * 4, 256), off_val = off_act + roundup(S.n * 4, 256),
+               off_rel = off_val + roundup(S.n * 4, 256), off_B = off_rel + roundup(S.n * 8, 256),
+               off_c = off_B + roundup((long)S.n * MAXD * MAXD * 16, 256),
+               off_it = off_c + roundup((long)S.n * MAXD * 16, 256), end = off_it + 256;
+  need[8] = end;
+  for (int k = 0; k < 12; ++k) LRCC_HIP(h, S.buf[k]->ensure(need[k]));
+  S.xi = S.buf[0]->as<double>();
+  S.x = S.buf[1]->as<double>();
+  S.s = S.buf[2]->as<double>();
+  S.xt = S.buf[3]->as<double>();
+  S.ev = S.buf[4]->as<double>();
+  S.b = S.buf[5]->as<double>();
+  S.x2 = S.buf[6]->as<double>();
+  S.rk = S.buf[7]->as<double>();
+  char* sm = S.buf[8]->as<char>();
+  S.omega = reinterpret_cast<double*>(sm + off_om);
+  S.eps = reinterpret_cast<double*>(sm + off_eps);
+  S.otab = reinterpret_cast<int*>(sm + off_ot);
+  S.active = reinterpret_cast<int*>(sm + off_act);
+  S.valid = reinterpret_cast<unsigned*>(sm + off_val);
+  S.relres = reinterpret_cast<double*>(sm + off_rel);
+  S.Bm = reinterpret_cast<double2*>(sm + off_B);
+  S.coef = reinterpret_cast<double2*>(sm + off_c);
+  S.itp = reinterpret_cast<int*>(sm + off_it);
+  S.part = S.buf[9]->as<double2>();
+  S.x32 = S.buf[10]->as<float>();
+  S.sx = S.buf[11]->as<double>();
+
+  std::vector<double> om(S.n);
+  for (int w = 0; w < nomega; ++w)
+    for (int x = 0; x < ncomp; ++x) om[w * ncomp + x] = omegas[w];
+  std::vector<int> ot(g.npo);
+  for (int i = 0, k = 0; i < o; ++i)
+    for (int j = i + 1; j < o; ++j) ot[k++] = (i << 16) | j;
+  LRCC_HIP(h, hipHostMalloc((void**)&S.h_active, S.n * sizeof(int), hipHostMallocDefault));
+  LRCC_HIP(h, hipHostMalloc((void**)&S.h_relres, S.n * sizeof(double), hipHostMallocDefault));
+  LRCC_HIP(h, hipHostMalloc((void**)&S.h_part, std::max((size_t)S.n, np_alpha) * S.nchunk *
+                                                   sizeof(double2),
+                            hipHostMallocDefault));
+  LRCC_HIP(h, hipMemcpyAsync(S.omega, om.data(), S.n * 8, hipMemcpyHostToDevice, st));
+  LRCC_HIP(h, hipMemcpyAsync(S.eps, eps, (o + v) * 8, hipMemcpyDeviceToDevice, st));
+  LRCC_HIP(h, hipMemcpyAsync(S.otab, ot.data(), g.npo * 4, hipMemcpyHostToDevice, st));
+  LRCC_HIP(h, hipStreamSynchronize(st));  // host vectors go out of scope below
+
+  hipLaunchKernelGGL(k_xi, grid_rhs(S, S.n), dim3(RB), 0, st, S.d, ncomp,
+                     static_cast<const double2*>(mu), tab, S.otab, S.xi);
+  LRCC_HIP(h, hipGetLastError());
+  // zero the iterates and the DIIS ring once so dead slots and pad rows hold
+  // zeros (the ladder kernel reads whole block-pair rows)
+  LRCC_HIP(h, fill_zero(S.x, vb, st));
+  LRCC_HIP(h, fill_zero(S.xt, vb * mdim, st));
+  LRCC_HIP(h, fill_zero(S.ev, vb * mdim, st));
+  hipLaunchKernelGGL(k_neg, dim3((unsigned)std::min<long>((2 * S.d.plane + RB - 1) / RB, 8192)),
+                     dim3(RB), 0, st, 2 * S.d.plane, (const double*)S.xi, S.b);
+  LRCC_HIP(h, hipGetLastError());
+  return LRCC_OK;
+}
 
 lrcc_status stage_for(Solver& S, const void* L, lrcc_prec prec, lrcc_cmul cmul) {
   lrcc_handle h = S.h;
@@ -541,68 +649,99 @@ lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul 
   return LRCC_OK;
 }
 
-dim3 grid_rhs(const Solver& S, int nr) { return dim3(S.nchunk, nr); }
+// Start of a Jacobi + DIIS run: active flags, empty subspace, iteration 0,
+// x = b / (D - w).
+lrcc_status start_iteration(Solver& S, const double* b, double* x, const int* h_active_in,
+                            hipStream_t st) {
+  lrcc_handle h = S.h;
+  LRCC_HIP(h, hipMemcpyAsync(S.active, h_active_in, S.n * sizeof(int), hipMemcpyHostToDevice, st));
+  LRCC_HIP(h, fill_zero(S.valid, roundup((long)S.n * 4, 16), st));
+  LRCC_HIP(h, fill_zero(S.itp, 16, st));
+  hipLaunchKernelGGL(k_start, grid_rhs(S, S.n), dim3(RB), 0, st, S.d, S.eps, S.omega, S.tab,
+                     S.otab, S.active, b, x);
+  LRCC_HIP(h, hipGetLastError());
+  S.act.assign(h_active_in, h_active_in + S.n);
+  return LRCC_OK;
+}
+
+// The vector part of one iteration after the ladder: residual pass, DIIS,
+// extrapolation, counter.  All launches on `st` (capturable).
+lrcc_status iterate_vectors(Solver& S, const double* b, double* x, double tol, int max_iter,
+                            hipStream_t st) {
+  lrcc_handle h = S.h;
+  hipLaunchKernelGGL(k_resid, grid_rhs(S, S.n), dim3(RB), 0, st, S.d, S.eps, S.omega, S.tab,
+                     S.otab, S.active, S.valid, (const int*)S.itp, S.mdim, b, x, S.s, S.xt, S.ev,
+                     S.part);
+  LRCC_HIP(h, hipGetLastError());
+  hipLaunchKernelGGL(k_diis, dim3(S.n), dim3(64), 0, st, S.nchunk, S.mdim, (const int*)S.itp,
+                     max_iter, tol, S.part, S.active, S.valid, S.Bm, S.coef, S.relres);
+  LRCC_HIP(h, hipGetLastError());
+  hipLaunchKernelGGL(k_extrap, grid_rhs(S, S.n), dim3(RB), 0, st, S.d, S.mdim, S.active,
+                     S.valid, S.coef, S.xt, x);
+  LRCC_HIP(h, hipGetLastError());
+  hipLaunchKernelGGL(k_inc, dim3(1), dim3(64), 0, st, S.itp);
+  LRCC_HIP(h, hipGetLastError());
+  return LRCC_OK;
+}
+
+// After an iteration: copy flags and residuals to the host (async on st).
+lrcc_status fetch_flags(Solver& S, hipStream_t st) {
+  lrcc_handle h = S.h;
+  LRCC_HIP(h, hipMemcpyAsync(S.h_active, S.active, S.n * sizeof(int), hipMemcpyDeviceToHost, st));
+  LRCC_HIP(h, hipMemcpyAsync(S.h_relres, S.relres, S.n * sizeof(double), hipMemcpyDeviceToHost,
+                             st));
+  return LRCC_OK;
+}
+
+// Host bookkeeping after fetch_flags completed; returns the number of RHS
+// still active and updates *result.
+int absorb_flags(Solver& S, int it, double tol, lrcc_status* result) {
+  int nact = 0;
+  for (int r = 0; r < S.n; ++r) {
+    if (!S.act[r]) continue;
+    if (!std::isfinite(S.h_relres[r])) *result = LRCC_ERR_NONFINITE;
+    if (S.h_active[r]) {
+      ++nact;
+    } else {
+      S.act[r] = 0;
+      if (S.h_relres[r] >= tol && *result == LRCC_OK) *result = LRCC_ERR_NOT_CONVERGED;
+    }
+  }
+  S.iters_max = std::max(S.iters_max, it);
+  return nact;
+}
 
 // Jacobi + DIIS for (A - w) x = b on the RHS whose active flag is set on
 // entry.  x receives the solution.  Returns LRCC_ERR_NOT_CONVERGED if any
 // RHS stopped at max_iter, LRCC_ERR_NONFINITE on NaN/Inf.
 lrcc_status jacobi_diis(Solver& S, const double* b, double* x, lrcc_prec prec, lrcc_cmul cmul,
-                        double tol, int max_iter, int* h_active_in) {
+                        double tol, int max_iter, const int* h_active_in) {
   lrcc_handle h = S.h;
-  const int n = S.n;
-  LRCC_HIP(h, hipMemcpyAsync(S.active, h_active_in, n * sizeof(int), hipMemcpyHostToDevice,
-                             h->stream));
-  LRCC_HIP(h, fill_zero(S.valid, roundup((long)n * 4, 16), h->stream));
-  hipLaunchKernelGGL(k_start, grid_rhs(S, n), dim3(RB), 0, h->stream, S.d, S.eps, S.omega,
-                     h->tab.as<int>(), S.otab, S.active, b, x);
-  LRCC_HIP(h, hipGetLastError());
-  std::vector<int> act(h_active_in, h_active_in + n);
+  lrcc_status st = start_iteration(S, b, x, h_active_in, h->stream);
+  if (st != LRCC_OK) return st;
   lrcc_status result = LRCC_OK;
   for (int it = 0;; ++it) {
-    lrcc_status st = apply_sigma(S, x, prec, cmul);
+    st = apply_sigma(S, x, prec, cmul);
     if (st != LRCC_OK) return st;
-    const int slot = it % S.mdim;
-    hipLaunchKernelGGL(k_resid, grid_rhs(S, n), dim3(RB), 0, h->stream, S.d, S.eps, S.omega,
-                       h->tab.as<int>(), S.otab, S.active, S.valid, slot, S.mdim, b, x, S.s,
-                       S.xt, S.ev, S.part);
-    LRCC_HIP(h, hipGetLastError());
-    hipLaunchKernelGGL(k_diis, dim3(n), dim3(64), 0, h->stream, S.nchunk, S.mdim, slot, it,
-                       max_iter, tol, S.part, S.active, S.valid, S.Bm, S.coef, S.relres);
-    LRCC_HIP(h, hipGetLastError());
-    hipLaunchKernelGGL(k_extrap, grid_rhs(S, n), dim3(RB), 0, h->stream, S.d, S.mdim, S.active,
-                       S.valid, S.coef, S.xt, x);
-    LRCC_HIP(h, hipGetLastError());
-    LRCC_HIP(h, hipMemcpyAsync(S.h_active, S.active, n * sizeof(int), hipMemcpyDeviceToHost,
-                               h->stream));
-    LRCC_HIP(h, hipMemcpyAsync(S.h_relres, S.relres, n * sizeof(double), hipMemcpyDeviceToHost,
-                               h->stream));
+    st = iterate_vectors(S, b, x, tol, max_iter, h->stream);
+    if (st != LRCC_OK) return st;
+    st = fetch_flags(S, h->stream);
+    if (st != LRCC_OK) return st;
     LRCC_HIP(h, hipStreamSynchronize(h->stream));
-    int nact = 0;
-    for (int r = 0; r < n; ++r) {
-      if (!act[r]) continue;
-      if (!std::isfinite(S.h_relres[r])) result = LRCC_ERR_NONFINITE;
-      if (S.h_active[r]) {
-        ++nact;
-      } else {
-        act[r] = 0;
-        if (S.h_relres[r] >= tol && result == LRCC_OK) result = LRCC_ERR_NOT_CONVERGED;
-      }
-    }
-    S.iters_max = std::max(S.iters_max, it);
+    const int nact = absorb_flags(S, it, tol, &result);
     if (nact == 0 || result == LRCC_ERR_NONFINITE) break;
   }
   return result;
 }
 
-lrcc_status finish_alpha(Solver& S, const double* x, double* alpha) {
+lrcc_status finish_alpha(Solver& S, const double* x, double* alpha, hipStream_t st) {
   lrcc_handle h = S.h;
   const int np = S.nomega * S.ncomp * S.ncomp;
-  hipLaunchKernelGGL(k_alpha, dim3(S.nchunk, np), dim3(RB), 0, h->stream, S.d, S.ncomp, S.xi, x,
-                     S.part);
+  hipLaunchKernelGGL(k_alpha, dim3(S.nchunk, np), dim3(RB), 0, st, S.d, S.ncomp, S.xi, x, S.part);
   LRCC_HIP(h, hipGetLastError());
   LRCC_HIP(h, hipMemcpyAsync(S.h_part, S.part, (size_t)np * S.nchunk * sizeof(double2),
-                             hipMemcpyDeviceToHost, h->stream));
-  LRCC_HIP(h, hipStreamSynchronize(h->stream));
+                             hipMemcpyDeviceToHost, st));
+  LRCC_HIP(h, hipStreamSynchronize(st));
   for (int p = 0; p < np; ++p) {
     double re = 0, im = 0;
     for (int c = 0; c < S.nchunk; ++c) {
@@ -615,135 +754,70 @@ lrcc_status finish_alpha(Solver& S, const double* x, double* alpha) {
   return LRCC_OK;
 }
 
+struct Opts {
+  double tol, inner_tol;
+  int max_iter, mdim, max_outer;
+};
+
+lrcc_status read_opts(lrcc_handle h, const lrcc_solve_opts* in, lrcc_solve_opts* op, Opts* o) {
+  *op = lrcc_solve_opts{};
+  if (in) *op = *in;
+  o->tol = op->tol > 0 ? op->tol : 1e-8;
+  o->max_iter = op->max_iter > 0 ? op->max_iter : 100;
+  o->mdim = op->diis_dim > 0 ? op->diis_dim : 8;
+  o->inner_tol = op->inner_tol > 0 ? op->inner_tol : 1e-5;
+  o->max_outer = op->max_outer > 0 ? op->max_outer : 6;
+  if (o->mdim > MAXD) return fail(h, LRCC_ERR_ARG, "diis_dim exceeds 12");
+  if (op->prec != LRCC_FP64 && op->prec != LRCC_FP32 && op->prec != LRCC_BF16X3)
+    return fail(h, LRCC_ERR_ARG, "unknown precision");
+  if (op->cmul != LRCC_CMUL_4M && op->cmul != LRCC_CMUL_3M)
+    return fail(h, LRCC_ERR_ARG, "unknown complex-multiply form");
+  if (op->deterministic) return fail(h, LRCC_ERR_UNSUPPORTED, "deterministic mode is reserved");
+  return LRCC_OK;
+}
+
 }  // namespace
 
 lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps, const void* L,
                        int ncomp, const void* mu, int nomega, const double* omegas,
                        const lrcc_solve_opts* opts_in, double* alpha, lrcc_solve_info* info) {
   auto t0 = std::chrono::steady_clock::now();
-  lrcc_solve_opts op{};
-  if (opts_in) op = *opts_in;
-  const double tol = op.tol > 0 ? op.tol : 1e-8;
-  const int max_iter = op.max_iter > 0 ? op.max_iter : 100;
-  const int mdim = op.diis_dim > 0 ? op.diis_dim : 8;
-  const double inner_tol = op.inner_tol > 0 ? op.inner_tol : 1e-5;
-  const int max_outer = op.max_outer > 0 ? op.max_outer : 6;
-  if (mdim > MAXD) return fail(h, LRCC_ERR_ARG, "diis_dim exceeds 12");
-  if (op.prec != LRCC_FP64 && op.prec != LRCC_FP32 && op.prec != LRCC_BF16X3)
-    return fail(h, LRCC_ERR_ARG, "unknown precision");
-  if (op.cmul != LRCC_CMUL_4M && op.cmul != LRCC_CMUL_3M)
-    return fail(h, LRCC_ERR_ARG, "unknown complex-multiply form");
-  if (op.deterministic) return fail(h, LRCC_ERR_UNSUPPORTED, "deterministic mode is reserved");
-
-  Solver S;
-  S.h = h;
-  S.n = nomega * ncomp;
-  S.ncomp = ncomp;
-  S.nomega = nomega;
-  S.mdim = mdim;
-  S.g = make_geom(o, v, nchol, S.n, 1);
-  const Geom& g = S.g;
-  if (g.M == 0 || g.npv == 0) {
-    for (int p = 0; p < 2 * nomega * ncomp * ncomp; ++p) alpha[p] = 0;
-    if (info) *info = lrcc_solve_info{0, 0, 0, 0.0, 0.0};
-    return LRCC_OK;
-  }
-  lrcc_status st = ensure_tab(h, g.nbv);
+  lrcc_solve_opts op;
+  Opts O;
+  lrcc_status st = read_opts(h, opts_in, &op, &O);
   if (st != LRCC_OK) return st;
-  S.d = Dims{g.Mp, g.npo, g.xb_plane(), g.nbp, v, o, (long)g.nbp * g.npo * 64};
-  S.nchunk = (int)std::max<long>(1, std::min<long>(256, (S.d.per_rhs + 4 * RB - 1) / (4 * RB)));
-
-  // workspace: 0 xi, 1 x, 2 s, 3 ring X~, 4 ring e, 5 b, 6 x2 (outer x), 7 rk,
-  // 8 small device state, 9 partials, 10 x32, 11 sx (ladder of the refined iterate)
-  const size_t vb = (size_t)2 * S.d.plane * 8;
   const bool ir = op.prec != LRCC_FP64;
-  size_t need[12] = {vb, vb, vb, vb * mdim, vb * mdim, vb, ir ? vb : 16, ir ? vb : 16, 0, 0,
-                     ir ? vb / 2 : 16,  // f32 planes, or 4 bf16 planes: same bytes
-                     ir ? vb : 16};
-  const size_t np_alpha = (size_t)nomega * ncomp * ncomp;
-  const size_t npart = std::max((size_t)S.n * (mdim + 1), np_alpha) * S.nchunk;
-  need[9] = npart * sizeof(double2);
-  // small state: omega[n], eps[o+v], otab[npo], active[n], valid[n], relres[n], B, coef
-  const size_t off_om = 0, off_eps = off_om + roundup(S.n * 8, 256),
-               off_ot = off_eps + roundup((o + v) * 8, 256),
-               off_act = off_ot + roundup(g.npo * 4, 256), off_val = off_act + roundup(S.n * 4, 256),
-               off_rel = off_val + roundup(S.n * 4, 256), off_B = off_rel + roundup(S.n * 8, 256),
-               off_c = off_B + roundup((long)S.n * MAXD * MAXD * 16, 256),
-               end = off_c + roundup((long)S.n * MAXD * 16, 256);
-  need[8] = end;
-  for (int k = 0; k < 12; ++k) LRCC_HIP(h, h->sv[k].ensure(need[k]));
-  S.xi = h->sv[0].as<double>();
-  S.x = h->sv[1].as<double>();
-  S.s = h->sv[2].as<double>();
-  S.xt = h->sv[3].as<double>();
-  S.ev = h->sv[4].as<double>();
-  S.b = h->sv[5].as<double>();
-  S.x2 = h->sv[6].as<double>();
-  S.rk = h->sv[7].as<double>();
-  char* sm = h->sv[8].as<char>();
-  S.omega = reinterpret_cast<double*>(sm + off_om);
-  S.eps = reinterpret_cast<double*>(sm + off_eps);
-  S.otab = reinterpret_cast<int*>(sm + off_ot);
-  S.active = reinterpret_cast<int*>(sm + off_act);
-  S.valid = reinterpret_cast<unsigned*>(sm + off_val);
-  S.relres = reinterpret_cast<double*>(sm + off_rel);
-  S.Bm = reinterpret_cast<double2*>(sm + off_B);
-  S.coef = reinterpret_cast<double2*>(sm + off_c);
-  S.part = h->sv[9].as<double2>();
-  S.x32 = h->sv[10].as<float>();
-  S.sx = h->sv[11].as<double>();
-
-  // host-side small state (pinned)
-  std::vector<double> om(S.n);
-  for (int w = 0; w < nomega; ++w)
-    for (int x = 0; x < ncomp; ++x) om[w * ncomp + x] = omegas[w];
-  std::vector<int> ot(g.npo);
-  for (int i = 0, k = 0; i < o; ++i)
-    for (int j = i + 1; j < o; ++j) ot[k++] = (i << 16) | j;
-  LRCC_HIP(h, hipHostMalloc((void**)&S.h_active, S.n * sizeof(int), hipHostMallocDefault));
-  struct Pinned {
-    Solver* s;
-    ~Pinned() {
-      if (s->h_active) (void)hipHostFree(s->h_active);
-      if (s->h_relres) (void)hipHostFree(s->h_relres);
-      if (s->h_part) (void)hipHostFree(s->h_part);
+  {
+    const Geom g = make_geom(o, v, nchol, nomega * ncomp, 1);
+    if (g.M == 0 || g.npv == 0) {
+      for (int p = 0; p < 2 * nomega * ncomp * ncomp; ++p) alpha[p] = 0;
+      if (info) *info = lrcc_solve_info{0, 0, 0, 0.0, 0.0};
+      return LRCC_OK;
     }
-  } pinned{&S};
-  LRCC_HIP(h, hipHostMalloc((void**)&S.h_relres, S.n * sizeof(double), hipHostMallocDefault));
-  LRCC_HIP(h, hipHostMalloc((void**)&S.h_part, np_alpha * S.nchunk * sizeof(double2),
-                            hipHostMallocDefault));
-  LRCC_HIP(h, hipMemcpyAsync(S.omega, om.data(), S.n * 8, hipMemcpyHostToDevice, h->stream));
-  LRCC_HIP(h, hipMemcpyAsync(S.eps, eps, (o + v) * 8, hipMemcpyDeviceToDevice, h->stream));
-  LRCC_HIP(h, hipMemcpyAsync(S.otab, ot.data(), g.npo * 4, hipMemcpyHostToDevice, h->stream));
-  LRCC_HIP(h, hipStreamSynchronize(h->stream));  // host vectors go out of scope below
-
-  // right-hand sides and staged Cholesky vectors
-  hipLaunchKernelGGL(k_xi, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, ncomp,
-                     static_cast<const double2*>(mu), h->tab.as<int>(), S.otab, S.xi);
-  LRCC_HIP(h, hipGetLastError());
-  // zero the iterates and the DIIS ring once so dead slots and pad rows hold
-  // zeros (the ladder kernel reads whole block-pair rows)
-  LRCC_HIP(h, fill_zero(S.x, vb, h->stream));
-  LRCC_HIP(h, fill_zero(S.xt, vb * mdim, h->stream));
-  LRCC_HIP(h, fill_zero(S.ev, vb * mdim, h->stream));
-  hipLaunchKernelGGL(k_neg, dim3((unsigned)std::min<long>((2 * S.d.plane + RB - 1) / RB, 8192)),
-                     dim3(RB), 0, h->stream, 2 * S.d.plane, (const double*)S.xi, S.b);
-  LRCC_HIP(h, hipGetLastError());
-  std::vector<int> all(S.n, 1);
+    st = ensure_tab(h, g.nbv);
+    if (st != LRCC_OK) return st;
+  }
+  Solver S;
+  for (int k = 0; k < 12; ++k) S.buf[k] = &h->sv[k];
+  st = setup(S, h, o, v, nchol, eps, ncomp, mu, nomega, omegas, O.mdim, ir, h->tab.as<int>(),
+             h->stream);
+  if (st != LRCC_OK) return st;
   st = stage_for(S, L, LRCC_FP64, LRCC_CMUL_4M);
   if (st != LRCC_OK) return st;
   if (ir) {
     st = stage_for(S, L, op.prec, op.cmul);
     if (st != LRCC_OK) return st;
   }
+  const size_t vb = (size_t)2 * S.d.plane * 8;
+  std::vector<int> all(S.n, 1);
 
   lrcc_status result = LRCC_OK;
   double final_rel = 0;
   if (!ir) {
-    result = jacobi_diis(S, S.b, S.x, LRCC_FP64, LRCC_CMUL_4M, tol, max_iter, all.data());
+    result = jacobi_diis(S, S.b, S.x, LRCC_FP64, LRCC_CMUL_4M, O.tol, O.max_iter, all.data());
     for (int r = 0; r < S.n; ++r) final_rel = std::max(final_rel, S.h_relres[r]);
     if (result == LRCC_ERR_NONFINITE) return fail(h, result, "non-finite residual");
-    st = finish_alpha(S, S.x, alpha);
+    st = finish_alpha(S, S.x, alpha, h->stream);
     if (st != LRCC_OK) return st;
   } else {
     // iterative refinement: x2 = 0, rk = b
@@ -752,8 +826,8 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
     std::vector<int> act(S.n, 1);
     std::vector<double> rel(S.n, 1.0);
     result = LRCC_ERR_NOT_CONVERGED;
-    for (int outer = 0; outer < max_outer; ++outer) {
-      lrcc_status is = jacobi_diis(S, S.rk, S.x, op.prec, op.cmul, inner_tol, max_iter,
+    for (int outer = 0; outer < O.max_outer; ++outer) {
+      lrcc_status is = jacobi_diis(S, S.rk, S.x, op.prec, op.cmul, O.inner_tol, O.max_iter,
                                    act.data());
       if (is == LRCC_ERR_NONFINITE) return fail(h, is, "non-finite residual");
       // x2 += d; sx = ladder(x2): FP64 ladder of the whole iterate in the
@@ -776,7 +850,7 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
         LRCC_HIP(h, hipGetLastError());
       }
       hipLaunchKernelGGL(k_outer, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.eps, S.omega,
-                         h->tab.as<int>(), S.otab, S.active, S.b, S.x2, S.sx, S.rk, S.part);
+                         S.tab, S.otab, S.active, S.b, S.x2, S.sx, S.rk, S.part);
       LRCC_HIP(h, hipGetLastError());
       LRCC_HIP(h, hipMemcpyAsync(S.h_part, S.part, (size_t)S.n * S.nchunk * sizeof(double2),
                                  hipMemcpyDeviceToHost, h->stream));
@@ -791,7 +865,7 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
         }
         rel[r] = std::sqrt(rr / bb);
         if (!std::isfinite(rel[r])) return fail(h, LRCC_ERR_NONFINITE, "non-finite residual");
-        if (rel[r] < tol) act[r] = 0;
+        if (rel[r] < O.tol) act[r] = 0;
         else ++nact;
       }
       if (nact == 0) {
@@ -800,7 +874,7 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
       }
     }
     for (int r = 0; r < S.n; ++r) final_rel = std::max(final_rel, rel[r]);
-    st = finish_alpha(S, S.x2, alpha);
+    st = finish_alpha(S, S.x2, alpha, h->stream);
     if (st != LRCC_OK) return st;
   }
   if (info) {
@@ -811,6 +885,190 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
     info->seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
+  if (result == LRCC_ERR_NOT_CONVERGED) return fail(h, result, "tolerance not reached");
+  return result;
+}
+
+// ---------------------------------------------------------------------------
+// Batched solve: every instance keeps its own state; per iteration one
+// persistent ladder launch serves all active instances from one work queue,
+// and the whole iteration (queue reset, accumulator zeroing, ladder, and each
+// instance's residual / DIIS / extrapolation / counter kernels) is captured
+// once into a hip graph and replayed until the active set changes.
+
+lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* inst,
+                               const lrcc_solve_opts* opts_in, lrcc_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  lrcc_solve_opts op;
+  Opts O;
+  lrcc_status st = read_opts(h, opts_in, &op, &O);
+  if (st != LRCC_OK) return st;
+  if (op.prec != LRCC_FP64 || op.cmul != LRCC_CMUL_4M)
+    return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve runs the FP64 4M ladder");
+  constexpr int KC = 16;  // chunk of the persistent FP64 ladder
+  std::vector<std::unique_ptr<Solver>> S(ninst);
+  std::vector<std::unique_ptr<Buf[]>> own(ninst);
+  std::vector<int> live;  // instances with work
+  struct Free {
+    std::vector<std::unique_ptr<Buf[]>>* o;
+    ~Free() {
+      for (auto& b : *o)
+        if (b)
+          for (int k = 0; k < NBUF; ++k) b[k].release();
+    }
+  } freer{&own};
+  hipStream_t cs = nullptr;
+  LRCC_HIP(h, hipStreamSynchronize(h->stream));
+  LRCC_HIP(h, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  struct StreamFree {
+    hipStream_t s;
+    ~StreamFree() {
+      if (s) (void)hipStreamDestroy(s);
+    }
+  } sfree{cs};
+  const int nx = std::max(1, h->ncu / 32);
+  for (int i = 0; i < ninst; ++i) {
+    const lrcc_instance& I = inst[i];
+    S[i].reset(new Solver());
+    own[i].reset(new Buf[NBUF]);
+    Solver& Si = *S[i];
+    for (int k = 0; k < NBUF; ++k) Si.buf[k] = &own[i][k];
+    const Geom g0 = make_geom(I.o, I.v, I.nchol, I.nomega * I.ncomp, 1);
+    if (g0.M == 0 || g0.npv == 0) {
+      for (int p = 0; p < 2 * I.nomega * I.ncomp * I.ncomp; ++p) I.alpha[p] = 0;
+      continue;
+    }
+    // block-pair table and tile order of this instance
+    std::vector<int> tab, ord;
+    block_pair_table(g0.nbv, &tab);
+    supertile_order(g0, 0, g0.nbp, 4, 1, &ord);
+    LRCC_HIP(h, own[i][13].ensure(tab.size() * 4));
+    LRCC_HIP(h, own[i][14].ensure(ord.size() * 4));
+    LRCC_HIP(h, hipMemcpyAsync(own[i][13].p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, cs));
+    LRCC_HIP(h, hipMemcpyAsync(own[i][14].p, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, cs));
+    LRCC_HIP(h, hipStreamSynchronize(cs));
+    st = setup(Si, h, I.o, I.v, I.nchol, I.eps, I.ncomp, I.mu, I.nomega, I.omegas, O.mdim, false,
+               own[i][13].as<int>(), cs);
+    if (st != LRCC_OK) return st;
+    Geom gs = Si.g;
+    gs.ncp = (int)roundup(gs.nchol, KC);
+    LRCC_HIP(h, own[i][12].ensure(ppl_ls_bytes(LRCC_FP64, LRCC_CMUL_4M, gs)));
+    if (gs.nchol > 0)
+      LRCC_HIP(h, stage_L<double>(I.L, LRCC_C128, gs, 2, false, own[i][12].as<double>(), cs));
+    std::vector<int> one(Si.n, 1);
+    st = start_iteration(Si, Si.b, Si.x, one.data(), cs);
+    if (st != LRCC_OK) return st;
+    LRCC_HIP(h, hipStreamSynchronize(cs));  // `one` goes out of scope
+    live.push_back(i);
+  }
+  (void)nx;
+  // queue descriptors, longest tile first (tile cost ~ 2 ncp + Mp)
+  Buf desc, counter;
+  struct DescFree {
+    Buf* a;
+    Buf* b;
+    ~DescFree() {
+      a->release();
+      b->release();
+    }
+  } dfree{&desc, &counter};
+  LRCC_HIP(h, desc.ensure(sizeof(BatchInst) * std::max(1, ninst)));
+  LRCC_HIP(h, counter.ensure(16));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  struct GraphFree {
+    hipGraph_t* g;
+    hipGraphExec_t* e;
+    ~GraphFree() {
+      if (*e) (void)hipGraphExecDestroy(*e);
+      if (*g) (void)hipGraphDestroy(*g);
+    }
+  } gfree{&graph, &exec};
+  std::vector<int> active_set;  // instances in the captured graph
+  lrcc_status result = LRCC_OK;
+  int n_launch = 0;
+  for (int it = 0;; ++it) {
+    std::vector<int> now;
+    for (int i : live) {
+      bool any = false;
+      for (int a : S[i]->act) any = any || a;
+      if (any) now.push_back(i);
+    }
+    if (now.empty()) break;
+    if (now != active_set) {
+      // (re)build the queue descriptors and capture one iteration
+      std::sort(now.begin(), now.end(), [&](int a, int b) {
+        const Solver &A = *S[a], &B = *S[b];
+        return 2 * roundup(A.g.nchol, KC) + A.g.Mp > 2 * roundup(B.g.nchol, KC) + B.g.Mp;
+      });
+      std::vector<BatchInst> d(now.size());
+      long total = 0;
+      for (size_t k = 0; k < now.size(); ++k) {
+        const Solver& Si = *S[now[k]];
+        d[k] = BatchInst{own[now[k]][12].as<double>(), Si.x, Si.s, Si.tab,
+                         own[now[k]][14].as<int>(), Si.g.nbv, Si.g.nbp,
+                         (int)roundup(Si.g.nchol, KC), (int)Si.g.Mp, Si.g.v, total};
+        total += Si.g.nchol > 0 ? (long)Si.g.nbp * Si.g.nbp : 0;
+      }
+      LRCC_HIP(h, hipMemcpyAsync(desc.p, d.data(), d.size() * sizeof(BatchInst),
+                                 hipMemcpyHostToDevice, cs));
+      LRCC_HIP(h, hipStreamSynchronize(cs));
+      if (exec) {
+        LRCC_HIP(h, hipGraphExecDestroy(exec));
+        exec = nullptr;
+      }
+      if (graph) {
+        LRCC_HIP(h, hipGraphDestroy(graph));
+        graph = nullptr;
+      }
+      LRCC_HIP(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      lrcc_status cst = LRCC_OK;
+      hipError_t ce = fill_zero(counter.p, 16, cs);
+      for (int i : now)
+        if (ce == hipSuccess) ce = fill_zero(S[i]->s, (size_t)2 * S[i]->d.plane * 8, cs);
+      if (ce == hipSuccess)
+        ce = ppl_queue_launch(desc.as<BatchInst>(), (int)now.size(), total,
+                              counter.as<unsigned>(), h->ncu, cs);
+      for (int i : now)
+        if (ce == hipSuccess && cst == LRCC_OK)
+          cst = iterate_vectors(*S[i], S[i]->b, S[i]->x, O.tol, O.max_iter, cs);
+      hipError_t ee = hipStreamEndCapture(cs, &graph);
+      if (ce != hipSuccess) return hip_fail(h, ce, "batched iteration capture");
+      if (cst != LRCC_OK) return cst;
+      LRCC_HIP(h, ee);
+      LRCC_HIP(h, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      active_set = now;
+    }
+    LRCC_HIP(h, hipGraphLaunch(exec, cs));
+    ++n_launch;
+    for (int i : now) {
+      st = fetch_flags(*S[i], cs);
+      if (st != LRCC_OK) return st;
+    }
+    LRCC_HIP(h, hipStreamSynchronize(cs));
+    for (int i : now) {
+      S[i]->n_sigma64 += 1;
+      absorb_flags(*S[i], it, O.tol, &result);
+    }
+    if (result == LRCC_ERR_NONFINITE) return fail(h, result, "non-finite residual");
+  }
+  double final_rel = 0;
+  int iters_max = 0, nsig = 0;
+  for (int i : live) {
+    st = finish_alpha(*S[i], S[i]->x, inst[i].alpha, cs);
+    if (st != LRCC_OK) return st;
+    for (int r = 0; r < S[i]->n; ++r) final_rel = std::max(final_rel, S[i]->h_relres[r]);
+    iters_max = std::max(iters_max, S[i]->iters_max);
+    nsig = std::max(nsig, S[i]->n_sigma64);
+  }
+  if (info) {
+    info->iters_max = iters_max;
+    info->n_sigma_fp64 = n_launch;
+    info->n_sigma_lowp = 0;
+    info->final_relres = final_rel;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  (void)nsig;
   if (result == LRCC_ERR_NOT_CONVERGED) return fail(h, result, "tolerance not reached");
   return result;
 }

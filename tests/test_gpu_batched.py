@@ -1,0 +1,58 @@
+"""Batched solve (one persistent ladder launch per iteration over every
+instance, graph-captured) against per-instance eager solves and the oracle."""
+import numpy as np
+import pytest
+
+import lrcc_synth as S
+from oracle import response
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+OMEGAS = [0.0, 0.0428, 0.0656, 0.0856]
+
+
+@pytest.fixture(scope="module")
+def lrcc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_12914_amd as m
+    return m
+
+
+def dev_inst(inst, omegas):
+    return {"eps": torch.from_numpy(inst.eps).cuda(), "L": torch.from_numpy(inst.L).cuda(),
+            "mu": torch.from_numpy(inst.mu).cuda(), "omegas": omegas}
+
+
+def test_uneven_batch_matches_single_solves_and_oracle(lrcc):
+    # uneven instances (v = 10 o, Nchol = 4 v as in the batched workload, scaled
+    # down), including one whose frequency list differs
+    shapes = [(2, 20, 80, 0), (3, 30, 120, 1), (4, 40, 160, 2), (5, 44, 100, 3)]
+    insts, devs = [], []
+    for (o, v, nchol, seed) in shapes:
+        inst = S.make_instance(o, v, nchol, ncomp=3, seed=seed, gamma=S.solve_gamma(v))
+        om = OMEGAS if seed != 1 else OMEGAS[:2]
+        insts.append((inst, om))
+        devs.append(dev_inst(inst, om))
+    alphas, info = lrcc.solve_batched(devs, tol=1e-8)
+    assert info["status"] == "LRCC_OK"
+    for (inst, om), a, d in zip(insts, alphas, devs):
+        single, sinfo = lrcc.solve(d["eps"], d["L"], d["mu"], om, tol=1e-8)
+        # the same arithmetic in the same order per instance
+        assert np.abs(a - single).max() <= 1e-12 * np.abs(single).max()
+        exact = response.solve_dense(inst.L, inst.eps, inst.mu, om, inst.o, inst.v)["alpha"]
+        assert np.abs(a - exact).max() < 1e-7 * np.abs(exact).max()
+    # the graph was replayed once per iteration
+    assert info["n_sigma_fp64"] >= info["iters_max"] + 1
+
+
+def test_batch_with_empty_and_single_instance(lrcc):
+    inst = S.make_instance(3, 16, 32, ncomp=1, seed=5, gamma=S.solve_gamma(16))
+    empty = S.make_instance(1, 16, 32, ncomp=1, seed=6)      # no occupied pairs
+    alphas, info = lrcc.solve_batched([dev_inst(inst, [0.0]), dev_inst(empty, [0.0])])
+    exact = response.solve_dense(inst.L, inst.eps, inst.mu, [0.0], 3, 16)["alpha"]
+    assert np.abs(alphas[0] - exact).max() < 1e-7 * np.abs(exact).max()
+    assert np.all(alphas[1] == 0)
+    with pytest.raises(lrcc.LrccError):
+        lrcc.solve_batched([dev_inst(inst, [0.0])], prec="fp32")
