@@ -167,6 +167,27 @@ lrcc_status lrcc_solve_batched(lrcc_handle h, int ninst, const lrcc_instance* in
 lrcc_status lrcc_set_timing(lrcc_handle h, int enable);
 lrcc_status lrcc_get_timing(lrcc_handle h, double* ms, long* launches);
 
+/* Result of lrcc_autotune. */
+typedef struct {
+  int supertile;   /* width, in blocks of 8 virtual indices, of the super-tiles
+                      that order the tile pairs (see below)                    */
+  int occupancy;   /* workgroups per CU of the fused 4M kernel (1 or 2)        */
+  double ms;       /* ladder kernel time of the chosen variant                 */
+  int candidates;  /* variants timed (0 when read from the cache)              */
+} lrcc_tune_result;
+
+/* Tile-shape autotuner.  Times the candidate launch variants of the ladder
+ * for this shape, precision and complex form on synthetic inputs: the width
+ * s in {2, 4, 8} of the super-tiles (tile pairs whose four Cholesky blocks
+ * come from s x s block sets are run together on one XCD) and, where the
+ * kernel fits, one or two workgroups per CU.  The fastest is kept in the
+ * handle for later calls.  cache_path (host, nullable): a text file of
+ * earlier results keyed by (arch, CU count, o, v, nchol, nrhs, prec, cmul);
+ * a hit skips the timing, a miss appends the new result.  Tuning restarts
+ * the totals of lrcc_get_timing. */
+lrcc_status lrcc_autotune(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc_prec prec,
+                          lrcc_cmul cmul, const char* cache_path, lrcc_tune_result* out);
+
 /* Host-only argument check of lrcc_ppl_sigma: runs the same validation and
  * launches nothing (usable without a GPU; h may be NULL). */
 lrcc_status lrcc_check_sigma_args(int o, int v, int nchol, int nrhs,

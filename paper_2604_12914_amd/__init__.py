@@ -57,6 +57,14 @@ class SolveInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("supertile", ctypes.c_int), ("occupancy", ctypes.c_int),
+                ("ms", ctypes.c_double), ("candidates", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Instance(ctypes.Structure):
     _fields_ = [("o", ctypes.c_int), ("v", ctypes.c_int), ("nchol", ctypes.c_int),
                 ("eps", ctypes.c_void_p), ("L", ctypes.c_void_p), ("ncomp", ctypes.c_int),
@@ -97,6 +105,7 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)],
             "lrcc_check_sigma_args": [i, i, i, i, vp, vp, vp, i, i, i],
             "lrcc_set_timing": [vp, i],
+            "lrcc_autotune": [vp, i, i, i, i, i, i, ctypes.c_char_p, ctypes.POINTER(TuneResult)],
             "lrcc_get_timing": [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_long)],
         }
         for name, args in sig.items():
@@ -199,6 +208,17 @@ def ppl_sigma_adjoint(L, X, G, o=None, want_dX=True, want_dL=True, prec="fp64", 
                                         _ptr(dX), _ptr(dL), _dtype_code(X), PREC[prec],
                                         CMUL[cmul]), h)
     return dX, dL
+
+
+def autotune(o, v, nchol, nrhs, prec="fp64", cmul="4m", cache_path=None, device=0):
+    """Time the ladder's launch variants for this shape and keep the fastest
+    in the device's handle; returns the choice as a dict."""
+    h = handle(device)
+    res = TuneResult()
+    cp = cache_path.encode() if cache_path else None
+    _check(lib().lrcc_autotune(h, o, v, nchol, nrhs, PREC[prec], CMUL[cmul], cp,
+                               ctypes.byref(res)), h)
+    return res.as_dict()
 
 
 def set_timing(enable: bool, device: int = 0):

@@ -177,7 +177,8 @@ lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, c
   lrcc_status ost;
   const int* ord = tile_order(h, g, 0, g.nbp, &ost);
   if (ost != LRCC_OK) return ost;
-  LRCC_HIP(h, ppl_launch(prec, cmul, acc64, g, Ls, Xb, Sb, h->tab.as<int>(), ord, h->stream));
+  LRCC_HIP(h, ppl_launch(prec, cmul, acc64, g, Ls, Xb, Sb, h->tab.as<int>(), ord, h->occ[prec],
+                         h->stream));
   if (h->timing) {
     LRCC_HIP(h, hipEventRecord(e1, h->stream));
     ++h->tev_used;
@@ -363,6 +364,19 @@ lrcc_status lrcc_set_stream(lrcc_handle h, void* stream) {
   if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
   h->stream = static_cast<hipStream_t>(stream);
   return LRCC_OK;
+}
+
+lrcc_status lrcc_autotune(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc_prec prec,
+                          lrcc_cmul cmul, const char* cache_path, lrcc_tune_result* out) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  lrcc_status st = check_sigma(h, o, v, nchol, nrhs, (const void*)16, (const void*)16,
+                               (const void*)(1L << 40), LRCC_C128, prec, cmul, "sigma");
+  if (st != LRCC_OK) return st;
+  if (prec == LRCC_BF16X3 && cmul == LRCC_CMUL_3M)
+    return fail(h, LRCC_ERR_UNSUPPORTED, "bf16x3 uses the 4M complex form only");
+  DeviceGuard dg(h->device);
+  h->err.clear();
+  return autotune_impl(h, o, v, nchol, nrhs, prec, cmul, cache_path, out);
 }
 
 lrcc_status lrcc_set_timing(lrcc_handle h, int enable) {

@@ -69,6 +69,7 @@ struct lrcc_handle_s {
   lrcc::Buf order;        // tile order (XCD-aware super-tiles), see tile_order()
   long order_key[5] = {-1, -1, -1, -1, -1};
   int order_s = 0;        // super-tile width in virtual blocks (0 = default)
+  int occ[3] = {0, 0, 0}; // workgroups per CU of the 4M kernel per precision (0 = default)
   lrcc::Buf vws;          // bf16x3: one panel of antisymmetrised integral tiles
   size_t panel_cap = 0;   // bytes allowed for vws (0 = not yet chosen)
   int tab_nbv = -1;
@@ -115,7 +116,7 @@ hipError_t fill_zero(void* p, size_t bytes, hipStream_t st);
 // Sb must be zeroed by the caller.
 hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
                       const void* Ls, const void* Xb, void* Sb, const int* tab,
-                      const int* order, hipStream_t st);
+                      const int* order, int occ, hipStream_t st);
 // One instance of the persistent FP64 ladder (k_ppl_queue): its staged
 // vectors, block-layout doubles and accumulator, geometry, tile order and
 // the first queue item that belongs to it.
@@ -131,8 +132,7 @@ struct BatchInst {
 hipError_t ppl_queue_launch(const BatchInst* inst, int ninst, long total, unsigned* counter,
                             int nwg, hipStream_t st);
 int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul);   // KC of the staged layout
-int ppl_variant_occ(lrcc_prec prec);             // 4M launch variant (1 or 2 WG/CU)
-void ppl_set_variant_occ(lrcc_prec prec, int occ);
+bool ppl_has_occ2(lrcc_prec prec, lrcc_cmul cmul);  // two-workgroup variant exists
 int ppl_planes(lrcc_prec prec, lrcc_cmul cmul);  // planes of the staged L
 size_t ppl_ls_bytes(lrcc_prec prec, lrcc_cmul cmul, const Geom& g);
 size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g);
@@ -174,6 +174,10 @@ const int* tile_order(lrcc_handle h, const Geom& g, int ab0, int ab1, lrcc_statu
 // (nx = number of XCDs to split the order over; 1 = plain super-tile order).
 void block_pair_table(int nbv, std::vector<int>* tab);
 void supertile_order(const Geom& g, int ab0, int ab1, int sw, int nx, std::vector<int>* ord);
+
+// Autotuner (tune.hip); arguments already validated.
+lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc_prec prec,
+                          lrcc_cmul cmul, const char* cache_path, lrcc_tune_result* out);
 
 // Batched solve (solver.hip); arguments already validated.
 lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* inst,

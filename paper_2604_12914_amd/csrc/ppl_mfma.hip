@@ -483,19 +483,14 @@ constexpr int KC32 = 32;
 
 }  // namespace
 
-// Launch variant of the 4M kernel: 1 = one workgroup per CU (chunk 16/32,
-// prefetch of the next rows), 2 = two workgroups per CU (chunk 8/16).  Set by
-// the tuner (lrcc_autotune) or the environment variable LRCC_OCC.
-static int g_occ[3] = {0, 0, 0};
-int ppl_variant_occ(lrcc_prec prec) {
-  int o = g_occ[prec];
-  if (o == 0) {
-    const char* e = getenv("LRCC_OCC");
-    o = (e && atoi(e) == 2) ? 2 : 1;
-  }
-  return o;
+// Launch variants of the 4M kernel: occupancy 1 = one workgroup per CU
+// (chunk 16 / 32, prefetch of the next rows), 2 = two workgroups per CU
+// (chunk 8 / 16; FP32 only: the FP64 accumulators need the full register
+// file).  Chosen by the tuner; the environment variable LRCC_OCC=2 sets the
+// default.
+bool ppl_has_occ2(lrcc_prec prec, lrcc_cmul cmul) {
+  return prec == LRCC_FP32 && cmul == LRCC_CMUL_4M;
 }
-void ppl_set_variant_occ(lrcc_prec prec, int occ) { g_occ[prec] = occ; }
 
 int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul) {
   if (cmul == LRCC_CMUL_3M) return prec == LRCC_FP64 ? 8 : 16;
@@ -515,7 +510,7 @@ size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g) {
 
 hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
                       const void* Ls, const void* Xb, void* Sb, const int* tab,
-                      const int* order, hipStream_t st) {
+                      const int* order, int occ, hipStream_t st) {
   const long ntile = (long)g.nbp * g.nbp;
   if (ntile == 0 || g.Mp == 0) return hipSuccess;
   if (ntile > 0x7fffffffL) return hipErrorInvalidValue;
@@ -537,10 +532,13 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
   hipLaunchKernelGGL((k_ppl_4m<T, TA, KC, OCC>), grid, block, 0, st,                         \
                      static_cast<const T*>(Ls), static_cast<const T*>(Xb), static_cast<TA*>(Sb), \
                      tab, order, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v)
-  const int occ = ppl_variant_occ(prec);
+  if (occ == 0) {
+    const char* e = getenv("LRCC_OCC");
+    occ = (e && atoi(e) == 2) ? 2 : 1;
+  }
+  if (!ppl_has_occ2(prec, cmul)) occ = 1;
   if (prec == LRCC_FP64) {
-    if (occ == 2) LRCC_L4(double, double, 8, 2);
-    else LRCC_L4(double, double, KC64, 1);
+    LRCC_L4(double, double, KC64, 1);
   } else if (prec == LRCC_FP32) {
     if (acc64) {
       if (occ == 2) LRCC_L4(float, double, 16, 2);

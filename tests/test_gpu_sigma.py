@@ -220,3 +220,41 @@ def test_autograd_function_and_finite_differences(lrcc):
         fdX = (f(L, X + h * EX) - f(L, X - h * EX)) / (2 * h)
         assert abs(fdL - np.real(np.vdot(gL, EL))) < 1e-7 * abs(fdL)
         assert abs(fdX - np.real(np.vdot(gX, EX))) < 1e-7 * abs(fdX)
+
+
+def test_autotune_cache_and_parity_after_tuning(lrcc, tmp_path):
+    cache = str(tmp_path / "tune.txt")
+    o, v, nchol, nrhs = 5, 44, 100, 3
+    for prec in ("fp64", "fp32"):
+        r = lrcc.autotune(o, v, nchol, nrhs, prec=prec, cache_path=cache)
+        assert r["supertile"] in (2, 4, 8) and r["occupancy"] in (1, 2)
+        assert r["candidates"] >= 2 and r["ms"] > 0
+        again = lrcc.autotune(o, v, nchol, nrhs, prec=prec, cache_path=cache)
+        assert again["candidates"] == 0
+        assert (again["supertile"], again["occupancy"]) == (r["supertile"], r["occupancy"])
+    rng = np.random.default_rng(500)
+    L = S.make_L(rng, nchol, v, hermitian=False)
+    X = S.make_packed(rng, nrhs, o, v)
+    assert rel(run(lrcc, L, X), ppl.sigma(L, X, o, v)) < 1e-10
+    assert rel(run(lrcc, L, X, prec="fp32"),
+               ppl.sigma(L.astype(np.complex64).astype(complex),
+                         X.astype(np.complex64).astype(complex), o, v)) < 2e-6
+
+
+def test_two_workgroups_per_cu_variant(lrcc, tmp_path):
+    # force the FP32 occupancy-2 launch variant through a cache entry and
+    # check parity with it, then restore occupancy 1
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    o, v, nchol, nrhs = 4, 36, 64, 2
+    rng = np.random.default_rng(501)
+    L = S.make_L(rng, nchol, v, hermitian=False)
+    X = S.make_packed(rng, nrhs, o, v)
+    ref = ppl.sigma(L.astype(np.complex64).astype(complex), X.astype(np.complex64).astype(complex),
+                    o, v)
+    for occ in (2, 1):
+        cache = tmp_path / f"force{occ}.txt"
+        cache.write_text(f"gfx950 {ncu} {o} {v} {nchol} {nrhs} 1 0 4 {occ} 1.0\n")
+        r = lrcc.autotune(o, v, nchol, nrhs, prec="fp32", cache_path=str(cache))
+        assert r["occupancy"] == occ and r["candidates"] == 0
+        for dtype in (torch.complex128, torch.complex64):
+            assert rel(run(lrcc, L, X, prec="fp32", dtype=dtype), ref) < 2e-6
