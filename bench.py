@@ -45,6 +45,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the per-precision extras")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device-to-device (a plain copy kernel of known "
+                         "size, to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -73,6 +76,14 @@ def main():
     L = torch.from_numpy(inst.L).cuda()
     mu = torch.from_numpy(inst.mu).cuda()
     F = flops_per_sigma(o, v, nchol, nrhs)
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- timed region: K full FP64 solves ---------------------------------
     for _ in range(args.warmup):
@@ -126,9 +137,11 @@ def main():
         extra = {}
         X = torch.from_numpy(S.make_packed(np.random.default_rng(3), nrhs, o, v)).cuda()
         Lraw = torch.from_numpy(S.make_L(np.random.default_rng(4), nchol, v)).cuda()
-        for prec in ("fp64", "fp32"):
+        for prec, cmul in (("fp64", "4m"), ("fp64", "3m"), ("fp32", "4m"), ("fp32", "3m"),
+                           ("bf16x3", "4m")):
             try:
-                s = lrcc.ppl_sigma(Lraw, X, prec=prec)
+                tune = lrcc.autotune(o, v, nchol, nrhs, prec=prec, cmul=cmul)
+                s = lrcc.ppl_sigma(Lraw, X, prec=prec, cmul=cmul)
                 torch.cuda.synchronize()
                 lrcc.set_timing(True)
                 ts = []
@@ -136,13 +149,14 @@ def main():
                     e0 = torch.cuda.Event(enable_timing=True)
                     e1 = torch.cuda.Event(enable_timing=True)
                     e0.record()
-                    lrcc.ppl_sigma(Lraw, X, prec=prec, out=s)
+                    lrcc.ppl_sigma(Lraw, X, prec=prec, cmul=cmul, out=s)
                     e1.record()
                     torch.cuda.synchronize()
                     ts.append(e0.elapsed_time(e1))
                 km, kn = lrcc.get_timing()
                 lrcc.set_timing(False)
-                extra[f"sigma_{prec}"] = {
+                extra[f"sigma_{prec}_{cmul}"] = {
+                    "tuned": {"supertile": tune["supertile"], "occupancy": tune["occupancy"]},
                     "call_ms": round(min(ts), 3),
                     "kernel_ms": round(km / kn, 3),
                     "tflops_call": round(F / (min(ts) * 1e-3) / 1e12, 2),
@@ -150,26 +164,32 @@ def main():
                     "frac_peak": round(F / (km / kn * 1e-3) / 1e12 / PEAK[prec], 4),
                 }
             except lrcc.LrccError as e:
-                extra[f"sigma_{prec}"] = {"error": str(e)}
-        for prec in ("fp32",):
+                extra[f"sigma_{prec}_{cmul}"] = {"error": str(e)}
+        exact = golden_alpha()
+        for prec in ("fp32", "bf16x3"):
             try:
                 lrcc.solve(eps, L, mu, omegas, prec=prec, tol=1e-8)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 a_lp, inf_lp = lrcc.solve(eps, L, mu, omegas, prec=prec, tol=1e-8)
                 t1 = time.perf_counter()
-                extra[f"solve_{prec}_ir"] = {
+                e = {
                     "ms": round((t1 - t0) * 1e3, 3),
                     "speedup_vs_fp64": round(ms_step / ((t1 - t0) * 1e3), 3),
-                    "max_abs_dalpha": float(np.abs(a_lp - alpha64).max()),
+                    "max_abs_dalpha_vs_fp64_solve": float(np.abs(a_lp - alpha64).max()),
                     "n_sigma_fp64": inf_lp["n_sigma_fp64"],
                     "n_sigma_lowp": inf_lp["n_sigma_lowp"],
                 }
-            except lrcc.LrccError as e:
-                extra[f"solve_{prec}_ir"] = {"error": str(e)}
+                if exact is not None:
+                    e["max_abs_dalpha_vs_exact"] = float(np.abs(a_lp - exact).max())
+                extra[f"solve_{prec}_ir"] = e
+            except lrcc.LrccError as err:
+                extra[f"solve_{prec}_ir"] = {"error": str(err)}
         extra["solve_fp64"] = {"ms": round(ms_step, 3), "iters_max": info["iters_max"],
                                "alpha_zz": [float(alpha64[w, 2, 2].real)
                                             for w in range(len(omegas))]}
+        if exact is not None:
+            extra["solve_fp64"]["max_abs_dalpha_vs_exact"] = float(np.abs(alpha64 - exact).max())
         out["extra"] = extra
 
     # ---- CPU oracle on a bounded share of one ladder application ----------
@@ -177,6 +197,17 @@ def main():
         out["cpu_baseline"] = cpu_baseline(inst.L, o, v, nchol, nrhs, F)
 
     print(json.dumps(out), flush=True)
+
+
+def golden_alpha():
+    """Exact alpha of this workload from tests/golden (written by the oracle)."""
+    import numpy as np
+    p = os.path.join(ROOT, "tests", "golden", "alpha_exact.json")
+    try:
+        g = json.load(open(p))["baseline"]
+    except (OSError, KeyError, ValueError):
+        return None
+    return np.array(g["alpha_re"]) + 1j * np.array(g["alpha_im"])
 
 
 def cpu_baseline(L, o, v, nchol, nrhs, F, budget_s=12.0):

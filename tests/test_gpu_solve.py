@@ -94,3 +94,25 @@ def test_refinement_reaches_fp64_answer(lrcc, prec, every):
         assert info["n_sigma_fp64"] <= 3
     else:
         assert info["n_sigma_fp64"] == 1
+
+
+def _golden(name):
+    import json
+    import os
+    p = os.path.join(os.path.dirname(__file__), "golden", "alpha_exact.json")
+    g = json.load(open(p))[name]
+    return g, np.array(g["alpha_re"]) + 1j * np.array(g["alpha_im"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_baseline_workload_matches_exact_alpha(lrcc, prec):
+    # the FP64 baseline workload (o=16, v=160, Nchol=640, 3 components x 2
+    # frequencies) against the oracle's exact sum-over-states alpha
+    g, exact = _golden("baseline")
+    print(f"baseline solve {prec}", flush=True)
+    inst = S.make_instance(g["o"], g["v"], g["nchol"], ncomp=g["ncomp"], seed=g["seed"],
+                           gamma=g["gamma"])
+    alpha, info = lrcc.solve(*to_dev(inst), g["omegas"], prec=prec, tol=1e-8)
+    assert info["final_relres"] < 1e-8
+    assert np.abs(alpha - exact).max() < 1e-5          # a.u., the accuracy target
+    assert rel(alpha, exact) < 1e-7
