@@ -111,6 +111,9 @@ typedef struct {
                         iterate in the first sweep only, later sweeps update it
                         by the reduced-precision ladder of the correction
                         (the ladder is linear); 1 = FP64 ladder every sweep   */
+  lrcc_prec anchor_prec; /* reduced precision: arithmetic of that full-iterate
+                        ladder: FP64 (default) or FP32 (then the residual is
+                        exact to FP32 ladder accuracy, about 1e-7 relative)   */
 } lrcc_solve_opts;
 
 typedef struct {

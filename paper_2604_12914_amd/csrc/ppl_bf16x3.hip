@@ -35,6 +35,13 @@ constexpr int KB = 32;                 // Cholesky vectors per chunk (MFMA k)
 constexpr int NPL = 4;                 // planes: re_hi, re_lo, im_hi, im_lo
 constexpr int CHUNK = NPL * NS * KB;   // bf16 per block per chunk (16 KB)
 constexpr int VT = NPL * NS * NS;      // bf16 per V tile (32 KB)
+// LDS rows are padded so that the 8 lanes of one 16-byte LDS read phase hit
+// distinct banks: operand rows of 32 bf16 (64 B) get a stride of 40 (80 B),
+// V rows of 64 bf16 (128 B) a stride of 72 (144 B).
+constexpr int KBP = KB + 8;
+constexpr int CHUNKP = NPL * NS * KBP;  // padded chunk in LDS
+constexpr int NSP = NS + 8;
+constexpr int VTP = NPL * NS * NSP;     // padded V tile in LDS
 
 __device__ __forceinline__ f4 mfma(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -130,12 +137,12 @@ __global__ void k_split_x16(long plane, const double* __restrict__ x, __bf16* __
 // ---------------------------------------------------------------------------
 // V panel build.  Waves 0,1 build W1 rows (a,c) 0-31 / 32-63 x all (b,d);
 // waves 2,3 build W2 rows (a,d) likewise x all (b,c).
-__global__ __launch_bounds__(WG, 1) void k_vbuild(const __bf16* __restrict__ Ls,
+__global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
                                                   const int* __restrict__ tab,
                                                   const int* __restrict__ order, int nbv, int nbp,
                                                   int ncp, int v, int ab0,
                                                   __bf16* __restrict__ Vws) {
-  __shared__ __attribute__((aligned(16))) __bf16 lds[4 * CHUNK];  // 64 KB
+  __shared__ __attribute__((aligned(16))) __bf16 lds[4 * CHUNKP];  // 80 KB
   const int tile = order[blockIdx.x];
   const int abl = tile / nbp, cd = tile - abl * nbp;
   const int pAB = tab[ab0 + abl], pCD = tab[cd];
@@ -176,24 +183,27 @@ __global__ __launch_bounds__(WG, 1) void k_vbuild(const __bf16* __restrict__ Ls,
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int k = 0; k < KPB; ++k)
-        reinterpret_cast<u4*>(lds + q * CHUNK)[k * WG + threadIdx.x] = pf[q * KPB + k];
+      for (int k = 0; k < KPB; ++k) {
+        // vector e of the chunk: plane-row (e / 4), 8-bf16 part (e % 4)
+        const int e = k * WG + threadIdx.x;
+        *reinterpret_cast<u4*>(lds + q * CHUNKP + (e >> 2) * KBP + (e & 3) * 8) = pf[q * KPB + k];
+      }
     __syncthreads();
     if (pc + 1 < nch) fetch(pc + 1);
     // operands: [plane][row][32 P], lane reads 8 consecutive P at 8*lk
-    const __bf16* la = lds + qa * CHUNK + 8 * lk;
-    const __bf16* lb = lds + qb * CHUNK + 8 * lk;
+    const __bf16* la = lds + qa * CHUNKP + 8 * lk;
+    const __bf16* lb = lds + qb * CHUNKP + 8 * lk;
     bf8 a[2][4], b[4][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int p = 0; p < 4; ++p)
-        a[i][p] = *reinterpret_cast<const bf8*>(la + p * NS * KB + (16 * (rb0 + i) + li) * KB);
+        a[i][p] = *reinterpret_cast<const bf8*>(la + (p * NS + 16 * (rb0 + i) + li) * KBP);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int p = 0; p < 4; ++p)
-        b[j][p] = *reinterpret_cast<const bf8*>(lb + p * NS * KB + (16 * j + li) * KB);
+        b[j][p] = *reinterpret_cast<const bf8*>(lb + (p * NS + 16 * j + li) * KBP);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const bf8 nih = neg(a[i][2]), nil = neg(a[i][3]);
@@ -272,7 +282,7 @@ __global__ __launch_bounds__(WG, 1) void k_contract(const __bf16* __restrict__ X
                                                     const __bf16* __restrict__ Vws, int nbp,
                                                     int Mp, int nmb, int ab0,
                                                     TA* __restrict__ Sb) {
-  __shared__ __attribute__((aligned(16))) __bf16 vt[VT];  // 32 KB
+  __shared__ __attribute__((aligned(16))) __bf16 vt[VTP];  // 36 KB
   const int mb = blockIdx.x % nmb, abl = blockIdx.x / nmb;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -321,7 +331,11 @@ __global__ __launch_bounds__(WG, 1) void k_contract(const __bf16* __restrict__ X
   for (int cd = 0; cd < nbp; ++cd) {
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < VV; ++k) reinterpret_cast<u4*>(vt)[k * WG + threadIdx.x] = vp[k];
+    for (int k = 0; k < VV; ++k) {
+      // vector e of the tile: plane-row (e / 8), 8-bf16 part (e % 8)
+      const int e = k * WG + threadIdx.x;
+      *reinterpret_cast<u4*>(vt + (e >> 3) * NSP + (e & 7) * 8) = vp[k];
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -340,7 +354,7 @@ __global__ __launch_bounds__(WG, 1) void k_contract(const __bf16* __restrict__ X
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int p = 0; p < 4; ++p)
-          b[j][p] = *reinterpret_cast<const bf8*>(vt + p * NS * NS + (16 * j + li) * NS +
+          b[j][p] = *reinterpret_cast<const bf8*>(vt + (p * NS + 16 * j + li) * NSP +
                                                   32 * ks + 8 * lk);
 #pragma unroll
       for (int i = 0; i < 2; ++i) {

@@ -595,17 +595,17 @@ lrcc_status setup(Solver& S, lrcc_handle h, int o, int v, int nchol, const doubl
   return LRCC_OK;
 }
 
-lrcc_status stage_for(Solver& S, const void* L, lrcc_prec prec, lrcc_cmul cmul) {
+// Stage L for a ladder of precision `prec` into dst.
+lrcc_status stage_for(Solver& S, const void* L, lrcc_prec prec, lrcc_cmul cmul, Buf& dst) {
   lrcc_handle h = S.h;
   Geom g = S.g;
   if (prec == LRCC_BF16X3) {
     g.ncp = (int)roundup(g.nchol, bf16x3_chunk());
-    LRCC_HIP(h, h->ls2.ensure(bf16x3_ls_bytes(g)));
-    if (g.nchol > 0) LRCC_HIP(h, bf16x3_stage_L(L, LRCC_C128, g, false, h->ls2.p, h->stream));
+    LRCC_HIP(h, dst.ensure(bf16x3_ls_bytes(g)));
+    if (g.nchol > 0) LRCC_HIP(h, bf16x3_stage_L(L, LRCC_C128, g, false, dst.p, h->stream));
     return LRCC_OK;
   }
   g.ncp = (int)roundup(g.nchol, ppl_chunk(prec, cmul));
-  Buf& dst = prec == LRCC_FP64 ? h->ls : h->ls2;
   LRCC_HIP(h, dst.ensure(ppl_ls_bytes(prec, cmul, g)));
   if (g.nchol > 0) {
     if (prec == LRCC_FP64)
@@ -618,8 +618,10 @@ lrcc_status stage_for(Solver& S, const void* L, lrcc_prec prec, lrcc_cmul cmul) 
   return LRCC_OK;
 }
 
-// s = ladder(xin) for all rows (block layout, FP64 accumulation).
-lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul cmul) {
+// s = ladder(xin) for all rows (block layout, FP64 accumulation), with the
+// Cholesky vectors staged for `prec` in ls.
+lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul cmul,
+                        const void* ls) {
   lrcc_handle h = S.h;
   Geom g = S.g;
   g.ncp = (int)roundup(g.nchol, ppl_chunk(prec, cmul));
@@ -628,7 +630,7 @@ lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul 
   if (prec == LRCC_BF16X3) {
     g.ncp = (int)roundup(g.nchol, bf16x3_chunk());
     LRCC_HIP(h, bf16x3_split_x(xin, g, S.x32, h->stream));
-    lrcc_status st = bf16x3_apply(h, g, h->ls2.p, S.x32, S.s, true);
+    lrcc_status st = bf16x3_apply(h, g, ls, S.x32, S.s, true);
     if (st != LRCC_OK) return st;
     ++S.n_sigma_lp;
     return LRCC_OK;
@@ -641,7 +643,6 @@ lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul 
     LRCC_HIP(h, hipGetLastError());
     xb = S.x32;
   }
-  const void* ls = prec == LRCC_FP64 ? h->ls.p : h->ls2.p;
   lrcc_status st = ppl_run(h, prec, cmul, true, g, ls, xb, S.s);
   if (st != LRCC_OK) return st;
   if (prec == LRCC_FP64) ++S.n_sigma64;
@@ -715,13 +716,13 @@ int absorb_flags(Solver& S, int it, double tol, lrcc_status* result) {
 // entry.  x receives the solution.  Returns LRCC_ERR_NOT_CONVERGED if any
 // RHS stopped at max_iter, LRCC_ERR_NONFINITE on NaN/Inf.
 lrcc_status jacobi_diis(Solver& S, const double* b, double* x, lrcc_prec prec, lrcc_cmul cmul,
-                        double tol, int max_iter, const int* h_active_in) {
+                        const void* ls, double tol, int max_iter, const int* h_active_in) {
   lrcc_handle h = S.h;
   lrcc_status st = start_iteration(S, b, x, h_active_in, h->stream);
   if (st != LRCC_OK) return st;
   lrcc_status result = LRCC_OK;
   for (int it = 0;; ++it) {
-    st = apply_sigma(S, x, prec, cmul);
+    st = apply_sigma(S, x, prec, cmul, ls);
     if (st != LRCC_OK) return st;
     st = iterate_vectors(S, b, x, tol, max_iter, h->stream);
     if (st != LRCC_OK) return st;
@@ -802,10 +803,15 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
   st = setup(S, h, o, v, nchol, eps, ncomp, mu, nomega, omegas, O.mdim, ir, h->tab.as<int>(),
              h->stream);
   if (st != LRCC_OK) return st;
-  st = stage_for(S, L, LRCC_FP64, LRCC_CMUL_4M);
+  // staged vectors: h->ls for the FP64 ladder (or the refinement's anchor
+  // ladder), h->ls2 for the reduced-precision inner ladder
+  const lrcc_prec anchor = ir ? op.anchor_prec : LRCC_FP64;
+  if (anchor != LRCC_FP64 && anchor != LRCC_FP32)
+    return fail(h, LRCC_ERR_ARG, "anchor_prec must be FP64 or FP32");
+  st = stage_for(S, L, anchor, LRCC_CMUL_4M, h->ls);
   if (st != LRCC_OK) return st;
   if (ir) {
-    st = stage_for(S, L, op.prec, op.cmul);
+    st = stage_for(S, L, op.prec, op.cmul, h->ls2);
     if (st != LRCC_OK) return st;
   }
   const size_t vb = (size_t)2 * S.d.plane * 8;
@@ -814,7 +820,8 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
   lrcc_status result = LRCC_OK;
   double final_rel = 0;
   if (!ir) {
-    result = jacobi_diis(S, S.b, S.x, LRCC_FP64, LRCC_CMUL_4M, O.tol, O.max_iter, all.data());
+    result = jacobi_diis(S, S.b, S.x, LRCC_FP64, LRCC_CMUL_4M, h->ls.p, O.tol, O.max_iter,
+                         all.data());
     for (int r = 0; r < S.n; ++r) final_rel = std::max(final_rel, S.h_relres[r]);
     if (result == LRCC_ERR_NONFINITE) return fail(h, result, "non-finite residual");
     st = finish_alpha(S, S.x, alpha, h->stream);
@@ -827,8 +834,8 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
     std::vector<double> rel(S.n, 1.0);
     result = LRCC_ERR_NOT_CONVERGED;
     for (int outer = 0; outer < O.max_outer; ++outer) {
-      lrcc_status is = jacobi_diis(S, S.rk, S.x, op.prec, op.cmul, O.inner_tol, O.max_iter,
-                                   act.data());
+      lrcc_status is = jacobi_diis(S, S.rk, S.x, op.prec, op.cmul, h->ls2.p, O.inner_tol,
+                                   O.max_iter, act.data());
       if (is == LRCC_ERR_NONFINITE) return fail(h, is, "non-finite residual");
       // x2 += d; sx = ladder(x2): FP64 ladder of the whole iterate in the
       // first sweep (or every sweep), else sx += reduced-precision ladder of
@@ -839,11 +846,11 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
                          S.x2);
       LRCC_HIP(h, hipGetLastError());
       if (outer == 0 || op.resid_fp64_every) {
-        st = apply_sigma(S, S.x2, LRCC_FP64, LRCC_CMUL_4M);
+        st = apply_sigma(S, S.x2, anchor, LRCC_CMUL_4M, h->ls.p);
         if (st != LRCC_OK) return st;
         LRCC_HIP(h, hipMemcpyAsync(S.sx, S.s, vb, hipMemcpyDeviceToDevice, h->stream));
       } else {
-        st = apply_sigma(S, S.x, op.prec, op.cmul);
+        st = apply_sigma(S, S.x, op.prec, op.cmul, h->ls2.p);
         if (st != LRCC_OK) return st;
         hipLaunchKernelGGL(k_acc, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.active, S.s,
                            S.sx);
