@@ -174,7 +174,10 @@ lrcc_status lrcc_get_timing(lrcc_handle h, double* ms, long* launches);
 typedef struct {
   int supertile;   /* width, in blocks of 8 virtual indices, of the super-tiles
                       that order the tile pairs (see below)                    */
-  int occupancy;   /* workgroups per CU of the fused 4M kernel (1 or 2)        */
+  int occupancy;   /* launch variant of the fused 4M kernel: 1 = one workgroup
+                      per CU, chunks through registers; 2 = two per CU (FP32);
+                      3 = one per CU, chunks loaded straight into a two-chunk
+                      LDS ring; 4 = two per CU with direct LDS loads           */
   double ms;       /* ladder kernel time of the chosen variant                 */
   int candidates;  /* variants timed (0 when read from the cache)              */
 } lrcc_tune_result;
@@ -182,8 +185,8 @@ typedef struct {
 /* Tile-shape autotuner.  Times the candidate launch variants of the ladder
  * for this shape, precision and complex form on synthetic inputs: the width
  * s in {2, 4, 8} of the super-tiles (tile pairs whose four Cholesky blocks
- * come from s x s block sets are run together on one XCD) and, where the
- * kernel fits, one or two workgroups per CU.  The fastest is kept in the
+ * come from s x s block sets are run together on one XCD) and the launch
+ * variants of the fused kernel that exist for the precision.  The fastest is kept in the
  * handle for later calls.  cache_path (host, nullable): a text file of
  * earlier results keyed by (arch, CU count, o, v, nchol, nrhs, prec, cmul);
  * a hit skips the timing, a miss appends the new result.  Tuning restarts

@@ -64,7 +64,7 @@ struct Smem {
 };
 
 // One tile pair (ab, cd) of the fused ladder, run by one 4-wave workgroup.
-template <typename T, typename TA, int KC, int OCC>
+template <typename T, typename TA, int KC, int OCC, bool DL>
 __device__ __forceinline__ void ppl_tile_4m(const T* __restrict__ Ls, const T* __restrict__ Xb,
                                             TA* __restrict__ Sb, const int* __restrict__ tab,
                                             int nbv, int nbp, int ncp, int Mp, int v, int ab,
@@ -95,12 +95,18 @@ __device__ __forceinline__ void ppl_tile_4m(const T* __restrict__ Ls, const T* _
     w2i[j] = w1r[j];
   }
 
-  // chunk of KC vectors of the four blocks: contiguous runs of CH elements,
-  // prefetched into registers one chunk ahead of the MFMA work
+  // chunk of KC vectors of the four blocks: contiguous runs of CH elements.
+  // DL = false: prefetched into registers one chunk ahead of the MFMA work,
+  // then stored to LDS.  DL = true: loaded straight into LDS (1 KB per wave
+  // instruction, lane i's 16 bytes at offset 16 i); with one workgroup per
+  // CU a two-chunk ring overlaps the next chunk's load with this chunk's
+  // MFMAs, with two workgroups per CU the other workgroup covers the wait.
   constexpr int nvec = 4 * CH / VN;
-  constexpr int NPF = nvec / WG;        // vectors per thread per chunk
-  constexpr int KPB = CH / VN / WG;     // of which per block
-  static_assert(NPF == 4 * KPB, "chunk must split evenly over the workgroup");
+  constexpr int NPF = DL ? 1 : nvec / WG;  // vectors per thread per chunk
+  constexpr int KPB = CH / VN / WG;        // of which per block
+  static_assert(DL || NPF == 4 * KPB, "chunk must split evenly over the workgroup");
+  constexpr int PPB = CH * (int)sizeof(T) / 1024;  // 1 KB pieces per block chunk
+  static_assert(!DL || (PPB % 4 == 0), "direct loads need whole pieces per wave");
   vec_t pf[NPF];
   auto fetch = [&](int p0) {
 #pragma unroll
@@ -110,24 +116,52 @@ __device__ __forceinline__ void ppl_tile_4m(const T* __restrict__ Ls, const T* _
       for (int k = 0; k < KPB; ++k) pf[q * KPB + k] = src[k * WG + threadIdx.x];
     }
   };
-  fetch(0);
-  for (int p0 = 0; p0 < ncp; p0 += KC) {
-    __syncthreads();
+  auto issue = [&](int p0, T* buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-      for (int k = 0; k < KPB; ++k)
-        reinterpret_cast<vec_t*>(lds + q * CH)[k * WG + threadIdx.x] = pf[q * KPB + k];
+    for (int k = 0; k < PPB; ++k) {  // PPB pieces per wave = 4 * PPB / 4 waves
+      const int q = k * 4 / PPB, pb = wave + 4 * (k % (PPB / 4));
+      const char* src = reinterpret_cast<const char*>(gblk[q] + (size_t)p0 * 2 * NS) +
+                        pb * 1024 + lane * 16;
+      __builtin_amdgcn_global_load_lds(
+          src, (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(buf + q * CH) +
+                                                         pb * 1024),
+          16, 0, 0);
     }
-    __syncthreads();
-    if (p0 + KC < ncp) fetch(p0 + KC);
+  };
+  T* const ring0 = lds;
+  T* const ring1 = lds + (DL && OCC == 1 ? 4 * CH : 0);
+  if (DL && OCC == 1) issue(0, ring0);
+  if (!DL) fetch(0);
+  for (int p0 = 0, c = 0; p0 < ncp; p0 += KC, ++c) {
+    T* cur = lds;
+    if (DL && OCC == 1) {
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this chunk has landed
+      __syncthreads();                     // every wave: loads landed, previous chunk done
+      cur = (c & 1) ? ring1 : ring0;
+      if (p0 + KC < ncp) issue(p0 + KC, (c & 1) ? ring0 : ring1);
+    } else if (DL) {
+      __syncthreads();
+      issue(p0, lds);
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+      __syncthreads();
+    } else {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int k = 0; k < KPB; ++k)
+          reinterpret_cast<vec_t*>(lds + q * CH)[k * WG + threadIdx.x] = pf[q * KPB + k];
+      }
+      __syncthreads();
+      if (p0 + KC < ncp) fetch(p0 + KC);
+    }
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
       const int p = 4 * ks + lk;  // vector within the chunk used by this lane
-      const T* lac = lds + 0 * CH + p * 2 * NS;
-      const T* lbd = lds + 1 * CH + p * 2 * NS;
-      const T* lad = lds + 2 * CH + p * 2 * NS;
-      const T* lbc = lds + 3 * CH + p * 2 * NS;
+      const T* lac = cur + 0 * CH + p * 2 * NS;
+      const T* lbd = cur + 1 * CH + p * 2 * NS;
+      const T* lad = cur + 2 * CH + p * 2 * NS;
+      const T* lbc = cur + 3 * CH + p * 2 * NS;
       const T acr = lac[16 * wave + li], aci = lac[NS + 16 * wave + li];
       const T adr = lad[16 * wave + li], adi = lad[NS + 16 * wave + li];
       T bdr[4], bdi[4], bcr[4], bci[4];
@@ -260,17 +294,19 @@ __device__ __forceinline__ void ppl_tile_4m(const T* __restrict__ Ls, const T* _
   }
 }
 
-template <typename T, typename TA, int KC, int OCC>
+template <typename T, typename TA, int KC, int OCC, bool DL>
 __global__ __launch_bounds__(WG, OCC) void k_ppl_4m(const T* __restrict__ Ls,
                                                     const T* __restrict__ Xb,
                                                     TA* __restrict__ Sb,
                                                     const int* __restrict__ tab,
                                                     const int* __restrict__ order, int nbv,
                                                     int nbp, int ncp, int Mp, int v) {
-  __shared__ __attribute__((aligned(16))) T lds[Smem<T, KC>::elems];
+  constexpr int NE = (DL && OCC == 1) ? 2 * Smem<T, KC>::build : Smem<T, KC>::elems;
+  __shared__ __attribute__((aligned(16))) T lds[NE > Smem<T, KC>::elems ? NE : Smem<T, KC>::elems];
   const int tile = order[blockIdx.x];
   const int ab = tile / nbp;
-  ppl_tile_4m<T, TA, KC, OCC>(Ls, Xb, Sb, tab, nbv, nbp, ncp, Mp, v, ab, tile - ab * nbp, lds);
+  ppl_tile_4m<T, TA, KC, OCC, DL>(Ls, Xb, Sb, tab, nbv, nbp, ncp, Mp, v, ab, tile - ab * nbp,
+                                  lds);
 }
 
 // Persistent ladder over several instances: every workgroup takes the next
@@ -293,7 +329,7 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_queue(const BatchInst* __restrict
     const long local = t - I.start;
     const int tile = I.order[local];
     const int ab = tile / I.nbp;
-    ppl_tile_4m<double, double, 16, 1>(I.Ls, I.Xb, I.Sb, I.tab, I.nbv, I.nbp, I.ncp, I.Mp, I.v,
+    ppl_tile_4m<double, double, 16, 1, false>(I.Ls, I.Xb, I.Sb, I.tab, I.nbv, I.nbp, I.ncp, I.Mp, I.v,
                                        ab, tile - ab * I.nbp, lds);
   }
 }
@@ -483,13 +519,17 @@ constexpr int KC32 = 32;
 
 }  // namespace
 
-// Launch variants of the 4M kernel: occupancy 1 = one workgroup per CU
-// (chunk 16 / 32, prefetch of the next rows), 2 = two workgroups per CU
-// (chunk 8 / 16; FP32 only: the FP64 accumulators need the full register
-// file).  Chosen by the tuner; the environment variable LRCC_OCC=2 sets the
-// default.
-bool ppl_has_occ2(lrcc_prec prec, lrcc_cmul cmul) {
-  return prec == LRCC_FP32 && cmul == LRCC_CMUL_4M;
+// Launch variants of the 4M kernel (chosen by the tuner; the environment
+// variable LRCC_VARIANT sets the default): 1 = one workgroup per CU, chunks
+// of 16 / 32 vectors prefetched through registers; 2 = two workgroups per CU
+// through registers (FP32 only: the FP64 accumulators need the full register
+// file); 3 = one workgroup per CU, chunks loaded straight into a two-chunk
+// LDS ring; 4 = two workgroups per CU, direct loads into one LDS chunk.
+bool ppl_has_variant(lrcc_prec prec, lrcc_cmul cmul, int variant) {
+  if (cmul != LRCC_CMUL_4M) return variant == 1;
+  if (prec == LRCC_FP64) return variant == 1 || variant == 3;  // 4 would spill
+  if (prec == LRCC_FP32) return variant >= 1 && variant <= 4;
+  return variant == 1;
 }
 
 int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul) {
@@ -528,24 +568,31 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
 #undef LRCC_L3
     return hipGetLastError();
   }
-#define LRCC_L4(T, TA, KC, OCC)                                                             \
-  hipLaunchKernelGGL((k_ppl_4m<T, TA, KC, OCC>), grid, block, 0, st,                         \
+#define LRCC_L4(T, TA, KC, OCC, DL)                                                         \
+  hipLaunchKernelGGL((k_ppl_4m<T, TA, KC, OCC, DL>), grid, block, 0, st,                     \
                      static_cast<const T*>(Ls), static_cast<const T*>(Xb), static_cast<TA*>(Sb), \
                      tab, order, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v)
+  // variant: 1 = one WG/CU with register prefetch, 2 = two WG/CU (FP32),
+  // 3 = one WG/CU with direct-to-LDS chunk ring, 4 = two WG/CU with direct loads
   if (occ == 0) {
-    const char* e = getenv("LRCC_OCC");
-    occ = (e && atoi(e) == 2) ? 2 : 1;
+    const char* e = getenv("LRCC_VARIANT");
+    occ = e ? atoi(e) : 1;
   }
-  if (!ppl_has_occ2(prec, cmul)) occ = 1;
+  if (!ppl_has_variant(prec, cmul, occ)) occ = 1;
   if (prec == LRCC_FP64) {
-    LRCC_L4(double, double, KC64, 1);
+    if (occ == 3) LRCC_L4(double, double, KC64, 1, true);
+    else LRCC_L4(double, double, KC64, 1, false);
   } else if (prec == LRCC_FP32) {
     if (acc64) {
-      if (occ == 2) LRCC_L4(float, double, 16, 2);
-      else LRCC_L4(float, double, KC32, 1);
+      if (occ == 2) LRCC_L4(float, double, 16, 2, false);
+      else if (occ == 3) LRCC_L4(float, double, KC32, 1, true);
+      else if (occ == 4) LRCC_L4(float, double, 16, 2, true);
+      else LRCC_L4(float, double, KC32, 1, false);
     } else {
-      if (occ == 2) LRCC_L4(float, float, 16, 2);
-      else LRCC_L4(float, float, KC32, 1);
+      if (occ == 2) LRCC_L4(float, float, 16, 2, false);
+      else if (occ == 3) LRCC_L4(float, float, KC32, 1, true);
+      else if (occ == 4) LRCC_L4(float, float, 16, 2, true);
+      else LRCC_L4(float, float, KC32, 1, false);
     }
   } else {
     return hipErrorNotSupported;

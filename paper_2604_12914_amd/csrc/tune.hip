@@ -1,8 +1,9 @@
 // Tile-shape autotuner of the ladder launch (lrcc_autotune).
 //
 // Candidates: the super-tile width s of the tile order (2, 4, 8 blocks of
-// virtual indices, capped by the number of blocks) and, where the kernel
-// variant exists, one or two workgroups per CU.  Each candidate runs the
+// virtual indices, capped by the number of blocks) and the launch variants
+// of the fused 4M kernel that exist for the precision (one or two workgroups
+// per CU; chunks through registers or loaded straight into LDS).  Each candidate runs the
 // ladder on synthetic inputs of the requested shape (one warm-up, then the
 // best of two HIP-event-timed launches); the fastest is kept in the handle.
 // Results are cached in a plain text file, one line per key:
@@ -55,7 +56,7 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
       std::istringstream rest(line.substr(key.size()));
       int s = 0, occ = 0;
       double ms = 0;
-      if (rest >> s >> occ >> ms && s > 0 && (occ == 1 || occ == 2)) {
+      if (rest >> s >> occ >> ms && s > 0 && occ >= 1 && occ <= 4) {
         h->order_s = s;
         h->occ[prec] = occ;
         if (out) *out = lrcc_tune_result{s, occ, ms, 0};
@@ -86,8 +87,9 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
   std::vector<int> widths;
   for (int s : {2, 4, 8})
     if (s == 2 || s <= g.nbv) widths.push_back(s);
-  std::vector<int> occs = {1};
-  if (ppl_has_occ2(prec, cmul)) occs.push_back(2);
+  std::vector<int> occs;
+  for (int var = 1; var <= 4; ++var)
+    if (ppl_has_variant(prec, cmul, var)) occs.push_back(var);
 
   const int saved_s = h->order_s, saved_occ = h->occ[prec];
   const bool saved_timing = h->timing;

@@ -227,7 +227,7 @@ def test_autotune_cache_and_parity_after_tuning(lrcc, tmp_path):
     o, v, nchol, nrhs = 5, 44, 100, 3
     for prec in ("fp64", "fp32"):
         r = lrcc.autotune(o, v, nchol, nrhs, prec=prec, cache_path=cache)
-        assert r["supertile"] in (2, 4, 8) and r["occupancy"] in (1, 2)
+        assert r["supertile"] in (2, 4, 8) and r["occupancy"] in (1, 2, 3, 4)
         assert r["candidates"] >= 2 and r["ms"] > 0
         again = lrcc.autotune(o, v, nchol, nrhs, prec=prec, cache_path=cache)
         assert again["candidates"] == 0
@@ -241,20 +241,29 @@ def test_autotune_cache_and_parity_after_tuning(lrcc, tmp_path):
                          X.astype(np.complex64).astype(complex), o, v)) < 2e-6
 
 
-def test_two_workgroups_per_cu_variant(lrcc, tmp_path):
-    # force the FP32 occupancy-2 launch variant through a cache entry and
-    # check parity with it, then restore occupancy 1
+@pytest.mark.parametrize("prec,variants", [("fp32", (2, 3, 4, 1)), ("fp64", (3, 1))])
+def test_launch_variants(lrcc, tmp_path, prec, variants):
+    # force each launch variant of the fused kernel through a tuner cache
+    # entry and check parity with it; the list ends with the default variant
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     o, v, nchol, nrhs = 4, 36, 64, 2
     rng = np.random.default_rng(501)
     L = S.make_L(rng, nchol, v, hermitian=False)
     X = S.make_packed(rng, nrhs, o, v)
-    ref = ppl.sigma(L.astype(np.complex64).astype(complex), X.astype(np.complex64).astype(complex),
-                    o, v)
-    for occ in (2, 1):
-        cache = tmp_path / f"force{occ}.txt"
-        cache.write_text(f"gfx950 {ncu} {o} {v} {nchol} {nrhs} 1 0 4 {occ} 1.0\n")
-        r = lrcc.autotune(o, v, nchol, nrhs, prec="fp32", cache_path=str(cache))
-        assert r["occupancy"] == occ and r["candidates"] == 0
+    # reference on complex64-rounded inputs: FP32 arithmetic, or FP64
+    # arithmetic on complex64 storage
+    ref64 = ppl.sigma(L.astype(np.complex64).astype(complex),
+                      X.astype(np.complex64).astype(complex), o, v)
+    bars = {("fp32", torch.complex128): (ref64, 2e-6), ("fp32", torch.complex64): (ref64, 2e-6),
+            ("fp64", torch.complex128): (ppl.sigma(L, X, o, v), 1e-10),
+            ("fp64", torch.complex64): (ref64, 1e-6)}
+    code = {"fp64": 0, "fp32": 1}[prec]
+    for var in variants:
+        print(f"{prec} variant {var}", flush=True)
+        cache = tmp_path / f"force{prec}{var}.txt"
+        cache.write_text(f"gfx950 {ncu} {o} {v} {nchol} {nrhs} {code} 0 4 {var} 1.0\n")
+        r = lrcc.autotune(o, v, nchol, nrhs, prec=prec, cache_path=str(cache))
+        assert r["occupancy"] == var and r["candidates"] == 0
         for dtype in (torch.complex128, torch.complex64):
-            assert rel(run(lrcc, L, X, prec="fp32", dtype=dtype), ref) < 2e-6
+            ref, tol = bars[(prec, dtype)]
+            assert rel(run(lrcc, L, X, prec=prec, dtype=dtype), ref) < tol
