@@ -4,10 +4,13 @@
 // virtual indices, capped by the number of blocks) and the launch variants
 // of the fused 4M kernel that exist for the precision (one or two workgroups
 // per CU; chunks through registers or loaded straight into LDS).  Each candidate runs the
-// ladder on synthetic inputs of the requested shape (one warm-up, then the
-// best of two HIP-event-timed launches); the fastest is kept in the handle.
+// ladder on synthetic inputs of a slice of the requested shape (at most
+// v = 256, nchol = 512; one warm-up, then the best of two HIP-event-timed
+// launches); the fastest is kept in the handle.  The cache key keeps the
+// requested shape.
 // Results are cached in a plain text file, one line per key:
 //   <arch> <cu> <o> <v> <nchol> <nrhs> <prec> <cmul> <s> <occ> <ms>
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -64,6 +67,11 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
       }
     }
   }
+  // time a reduced shape: the variants differ in per-tile efficiency, which a
+  // slice of at most 32 virtual blocks and 512 Cholesky vectors ranks the
+  // same way at a small fraction of the cost of the full ladder
+  v = std::min(v, 256);
+  nchol = std::min(nchol, 512);
   Geom g = make_geom(o, v, nchol, nrhs, 1);
   if (g.M == 0 || g.npv == 0 || nchol == 0) {
     if (out) *out = lrcc_tune_result{h->order_s > 0 ? h->order_s : 4, 1, 0.0, 0};
