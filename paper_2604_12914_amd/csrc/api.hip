@@ -97,7 +97,8 @@ void block_pair_table(int nbv, std::vector<int>* tab) {
   if (tab->empty()) tab->push_back(0);
 }
 
-void supertile_order(const Geom& g, int ab0, int ab1, int sw, int nx, std::vector<int>* ord) {
+void supertile_order(const Geom& g, int ab0, int ab1, int sw, int nx, bool upper,
+                     std::vector<int>* ord) {
   const int nbv = g.nbv, nbp = g.nbp;
   std::vector<int> A(nbp), B(nbp);
   for (int a = 0, k = 0; a < nbv; ++a)
@@ -113,17 +114,17 @@ void supertile_order(const Geom& g, int ab0, int ab1, int sw, int nx, std::vecto
     gcd[gk].push_back(bp);
     if (bp >= ab0 && bp < ab1) gab[gk].push_back(bp);
   }
-  const long total = (long)(ab1 - ab0) * nbp;
   std::vector<int> all;
-  all.reserve(total);
   for (const auto& ga : gab) {
     if (ga.empty()) continue;
     for (const auto& gc : gcd) {
       if (gc.empty()) continue;
       for (int ab : ga)
-        for (int cd : gc) all.push_back((ab - ab0) * nbp + cd);
+        for (int cd : gc)
+          if (!upper || cd >= ab) all.push_back((ab - ab0) * nbp + cd);
     }
   }
+  const long total = (long)all.size();
   // contiguous share per XCD; workgroup w runs on XCD w % nx, as the j-th
   // (j = w / nx) of that XCD's workgroups
   const long q = total / nx, r = total % nx;
@@ -134,17 +135,18 @@ void supertile_order(const Geom& g, int ab0, int ab1, int sw, int nx, std::vecto
   }
 }
 
-const int* tile_order(lrcc_handle h, const Geom& g, int ab0, int ab1, lrcc_status* st) {
+const int* tile_order(lrcc_handle h, const Geom& g, int ab0, int ab1, bool upper,
+                      lrcc_status* st) {
   const int sw = h->order_s > 0 ? h->order_s : 4;
-  const long key[5] = {g.nbv, ab0, ab1, sw, h->ncu};
+  const long key[6] = {g.nbv, ab0, ab1, sw, h->ncu, upper};
   bool same = true;
-  for (int k = 0; k < 5; ++k) same = same && key[k] == h->order_key[k];
+  for (int k = 0; k < 6; ++k) same = same && key[k] == h->order_key[k];
   if (same) {
     *st = LRCC_OK;
     return h->order.as<int>();
   }
   std::vector<int> ord;
-  supertile_order(g, ab0, ab1, sw, std::max(1, h->ncu / 32), &ord);
+  supertile_order(g, ab0, ab1, sw, std::max(1, h->ncu / 32), upper, &ord);
   hipError_t e = h->order.ensure(ord.size() * sizeof(int));
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->order.p, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice,
@@ -154,13 +156,13 @@ const int* tile_order(lrcc_handle h, const Geom& g, int ab0, int ab1, lrcc_statu
     *st = hip_fail(h, e, "tile order upload");
     return nullptr;
   }
-  for (int k = 0; k < 5; ++k) h->order_key[k] = key[k];
+  for (int k = 0; k < 6; ++k) h->order_key[k] = key[k];
   *st = LRCC_OK;
   return h->order.as<int>();
 }
 
 lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
-                    const void* Ls, const void* Xb, void* Sb) {
+                    const void* Ls, const void* Xb, void* Sb, const int* nonherm) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->timing) {
     if (h->tev.size() < 2 * (h->tev_used + 1)) {
@@ -175,10 +177,10 @@ lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, c
     LRCC_HIP(h, hipEventRecord(e0, h->stream));
   }
   lrcc_status ost;
-  const int* ord = tile_order(h, g, 0, g.nbp, &ost);
+  const int* ord = tile_order(h, g, 0, g.nbp, true, &ost);
   if (ost != LRCC_OK) return ost;
-  LRCC_HIP(h, ppl_launch(prec, cmul, acc64, g, Ls, Xb, Sb, h->tab.as<int>(), ord, h->occ[prec],
-                         h->stream));
+  LRCC_HIP(h, ppl_launch(prec, cmul, acc64, g, Ls, Xb, Sb, h->tab.as<int>(), ord, nonherm,
+                         h->occ[prec], h->stream));
   if (h->timing) {
     LRCC_HIP(h, hipEventRecord(e1, h->stream));
     ++h->tev_used;
@@ -294,6 +296,8 @@ lrcc_status sigma_packed(lrcc_handle h, const Geom& g, const void* L, bool conj_
   LRCC_HIP(h, fill_zero(h->sb.p, sbytes, h->stream));
   if (g.nchol > 0) {
     const int np = ppl_planes(prec, cmul);
+    LRCC_HIP(h, h->hflag.ensure(16));
+    LRCC_HIP(h, herm_check(L, dt, g.v, g.nchol, h->hflag.as<int>(), h->stream));
     if (prec == LRCC_FP64) {
       LRCC_HIP(h, stage_L<double>(L, dt, g, np, conj_t, h->ls.as<double>(), h->stream));
       LRCC_HIP(h, pack_to_block<double>(X, dt, g, tab, h->xb.as<double>(), h->stream));
@@ -301,7 +305,7 @@ lrcc_status sigma_packed(lrcc_handle h, const Geom& g, const void* L, bool conj_
       LRCC_HIP(h, stage_L<float>(L, dt, g, np, conj_t, h->ls.as<float>(), h->stream));
       LRCC_HIP(h, pack_to_block<float>(X, dt, g, tab, h->xb.as<float>(), h->stream));
     }
-    st = ppl_run(h, prec, cmul, acc64, g, h->ls.p, h->xb.p, h->sb.p);
+    st = ppl_run(h, prec, cmul, acc64, g, h->ls.p, h->xb.p, h->sb.p, h->hflag.as<int>());
     if (st != LRCC_OK) return st;
   }
   if (acc64)

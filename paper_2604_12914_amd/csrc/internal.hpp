@@ -66,8 +66,9 @@ struct lrcc_handle_s {
   lrcc::Buf ls, ls2;      // staged Cholesky vectors (ls2: second operand set)
   lrcc::Buf xb, sb, gb;   // block-layout doubles: input, accumulator, gradient
   lrcc::Buf tab;          // block-pair table
+  lrcc::Buf hflag;        // nonzero when the staged L is not Hermitian (device int)
   lrcc::Buf order;        // tile order (XCD-aware super-tiles), see tile_order()
-  long order_key[5] = {-1, -1, -1, -1, -1};
+  long order_key[6] = {-1, -1, -1, -1, -1, -1};
   int order_s = 0;        // super-tile width in virtual blocks (0 = default)
   int occ[3] = {0, 0, 0}; // 4M launch variant per precision (1-4, 0 = default)
   lrcc::Buf vws;          // bf16x3: one panel of antisymmetrised integral tiles
@@ -110,13 +111,22 @@ template <typename T>
 hipError_t block_to_pack(const T* Sb, const Geom& g, const int* tab, void* S,
                          lrcc_dtype dt, hipStream_t st);
 hipError_t fill_zero(void* p, size_t bytes, hipStream_t st);
+// nonherm[0] = 0 if every L^P is exactly Hermitian (L^P_ca == conj L^P_ac,
+// compared bit for bit after conversion to double), 1 otherwise.  nonherm
+// must point to at least 16 bytes; it is cleared here with a fill kernel.
+hipError_t herm_check(const void* L, lrcc_dtype dt, int v, int nchol, int* nonherm,
+                      hipStream_t st);
 
 // Ladder launchers (ppl_mfma.hip) -------------------------------------------
-// Sb (2 planes, accumulated with atomics) += PPL of Xb for all tile pairs.
-// Sb must be zeroed by the caller.
+// Sb (2 planes, accumulated with atomics) += PPL of Xb.  One workgroup per
+// tile pair (ab, cd) with ab <= cd (ppl_ntile of them, listed by `order`),
+// which also covers the mirror (cd, ab); *nonherm (device) selects whether
+// the mirror reuses the tile (Hermitian L) or is built.  Sb must be zeroed
+// by the caller.
+long ppl_ntile(const Geom& g);
 hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
                       const void* Ls, const void* Xb, void* Sb, const int* tab,
-                      const int* order, int occ, hipStream_t st);
+                      const int* order, const int* nonherm, int occ, hipStream_t st);
 // One instance of the persistent FP64 ladder (k_ppl_queue): its staged
 // vectors, block-layout doubles and accumulator, geometry, tile order and
 // the first queue item that belongs to it.
@@ -125,7 +135,8 @@ struct BatchInst {
   const double* Xb;
   double* Sb;
   const int* tab;
-  const int* order;
+  const int* order;    // ppl_ntile tile pairs ab <= cd
+  const int* nonherm;  // device flag of this instance's L
   int nbv, nbp, ncp, Mp, v;
   long start;
 };
@@ -140,7 +151,7 @@ size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g);
 // ppl_launch on the handle's stream, bracketed by timing events when the
 // handle has timing enabled.
 lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
-                    const void* Ls, const void* Xb, void* Sb);
+                    const void* Ls, const void* Xb, void* Sb, const int* nonherm);
 
 // bf16x3 ladder (ppl_bf16x3.hip): staged layouts and the panel driver.
 int bf16x3_chunk();
@@ -162,18 +173,21 @@ lrcc_status bf16x3_apply(lrcc_handle h, const Geom& g, const void* Ls, const voi
 lrcc_status grad_L(lrcc_handle h, const Geom& g, const void* L, const void* X, const void* G,
                    void* dL, lrcc_dtype dt);
 
-// Tile order for a launch over AB block pairs [ab0, ab1) x all CD: entry w
-// is the tile (ab - ab0) * nbp + cd run by workgroup w.  Tiles are grouped
+// Tile order for a launch over AB block pairs [ab0, ab1) x all CD (upper:
+// only CD >= AB): entry w is the tile (ab - ab0) * nbp + cd run by workgroup
+// w.  Tiles are grouped
 // into super-tiles whose AB and CD pairs come from s-wide ranges of virtual
 // blocks (so the four Cholesky blocks a tile reads fall in s x s sets), and
 // each XCD receives a contiguous run of super-tiles (workgroups go to XCDs
 // round-robin).  Returns a device pointer owned by the handle.
-const int* tile_order(lrcc_handle h, const Geom& g, int ab0, int ab1, lrcc_status* st);
+const int* tile_order(lrcc_handle h, const Geom& g, int ab0, int ab1, bool upper,
+                      lrcc_status* st);
 
 // Host-side builders of the block-pair table and of the super-tile order
 // (nx = number of XCDs to split the order over; 1 = plain super-tile order).
 void block_pair_table(int nbv, std::vector<int>* tab);
-void supertile_order(const Geom& g, int ab0, int ab1, int sw, int nx, std::vector<int>* ord);
+void supertile_order(const Geom& g, int ab0, int ab1, int sw, int nx, bool upper,
+                     std::vector<int>* ord);
 
 // Autotuner (tune.hip); arguments already validated.
 lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc_prec prec,

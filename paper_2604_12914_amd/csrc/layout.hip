@@ -1,6 +1,8 @@
 // Staging and layout kernels: packed <-> block-pair layout, Cholesky
 // vectors -> planar 8x8 blocks.  All are HBM-bound streaming kernels with one
 // thread per output element of the block layout.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace lrcc {
@@ -93,6 +95,22 @@ __global__ void k_block_to_pack(const T* __restrict__ Sb, int v, long npv, long 
   }
 }
 
+// One pass over L comparing L^P_ac with conj L^P_ca for a <= c; a wave that
+// finds a mismatch stores 1 (a plain store: every writer writes the same).
+__global__ void k_herm_check(const void* __restrict__ L, lrcc_dtype dt, int v, long n,
+                             int* __restrict__ nonherm) {
+  bool bad = false;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x) {
+    const int c = e % v, a = (e / v) % v;
+    if (a > c) continue;
+    const double2 z = load_c(L, dt, e);
+    const double2 w = load_c(L, dt, e + (long)(c - a) * (v - 1));  // element (c, a)
+    bad = bad || !(z.x == w.x && z.y == -w.y);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) *nonherm = 1;
+}
+
 __global__ void k_zero(uint4* p, size_t n16) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16;
        i += (size_t)gridDim.x * blockDim.x)
@@ -138,6 +156,17 @@ hipError_t fill_zero(void* p, size_t bytes, hipStream_t st) {
   if (bytes % 16 != 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_zero, dim3(grid_for((long)(bytes / 16))), dim3(256), 0, st,
                      static_cast<uint4*>(p), bytes / 16);
+  return hipGetLastError();
+}
+
+hipError_t herm_check(const void* L, lrcc_dtype dt, int v, int nchol, int* nonherm,
+                      hipStream_t st) {
+  hipError_t e = fill_zero(nonherm, 16, st);
+  if (e != hipSuccess) return e;
+  const long n = (long)nchol * v * v;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_herm_check, dim3(std::min(grid_for(n), 4096)), dim3(256), 0, st, L, dt,
+                     v, n, nonherm);
   return hipGetLastError();
 }
 

@@ -432,7 +432,7 @@ hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* 
     const long nb = (long)n * g.nbp;
     if (nb > 0x7fffffffL) return hipErrorInvalidValue;
     lrcc_status ost;
-    const int* ord = tile_order(h, g, ab0, ab0 + n, &ost);
+    const int* ord = tile_order(h, g, ab0, ab0 + n, false, &ost);
     if (ost != LRCC_OK) return hipErrorUnknown;
     hipLaunchKernelGGL(k_vbuild, dim3((unsigned)nb), dim3(WG), 0, st,
                        static_cast<const __bf16*>(Ls), tab, ord, g.nbv, g.nbp, g.ncp, g.v, ab0,

@@ -1,7 +1,7 @@
 // Fused particle-particle-ladder kernel for gfx950 (FP64 and FP32 MFMA).
 //
 // One workgroup (4 waves) owns one tile pair (AB, CD) of virtual block pairs
-// and does, without leaving the CU:
+// with bp(AB) <= bp(CD) and does, without leaving the CU:
 //   1. build   W1[(a,c),(b,d)] = sum_P L^P_ac L^P_bd   (a in A, c in C, b in B, d in D)
 //              W2[(a,d),(b,c)] = sum_P L^P_ad L^P_bc
 //      as two 64 x 64 complex GEMMs over the Cholesky index on the matrix
@@ -12,7 +12,14 @@
 //      c<d sum);
 //   3. contract   sigma[m, ab] += sum_cd X[m, cd] V[ab, cd] for every row m,
 //      on the matrix cores, and add the 64-slot partial sums to the block-
-//      layout accumulator with device-scope atomics.
+//      layout accumulator with device-scope atomics;
+//   4. for AB != CD, the mirror tile (CD, AB): when every L^P is Hermitian
+//      (L^P_ca = conj L^P_ac) the ladder operator is Hermitian,
+//      V[cd, ab] = conj V[ab, cd], and the same LDS tile is contracted a
+//      second time, transposed and conjugated, into sigma[:, CD] (half the
+//      integral builds); otherwise the mirror tile is built and contracted
+//      like the first.  A flag written by the staging pass on the device
+//      selects the branch, so the launch needs no host round trip.
 // The integral tile never reaches HBM.
 #include <cstdlib>
 
@@ -53,22 +60,27 @@ template <> struct Vec16<float> { typedef fv4 t; static constexpr int n = 4; };
 __device__ __forceinline__ void atomic_add(double* p, double x) { unsafeAtomicAdd(p, x); }
 __device__ __forceinline__ void atomic_add(float* p, float x) { unsafeAtomicAdd(p, x); }
 
+// Row stride of the V tile in LDS: one element of padding makes both the
+// row-wise reads of the first contraction and the column-wise reads of the
+// mirror contraction (and the antisymmetrisation stores) conflict-free.
+constexpr int VS = NS + 1;
+
 // LDS bytes: 4 blocks x KC vectors x 2 planes x 64 of T; the 64 x 64 complex
-// V tile (2 planes x 4096 of T) reuses the same space after the build.
+// V tile (2 planes x 64 x VS of T) reuses the same space after the build.
 template <typename T, int KC>
 struct Smem {
   static constexpr int chunk = 2 * NS * KC;        // elements of one block's chunk
   static constexpr int build = 4 * chunk;
-  static constexpr int vtile = 2 * NS * NS;
+  static constexpr int vtile = 2 * NS * VS;
   static constexpr int elems = build > vtile ? build : vtile;
 };
 
-// One tile pair (ab, cd) of the fused ladder, run by one 4-wave workgroup.
-template <typename T, typename TA, int KC, int OCC, bool DL>
-__device__ __forceinline__ void ppl_tile_4m(const T* __restrict__ Ls, const T* __restrict__ Xb,
-                                            TA* __restrict__ Sb, const int* __restrict__ tab,
-                                            int nbv, int nbp, int ncp, int Mp, int v, int ab,
-                                            int cd, T* lds) {
+// Integral tile of block pairs (ab, cd): V[(ab),(cd)] = 2 <ab||cd>, built on
+// the matrix cores (4M form) and left in LDS as V[cd slot * VS + ab slot]
+// (planes re, im).  Ends with a barrier: every wave may read V.
+template <typename T, int KC, int OCC, bool DL>
+__device__ __forceinline__ void build_v_4m(const T* __restrict__ Ls, const int* __restrict__ tab,
+                                           int nbv, int ncp, int v, int ab, int cd, T* lds) {
   typedef typename Acc<T>::t acc_t;
   typedef typename Vec16<T>::t vec_t;
   constexpr int VN = Vec16<T>::n;
@@ -130,6 +142,7 @@ __device__ __forceinline__ void ppl_tile_4m(const T* __restrict__ Ls, const T* _
   };
   T* const ring0 = lds;
   T* const ring1 = lds + (DL && OCC == 1 ? 4 * CH : 0);
+  __syncthreads();  // LDS may still hold the V tile of a previous contraction
   if (DL && OCC == 1) issue(0, ring0);
   if (!DL) fetch(0);
   for (int p0 = 0, c = 0; p0 < ncp; p0 += KC, ++c) {
@@ -192,14 +205,14 @@ __device__ __forceinline__ void ppl_tile_4m(const T* __restrict__ Ls, const T* _
 
   // ---- 2. antisymmetrise into V[cd][ab] (planar) in LDS --------------------
   T* Vr = lds;
-  T* Vi = lds + NS * NS;
+  T* Vi = lds + NS * VS;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * wave + out_row<T>(lk, r), jj = 16 * j + li;
       // W1 element: i = (a_l, c_l), jj = (b_l, d_l)
-      const int idx = ((i & 7) * TB + (jj & 7)) * NS + (i >> 3) * TB + (jj >> 3);
+      const int idx = ((i & 7) * TB + (jj & 7)) * VS + (i >> 3) * TB + (jj >> 3);
       Vr[idx] = (T)2 * w1r[j][r];
       Vi[idx] = (T)2 * w1i[j][r];
     }
@@ -212,7 +225,7 @@ __device__ __forceinline__ void ppl_tile_4m(const T* __restrict__ Ls, const T* _
       const int i = 16 * wave + out_row<T>(lk, r), jj = 16 * j + li;
       // W2 element: i = (a_l, d_l), jj = (b_l, c_l)
       const int al = i >> 3, dl = i & 7, bl = jj >> 3, cl = jj & 7;
-      const int idx = (cl * TB + dl) * NS + al * TB + bl;
+      const int idx = (cl * TB + dl) * VS + al * TB + bl;
       const bool live = (A < B || al < bl) && (B * TB + bl < v) && (C < D || cl < dl) &&
                         (D * TB + dl < v);
       Vr[idx] = live ? Vr[idx] - (T)2 * w2r[j][r] : (T)0;
@@ -220,12 +233,29 @@ __device__ __forceinline__ void ppl_tile_4m(const T* __restrict__ Ls, const T* _
     }
   }
   __syncthreads();
+}
 
-  // ---- 3. contract against X[:, CD] and accumulate into sigma[:, AB] ------
+// Contraction of the LDS tile V of block pairs (x, y) with the rows of X:
+//   TR = false:  sigma[m, x slots] += sum_k X[m, y slot k] V[x, k]
+//   TR = true:   sigma[m, y slots] += sum_k X[m, x slot k] conj V[k, y]
+// (the second is the mirror tile (y, x) of a Hermitian operator).  src / dst
+// are the block pairs whose X rows are read and whose sigma rows receive the
+// 64-slot partial sums (device-scope atomics).  V is only read.
+template <typename T, typename TA, int OCC, bool TR>
+__device__ __forceinline__ void contract_v(const T* lds, const T* __restrict__ Xb,
+                                           TA* __restrict__ Sb, int nbp, int Mp, int src,
+                                           int dst) {
+  typedef typename Acc<T>::t acc_t;
+  typedef typename Vec16<T>::t vec_t;
+  constexpr int VN = Vec16<T>::n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const T* Vr = lds;
+  const T* Vi = lds + NS * VS;
   const size_t plane = (size_t)nbp * Mp * NS;
-  const T* xr_g = Xb + (size_t)cd * Mp * NS;
+  const T* xr_g = Xb + (size_t)src * Mp * NS;
   const T* xi_g = xr_g + plane;
-  TA* sr_g = Sb + (size_t)ab * Mp * NS;
+  TA* sr_g = Sb + (size_t)dst * Mp * NS;
   TA* si_g = sr_g + plane;
   // lane (row li, group lk) holds X[m0+li][16 lk .. 16 lk + 15]; the rows of
   // the next m-chunk are fetched while this one is contracted
@@ -264,22 +294,26 @@ __device__ __forceinline__ void ppl_tile_4m(const T* __restrict__ Ls, const T* _
     }
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const int k = 16 * lk + s;  // cd slot fed by this lane at step s
+      const int k = 16 * lk + s;  // contracted slot fed by this lane at step s
       T vr[4], vi[4];
 #pragma unroll
       for (int n = 0; n < 4; ++n) {
-        vr[n] = Vr[k * NS + 16 * n + li];
-        vi[n] = Vi[k * NS + 16 * n + li];
+        const int a = TR ? (16 * n + li) * VS + k : k * VS + 16 * n + li;
+        vr[n] = Vr[a];
+        vi[n] = Vi[a];
+      }
+      // (xr + i xi)(vr + i vi), or (xr + i xi)(vr - i vi) for the mirror
+      const T xrs = xr[s], xis = xi[s];
+      const T s_r = TR ? xis : -xis, s_i = TR ? -xrs : xrs;
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        sr[n] = mfma(xrs, vr[n], sr[n]);
+        si[n] = mfma(s_i, vi[n], si[n]);
       }
 #pragma unroll
       for (int n = 0; n < 4; ++n) {
-        sr[n] = mfma(xr[s], vr[n], sr[n]);
-        si[n] = mfma(xr[s], vi[n], si[n]);
-      }
-#pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        sr[n] = mfma(-xi[s], vi[n], sr[n]);
-        si[n] = mfma(xi[s], vr[n], si[n]);
+        sr[n] = mfma(s_r, vi[n], sr[n]);
+        si[n] = mfma(xis, vr[n], si[n]);
       }
     }
 #pragma unroll
@@ -294,19 +328,53 @@ __device__ __forceinline__ void ppl_tile_4m(const T* __restrict__ Ls, const T* _
   }
 }
 
+// Work item w of a ladder launch over the ntile tile pairs (ab, cd), ab <= cd,
+// listed by `order`: items [0, ntile) build tile (ab, cd), contract it into
+// sigma[:, AB] and, for a Hermitian operator, its conjugate transpose into
+// sigma[:, CD]; items [ntile, 2 ntile) build the mirror tiles (cd, ab) of a
+// non-Hermitian operator (nothing to do for a Hermitian one or ab = cd).
+// Returns false for an empty item (uniform over the workgroup).
+__device__ __forceinline__ bool decode_item(const int* __restrict__ order, long ntile, int nbp,
+                                            long w, bool nonherm, int* x, int* y,
+                                            bool* mirror) {
+  const bool second = w >= ntile;
+  if (second && !nonherm) return false;
+  const int tile = order[second ? w - ntile : w];
+  const int ab = tile / nbp, cd = tile - ab * nbp;
+  if (second && ab == cd) return false;
+  *x = second ? cd : ab;
+  *y = second ? ab : cd;
+  *mirror = !nonherm && ab != cd;
+  return true;
+}
+
+template <typename T, typename TA, int OCC, typename Build>
+__device__ __forceinline__ void tile_item(Build build, const T* __restrict__ Xb,
+                                          TA* __restrict__ Sb, int nbp, int Mp, int x, int y,
+                                          bool mirror, T* lds) {
+  build(x, y);
+  contract_v<T, TA, OCC, false>(lds, Xb, Sb, nbp, Mp, y, x);
+  if (mirror) contract_v<T, TA, OCC, true>(lds, Xb, Sb, nbp, Mp, x, y);
+}
+
 template <typename T, typename TA, int KC, int OCC, bool DL>
 __global__ __launch_bounds__(WG, OCC) void k_ppl_4m(const T* __restrict__ Ls,
                                                     const T* __restrict__ Xb,
                                                     TA* __restrict__ Sb,
                                                     const int* __restrict__ tab,
-                                                    const int* __restrict__ order, int nbv,
+                                                    const int* __restrict__ order,
+                                                    const int* __restrict__ nonherm, int nbv,
                                                     int nbp, int ncp, int Mp, int v) {
   constexpr int NE = (DL && OCC == 1) ? 2 * Smem<T, KC>::build : Smem<T, KC>::elems;
   __shared__ __attribute__((aligned(16))) T lds[NE > Smem<T, KC>::elems ? NE : Smem<T, KC>::elems];
-  const int tile = order[blockIdx.x];
-  const int ab = tile / nbp;
-  ppl_tile_4m<T, TA, KC, OCC, DL>(Ls, Xb, Sb, tab, nbv, nbp, ncp, Mp, v, ab, tile - ab * nbp,
-                                  lds);
+  int x, y;
+  bool mirror;
+  if (!decode_item(order, (long)nbp * (nbp + 1) / 2, nbp, blockIdx.x, *nonherm != 0, &x, &y,
+                   &mirror))
+    return;
+  tile_item<T, TA, OCC>(
+      [&](int p, int q) { build_v_4m<T, KC, OCC, DL>(Ls, tab, nbv, ncp, v, p, q, lds); }, Xb,
+      Sb, nbp, Mp, x, y, mirror, lds);
 }
 
 // Persistent ladder over several instances: every workgroup takes the next
@@ -321,16 +389,24 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_queue(const BatchInst* __restrict
     __syncthreads();  // every wave is done with the previous item and its LDS
     if (threadIdx.x == 0) item = (long)atomicAdd(counter, 1u);
     __syncthreads();
-    const long t = item;
+    // the item is the same for every lane: keep it (and what is derived from
+    // it) in scalar registers
+    const long t = ((long)__builtin_amdgcn_readfirstlane((int)(item >> 32)) << 32) |
+                   (unsigned)__builtin_amdgcn_readfirstlane((int)item);
     if (t >= total) break;
     int i = 0;
     while (i + 1 < ninst && t >= inst[i + 1].start) ++i;
     const BatchInst& I = inst[i];
-    const long local = t - I.start;
-    const int tile = I.order[local];
-    const int ab = tile / I.nbp;
-    ppl_tile_4m<double, double, 16, 1, false>(I.Ls, I.Xb, I.Sb, I.tab, I.nbv, I.nbp, I.ncp, I.Mp, I.v,
-                                       ab, tile - ab * I.nbp, lds);
+    int x, y;
+    bool mirror;
+    if (!decode_item(I.order, (long)I.nbp * (I.nbp + 1) / 2, I.nbp, t - I.start,
+                     *I.nonherm != 0, &x, &y, &mirror))
+      continue;
+    tile_item<double, double, 1>(
+        [&](int p, int q) {
+          build_v_4m<double, 16, 1, false>(I.Ls, I.tab, I.nbv, I.ncp, I.v, p, q, lds);
+        },
+        I.Xb, I.Sb, I.nbp, I.Mp, x, y, mirror, lds);
   }
 }
 
@@ -338,22 +414,19 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_queue(const BatchInst* __restrict
 // Cholesky blocks, T1 = sum ar br, T2 = sum ai bi, T3 = sum (ar+ai)(br+bi)
 // give re = T1 - T2 and im = T3 - T1 - T2: three real MFMA products per
 // complex product instead of four.  The contraction keeps the 4M form.
-template <typename T, typename TA, int KC>
-__global__ __launch_bounds__(WG, 1) void k_ppl_3m(const T* __restrict__ Ls,
-                                                  const T* __restrict__ Xb,
-                                                  TA* __restrict__ Sb,
-                                                  const int* __restrict__ tab,
-                                                  const int* __restrict__ order, int nbv,
-                                                  int nbp, int ncp, int Mp, int v) {
+template <typename T, int KC>
+struct Smem3 {
+  static constexpr int chunk = 3 * NS * KC;  // one block's chunk: KC vectors x 3 planes x 64
+  static constexpr int elems = 4 * chunk > 2 * NS * VS ? 4 * chunk : 2 * NS * VS;
+};
+
+template <typename T, int KC>
+__device__ __forceinline__ void build_v_3m(const T* __restrict__ Ls, const int* __restrict__ tab,
+                                           int nbv, int ncp, int v, int ab, int cd, T* lds) {
   typedef typename Acc<T>::t acc_t;
   typedef typename Vec16<T>::t vec_t;
   constexpr int VN = Vec16<T>::n;
-  constexpr int CH = 3 * NS * KC;  // one block's chunk: KC vectors x 3 planes x 64
-  constexpr int ELEMS = 4 * CH > 2 * NS * NS ? 4 * CH : 2 * NS * NS;
-  __shared__ __attribute__((aligned(16))) T lds[ELEMS];
-
-  const int tile = order[blockIdx.x];
-  const int ab = tile / nbp, cd = tile - ab * nbp;
+  constexpr int CH = Smem3<T, KC>::chunk;
   const int pAB = tab[ab], pCD = tab[cd];
   const int A = pAB >> 16, B = pAB & 0xffff, C = pCD >> 16, D = pCD & 0xffff;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -386,7 +459,7 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_3m(const T* __restrict__ Ls,
   };
   fetch(0);
   for (int p0 = 0; p0 < ncp; p0 += KC) {
-    __syncthreads();
+    __syncthreads();  // previous chunk (or a previous V tile) no longer read
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -415,15 +488,15 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_3m(const T* __restrict__ Ls,
   }
   __syncthreads();
 
-  // ---- 2. antisymmetrise into V[cd][ab] (planar re, im) in LDS -----------
+  // antisymmetrise into V[cd][ab] (planar re, im) in LDS
   T* Vr = lds;
-  T* Vi = lds + NS * NS;
+  T* Vi = lds + NS * VS;
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * wave + out_row<T>(lk, r), jj = 16 * j + li;  // (a,c), (b,d)
-      const int idx = ((i & 7) * TB + (jj & 7)) * NS + (i >> 3) * TB + (jj >> 3);
+      const int idx = ((i & 7) * TB + (jj & 7)) * VS + (i >> 3) * TB + (jj >> 3);
       Vr[idx] = (T)2 * (t1[0][j][r] - t2[0][j][r]);
       Vi[idx] = (T)2 * (t3[0][j][r] - t1[0][j][r] - t2[0][j][r]);
     }
@@ -434,7 +507,7 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_3m(const T* __restrict__ Ls,
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * wave + out_row<T>(lk, r), jj = 16 * j + li;  // (a,d), (b,c)
       const int al = i >> 3, dl = i & 7, bl = jj >> 3, cl = jj & 7;
-      const int idx = (cl * TB + dl) * NS + al * TB + bl;
+      const int idx = (cl * TB + dl) * VS + al * TB + bl;
       const bool live = (A < B || al < bl) && (B * TB + bl < v) && (C < D || cl < dl) &&
                         (D * TB + dl < v);
       const T re = t1[1][j][r] - t2[1][j][r], im = t3[1][j][r] - t1[1][j][r] - t2[1][j][r];
@@ -442,75 +515,24 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_3m(const T* __restrict__ Ls,
       Vi[idx] = live ? Vi[idx] - (T)2 * im : (T)0;
     }
   __syncthreads();
+}
 
-  // ---- 3. contract against X[:, CD] and accumulate into sigma[:, AB] ------
-  const size_t plane = (size_t)nbp * Mp * NS;
-  const T* xr_g = Xb + (size_t)cd * Mp * NS;
-  const T* xi_g = xr_g + plane;
-  TA* sr_g = Sb + (size_t)ab * Mp * NS;
-  TA* si_g = sr_g + plane;
-  // lane (row li, group lk) holds X[m0+li][16 lk .. 16 lk + 15]; the rows of
-  // the next m-chunk are fetched while this one is contracted
-  constexpr int NX = 16 / VN;
-  vec_t xpr[NX], xpi[NX];
-  auto fetch_x = [&](int m0) {
-    const vec_t* pr = reinterpret_cast<const vec_t*>(xr_g + (size_t)(m0 + li) * NS + 16 * lk);
-    const vec_t* pi = reinterpret_cast<const vec_t*>(xi_g + (size_t)(m0 + li) * NS + 16 * lk);
-#pragma unroll
-    for (int k = 0; k < NX; ++k) {
-      xpr[k] = pr[k];
-      xpi[k] = pi[k];
-    }
-  };
-  if (wave < Mp / 16) fetch_x(wave * 16);
-  for (int mc = wave; mc < Mp / 16; mc += 4) {
-    const int m0 = mc * 16;
-    T xr[16], xi[16];
-#pragma unroll
-    for (int k = 0; k < NX; ++k) {
-#pragma unroll
-      for (int t = 0; t < VN; ++t) {
-        xr[k * VN + t] = xpr[k][t];
-        xi[k * VN + t] = xpi[k][t];
-      }
-    }
-    if (mc + 4 < Mp / 16) fetch_x(m0 + 64);
-    acc_t sr[4], si[4];
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      sr[n] = acc_t{0, 0, 0, 0};
-      si[n] = sr[n];
-    }
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int k = 16 * lk + s;  // cd slot fed by this lane at step s
-      T vr[4], vi[4];
-#pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        vr[n] = Vr[k * NS + 16 * n + li];
-        vi[n] = Vi[k * NS + 16 * n + li];
-      }
-#pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        sr[n] = mfma(xr[s], vr[n], sr[n]);
-        si[n] = mfma(xr[s], vi[n], si[n]);
-      }
-#pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        sr[n] = mfma(-xi[s], vi[n], sr[n]);
-        si[n] = mfma(xi[s], vr[n], si[n]);
-      }
-    }
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const size_t o = (size_t)(m0 + out_row<T>(lk, r)) * NS + 16 * n + li;
-        atomic_add(sr_g + o, (TA)sr[n][r]);
-        atomic_add(si_g + o, (TA)si[n][r]);
-      }
-    }
-  }
+template <typename T, typename TA, int KC>
+__global__ __launch_bounds__(WG, 1) void k_ppl_3m(const T* __restrict__ Ls,
+                                                  const T* __restrict__ Xb,
+                                                  TA* __restrict__ Sb,
+                                                  const int* __restrict__ tab,
+                                                  const int* __restrict__ order,
+                                                  const int* __restrict__ nonherm, int nbv,
+                                                  int nbp, int ncp, int Mp, int v) {
+  __shared__ __attribute__((aligned(16))) T lds[Smem3<T, KC>::elems];
+  int x, y;
+  bool mirror;
+  if (!decode_item(order, (long)nbp * (nbp + 1) / 2, nbp, blockIdx.x, *nonherm != 0, &x, &y,
+                   &mirror))
+    return;
+  tile_item<T, TA, 1>([&](int p, int q) { build_v_3m<T, KC>(Ls, tab, nbv, ncp, v, p, q, lds); },
+                      Xb, Sb, nbp, Mp, x, y, mirror, lds);
 }
 
 
@@ -548,19 +570,20 @@ size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g) {
   return (size_t)2 * g.xb_plane() * (prec == LRCC_FP64 ? 8 : 4);
 }
 
+long ppl_ntile(const Geom& g) { return (long)g.nbp * (g.nbp + 1) / 2; }
+
 hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
                       const void* Ls, const void* Xb, void* Sb, const int* tab,
-                      const int* order, int occ, hipStream_t st) {
-  const long ntile = (long)g.nbp * g.nbp;
+                      const int* order, const int* nonherm, int occ, hipStream_t st) {
+  const long ntile = ppl_ntile(g);
   if (ntile == 0 || g.Mp == 0) return hipSuccess;
-  if (ntile > 0x7fffffffL) return hipErrorInvalidValue;
-  dim3 grid((unsigned)ntile), block(WG);
+  if (2 * ntile > 0x7fffffffL) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(2 * ntile)), block(WG);  // tiles, then their mirrors
   if (cmul == LRCC_CMUL_3M) {
 #define LRCC_L3(T, TA, KC)                                                                      \
   hipLaunchKernelGGL((k_ppl_3m<T, TA, KC>), grid, block, 0, st, static_cast<const T*>(Ls),     \
-                     static_cast<const T*>(Xb), static_cast<TA*>(Sb), tab, order, g.nbv, g.nbp, \
-                     g.ncp,                                                                     \
-                     (int)g.Mp, g.v)
+                     static_cast<const T*>(Xb), static_cast<TA*>(Sb), tab, order, nonherm, g.nbv, \
+                     g.nbp, g.ncp, (int)g.Mp, g.v)
     if (prec == LRCC_FP64) LRCC_L3(double, double, 8);
     else if (prec == LRCC_FP32 && acc64) LRCC_L3(float, double, 16);
     else if (prec == LRCC_FP32) LRCC_L3(float, float, 16);
@@ -571,7 +594,7 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
 #define LRCC_L4(T, TA, KC, OCC, DL)                                                         \
   hipLaunchKernelGGL((k_ppl_4m<T, TA, KC, OCC, DL>), grid, block, 0, st,                     \
                      static_cast<const T*>(Ls), static_cast<const T*>(Xb), static_cast<TA*>(Sb), \
-                     tab, order, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v)
+                     tab, order, nonherm, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v)
   // variant: 1 = one WG/CU with register prefetch, 2 = two WG/CU (FP32),
   // 3 = one WG/CU with direct-to-LDS chunk ring, 4 = two WG/CU with direct loads
   if (occ == 0) {

@@ -493,6 +493,7 @@ struct Solver {
   double *omega = nullptr, *eps = nullptr, *x2 = nullptr, *rk = nullptr, *sx = nullptr;
   float* x32 = nullptr;
   int *otab = nullptr, *active = nullptr, *itp = nullptr;
+  int* nonherm = nullptr;  // Hermiticity flag of L (herm_check)
   unsigned* valid = nullptr;
   double2 *Bm = nullptr, *coef = nullptr, *part = nullptr;
   double* relres = nullptr;
@@ -540,7 +541,8 @@ lrcc_status setup(Solver& S, lrcc_handle h, int o, int v, int nchol, const doubl
                off_act = off_ot + roundup(g.npo * 4, 256), off_val = off_act + roundup(S.n * 4, 256),
                off_rel = off_val + roundup(S.n * 4, 256), off_B = off_rel + roundup(S.n * 8, 256),
                off_c = off_B + roundup((long)S.n * MAXD * MAXD * 16, 256),
-               off_it = off_c + roundup((long)S.n * MAXD * 16, 256), end = off_it + 256;
+               off_it = off_c + roundup((long)S.n * MAXD * 16, 256), off_nh = off_it + 256,
+               end = off_nh + 256;
   need[8] = end;
   for (int k = 0; k < 12; ++k) LRCC_HIP(h, S.buf[k]->ensure(need[k]));
   S.xi = S.buf[0]->as<double>();
@@ -561,6 +563,7 @@ lrcc_status setup(Solver& S, lrcc_handle h, int o, int v, int nchol, const doubl
   S.Bm = reinterpret_cast<double2*>(sm + off_B);
   S.coef = reinterpret_cast<double2*>(sm + off_c);
   S.itp = reinterpret_cast<int*>(sm + off_it);
+  S.nonherm = reinterpret_cast<int*>(sm + off_nh);
   S.part = S.buf[9]->as<double2>();
   S.x32 = S.buf[10]->as<float>();
   S.sx = S.buf[11]->as<double>();
@@ -643,7 +646,7 @@ lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul 
     LRCC_HIP(h, hipGetLastError());
     xb = S.x32;
   }
-  lrcc_status st = ppl_run(h, prec, cmul, true, g, ls, xb, S.s);
+  lrcc_status st = ppl_run(h, prec, cmul, true, g, ls, xb, S.s, S.nonherm);
   if (st != LRCC_OK) return st;
   if (prec == LRCC_FP64) ++S.n_sigma64;
   else ++S.n_sigma_lp;
@@ -808,6 +811,7 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
   const lrcc_prec anchor = ir ? op.anchor_prec : LRCC_FP64;
   if (anchor != LRCC_FP64 && anchor != LRCC_FP32)
     return fail(h, LRCC_ERR_ARG, "anchor_prec must be FP64 or FP32");
+  LRCC_HIP(h, herm_check(L, LRCC_C128, v, nchol, S.nonherm, h->stream));
   st = stage_for(S, L, anchor, LRCC_CMUL_4M, h->ls);
   if (st != LRCC_OK) return st;
   if (ir) {
@@ -948,7 +952,7 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
     // block-pair table and tile order of this instance
     std::vector<int> tab, ord;
     block_pair_table(g0.nbv, &tab);
-    supertile_order(g0, 0, g0.nbp, h->order_s > 0 ? h->order_s : 4, 1, &ord);
+    supertile_order(g0, 0, g0.nbp, h->order_s > 0 ? h->order_s : 4, 1, true, &ord);
     LRCC_HIP(h, own[i][13].ensure(tab.size() * 4));
     LRCC_HIP(h, own[i][14].ensure(ord.size() * 4));
     LRCC_HIP(h, hipMemcpyAsync(own[i][13].p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, cs));
@@ -960,6 +964,7 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
     Geom gs = Si.g;
     gs.ncp = (int)roundup(gs.nchol, KC);
     LRCC_HIP(h, own[i][12].ensure(ppl_ls_bytes(LRCC_FP64, LRCC_CMUL_4M, gs)));
+    LRCC_HIP(h, herm_check(I.L, LRCC_C128, I.v, I.nchol, Si.nonherm, cs));
     if (gs.nchol > 0)
       LRCC_HIP(h, stage_L<double>(I.L, LRCC_C128, gs, 2, false, own[i][12].as<double>(), cs));
     std::vector<int> one(Si.n, 1);
@@ -1013,9 +1018,9 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
       for (size_t k = 0; k < now.size(); ++k) {
         const Solver& Si = *S[now[k]];
         d[k] = BatchInst{own[now[k]][12].as<double>(), Si.x, Si.s, Si.tab,
-                         own[now[k]][14].as<int>(), Si.g.nbv, Si.g.nbp,
+                         own[now[k]][14].as<int>(), Si.nonherm, Si.g.nbv, Si.g.nbp,
                          (int)roundup(Si.g.nchol, KC), (int)Si.g.Mp, Si.g.v, total};
-        total += Si.g.nchol > 0 ? (long)Si.g.nbp * Si.g.nbp : 0;
+        total += Si.g.nchol > 0 ? 2 * ppl_ntile(Si.g) : 0;  // tiles, then mirrors
       }
       LRCC_HIP(h, hipMemcpyAsync(desc.p, d.data(), d.size() * sizeof(BatchInst),
                                  hipMemcpyHostToDevice, cs));

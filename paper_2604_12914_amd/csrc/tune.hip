@@ -4,7 +4,7 @@
 // virtual indices, capped by the number of blocks) and the launch variants
 // of the fused 4M kernel that exist for the precision (one or two workgroups
 // per CU; chunks through registers or loaded straight into LDS).  Each candidate runs the
-// ladder on synthetic inputs of a slice of the requested shape (at most
+// ladder on synthetic inputs (Hermitian L^P) of a slice of the requested shape (at most
 // v = 256, nchol = 512; one warm-up, then the best of two HIP-event-timed
 // launches); the fastest is kept in the handle.  The cache key keeps the
 // requested shape.
@@ -33,6 +33,21 @@ __global__ void k_fill_uniform(double* p, size_t n, unsigned long long seed) {
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
     p[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+
+// Make every L^P Hermitian (the structure of Cholesky vectors of a Hermitian
+// Coulomb metric): lower triangle = conj(upper), real diagonal.
+__global__ void k_hermitize(double2* L, int v, long n) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x) {
+    const int c = e % v, a = (e / v) % v;
+    if (a > c) {
+      const double2 z = L[e - (long)(a - c) * (v - 1)];  // element (c, a)
+      L[e] = make_double2(z.x, -z.y);
+    } else if (a == c) {
+      L[e].y = 0.0;
+    }
   }
 }
 
@@ -90,6 +105,8 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
   double* S = X + nx;
   hipLaunchKernelGGL(k_fill_uniform, dim3(1024), dim3(256), 0, h->stream, L, nl, 1ull);
   hipLaunchKernelGGL(k_fill_uniform, dim3(1024), dim3(256), 0, h->stream, X, nx, 2ull);
+  hipLaunchKernelGGL(k_hermitize, dim3(1024), dim3(256), 0, h->stream,
+                     reinterpret_cast<double2*>(L), v, (long)nchol * v * v);
   LRCC_HIP(h, hipGetLastError());
 
   std::vector<int> widths;

@@ -27,11 +27,13 @@ def dev_inst(inst, omegas):
 
 def test_uneven_batch_matches_single_solves_and_oracle(lrcc):
     # uneven instances (v = 10 o, Nchol = 4 v as in the batched workload, scaled
-    # down), including one whose frequency list differs
+    # down), including one whose frequency list differs and one with general
+    # (non-Hermitian) Cholesky vectors, so the queue mixes both tile paths
     shapes = [(2, 20, 80, 0), (3, 30, 120, 1), (4, 40, 160, 2), (5, 44, 100, 3)]
     insts, devs = [], []
     for (o, v, nchol, seed) in shapes:
-        inst = S.make_instance(o, v, nchol, ncomp=3, seed=seed, gamma=S.solve_gamma(v))
+        inst = S.make_instance(o, v, nchol, ncomp=3, seed=seed, gamma=S.solve_gamma(v),
+                               hermitian=seed != 2)
         om = OMEGAS if seed != 1 else OMEGAS[:2]
         insts.append((inst, om))
         devs.append(dev_inst(inst, om))

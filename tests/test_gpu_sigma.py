@@ -33,16 +33,19 @@ def run(lrcc, L, X, prec="fp64", cmul="4m", dtype=torch.complex128):
     return s.cpu().numpy().astype(np.complex128)
 
 
-# (o, v, nchol, nrhs, hermitian): several tiles, ragged virtual blocks
-# (v not a multiple of 8), nchol not a multiple of the chunk, several RHS.
-CASES = [
-    (4, 24, 64, 1, True),      # tiny workload
-    (5, 44, 100, 3, False),    # ragged v, general complex L
-    (3, 37, 7, 2, False),      # short Cholesky index, odd v
-    (6, 16, 33, 1, True),
-    (2, 9, 16, 1, False),      # one full block plus a 1-wide tail
-    (7, 2, 5, 2, False),       # a single virtual pair
+# (o, v, nchol, nrhs): several tiles, ragged virtual blocks (v not a
+# multiple of 8), nchol not a multiple of the chunk, several RHS.  Each runs
+# with Hermitian L^P (one integral build per tile pair, the mirror tile taken
+# as its conjugate transpose) and with general complex L^P (both built).
+SHAPES = [
+    (4, 24, 64, 1),      # tiny workload
+    (5, 44, 100, 3),     # ragged v
+    (3, 37, 7, 2),       # short Cholesky index, odd v
+    (6, 16, 33, 1),
+    (2, 9, 16, 1),       # one full block plus a 1-wide tail
+    (7, 2, 5, 2),        # a single virtual pair
 ]
+CASES = [c + (h,) for c in SHAPES for h in (True, False)]
 
 
 @pytest.mark.parametrize("o,v,nchol,nrhs,herm", CASES)
@@ -56,12 +59,13 @@ def test_fp64_matches_oracle(lrcc, o, v, nchol, nrhs, herm):
     assert rel(got, ref) < 1e-10
 
 
+@pytest.mark.parametrize("herm", [True, False])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-6)])
 @pytest.mark.parametrize("o,v,nchol,nrhs", [(5, 44, 100, 3), (3, 37, 7, 2), (4, 24, 64, 1)])
-def test_3m_matches_oracle(lrcc, prec, tol, o, v, nchol, nrhs):
-    print(f"3M {prec} parity o={o} v={v} nchol={nchol} nrhs={nrhs}", flush=True)
+def test_3m_matches_oracle(lrcc, prec, tol, o, v, nchol, nrhs, herm):
+    print(f"3M {prec} parity o={o} v={v} nchol={nchol} nrhs={nrhs} herm={herm}", flush=True)
     rng = np.random.default_rng(400 + v)
-    L = S.make_L(rng, nchol, v, hermitian=False)
+    L = S.make_L(rng, nchol, v, hermitian=herm)
     X = S.make_packed(rng, nrhs, o, v)
     got = run(lrcc, L, X, prec=prec, cmul="3m")
     if prec == "fp32":
@@ -79,11 +83,12 @@ def test_fp64_complex64_storage(lrcc):
     assert rel(got, ref) < 1e-6       # only the final rounding to complex64
 
 
+@pytest.mark.parametrize("herm", [True, False])
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-def test_fp32_matches_oracle(lrcc, dtype):
+def test_fp32_matches_oracle(lrcc, dtype, herm):
     rng = np.random.default_rng(8)
     o, v, nchol = 5, 40, 160
-    L = S.make_L(rng, nchol, v)
+    L = S.make_L(rng, nchol, v, hermitian=herm)
     X = S.make_packed(rng, 2, o, v)
     got = run(lrcc, L, X, prec="fp32", dtype=dtype)
     ref = ppl.sigma(L.astype(np.complex64).astype(np.complex128),
@@ -109,6 +114,28 @@ def test_bf16x3_matches_oracle(lrcc, o, v, nchol, nrhs, dtype):
     err = rel(got, ref)
     print(f"bf16x3 relative error {err:.2e}", flush=True)
     assert err < 6e-5
+
+
+@pytest.mark.parametrize("where", ["off-diagonal", "diagonal imaginary", "last element"])
+def test_almost_hermitian_L_takes_the_general_path(lrcc, where):
+    # one element of a Hermitian L breaks the symmetry: the device-side check
+    # must see it (else the mirror tiles would be taken as conjugate
+    # transposes and miss the change); a Hermitian call before and after on
+    # the same handle checks that the flag is recomputed per call
+    rng = np.random.default_rng(11)
+    o, v, nchol = 4, 37, 24
+    L = S.make_L(rng, nchol, v)
+    X = S.make_packed(rng, 2, o, v)
+    Lb = L.copy()
+    if where == "off-diagonal":
+        Lb[5, 3, 30] += 1e-3
+    elif where == "diagonal imaginary":
+        Lb[0, 17, 17] += 1e-3j
+    else:
+        Lb[-1, v - 1, v - 2] += 1e-3
+    for Lx in (L, Lb, L):
+        got = run(lrcc, Lx, X)
+        assert rel(got, ppl.sigma(Lx, X, o, v)) < 1e-10
 
 
 def test_empty_and_degenerate(lrcc):
