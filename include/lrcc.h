@@ -170,6 +170,15 @@ lrcc_status lrcc_solve_batched(lrcc_handle h, int ninst, const lrcc_instance* in
 lrcc_status lrcc_set_timing(lrcc_handle h, int enable);
 lrcc_status lrcc_get_timing(lrcc_handle h, double* ms, long* launches);
 
+/* Workspace limit of the bf16x3 ladder.  That path stores antisymmetrised
+ * integral tiles (64 KB per tile pair with its mirror) for one panel of
+ * block pairs at a time; the panel holds as many rows of the block-pair
+ * triangle as fit in `bytes` (at least one row).  0 restores the default:
+ * min(16 GiB, half the free device memory at first use), overridable by the
+ * environment variable LRCC_PANEL_MB.  The workspace itself is allocated on
+ * the next bf16x3 ladder and kept by the handle. */
+lrcc_status lrcc_set_workspace_limit(lrcc_handle h, size_t bytes);
+
 /* Result of lrcc_autotune. */
 typedef struct {
   int supertile;   /* width, in blocks of 8 virtual indices, of the super-tiles

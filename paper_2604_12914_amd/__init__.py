@@ -105,6 +105,7 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)],
             "lrcc_check_sigma_args": [i, i, i, i, vp, vp, vp, i, i, i],
             "lrcc_set_timing": [vp, i],
+            "lrcc_set_workspace_limit": [vp, ctypes.c_size_t],
             "lrcc_autotune": [vp, i, i, i, i, i, i, ctypes.c_char_p, ctypes.POINTER(TuneResult)],
             "lrcc_get_timing": [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_long)],
         }
@@ -225,6 +226,12 @@ def set_timing(enable: bool, device: int = 0):
     """Start (clearing totals) or stop HIP-event timing of ladder kernels."""
     h = handle(device)
     _check(lib().lrcc_set_timing(h, 1 if enable else 0), h)
+
+
+def set_workspace_limit(nbytes: int, device: int = 0):
+    """Cap the bf16x3 ladder's integral-panel workspace (0 = default)."""
+    h = handle(device)
+    _check(lib().lrcc_set_workspace_limit(h, int(nbytes)), h)
 
 
 def get_timing(device: int = 0):

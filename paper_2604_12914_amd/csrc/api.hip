@@ -189,7 +189,7 @@ lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, c
 }
 
 lrcc_status bf16x3_apply(lrcc_handle h, const Geom& g, const void* Ls, const void* Xb, void* Sb,
-                         bool acc64) {
+                         bool acc64, const int* nonherm) {
   if (h->panel_cap == 0) {
     size_t freeb = 0, totalb = 0;
     LRCC_HIP(h, hipMemGetInfo(&freeb, &totalb));
@@ -197,9 +197,11 @@ lrcc_status bf16x3_apply(lrcc_handle h, const Geom& g, const void* Ls, const voi
     if (const char* e = getenv("LRCC_PANEL_MB")) cap = (size_t)atol(e) << 20;
     h->panel_cap = std::max<size_t>(std::min(cap, freeb / 2), (size_t)64 << 20);
   }
-  const size_t per_ab = bf16x3_panel_bytes(g, 1);
-  int panel = (int)std::min<size_t>((size_t)g.nbp, std::max<size_t>(1, h->panel_cap / per_ab));
-  LRCC_HIP(h, h->vws.ensure(bf16x3_panel_bytes(g, panel)));
+  // the workspace holds the largest panel: the whole triangle if it fits,
+  // else as many rows as the limit allows (at least the first, longest row)
+  const size_t need = std::min(bf16x3_panel_bytes(g, 0, g.nbp),
+                               std::max(h->panel_cap, bf16x3_panel_bytes(g, 0, 1)));
+  LRCC_HIP(h, h->vws.ensure(need));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->timing) {
     while (h->tev.size() < 2 * (h->tev_used + 1)) {
@@ -211,7 +213,8 @@ lrcc_status bf16x3_apply(lrcc_handle h, const Geom& g, const void* Ls, const voi
     e1 = h->tev[2 * h->tev_used + 1];
     LRCC_HIP(h, hipEventRecord(e0, h->stream));
   }
-  LRCC_HIP(h, bf16x3_run(h, g, Ls, Xb, Sb, acc64, h->vws.p, panel, h->tab.as<int>(), h->stream));
+  LRCC_HIP(h, bf16x3_run(h, g, Ls, Xb, Sb, acc64, h->vws.p, need, h->tab.as<int>(), nonherm,
+                         h->stream));
   if (h->timing) {
     LRCC_HIP(h, hipEventRecord(e1, h->stream));
     ++h->tev_used;
@@ -280,7 +283,9 @@ lrcc_status sigma_packed(lrcc_handle h, const Geom& g, const void* L, bool conj_
       LRCC_HIP(h, h->xb.ensure(bf16x3_xb_bytes(gb)));
       LRCC_HIP(h, bf16x3_stage_L(L, dt, gb, conj_t, h->ls.p, h->stream));
       LRCC_HIP(h, bf16x3_pack_x(X, dt, gb, tab, h->xb.p, h->stream));
-      st = bf16x3_apply(h, gb, h->ls.p, h->xb.p, h->sb.p, acc64);
+      LRCC_HIP(h, h->hflag.ensure(16));
+      LRCC_HIP(h, herm_check(L, dt, g.v, g.nchol, h->hflag.as<int>(), h->stream));
+      st = bf16x3_apply(h, gb, h->ls.p, h->xb.p, h->sb.p, acc64, h->hflag.as<int>());
       if (st != LRCC_OK) return st;
     }
     if (acc64)
@@ -387,6 +392,12 @@ lrcc_status lrcc_set_timing(lrcc_handle h, int enable) {
   if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
   h->timing = enable != 0;
   h->tev_used = 0;
+  return LRCC_OK;
+}
+
+lrcc_status lrcc_set_workspace_limit(lrcc_handle h, size_t bytes) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  h->panel_cap = bytes;
   return LRCC_OK;
 }
 

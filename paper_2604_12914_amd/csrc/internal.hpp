@@ -157,17 +157,22 @@ lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, c
 int bf16x3_chunk();
 size_t bf16x3_ls_bytes(const Geom& g);
 size_t bf16x3_xb_bytes(const Geom& g);
-size_t bf16x3_panel_bytes(const Geom& g, int panel_ab);
+// Panel rows [ab0, ab0 + n): upper tiles, and bytes with their mirrors.
+long bf16x3_panel_tiles(const Geom& g, int ab0, int n);
+size_t bf16x3_panel_bytes(const Geom& g, int ab0, int n);
 hipError_t bf16x3_stage_L(const void* L, lrcc_dtype dt, const Geom& g, bool conj_t, void* Ls,
                           hipStream_t st);
 hipError_t bf16x3_pack_x(const void* X, lrcc_dtype dt, const Geom& g, const int* tab, void* Xb,
                          hipStream_t st);
 hipError_t bf16x3_split_x(const double* x, const Geom& g, void* Xb, hipStream_t st);
+// Panels of at most `cap` bytes (at least one row each) in Vws; Sb zeroed by
+// the caller; *nonherm (device) as for ppl_launch.
 hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* Xb, void* Sb,
-                      bool acc64, void* Vws, int panel_ab, const int* tab, hipStream_t st);
+                      bool acc64, void* Vws, size_t cap, const int* tab, const int* nonherm,
+                      hipStream_t st);
 // Run the bf16x3 ladder with the handle's panel workspace (sized here).
 lrcc_status bf16x3_apply(lrcc_handle h, const Geom& g, const void* Ls, const void* Xb, void* Sb,
-                         bool acc64);
+                         bool acc64, const int* nonherm);
 
 // dL = gradient of sigma with respect to L (ppl_grad.hip); packed X, G.
 lrcc_status grad_L(lrcc_handle h, const Geom& g, const void* L, const void* X, const void* G,

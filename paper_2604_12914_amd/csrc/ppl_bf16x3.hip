@@ -6,16 +6,23 @@
 // cores (16x16x32 MFMA) with FP32 accumulation.  Complex products use the
 // 4M form, so one complex multiply-accumulate costs 12 bf16 MFMA products.
 //
-// The ladder is evaluated in panels of virtual block pairs AB:
-//   k_vbuild   one workgroup per tile (AB, CD): W1 = sum_P L_AC (x) L_BD and
-//              W2 = sum_P L_AD (x) L_BC on the matrix cores, antisymmetrised
-//              in LDS to V = 2 <ab||cd>, split to hi/lo and written to the
-//              panel workspace (32 KB per tile);
-//   k_contract sigma[m, AB] = sum_CD X[m, CD] V[AB, CD]^T, a bf16x3 GEMM in
-//              which each workgroup owns its output tile (128 rows x 64
-//              slots) and loops over all CD: no atomics, every sigma entry
-//              written once.
-// The integral panel is transient: at most one panel of AB rows exists.
+// The ladder is evaluated in panels of consecutive block pairs AB, each
+// holding the tiles (AB, CD) with CD >= AB (the upper triangle of the block-
+// pair matrix) in both orientations:
+//   k_vbuild   one workgroup per upper tile (AB, CD): W1 = sum_P L_AC (x) L_BD
+//              and W2 = sum_P L_AD (x) L_BC on the matrix cores,
+//              antisymmetrised in LDS to V = 2 <ab||cd>, split to hi/lo and
+//              written to the panel (32 KB per tile).  The mirror tile
+//              V(CD, AB) goes beside it: for Hermitian L^P it is the conjugate
+//              transpose of the tile just built (one build per pair), otherwise
+//              a second wave of workgroups builds it (a flag set on the device
+//              by the staging pass decides, so no host round trip);
+//   k_contract sigma[m, Q] += sum_{CD >= Q} X[m, CD] V(Q, CD)^T
+//                           + sum_{AB < Q, AB in panel} X[m, AB] V(Q, AB)^T,
+//              a bf16x3 GEMM in which each workgroup owns its output tile
+//              (128 rows x 64 slots of block pair Q) for the whole panel: no
+//              atomics.  With one panel every workgroup runs over nbp tiles.
+// The integral panel is transient: at most one panel exists.
 // The reason for the split: the fused kernel's atomic accumulation of sigma
 // across CD tiles runs at the device's atomic throughput, which caps the fast
 // bf16 arithmetic; a panel costs one extra write and read of V per apply.
@@ -137,15 +144,32 @@ __global__ void k_split_x16(long plane, const double* __restrict__ x, __bf16* __
 // ---------------------------------------------------------------------------
 // V panel build.  Waves 0,1 build W1 rows (a,c) 0-31 / 32-63 x all (b,d);
 // waves 2,3 build W2 rows (a,d) likewise x all (b,c).
+// Tile index, within the panel that starts at block pair ab0, of the upper
+// tile (ab0 + abl, cd), cd >= ab0 + abl: rows of the triangle one after another.
+__device__ __forceinline__ long panel_tile(int nbp, int ab0, int abl, int cd) {
+  return (long)abl * nbp - (long)abl * ab0 - (long)abl * (abl - 1) / 2 + (cd - ab0 - abl);
+}
+
+// Workgroup w < ptiles: upper tile order[w]; w >= ptiles: its mirror when L
+// is not Hermitian (otherwise, or on the diagonal, nothing to do).
 __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
                                                   const int* __restrict__ tab,
-                                                  const int* __restrict__ order, int nbv, int nbp,
-                                                  int ncp, int v, int ab0,
-                                                  __bf16* __restrict__ Vws) {
+                                                  const int* __restrict__ order,
+                                                  const int* __restrict__ nonherm, int nbv,
+                                                  int nbp, int ncp, int v, int ab0, long ptiles,
+                                                  __bf16* __restrict__ Vdir,
+                                                  __bf16* __restrict__ Vmir) {
   __shared__ __attribute__((aligned(16))) __bf16 lds[4 * CHUNKP];  // 80 KB
-  const int tile = order[blockIdx.x];
-  const int abl = tile / nbp, cd = tile - abl * nbp;
-  const int pAB = tab[ab0 + abl], pCD = tab[cd];
+  const bool nh = *nonherm != 0;
+  const bool second = blockIdx.x >= ptiles;
+  if (second && !nh) return;
+  const int tile = order[second ? blockIdx.x - ptiles : blockIdx.x];
+  const int abl = tile / nbp, cdu = tile - abl * nbp, abu = ab0 + abl;
+  if (second && abu == cdu) return;
+  const long t = panel_tile(nbp, ab0, abl, cdu);
+  // built pair (ab, cd): the upper tile, or its mirror (cdu, abu)
+  const int ab = second ? cdu : abu, cd = second ? abu : cdu;
+  const int pAB = tab[ab], pCD = tab[cd];
   const int A = pAB >> 16, B = pAB & 0xffff, C = pCD >> 16, D = pCD & 0xffff;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -218,9 +242,11 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
   }
   __syncthreads();
 
-  // antisymmetrise into V32[plane][ab][cd] (f32, 32 KB) in the chunk space
+  // antisymmetrise into V32[plane][ab][cd] (f32, rows padded to VR) in the
+  // chunk space
+  constexpr int VR = NS + 1;
   float* Vr = reinterpret_cast<float*>(lds);
-  float* Vi = Vr + NS * NS;
+  float* Vi = Vr + NS * VR;
   if (wsel == 0) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -229,7 +255,7 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int ii = 16 * (rb0 + i) + out_row(lk, r), jj = 16 * j + li;  // (a,c), (b,d)
-          const int idx = ((ii >> 3) * TB + (jj >> 3)) * NS + (ii & 7) * TB + (jj & 7);
+          const int idx = ((ii >> 3) * TB + (jj >> 3)) * VR + (ii & 7) * TB + (jj & 7);
           Vr[idx] = 2.f * wr[i][j][r];
           Vi[idx] = 2.f * wi[i][j][r];
         }
@@ -244,7 +270,7 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
         for (int r = 0; r < 4; ++r) {
           const int ii = 16 * (rb0 + i) + out_row(lk, r), jj = 16 * j + li;  // (a,d), (b,c)
           const int al = ii >> 3, dl = ii & 7, bl = jj >> 3, cl = jj & 7;
-          const int idx = (al * TB + bl) * NS + cl * TB + dl;
+          const int idx = (al * TB + bl) * VR + cl * TB + dl;
           const bool live = (A < B || al < bl) && (B * TB + bl < v) && (C < D || cl < dl) &&
                             (D * TB + dl < v);
           Vr[idx] = live ? Vr[idx] - 2.f * wr[i][j][r] : 0.f;
@@ -252,38 +278,61 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
         }
   }
   __syncthreads();
-  // split and write the tile: Vws[abl][cd][plane][ab][cd_slot]
-  __bf16* dst = Vws + ((size_t)abl * nbp + cd) * VT;
-  for (int w = threadIdx.x; w < NS * (NS / 8); w += WG) {
-    const int ab = w >> 3, q = (w & 7) * 8;
-    bf8 rh, rl, ih, il;
+  // split and write the tile as [plane][row slot][column slot]: the built
+  // pair's V (rows ab) to the upper slot t, or, for a mirror workgroup, to
+  // the mirror slot; for Hermitian L the conjugate transpose goes to the
+  // mirror slot as well (V(cd, ab) = V(ab, cd)^H)
+  auto store = [&](__bf16* dst, bool ct) {
+    for (int w = threadIdx.x; w < NS * (NS / 8); w += WG) {
+      const int row = w >> 3, q = (w & 7) * 8;
+      bf8 rh, rl, ih, il;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      __bf16 h, l;
-      split(Vr[ab * NS + q + t], h, l);
-      rh[t] = h;
-      rl[t] = l;
-      split(Vi[ab * NS + q + t], h, l);
-      ih[t] = h;
-      il[t] = l;
+      for (int e = 0; e < 8; ++e) {
+        const int idx = ct ? (q + e) * VR + row : row * VR + q + e;
+        __bf16 h, l;
+        split(Vr[idx], h, l);
+        rh[e] = h;
+        rl[e] = l;
+        split(ct ? -Vi[idx] : Vi[idx], h, l);
+        ih[e] = h;
+        il[e] = l;
+      }
+      *reinterpret_cast<bf8*>(dst + 0 * NS * NS + row * NS + q) = rh;
+      *reinterpret_cast<bf8*>(dst + 1 * NS * NS + row * NS + q) = rl;
+      *reinterpret_cast<bf8*>(dst + 2 * NS * NS + row * NS + q) = ih;
+      *reinterpret_cast<bf8*>(dst + 3 * NS * NS + row * NS + q) = il;
     }
-    *reinterpret_cast<bf8*>(dst + 0 * NS * NS + ab * NS + q) = rh;
-    *reinterpret_cast<bf8*>(dst + 1 * NS * NS + ab * NS + q) = rl;
-    *reinterpret_cast<bf8*>(dst + 2 * NS * NS + ab * NS + q) = ih;
-    *reinterpret_cast<bf8*>(dst + 3 * NS * NS + ab * NS + q) = il;
-  }
+  };
+  store((second ? Vmir : Vdir) + t * VT, false);
+  if (!second && !nh && abu != cdu) store(Vmir + t * VT, true);
 }
 
 // ---------------------------------------------------------------------------
-// Contraction of one panel: workgroup (m-block of 128 rows, AB); wave w owns
-// rows 32w .. 32w+31 of the block and all 64 ab slots.
+// Contraction of one panel [ab0, ab1): workgroup (m-block of 128 rows, block
+// pair q >= ab0); wave w owns rows 32w .. 32w+31 of the block and all 64
+// slots of q.  Its tiles: the upper tiles (q, cd), cd >= q, when q is in the
+// panel, then the mirror tiles V(q, ab) of the panel rows ab < q.
 template <typename TA>
 __global__ __launch_bounds__(WG, 1) void k_contract(const __bf16* __restrict__ Xb,
-                                                    const __bf16* __restrict__ Vws, int nbp,
-                                                    int Mp, int nmb, int ab0,
+                                                    const __bf16* __restrict__ Vdir,
+                                                    const __bf16* __restrict__ Vmir, int nbp,
+                                                    int Mp, int nmb, int ab0, int ab1,
                                                     TA* __restrict__ Sb) {
   __shared__ __attribute__((aligned(16))) __bf16 vt[VTP];  // 36 KB
-  const int mb = blockIdx.x % nmb, abl = blockIdx.x / nmb;
+  const int mb = blockIdx.x % nmb, q = ab0 + blockIdx.x / nmb;
+  const int ndir = q < ab1 ? nbp - q : 0;
+  const int nmir = (q < ab1 ? q : ab1) - ab0;
+  const int ntl = ndir + nmir;
+  // tile it of this workgroup and the block pair whose X rows it contracts
+  auto tile_of = [&](int it, int* xblk) -> const __bf16* {
+    if (it < ndir) {
+      *xblk = q + it;
+      return Vdir + panel_tile(nbp, ab0, q - ab0, q + it) * VT;
+    }
+    const int abl = it - ndir;
+    *xblk = ab0 + abl;
+    return Vmir + panel_tile(nbp, ab0, abl, q) * VT;
+  };
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const size_t plane = (size_t)nbp * Mp * NS;
@@ -320,15 +369,15 @@ __global__ __launch_bounds__(WG, 1) void k_contract(const __bf16* __restrict__ X
   };
   constexpr int VV = VT / 8 / WG;  // 16-byte vectors per thread per V tile (8)
   u4 vp[VV];
-  const __bf16* vsrc = Vws + (size_t)abl * nbp * VT;
-  auto fetch_v = [&](int cd) {
+  auto fetch = [&](int it) {
+    int xblk;
+    const __bf16* src = tile_of(it, &xblk);
 #pragma unroll
-    for (int k = 0; k < VV; ++k)
-      vp[k] = reinterpret_cast<const u4*>(vsrc + (size_t)cd * VT)[k * WG + threadIdx.x];
+    for (int k = 0; k < VV; ++k) vp[k] = reinterpret_cast<const u4*>(src)[k * WG + threadIdx.x];
+    fetch_x(xblk, xn);
   };
-  fetch_v(0);
-  fetch_x(0, xn);
-  for (int cd = 0; cd < nbp; ++cd) {
+  if (ntl > 0) fetch(0);
+  for (int it = 0; it < ntl; ++it) {
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < VV; ++k) {
@@ -343,10 +392,7 @@ __global__ __launch_bounds__(WG, 1) void k_contract(const __bf16* __restrict__ X
 #pragma unroll
         for (int p = 0; p < 4; ++p) xa[i][ks][p] = xn[i][ks][p];
     __syncthreads();
-    if (cd + 1 < nbp) {
-      fetch_v(cd + 1);
-      fetch_x(cd + 1, xn);
-    }
+    if (it + 1 < ntl) fetch(it + 1);
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
       bf8 b[4][4];
@@ -369,8 +415,7 @@ __global__ __launch_bounds__(WG, 1) void k_contract(const __bf16* __restrict__ X
       }
     }
   }
-  // sole writer of sigma[rows, AB]
-  const int ab = ab0 + abl;
+  // sole writer of sigma[rows, q] in this panel: add the panel's share
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     if (!mok[i]) continue;
@@ -378,9 +423,9 @@ __global__ __launch_bounds__(WG, 1) void k_contract(const __bf16* __restrict__ X
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const size_t o = ((size_t)ab * Mp + mrow[i] + out_row(lk, r)) * NS + 16 * j + li;
-        Sb[o] = (TA)sr[i][j][r];
-        Sb[o + plane] = (TA)si[i][j][r];
+        const size_t o = ((size_t)q * Mp + mrow[i] + out_row(lk, r)) * NS + 16 * j + li;
+        Sb[o] += (TA)sr[i][j][r];
+        Sb[o + plane] += (TA)si[i][j][r];
       }
   }
 }
@@ -417,36 +462,49 @@ hipError_t bf16x3_split_x(const double* x, const Geom& g, void* Xb, hipStream_t 
   return hipGetLastError();
 }
 
-size_t bf16x3_panel_bytes(const Geom& g, int panel_ab) {
-  return (size_t)panel_ab * g.nbp * VT * sizeof(__bf16);
+// Upper tiles of the panel rows [ab0, ab0 + n).
+long bf16x3_panel_tiles(const Geom& g, int ab0, int n) {
+  return (long)n * g.nbp - (long)n * ab0 - (long)n * (n - 1) / 2;
 }
 
-// Panels of `panel_ab` AB block pairs: build, then contract.  Sb receives
-// every live sigma entry exactly once (FP64 or FP32 planes).
+size_t bf16x3_panel_bytes(const Geom& g, int ab0, int n) {
+  return (size_t)bf16x3_panel_tiles(g, ab0, n) * 2 * VT * sizeof(__bf16);  // tile + mirror
+}
+
+// Panels of consecutive block pairs, each as many rows as fit in `cap` bytes
+// (at least one): build, then contract.  Sb (zeroed by the caller, FP64 or
+// FP32 planes) receives the panels' shares.  *nonherm (device) selects the
+// mirror tiles' source.
 hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* Xb, void* Sb,
-                      bool acc64, void* Vws, int panel_ab, const int* tab, hipStream_t st) {
+                      bool acc64, void* Vws, size_t cap, const int* tab, const int* nonherm,
+                      hipStream_t st) {
   if (g.nbp == 0 || g.Mp == 0) return hipSuccess;
   const int nmb = (int)((g.Mp + 127) / 128);
-  for (int ab0 = 0; ab0 < g.nbp; ab0 += panel_ab) {
-    const int n = std::min(panel_ab, g.nbp - ab0);
-    const long nb = (long)n * g.nbp;
-    if (nb > 0x7fffffffL) return hipErrorInvalidValue;
+  for (int ab0 = 0, n = 1; ab0 < g.nbp; ab0 += n) {
+    n = 1;
+    while (ab0 + n < g.nbp && bf16x3_panel_bytes(g, ab0, n + 1) <= cap) ++n;
+    const long pt = bf16x3_panel_tiles(g, ab0, n);
+    if (2 * pt > 0x7fffffffL || (long)nmb * (g.nbp - ab0) > 0x7fffffffL)
+      return hipErrorInvalidValue;
     lrcc_status ost;
-    const int* ord = tile_order(h, g, ab0, ab0 + n, false, &ost);
+    const int* ord = tile_order(h, g, ab0, ab0 + n, true, &ost);
     if (ost != LRCC_OK) return hipErrorUnknown;
-    hipLaunchKernelGGL(k_vbuild, dim3((unsigned)nb), dim3(WG), 0, st,
-                       static_cast<const __bf16*>(Ls), tab, ord, g.nbv, g.nbp, g.ncp, g.v, ab0,
-                       static_cast<__bf16*>(Vws));
+    __bf16* Vdir = static_cast<__bf16*>(Vws);
+    __bf16* Vmir = Vdir + (size_t)pt * VT;
+    hipLaunchKernelGGL(k_vbuild, dim3((unsigned)(2 * pt)), dim3(WG), 0, st,
+                       static_cast<const __bf16*>(Ls), tab, ord, nonherm, g.nbv, g.nbp, g.ncp,
+                       g.v, ab0, pt, Vdir, Vmir);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)(nmb * (g.nbp - ab0)));
     if (acc64)
-      hipLaunchKernelGGL(k_contract<double>, dim3((unsigned)(nmb * n)), dim3(WG), 0, st,
-                         static_cast<const __bf16*>(Xb), static_cast<const __bf16*>(Vws), g.nbp,
-                         (int)g.Mp, nmb, ab0, static_cast<double*>(Sb));
+      hipLaunchKernelGGL(k_contract<double>, grid, dim3(WG), 0, st,
+                         static_cast<const __bf16*>(Xb), Vdir, Vmir, g.nbp, (int)g.Mp, nmb, ab0,
+                         ab0 + n, static_cast<double*>(Sb));
     else
-      hipLaunchKernelGGL(k_contract<float>, dim3((unsigned)(nmb * n)), dim3(WG), 0, st,
-                         static_cast<const __bf16*>(Xb), static_cast<const __bf16*>(Vws), g.nbp,
-                         (int)g.Mp, nmb, ab0, static_cast<float*>(Sb));
+      hipLaunchKernelGGL(k_contract<float>, grid, dim3(WG), 0, st,
+                         static_cast<const __bf16*>(Xb), Vdir, Vmir, g.nbp, (int)g.Mp, nmb, ab0,
+                         ab0 + n, static_cast<float*>(Sb));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

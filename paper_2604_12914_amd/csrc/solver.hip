@@ -633,7 +633,7 @@ lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul 
   if (prec == LRCC_BF16X3) {
     g.ncp = (int)roundup(g.nchol, bf16x3_chunk());
     LRCC_HIP(h, bf16x3_split_x(xin, g, S.x32, h->stream));
-    lrcc_status st = bf16x3_apply(h, g, ls, S.x32, S.s, true);
+    lrcc_status st = bf16x3_apply(h, g, ls, S.x32, S.s, true, S.nonherm);
     if (st != LRCC_OK) return st;
     ++S.n_sigma_lp;
     return LRCC_OK;

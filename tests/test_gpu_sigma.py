@@ -97,14 +97,15 @@ def test_fp32_matches_oracle(lrcc, dtype, herm):
     assert rel(got, ref) < 2e-6
 
 
+@pytest.mark.parametrize("herm", [True, False])
 @pytest.mark.parametrize("o,v,nchol,nrhs,dtype", [(5, 44, 100, 3, torch.complex128),
                                                   (4, 24, 64, 1, torch.complex128),
                                                   (3, 37, 7, 2, torch.complex64),
                                                   (6, 96, 200, 2, torch.complex128)])
-def test_bf16x3_matches_oracle(lrcc, o, v, nchol, nrhs, dtype):
-    print(f"bf16x3 parity o={o} v={v} nchol={nchol} nrhs={nrhs}", flush=True)
+def test_bf16x3_matches_oracle(lrcc, o, v, nchol, nrhs, dtype, herm):
+    print(f"bf16x3 parity o={o} v={v} nchol={nchol} nrhs={nrhs} herm={herm}", flush=True)
     rng = np.random.default_rng(200 + v)
-    L = S.make_L(rng, nchol, v, hermitian=False)
+    L = S.make_L(rng, nchol, v, hermitian=herm)
     X = S.make_packed(rng, nrhs, o, v)
     got = run(lrcc, L, X, prec="bf16x3", dtype=dtype)
     ref = ppl.sigma(L, X, o, v)
@@ -114,6 +115,28 @@ def test_bf16x3_matches_oracle(lrcc, o, v, nchol, nrhs, dtype):
     err = rel(got, ref)
     print(f"bf16x3 relative error {err:.2e}", flush=True)
     assert err < 6e-5
+
+
+@pytest.mark.parametrize("herm", [True, False])
+@pytest.mark.parametrize("limit", [1 << 20, 3 << 20])
+def test_bf16x3_several_panels(lrcc, limit, herm):
+    # a workspace limit far below the triangle's 14.8 MB (v = 44: 231 tile
+    # pairs x 64 KB) splits the ladder into panels of one or a few rows; the
+    # result must not depend on the split
+    rng = np.random.default_rng(21)
+    o, v, nchol = 5, 44, 70
+    L = S.make_L(rng, nchol, v, hermitian=herm)
+    X = S.make_packed(rng, 2, o, v)
+    whole = run(lrcc, L, X, prec="bf16x3")
+    lrcc.set_workspace_limit(limit)
+    try:
+        split = run(lrcc, L, X, prec="bf16x3")
+    finally:
+        lrcc.set_workspace_limit(0)
+    ref = ppl.sigma(L, X, o, v)
+    assert rel(split, ref) < 6e-5
+    # the same products, summed in another order per panel: FP32 rounding only
+    assert rel(split, whole) < 1e-6
 
 
 @pytest.mark.parametrize("where", ["off-diagonal", "diagonal imaginary", "last element"])
