@@ -159,7 +159,7 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
                                                   int nbp, int ncp, int v, int ab0, long ptiles,
                                                   __bf16* __restrict__ Vdir,
                                                   __bf16* __restrict__ Vmir) {
-  __shared__ __attribute__((aligned(16))) __bf16 lds[4 * CHUNKP];  // 80 KB
+  __shared__ __attribute__((aligned(16))) __bf16 lds[2 * CHUNKP];  // 40 KB
   const bool nh = *nonherm != 0;
   const bool second = blockIdx.x >= ptiles;
   if (second && !nh) return;
@@ -175,11 +175,12 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
   const int li = lane & 15, lk = lane >> 4;
   const int wsel = wave >> 1, rb0 = (wave & 1) * 2;
   const int nch = ncp / KB;
-  const __bf16* gblk[4] = {Ls + (size_t)(A * nbv + C) * nch * CHUNK,
-                           Ls + (size_t)(B * nbv + D) * nch * CHUNK,
-                           Ls + (size_t)(A * nbv + D) * nch * CHUNK,
-                           Ls + (size_t)(B * nbv + C) * nch * CHUNK};
-  const int qa = wsel ? 2 : 0, qb = wsel ? 3 : 1;
+  // row side (per wave, straight from global memory into registers) and
+  // column side (shared by the two waves of one product, staged in LDS):
+  // W1 = L_AC (x) L_BD for waves 0, 1; W2 = L_AD (x) L_BC for waves 2, 3
+  const __bf16* const grow = Ls + (size_t)(wsel ? A * nbv + D : A * nbv + C) * nch * CHUNK;
+  const __bf16* const gcol[2] = {Ls + (size_t)(B * nbv + D) * nch * CHUNK,
+                                 Ls + (size_t)(B * nbv + C) * nch * CHUNK};
 
   f4 wr[2][4], wi[2][4];
 #pragma unroll
@@ -192,51 +193,56 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
 
   constexpr int V16 = CHUNK / 8;        // 16-byte vectors per block chunk (1024)
   constexpr int KPB = V16 / WG;         // per thread per block (4)
-  u4 pf[4 * KPB];
+  u4 pf[2 * KPB];
+  bf8 an[2][4];                         // next chunk's row-side fragments
   auto fetch = [&](int pc) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const u4* src = reinterpret_cast<const u4*>(gblk[q] + (size_t)pc * CHUNK);
+    for (int q = 0; q < 2; ++q) {
+      const u4* src = reinterpret_cast<const u4*>(gcol[q] + (size_t)pc * CHUNK);
 #pragma unroll
       for (int k = 0; k < KPB; ++k) pf[q * KPB + k] = src[k * WG + threadIdx.x];
     }
+    // A fragment of MFMA block i, plane p: row 16 (rb0 + i) + li, P = 8 lk .. 8 lk + 7
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        an[i][p] = *reinterpret_cast<const bf8*>(grow + (size_t)pc * CHUNK +
+                                                 (p * NS + 16 * (rb0 + i) + li) * KB + 8 * lk);
   };
   fetch(0);
   for (int pc = 0; pc < nch; ++pc) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int k = 0; k < KPB; ++k) {
         // vector e of the chunk: plane-row (e / 4), 8-bf16 part (e % 4)
         const int e = k * WG + threadIdx.x;
         *reinterpret_cast<u4*>(lds + q * CHUNKP + (e >> 2) * KBP + (e & 3) * 8) = pf[q * KPB + k];
       }
-    __syncthreads();
-    if (pc + 1 < nch) fetch(pc + 1);
-    // operands: [plane][row][32 P], lane reads 8 consecutive P at 8*lk
-    const __bf16* la = lds + qa * CHUNKP + 8 * lk;
-    const __bf16* lb = lds + qb * CHUNKP + 8 * lk;
-    bf8 a[2][4], b[4][4];
+    bf8 a[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
+      for (int p = 0; p < 4; ++p) a[i][p] = an[i][p];
+    __syncthreads();
+    if (pc + 1 < nch) fetch(pc + 1);
+    // column operands: [plane][row][32 P], lane reads 8 consecutive P at 8*lk
+    const __bf16* lb = lds + wsel * CHUNKP + 8 * lk;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bf8 b[4];
+#pragma unroll
       for (int p = 0; p < 4; ++p)
-        a[i][p] = *reinterpret_cast<const bf8*>(la + (p * NS + 16 * (rb0 + i) + li) * KBP);
+        b[p] = *reinterpret_cast<const bf8*>(lb + (p * NS + 16 * j + li) * KBP);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-        b[j][p] = *reinterpret_cast<const bf8*>(lb + (p * NS + 16 * j + li) * KBP);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const bf8 nih = neg(a[i][2]), nil = neg(a[i][3]);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        wr[i][j] = mac3(a[i][0], a[i][1], b[j][0], b[j][1], wr[i][j]);  // Ar Br
-        wi[i][j] = mac3(a[i][0], a[i][1], b[j][2], b[j][3], wi[i][j]);  // Ar Bi
-        wr[i][j] = mac3(nih, nil, b[j][2], b[j][3], wr[i][j]);          // -Ai Bi
-        wi[i][j] = mac3(a[i][2], a[i][3], b[j][0], b[j][1], wi[i][j]);  // Ai Br
+      for (int i = 0; i < 2; ++i) {
+        const bf8 nih = neg(a[i][2]), nil = neg(a[i][3]);
+        wr[i][j] = mac3(a[i][0], a[i][1], b[0], b[1], wr[i][j]);  // Ar Br
+        wi[i][j] = mac3(a[i][0], a[i][1], b[2], b[3], wi[i][j]);  // Ar Bi
+        wr[i][j] = mac3(nih, nil, b[2], b[3], wr[i][j]);          // -Ai Bi
+        wi[i][j] = mac3(a[i][2], a[i][3], b[0], b[1], wi[i][j]);  // Ai Br
       }
     }
   }
@@ -312,8 +318,10 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
 // pair q >= ab0); wave w owns rows 32w .. 32w+31 of the block and all 64
 // slots of q.  Its tiles: the upper tiles (q, cd), cd >= q, when q is in the
 // panel, then the mirror tiles V(q, ab) of the panel rows ab < q.
+// Two workgroups per CU: while one waits for its tile's X rows (loaded per
+// tile, straight into registers) the other keeps the matrix cores busy.
 template <typename TA>
-__global__ __launch_bounds__(WG, 1) void k_contract(const __bf16* __restrict__ Xb,
+__global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ Xb,
                                                     const __bf16* __restrict__ Vdir,
                                                     const __bf16* __restrict__ Vmir, int nbp,
                                                     int Mp, int nmb, int ab0, int ab1,
@@ -352,7 +360,7 @@ __global__ __launch_bounds__(WG, 1) void k_contract(const __bf16* __restrict__ X
       si[i][j] = sr[i][j];
     }
   // X operands of one CD: [mblk][k-step][plane], 8 consecutive cd per lane
-  bf8 xa[2][2][4], xn[2][2][4];
+  bf8 xa[2][2][4];
   auto fetch_x = [&](int cd, bf8 (&dst)[2][2][4]) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -369,15 +377,15 @@ __global__ __launch_bounds__(WG, 1) void k_contract(const __bf16* __restrict__ X
   };
   constexpr int VV = VT / 8 / WG;  // 16-byte vectors per thread per V tile (8)
   u4 vp[VV];
+  int xnext = 0;
   auto fetch = [&](int it) {
-    int xblk;
-    const __bf16* src = tile_of(it, &xblk);
+    const __bf16* src = tile_of(it, &xnext);
 #pragma unroll
     for (int k = 0; k < VV; ++k) vp[k] = reinterpret_cast<const u4*>(src)[k * WG + threadIdx.x];
-    fetch_x(xblk, xn);
   };
   if (ntl > 0) fetch(0);
   for (int it = 0; it < ntl; ++it) {
+    const int xcur = xnext;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < VV; ++k) {
@@ -385,32 +393,30 @@ __global__ __launch_bounds__(WG, 1) void k_contract(const __bf16* __restrict__ X
       const int e = k * WG + threadIdx.x;
       *reinterpret_cast<u4*>(vt + (e >> 3) * NSP + (e & 7) * 8) = vp[k];
     }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int p = 0; p < 4; ++p) xa[i][ks][p] = xn[i][ks][p];
     __syncthreads();
     if (it + 1 < ntl) fetch(it + 1);
+    fetch_x(xcur, xa);
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
-      bf8 b[4][4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-          b[j][p] = *reinterpret_cast<const bf8*>(vt + (p * NS + 16 * j + li) * NSP +
-                                                  32 * ks + 8 * lk);
+      bf8 nx[2][2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const bf8 nih = neg(xa[i][ks][2]), nil = neg(xa[i][ks][3]);
+        nx[i][0] = neg(xa[i][ks][2]);
+        nx[i][1] = neg(xa[i][ks][3]);
+      }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          sr[i][j] = mac3(xa[i][ks][0], xa[i][ks][1], b[j][0], b[j][1], sr[i][j]);
-          si[i][j] = mac3(xa[i][ks][0], xa[i][ks][1], b[j][2], b[j][3], si[i][j]);
-          sr[i][j] = mac3(nih, nil, b[j][2], b[j][3], sr[i][j]);
-          si[i][j] = mac3(xa[i][ks][2], xa[i][ks][3], b[j][0], b[j][1], si[i][j]);
+      for (int j = 0; j < 4; ++j) {
+        bf8 b[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          b[p] = *reinterpret_cast<const bf8*>(vt + (p * NS + 16 * j + li) * NSP + 32 * ks +
+                                               8 * lk);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          sr[i][j] = mac3(xa[i][ks][0], xa[i][ks][1], b[0], b[1], sr[i][j]);
+          si[i][j] = mac3(xa[i][ks][0], xa[i][ks][1], b[2], b[3], si[i][j]);
+          sr[i][j] = mac3(nx[i][0], nx[i][1], b[2], b[3], sr[i][j]);
+          si[i][j] = mac3(xa[i][ks][2], xa[i][ks][3], b[0], b[1], si[i][j]);
         }
       }
     }
