@@ -58,6 +58,29 @@ def issued_flops(o, v, nchol, nrhs, prec="fp64", cmul="4m"):
     return build + 8.0 * 4096 * mp * nbp * nbp
 
 
+TRAFFIC_PROFILE = "profiles/k_ppl_4m_fp64_o16_v160_nchol640_hbm_traffic.md"
+TRAFFIC_SOURCES = ("paper_2604_12914_amd/csrc/ppl_mfma.hip", "paper_2604_12914_amd/csrc/internal.hpp")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused FP64 kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary, or None when the kernel sources
+    have changed since the counters were taken (their hash differs)."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, TRAFFIC_PROFILE)).read()
+        h = hashlib.sha256()
+        for f in TRAFFIC_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("traffic_bytes_per_launch: ", "source_sha256: ")))
+    if fields.get("source_sha256", "").strip() != h.hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,7 +170,10 @@ def main():
         },
         "roofline": {
             "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"],
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4),
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
+                            "null when the kernel changed since the counters were taken)",
             "kernel": "k_ppl_4m<double> (fused build + antisymmetrise + contract)",
             "kernel_ms_avg": round(k_avg, 4), "launches": nlaunch,
             "issued_tflops": round(issued, 3), "issued_frac": round(issued / PEAK["fp64"], 4),
