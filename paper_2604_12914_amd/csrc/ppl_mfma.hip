@@ -235,17 +235,70 @@ __device__ __forceinline__ void build_v_4m(const T* __restrict__ Ls, const int* 
   __syncthreads();
 }
 
+// Contraction of 16 rows m0 .. m0 + 15 (this lane holds X[m0 + li][16 lk + s]
+// in xr[s], xi[s]) with NN column blocks n0 .. n0 + NN - 1 of the LDS tile V,
+// added to sigma with device-scope atomics (see contract_v for TR).
+template <typename T, typename TA, bool TR, int NN>
+__device__ __forceinline__ void contract_rows(const T* Vr, const T* Vi, const T (&xr)[16],
+                                              const T (&xi)[16], int n0, int m0, TA* sr_g,
+                                              TA* si_g) {
+  typedef typename Acc<T>::t acc_t;
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  acc_t sr[NN], si[NN];
+#pragma unroll
+  for (int n = 0; n < NN; ++n) {
+    sr[n] = acc_t{0, 0, 0, 0};
+    si[n] = sr[n];
+  }
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int k = 16 * lk + s;  // contracted slot fed by this lane at step s
+    T vr[NN], vi[NN];
+#pragma unroll
+    for (int n = 0; n < NN; ++n) {
+      const int c = 16 * (n0 + n) + li;
+      const int a = TR ? c * VS + k : k * VS + c;
+      vr[n] = Vr[a];
+      vi[n] = Vi[a];
+    }
+    // (xr + i xi)(vr + i vi), or (xr + i xi)(vr - i vi) for the mirror
+    const T xrs = xr[s], xis = xi[s];
+    const T s_r = TR ? xis : -xis, s_i = TR ? -xrs : xrs;
+#pragma unroll
+    for (int n = 0; n < NN; ++n) {
+      sr[n] = mfma(xrs, vr[n], sr[n]);
+      si[n] = mfma(s_i, vi[n], si[n]);
+    }
+#pragma unroll
+    for (int n = 0; n < NN; ++n) {
+      sr[n] = mfma(s_r, vi[n], sr[n]);
+      si[n] = mfma(xis, vr[n], si[n]);
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < NN; ++n) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const size_t o = (size_t)(m0 + out_row<T>(lk, r)) * NS + 16 * (n0 + n) + li;
+      atomic_add(sr_g + o, (TA)sr[n][r]);
+      atomic_add(si_g + o, (TA)si[n][r]);
+    }
+  }
+}
+
 // Contraction of the LDS tile V of block pairs (x, y) with the rows of X:
 //   TR = false:  sigma[m, x slots] += sum_k X[m, y slot k] V[x, k]
 //   TR = true:   sigma[m, y slots] += sum_k X[m, x slot k] conj V[k, y]
 // (the second is the mirror tile (y, x) of a Hermitian operator).  src / dst
 // are the block pairs whose X rows are read and whose sigma rows receive the
-// 64-slot partial sums (device-scope atomics).  V is only read.
+// 64-slot partial sums (device-scope atomics).  V is only read.  Chunks of 16
+// rows go to the waves in turn; the last Mp/16 mod 4 chunks are shared by all
+// four waves, one block of 16 columns each, so no wave does an extra chunk.
 template <typename T, typename TA, int OCC, bool TR>
 __device__ __forceinline__ void contract_v(const T* lds, const T* __restrict__ Xb,
                                            TA* __restrict__ Sb, int nbp, int Mp, int src,
                                            int dst) {
-  typedef typename Acc<T>::t acc_t;
   typedef typename Vec16<T>::t vec_t;
   constexpr int VN = Vec16<T>::n;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -257,6 +310,7 @@ __device__ __forceinline__ void contract_v(const T* lds, const T* __restrict__ X
   const T* xi_g = xr_g + plane;
   TA* sr_g = Sb + (size_t)dst * Mp * NS;
   TA* si_g = sr_g + plane;
+  const int nch = Mp / 16, nfull = nch & ~3;
   // lane (row li, group lk) holds X[m0+li][16 lk .. 16 lk + 15]; the rows of
   // the next m-chunk are fetched while this one is contracted
   constexpr int NX = 16 / VN;
@@ -270,13 +324,7 @@ __device__ __forceinline__ void contract_v(const T* lds, const T* __restrict__ X
       xpi[k] = pi[k];
     }
   };
-  // with one workgroup per CU the next rows are prefetched; with two, the
-  // other workgroup covers the load latency and the registers are scarce
-  if (OCC == 1 && wave < Mp / 16) fetch_x(wave * 16);
-  for (int mc = wave; mc < Mp / 16; mc += 4) {
-    const int m0 = mc * 16;
-    if (OCC > 1) fetch_x(m0);
-    T xr[16], xi[16];
+  auto unpack = [&](T (&xr)[16], T (&xi)[16]) {
 #pragma unroll
     for (int k = 0; k < NX; ++k) {
 #pragma unroll
@@ -285,46 +333,24 @@ __device__ __forceinline__ void contract_v(const T* lds, const T* __restrict__ X
         xi[k * VN + t] = xpi[k][t];
       }
     }
-    if (OCC == 1 && mc + 4 < Mp / 16) fetch_x(m0 + 64);
-    acc_t sr[4], si[4];
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      sr[n] = acc_t{0, 0, 0, 0};
-      si[n] = sr[n];
-    }
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int k = 16 * lk + s;  // contracted slot fed by this lane at step s
-      T vr[4], vi[4];
-#pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        const int a = TR ? (16 * n + li) * VS + k : k * VS + 16 * n + li;
-        vr[n] = Vr[a];
-        vi[n] = Vi[a];
-      }
-      // (xr + i xi)(vr + i vi), or (xr + i xi)(vr - i vi) for the mirror
-      const T xrs = xr[s], xis = xi[s];
-      const T s_r = TR ? xis : -xis, s_i = TR ? -xrs : xrs;
-#pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        sr[n] = mfma(xrs, vr[n], sr[n]);
-        si[n] = mfma(s_i, vi[n], si[n]);
-      }
-#pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        sr[n] = mfma(s_r, vi[n], sr[n]);
-        si[n] = mfma(xis, vr[n], si[n]);
-      }
-    }
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const size_t o = (size_t)(m0 + out_row<T>(lk, r)) * NS + 16 * n + li;
-        atomic_add(sr_g + o, (TA)sr[n][r]);
-        atomic_add(si_g + o, (TA)si[n][r]);
-      }
-    }
+  };
+  // with one workgroup per CU the next rows are prefetched; with two, the
+  // other workgroup covers the load latency and the registers are scarce
+  if (OCC == 1 && wave < nfull) fetch_x(wave * 16);
+  for (int mc = wave; mc < nfull; mc += 4) {
+    const int m0 = mc * 16;
+    if (OCC > 1) fetch_x(m0);
+    T xr[16], xi[16];
+    unpack(xr, xi);
+    if (OCC == 1 && mc + 4 < nfull) fetch_x(m0 + 64);
+    contract_rows<T, TA, TR, 4>(Vr, Vi, xr, xi, 0, m0, sr_g, si_g);
+  }
+  for (int mc = nfull; mc < nch; ++mc) {
+    const int m0 = mc * 16;
+    fetch_x(m0);
+    T xr[16], xi[16];
+    unpack(xr, xi);
+    contract_rows<T, TA, TR, 1>(Vr, Vi, xr, xi, wave, m0, sr_g, si_g);
   }
 }
 
@@ -598,8 +624,10 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
   // variant: 1 = one WG/CU with register prefetch, 2 = two WG/CU (FP32),
   // 3 = one WG/CU with direct-to-LDS chunk ring, 4 = two WG/CU with direct loads
   if (occ == 0) {
+    // untuned default: direct-to-LDS chunk ring for FP64 (measured about 1.5 %
+    // ahead of register prefetch), register prefetch otherwise
     const char* e = getenv("LRCC_VARIANT");
-    occ = e ? atoi(e) : 1;
+    occ = e ? atoi(e) : (prec == LRCC_FP64 && cmul == LRCC_CMUL_4M ? 3 : 1);
   }
   if (!ppl_has_variant(prec, cmul, occ)) occ = 1;
   if (prec == LRCC_FP64) {
