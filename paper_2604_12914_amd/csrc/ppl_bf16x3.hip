@@ -316,30 +316,60 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
 // ---------------------------------------------------------------------------
 // Contraction of one panel [ab0, ab1): workgroup (m-block of 128 rows, block
 // pair q >= ab0); wave w owns rows 32w .. 32w+31 of the block and all 64
-// slots of q.  Its tiles: the upper tiles (q, cd), cd >= q, when q is in the
-// panel, then the mirror tiles V(q, ab) of the panel rows ab < q.
+// slots of q.  Its tiles, in ascending order of the contracted block pair b:
+// the mirror tiles V(q, b) of the panel rows b < q, then the upper tiles
+// V(q, b), b >= q, when q is in the panel.  With one panel every workgroup
+// visits b = 0, 1, ..., nbp - 1 in the same order, so workgroups of
+// different q read the same X rows at about the same time.
+//
+// Workgroup w runs on XCD w mod nx (round-robin dispatch).  Each XCD takes a
+// contiguous share of the logical work list, which is ordered in groups of
+// QG block pairs x all m-blocks: the workgroups resident on one XCD then
+// share the V tiles of a few q (across m-blocks) and the X rows of a few
+// m-blocks (across q) in its L2.
+constexpr int QG = 8;
+
+// The list is split into nsplit parts (outermost): part p of a workgroup's
+// tiles goes to a workgroup of its own, so that short grids still fill whole
+// rounds of resident workgroups; parts add their sums atomically.
+__device__ __forceinline__ void contract_item(int w, int total, int nx, int nmb, int nq,
+                                              int* q, int* mb, int* part) {
+  const int x = w % nx, j = w / nx;
+  const int share = total / nx, rem = total % nx;
+  int L = x * share + (x < rem ? x : rem) + j;
+  *part = L / (nmb * nq);
+  L -= *part * nmb * nq;
+  const int group = L / (QG * nmb), r = L - group * QG * nmb;
+  const int gq = min(QG, nq - group * QG);
+  *mb = r / gq;
+  *q = group * QG + r % gq;
+}
 // Two workgroups per CU: while one waits for its tile's X rows (loaded per
 // tile, straight into registers) the other keeps the matrix cores busy.
 template <typename TA>
 __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ Xb,
                                                     const __bf16* __restrict__ Vdir,
                                                     const __bf16* __restrict__ Vmir, int nbp,
-                                                    int Mp, int nmb, int ab0, int ab1,
+                                                    int Mp, int nmb, int ab0, int ab1, int nx,
                                                     TA* __restrict__ Sb) {
   __shared__ __attribute__((aligned(16))) __bf16 vt[VTP];  // 36 KB
-  const int mb = blockIdx.x % nmb, q = ab0 + blockIdx.x / nmb;
+  int mb, ql, part;
+  contract_item(blockIdx.x, (int)gridDim.x, nx, nmb, nbp - ab0, &ql, &mb, &part);
+  const int nsplit = (int)gridDim.x / (nmb * (nbp - ab0));
+  const int q = ab0 + ql;
   const int ndir = q < ab1 ? nbp - q : 0;
   const int nmir = (q < ab1 ? q : ab1) - ab0;
-  const int ntl = ndir + nmir;
+  const int it0 = (int)((long)(ndir + nmir) * part / nsplit);
+  const int ntl = (int)((long)(ndir + nmir) * (part + 1) / nsplit);
   // tile it of this workgroup and the block pair whose X rows it contracts
   auto tile_of = [&](int it, int* xblk) -> const __bf16* {
-    if (it < ndir) {
-      *xblk = q + it;
-      return Vdir + panel_tile(nbp, ab0, q - ab0, q + it) * VT;
+    if (it < nmir) {
+      *xblk = ab0 + it;
+      return Vmir + panel_tile(nbp, ab0, it, q) * VT;
     }
-    const int abl = it - ndir;
-    *xblk = ab0 + abl;
-    return Vmir + panel_tile(nbp, ab0, abl, q) * VT;
+    const int d = it - nmir;
+    *xblk = q + d;
+    return Vdir + panel_tile(nbp, ab0, q - ab0, q + d) * VT;
   };
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -383,8 +413,8 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
 #pragma unroll
     for (int k = 0; k < VV; ++k) vp[k] = reinterpret_cast<const u4*>(src)[k * WG + threadIdx.x];
   };
-  if (ntl > 0) fetch(0);
-  for (int it = 0; it < ntl; ++it) {
+  if (ntl > it0) fetch(it0);
+  for (int it = it0; it < ntl; ++it) {
     const int xcur = xnext;
     __syncthreads();
 #pragma unroll
@@ -421,7 +451,8 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
       }
     }
   }
-  // sole writer of sigma[rows, q] in this panel: add the panel's share
+  // add this part's share of sigma[rows, q]: a plain update when the
+  // workgroup is the only writer in this launch, atomic across parts
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     if (!mok[i]) continue;
@@ -430,8 +461,13 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const size_t o = ((size_t)q * Mp + mrow[i] + out_row(lk, r)) * NS + 16 * j + li;
-        Sb[o] += (TA)sr[i][j][r];
-        Sb[o + plane] += (TA)si[i][j][r];
+        if (nsplit == 1) {
+          Sb[o] += (TA)sr[i][j][r];
+          Sb[o + plane] += (TA)si[i][j][r];
+        } else {
+          unsafeAtomicAdd(Sb + o, (TA)sr[i][j][r]);
+          unsafeAtomicAdd(Sb + o + plane, (TA)si[i][j][r]);
+        }
       }
   }
 }
@@ -502,15 +538,31 @@ hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* 
                        g.v, ab0, pt, Vdir, Vmir);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 grid((unsigned)(nmb * (g.nbp - ab0)));
+    // parts per contraction list: the fewest that fill whole rounds of the
+    // resident workgroups (two per CU) to within 5 %, at most 8
+    const long items = (long)nmb * (g.nbp - ab0), slots = 2L * std::max(1, h->ncu);
+    int nsplit = 1;
+    double best = 0;
+    for (int sp = 1; sp <= 8 && (long)sp * 4 <= g.nbp; ++sp) {
+      const long tot = sp * items, rounds = (tot + slots - 1) / slots;
+      const double eff = (double)tot / (double)(rounds * slots);
+      if (eff > best + 1e-9) {
+        best = eff;
+        nsplit = sp;
+      }
+      if (eff >= 0.95) break;
+    }
+    if ((long)nsplit * items > 0x7fffffffL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(nsplit * items));
+    const int nx = std::max(1, h->ncu / 32);  // XCDs
     if (acc64)
       hipLaunchKernelGGL(k_contract<double>, grid, dim3(WG), 0, st,
                          static_cast<const __bf16*>(Xb), Vdir, Vmir, g.nbp, (int)g.Mp, nmb, ab0,
-                         ab0 + n, static_cast<double*>(Sb));
+                         ab0 + n, nx, static_cast<double*>(Sb));
     else
       hipLaunchKernelGGL(k_contract<float>, grid, dim3(WG), 0, st,
                          static_cast<const __bf16*>(Xb), Vdir, Vmir, g.nbp, (int)g.Mp, nmb, ab0,
-                         ab0 + n, static_cast<float*>(Sb));
+                         ab0 + n, nx, static_cast<float*>(Sb));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
