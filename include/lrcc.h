@@ -113,7 +113,9 @@ typedef struct {
                         (the ladder is linear); 1 = FP64 ladder every sweep   */
   lrcc_prec anchor_prec; /* reduced precision: arithmetic of that full-iterate
                         ladder: FP64 (default) or FP32 (then the residual is
-                        exact to FP32 ladder accuracy, about 1e-7 relative)   */
+                        exact to FP32 ladder accuracy, about 1e-6 relative).
+                        Inside the solve an FP32 ladder sums its tile partials
+                        in FP32 too                                          */
 } lrcc_solve_opts;
 
 typedef struct {

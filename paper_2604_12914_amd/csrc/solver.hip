@@ -468,6 +468,12 @@ __global__ void k_to_f32(long n, const double* __restrict__ a, float* __restrict
     b[i] = (float)a[i];
 }
 
+// The FP32 ladder's float sums back to the FP64 planes.
+__global__ void k_to_f64(long n, const float* __restrict__ a, double* __restrict__ b) {
+  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB)
+    b[i] = (double)a[i];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -476,7 +482,7 @@ __global__ void k_to_f32(long n, const double* __restrict__ a, float* __restrict
 namespace {
 
 // Workspace slots of one solve: 0 xi, 1 x, 2 s, 3 ring X~, 4 ring e, 5 b,
-// 6 x2 (refined iterate), 7 rk, 8 small device state, 9 partials, 10 x32,
+// 6 x2 (refined iterate), 7 rk, 8 small device state, 9 partials, 10 x32 and s32,
 // 11 sx (ladder of the refined iterate), 12 staged FP64 vectors, 13 block-pair
 // table, 14 tile order (the last three only for batched instances).
 constexpr int NBUF = 15;
@@ -492,6 +498,7 @@ struct Solver {
   double *xi = nullptr, *x = nullptr, *s = nullptr, *xt = nullptr, *ev = nullptr, *b = nullptr;
   double *omega = nullptr, *eps = nullptr, *x2 = nullptr, *rk = nullptr, *sx = nullptr;
   float* x32 = nullptr;
+  float* s32 = nullptr;  // float sums of the FP32 ladder
   int *otab = nullptr, *active = nullptr, *itp = nullptr;
   int* nonherm = nullptr;  // Hermiticity flag of L (herm_check)
   unsigned* valid = nullptr;
@@ -529,7 +536,7 @@ lrcc_status setup(Solver& S, lrcc_handle h, int o, int v, int nchol, const doubl
   S.nchunk = (int)std::max<long>(1, std::min<long>(256, (S.d.per_rhs + 4 * RB - 1) / (4 * RB)));
   const size_t vb = (size_t)2 * S.d.plane * 8;
   size_t need[12] = {vb, vb, vb, vb * mdim, vb * mdim, vb, ir ? vb : 16, ir ? vb : 16, 0, 0,
-                     ir ? vb / 2 : 16,  // f32 planes, or 4 bf16 planes: same bytes
+                     ir ? vb : 16,  // x32 (f32 planes, or 4 bf16 planes: same bytes), s32
                      ir ? vb : 16};
   const size_t np_alpha = (size_t)nomega * ncomp * ncomp;
   const size_t npart = std::max((size_t)S.n * (mdim + 1), np_alpha) * S.nchunk;
@@ -566,6 +573,7 @@ lrcc_status setup(Solver& S, lrcc_handle h, int o, int v, int nchol, const doubl
   S.nonherm = reinterpret_cast<int*>(sm + off_nh);
   S.part = S.buf[9]->as<double2>();
   S.x32 = S.buf[10]->as<float>();
+  S.s32 = ir ? S.x32 + S.d.plane * 2 : nullptr;
   S.sx = S.buf[11]->as<double>();
 
   std::vector<double> om(S.n);
@@ -638,18 +646,25 @@ lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul 
     ++S.n_sigma_lp;
     return LRCC_OK;
   }
-  const void* xb = xin;
-  if (prec != LRCC_FP64) {
-    const long n = 2 * S.d.plane;
-    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)std::min<long>((n + RB - 1) / RB, 8192)),
-                       dim3(RB), 0, h->stream, n, xin, S.x32);
-    LRCC_HIP(h, hipGetLastError());
-    xb = S.x32;
+  if (prec == LRCC_FP64) {
+    lrcc_status st = ppl_run(h, prec, cmul, true, g, ls, xin, S.s, S.nonherm);
+    if (st != LRCC_OK) return st;
+    ++S.n_sigma64;
+    return LRCC_OK;
   }
-  lrcc_status st = ppl_run(h, prec, cmul, true, g, ls, xb, S.s, S.nonherm);
+  // FP32: float operands and float sums across tiles (the atomic additions
+  // of the partial sums cost half the memory traffic of FP64 ones), widened
+  // to the FP64 planes afterwards
+  const long n = 2 * S.d.plane;
+  const dim3 grid((unsigned)std::min<long>((n + RB - 1) / RB, 8192));
+  hipLaunchKernelGGL(k_to_f32, grid, dim3(RB), 0, h->stream, n, xin, S.x32);
+  LRCC_HIP(h, hipGetLastError());
+  LRCC_HIP(h, fill_zero(S.s32, (size_t)n * 4, h->stream));
+  lrcc_status st = ppl_run(h, prec, cmul, false, g, ls, S.x32, S.s32, S.nonherm);
   if (st != LRCC_OK) return st;
-  if (prec == LRCC_FP64) ++S.n_sigma64;
-  else ++S.n_sigma_lp;
+  hipLaunchKernelGGL(k_to_f64, grid, dim3(RB), 0, h->stream, n, S.s32, S.s);
+  LRCC_HIP(h, hipGetLastError());
+  ++S.n_sigma_lp;
   return LRCC_OK;
 }
 
