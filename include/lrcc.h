@@ -188,7 +188,8 @@ typedef struct {
   int occupancy;   /* launch variant of the fused 4M kernel: 1 = one workgroup
                       per CU, chunks through registers; 2 = two per CU (FP32);
                       3 = one per CU, chunks loaded straight into a two-chunk
-                      LDS ring; 4 = two per CU with direct LDS loads           */
+                      LDS ring; 4 = two per CU with direct LDS loads; 5 = as 3
+                      with eight waves per workgroup (two per SIMD)            */
   double ms;       /* ladder kernel time of the chosen variant                 */
   int candidates;  /* variants timed (0 when read from the cache)              */
 } lrcc_tune_result;

@@ -70,7 +70,7 @@ struct lrcc_handle_s {
   lrcc::Buf order;        // tile order (XCD-aware super-tiles), see tile_order()
   long order_key[6] = {-1, -1, -1, -1, -1, -1};
   int order_s = 0;        // super-tile width in virtual blocks (0 = default)
-  int occ[3] = {0, 0, 0}; // 4M launch variant per precision (1-4, 0 = default)
+  int occ[3] = {0, 0, 0}; // 4M launch variant per precision (1-5, 0 = default)
   lrcc::Buf vws;          // bf16x3: one panel of antisymmetrised integral tiles
   size_t panel_cap = 0;   // bytes allowed for vws (0 = not yet chosen)
   int tab_nbv = -1;
@@ -143,7 +143,7 @@ struct BatchInst {
 hipError_t ppl_queue_launch(const BatchInst* inst, int ninst, long total, unsigned* counter,
                             int nwg, hipStream_t st);
 int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul);   // KC of the staged layout
-bool ppl_has_variant(lrcc_prec prec, lrcc_cmul cmul, int variant);  // 4M launch variants 1-4
+bool ppl_has_variant(lrcc_prec prec, lrcc_cmul cmul, int variant);  // 4M launch variants 1-5
 int ppl_planes(lrcc_prec prec, lrcc_cmul cmul);  // planes of the staged L
 size_t ppl_ls_bytes(lrcc_prec prec, lrcc_cmul cmul, const Geom& g);
 size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g);

@@ -77,8 +77,10 @@ struct Smem {
 
 // Integral tile of block pairs (ab, cd): V[(ab),(cd)] = 2 <ab||cd>, built on
 // the matrix cores (4M form) and left in LDS as V[cd slot * VS + ab slot]
-// (planes re, im).  Ends with a barrier: every wave may read V.
-template <typename T, int KC, int OCC, bool DL>
+// (planes re, im).  Ends with a barrier: every wave may read V.  NW waves:
+// wave w builds rows 16 (w mod 4) .. + 15 of W1 and W2 and, with 8 waves,
+// half of the 64 columns (two waves per SIMD, half the accumulators each).
+template <typename T, int KC, int OCC, bool DL, int NW>
 __device__ __forceinline__ void build_v_4m(const T* __restrict__ Ls, const int* __restrict__ tab,
                                            int nbv, int ncp, int v, int ab, int cd, T* lds) {
   typedef typename Acc<T>::t acc_t;
@@ -88,19 +90,22 @@ __device__ __forceinline__ void build_v_4m(const T* __restrict__ Ls, const int* 
   const int pAB = tab[ab], pCD = tab[cd];
   const int A = pAB >> 16, B = pAB & 0xffff, C = pCD >> 16, D = pCD & 0xffff;
 
+  static_assert(NW == 4 || (NW == 8 && DL), "eight waves load chunks straight into LDS");
+  constexpr int NJ = 16 / NW;  // 16-column blocks per wave
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  const int rw = wave & 3, j0 = (wave >> 2) * NJ;
 
-  // ---- 1. build W1 (rows (a,c) of this wave, all columns (b,d)) and W2 ----
+  // ---- 1. build W1 (rows (a,c) of this wave, its columns (b,d)) and W2 ----
   const size_t bstride = (size_t)ncp * 2 * NS;
   const T* const gblk[4] = {Ls + (size_t)(A * nbv + C) * bstride,
                             Ls + (size_t)(B * nbv + D) * bstride,
                             Ls + (size_t)(A * nbv + D) * bstride,
                             Ls + (size_t)(B * nbv + C) * bstride};
 
-  acc_t w1r[4], w1i[4], w2r[4], w2i[4];
+  acc_t w1r[NJ], w1i[NJ], w2r[NJ], w2i[NJ];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < NJ; ++j) {
     w1r[j] = acc_t{0, 0, 0, 0};
     w1i[j] = w1r[j];
     w2r[j] = w1r[j];
@@ -118,7 +123,7 @@ __device__ __forceinline__ void build_v_4m(const T* __restrict__ Ls, const int* 
   constexpr int KPB = CH / VN / WG;        // of which per block
   static_assert(DL || NPF == 4 * KPB, "chunk must split evenly over the workgroup");
   constexpr int PPB = CH * (int)sizeof(T) / 1024;  // 1 KB pieces per block chunk
-  static_assert(!DL || (PPB % 4 == 0), "direct loads need whole pieces per wave");
+  static_assert(!DL || (PPB % NW == 0), "direct loads need whole pieces per wave");
   vec_t pf[NPF];
   auto fetch = [&](int p0) {
 #pragma unroll
@@ -130,8 +135,8 @@ __device__ __forceinline__ void build_v_4m(const T* __restrict__ Ls, const int* 
   };
   auto issue = [&](int p0, T* buf) {
 #pragma unroll
-    for (int k = 0; k < PPB; ++k) {  // PPB pieces per wave = 4 * PPB / 4 waves
-      const int q = k * 4 / PPB, pb = wave + 4 * (k % (PPB / 4));
+    for (int k = 0; k < 4 * PPB / NW; ++k) {  // block q, piece wave + NW m
+      const int q = k / (PPB / NW), pb = wave + NW * (k % (PPB / NW));
       const char* src = reinterpret_cast<const char*>(gblk[q] + (size_t)p0 * 2 * NS) +
                         pb * 1024 + lane * 16;
       __builtin_amdgcn_global_load_lds(
@@ -151,7 +156,9 @@ __device__ __forceinline__ void build_v_4m(const T* __restrict__ Ls, const int* 
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this chunk has landed
       __syncthreads();                     // every wave: loads landed, previous chunk done
       cur = (c & 1) ? ring1 : ring0;
-      if (p0 + KC < ncp) issue(p0 + KC, (c & 1) ? ring0 : ring1);
+      // the next chunk (the last one again on the last pass: a branch-free
+      // loop body keeps the accumulators in place across iterations)
+      issue(min(p0 + KC, ncp - KC), (c & 1) ? ring0 : ring1);
     } else if (DL) {
       __syncthreads();
       issue(p0, lds);
@@ -166,7 +173,7 @@ __device__ __forceinline__ void build_v_4m(const T* __restrict__ Ls, const int* 
           reinterpret_cast<vec_t*>(lds + q * CH)[k * WG + threadIdx.x] = pf[q * KPB + k];
       }
       __syncthreads();
-      if (p0 + KC < ncp) fetch(p0 + KC);
+      fetch(min(p0 + KC, ncp - KC));  // branch-free, as above
     }
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
@@ -175,25 +182,25 @@ __device__ __forceinline__ void build_v_4m(const T* __restrict__ Ls, const int* 
       const T* lbd = cur + 1 * CH + p * 2 * NS;
       const T* lad = cur + 2 * CH + p * 2 * NS;
       const T* lbc = cur + 3 * CH + p * 2 * NS;
-      const T acr = lac[16 * wave + li], aci = lac[NS + 16 * wave + li];
-      const T adr = lad[16 * wave + li], adi = lad[NS + 16 * wave + li];
-      T bdr[4], bdi[4], bcr[4], bci[4];
+      const T acr = lac[16 * rw + li], aci = lac[NS + 16 * rw + li];
+      const T adr = lad[16 * rw + li], adi = lad[NS + 16 * rw + li];
+      T bdr[NJ], bdi[NJ], bcr[NJ], bci[NJ];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        bdr[j] = lbd[16 * j + li];
-        bdi[j] = lbd[NS + 16 * j + li];
-        bcr[j] = lbc[16 * j + li];
-        bci[j] = lbc[NS + 16 * j + li];
+      for (int j = 0; j < NJ; ++j) {
+        bdr[j] = lbd[16 * (j0 + j) + li];
+        bdi[j] = lbd[NS + 16 * (j0 + j) + li];
+        bcr[j] = lbc[16 * (j0 + j) + li];
+        bci[j] = lbc[NS + 16 * (j0 + j) + li];
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < NJ; ++j) {
         w1r[j] = mfma(acr, bdr[j], w1r[j]);
         w1i[j] = mfma(acr, bdi[j], w1i[j]);
         w2r[j] = mfma(adr, bcr[j], w2r[j]);
         w2i[j] = mfma(adr, bci[j], w2i[j]);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < NJ; ++j) {
         w1r[j] = mfma(-aci, bdi[j], w1r[j]);
         w1i[j] = mfma(aci, bdr[j], w1i[j]);
         w2r[j] = mfma(-adi, bci[j], w2r[j]);
@@ -201,16 +208,17 @@ __device__ __forceinline__ void build_v_4m(const T* __restrict__ Ls, const int* 
       }
     }
   }
+  if (DL && OCC == 1) __builtin_amdgcn_s_waitcnt(0x0F70);  // the spare load has landed
   __syncthreads();  // every wave is done with the chunk buffers
 
   // ---- 2. antisymmetrise into V[cd][ab] (planar) in LDS --------------------
   T* Vr = lds;
   T* Vi = lds + NS * VS;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < NJ; ++j) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = 16 * wave + out_row<T>(lk, r), jj = 16 * j + li;
+      const int i = 16 * rw + out_row<T>(lk, r), jj = 16 * (j0 + j) + li;
       // W1 element: i = (a_l, c_l), jj = (b_l, d_l)
       const int idx = ((i & 7) * TB + (jj & 7)) * VS + (i >> 3) * TB + (jj >> 3);
       Vr[idx] = (T)2 * w1r[j][r];
@@ -219,10 +227,10 @@ __device__ __forceinline__ void build_v_4m(const T* __restrict__ Ls, const int* 
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < NJ; ++j) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = 16 * wave + out_row<T>(lk, r), jj = 16 * j + li;
+      const int i = 16 * rw + out_row<T>(lk, r), jj = 16 * (j0 + j) + li;
       // W2 element: i = (a_l, d_l), jj = (b_l, c_l)
       const int al = i >> 3, dl = i & 7, bl = jj >> 3, cl = jj & 7;
       const int idx = (cl * TB + dl) * VS + al * TB + bl;
@@ -275,6 +283,9 @@ __device__ __forceinline__ void contract_rows(const T* Vr, const T* Vi, const T 
       sr[n] = mfma(s_r, vi[n], sr[n]);
       si[n] = mfma(xis, vr[n], si[n]);
     }
+    // keep the scheduler from hoisting every step's LDS reads to the top
+    // (that would hold 16 steps of V operands in registers at once)
+    if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int n = 0; n < NN; ++n) {
@@ -293,9 +304,10 @@ __device__ __forceinline__ void contract_rows(const T* Vr, const T* Vi, const T 
 // (the second is the mirror tile (y, x) of a Hermitian operator).  src / dst
 // are the block pairs whose X rows are read and whose sigma rows receive the
 // 64-slot partial sums (device-scope atomics).  V is only read.  Chunks of 16
-// rows go to the waves in turn; the last Mp/16 mod 4 chunks are shared by all
-// four waves, one block of 16 columns each, so no wave does an extra chunk.
-template <typename T, typename TA, int OCC, bool TR>
+// rows go to the NW waves in turn; the last Mp/16 mod NW chunks are split into
+// (chunk, 16-column block) items dealt out to all waves, so no wave does an
+// extra whole chunk.
+template <typename T, typename TA, int OCC, bool TR, int NW>
 __device__ __forceinline__ void contract_v(const T* lds, const T* __restrict__ Xb,
                                            TA* __restrict__ Sb, int nbp, int Mp, int src,
                                            int dst) {
@@ -310,7 +322,7 @@ __device__ __forceinline__ void contract_v(const T* lds, const T* __restrict__ X
   const T* xi_g = xr_g + plane;
   TA* sr_g = Sb + (size_t)dst * Mp * NS;
   TA* si_g = sr_g + plane;
-  const int nch = Mp / 16, nfull = nch & ~3;
+  const int nch = Mp / 16, nfull = nch - nch % NW;
   // lane (row li, group lk) holds X[m0+li][16 lk .. 16 lk + 15]; the rows of
   // the next m-chunk are fetched while this one is contracted
   constexpr int NX = 16 / VN;
@@ -334,23 +346,25 @@ __device__ __forceinline__ void contract_v(const T* lds, const T* __restrict__ X
       }
     }
   };
-  // with one workgroup per CU the next rows are prefetched; with two, the
-  // other workgroup covers the load latency and the registers are scarce
-  if (OCC == 1 && wave < nfull) fetch_x(wave * 16);
-  for (int mc = wave; mc < nfull; mc += 4) {
+  // with one wave per SIMD the next rows are prefetched; with two (two
+  // workgroups per CU, or eight waves), the other wave covers the load
+  // latency and the registers are scarce
+  constexpr bool PF = OCC == 1 && NW == 4;
+  if (PF && wave < nfull) fetch_x(wave * 16);
+  for (int mc = wave; mc < nfull; mc += NW) {
     const int m0 = mc * 16;
-    if (OCC > 1) fetch_x(m0);
+    if (!PF) fetch_x(m0);
     T xr[16], xi[16];
     unpack(xr, xi);
-    if (OCC == 1 && mc + 4 < nfull) fetch_x(m0 + 64);
+    if (PF && mc + NW < nfull) fetch_x(m0 + 16 * NW);
     contract_rows<T, TA, TR, 4>(Vr, Vi, xr, xi, 0, m0, sr_g, si_g);
   }
-  for (int mc = nfull; mc < nch; ++mc) {
-    const int m0 = mc * 16;
+  for (int it = wave; it < (nch - nfull) * 4; it += NW) {
+    const int m0 = (nfull + it / 4) * 16;
     fetch_x(m0);
     T xr[16], xi[16];
     unpack(xr, xi);
-    contract_rows<T, TA, TR, 1>(Vr, Vi, xr, xi, wave, m0, sr_g, si_g);
+    contract_rows<T, TA, TR, 1>(Vr, Vi, xr, xi, it % 4, m0, sr_g, si_g);
   }
 }
 
@@ -374,17 +388,17 @@ __device__ __forceinline__ bool decode_item(const int* __restrict__ order, long 
   return true;
 }
 
-template <typename T, typename TA, int OCC, typename Build>
+template <typename T, typename TA, int OCC, int NW, typename Build>
 __device__ __forceinline__ void tile_item(Build build, const T* __restrict__ Xb,
                                           TA* __restrict__ Sb, int nbp, int Mp, int x, int y,
                                           bool mirror, T* lds) {
   build(x, y);
-  contract_v<T, TA, OCC, false>(lds, Xb, Sb, nbp, Mp, y, x);
-  if (mirror) contract_v<T, TA, OCC, true>(lds, Xb, Sb, nbp, Mp, x, y);
+  contract_v<T, TA, OCC, false, NW>(lds, Xb, Sb, nbp, Mp, y, x);
+  if (mirror) contract_v<T, TA, OCC, true, NW>(lds, Xb, Sb, nbp, Mp, x, y);
 }
 
-template <typename T, typename TA, int KC, int OCC, bool DL>
-__global__ __launch_bounds__(WG, OCC) void k_ppl_4m(const T* __restrict__ Ls,
+template <typename T, typename TA, int KC, int OCC, bool DL, int NW>
+__global__ __launch_bounds__(64 * NW, OCC) void k_ppl_4m(const T* __restrict__ Ls,
                                                     const T* __restrict__ Xb,
                                                     TA* __restrict__ Sb,
                                                     const int* __restrict__ tab,
@@ -398,9 +412,9 @@ __global__ __launch_bounds__(WG, OCC) void k_ppl_4m(const T* __restrict__ Ls,
   if (!decode_item(order, (long)nbp * (nbp + 1) / 2, nbp, blockIdx.x, *nonherm != 0, &x, &y,
                    &mirror))
     return;
-  tile_item<T, TA, OCC>(
-      [&](int p, int q) { build_v_4m<T, KC, OCC, DL>(Ls, tab, nbv, ncp, v, p, q, lds); }, Xb,
-      Sb, nbp, Mp, x, y, mirror, lds);
+  tile_item<T, TA, OCC, NW>(
+      [&](int p, int q) { build_v_4m<T, KC, OCC, DL, NW>(Ls, tab, nbv, ncp, v, p, q, lds); },
+      Xb, Sb, nbp, Mp, x, y, mirror, lds);
 }
 
 // Persistent ladder over several instances: every workgroup takes the next
@@ -428,9 +442,9 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_queue(const BatchInst* __restrict
     if (!decode_item(I.order, (long)I.nbp * (I.nbp + 1) / 2, I.nbp, t - I.start,
                      *I.nonherm != 0, &x, &y, &mirror))
       continue;
-    tile_item<double, double, 1>(
+    tile_item<double, double, 1, 4>(
         [&](int p, int q) {
-          build_v_4m<double, 16, 1, false>(I.Ls, I.tab, I.nbv, I.ncp, I.v, p, q, lds);
+          build_v_4m<double, 16, 1, false, 4>(I.Ls, I.tab, I.nbv, I.ncp, I.v, p, q, lds);
         },
         I.Xb, I.Sb, I.nbp, I.Mp, x, y, mirror, lds);
   }
@@ -557,8 +571,9 @@ __global__ __launch_bounds__(WG, 1) void k_ppl_3m(const T* __restrict__ Ls,
   if (!decode_item(order, (long)nbp * (nbp + 1) / 2, nbp, blockIdx.x, *nonherm != 0, &x, &y,
                    &mirror))
     return;
-  tile_item<T, TA, 1>([&](int p, int q) { build_v_3m<T, KC>(Ls, tab, nbv, ncp, v, p, q, lds); },
-                      Xb, Sb, nbp, Mp, x, y, mirror, lds);
+  tile_item<T, TA, 1, 4>(
+      [&](int p, int q) { build_v_3m<T, KC>(Ls, tab, nbv, ncp, v, p, q, lds); }, Xb, Sb, nbp,
+      Mp, x, y, mirror, lds);
 }
 
 
@@ -572,11 +587,13 @@ constexpr int KC32 = 32;
 // of 16 / 32 vectors prefetched through registers; 2 = two workgroups per CU
 // through registers (FP32 only: the FP64 accumulators need the full register
 // file); 3 = one workgroup per CU, chunks loaded straight into a two-chunk
-// LDS ring; 4 = two workgroups per CU, direct loads into one LDS chunk.
+// LDS ring; 4 = two workgroups per CU, direct loads into one LDS chunk;
+// 5 = as 3 with eight waves (two per SIMD, each holding half the tile's
+// accumulators).
 bool ppl_has_variant(lrcc_prec prec, lrcc_cmul cmul, int variant) {
   if (cmul != LRCC_CMUL_4M) return variant == 1;
-  if (prec == LRCC_FP64) return variant == 1 || variant == 3;  // 4 would spill
-  if (prec == LRCC_FP32) return variant >= 1 && variant <= 4;
+  if (prec == LRCC_FP64) return variant == 1 || variant == 3 || variant == 5;  // 4 would spill
+  if (prec == LRCC_FP32) return variant >= 1 && variant <= 5;
   return variant == 1;
 }
 
@@ -604,7 +621,7 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
   const long ntile = ppl_ntile(g);
   if (ntile == 0 || g.Mp == 0) return hipSuccess;
   if (2 * ntile > 0x7fffffffL) return hipErrorInvalidValue;
-  dim3 grid((unsigned)(2 * ntile)), block(WG);  // tiles, then their mirrors
+  dim3 grid((unsigned)(2 * ntile)), block(WG);  // tiles, then their mirrors (3M: 4 waves)
   if (cmul == LRCC_CMUL_3M) {
 #define LRCC_L3(T, TA, KC)                                                                      \
   hipLaunchKernelGGL((k_ppl_3m<T, TA, KC>), grid, block, 0, st, static_cast<const T*>(Ls),     \
@@ -617,33 +634,38 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
 #undef LRCC_L3
     return hipGetLastError();
   }
-#define LRCC_L4(T, TA, KC, OCC, DL)                                                         \
-  hipLaunchKernelGGL((k_ppl_4m<T, TA, KC, OCC, DL>), grid, block, 0, st,                     \
+#define LRCC_L4(T, TA, KC, OCC, DL, NW)                                                     \
+  hipLaunchKernelGGL((k_ppl_4m<T, TA, KC, OCC, DL, NW>), grid, dim3(64 * NW), 0, st,         \
                      static_cast<const T*>(Ls), static_cast<const T*>(Xb), static_cast<TA*>(Sb), \
                      tab, order, nonherm, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v)
   // variant: 1 = one WG/CU with register prefetch, 2 = two WG/CU (FP32),
   // 3 = one WG/CU with direct-to-LDS chunk ring, 4 = two WG/CU with direct loads
   if (occ == 0) {
-    // untuned default: direct-to-LDS chunk ring for FP64 (measured about 1.5 %
-    // ahead of register prefetch), register prefetch otherwise
+    // untuned default (the fastest measured at the baseline and precision
+    // workloads): FP64 eight waves with the direct-to-LDS chunk ring; FP32
+    // two workgroups per CU, with direct loads when the sums are FP32
     const char* e = getenv("LRCC_VARIANT");
-    occ = e ? atoi(e) : (prec == LRCC_FP64 && cmul == LRCC_CMUL_4M ? 3 : 1);
+    occ = e ? atoi(e)
+            : cmul != LRCC_CMUL_4M ? 1 : prec == LRCC_FP64 ? 5 : acc64 ? 2 : 4;
   }
   if (!ppl_has_variant(prec, cmul, occ)) occ = 1;
   if (prec == LRCC_FP64) {
-    if (occ == 3) LRCC_L4(double, double, KC64, 1, true);
-    else LRCC_L4(double, double, KC64, 1, false);
+    if (occ == 3) LRCC_L4(double, double, KC64, 1, true, 4);
+    else if (occ == 5) LRCC_L4(double, double, KC64, 1, true, 8);
+    else LRCC_L4(double, double, KC64, 1, false, 4);
   } else if (prec == LRCC_FP32) {
     if (acc64) {
-      if (occ == 2) LRCC_L4(float, double, 16, 2, false);
-      else if (occ == 3) LRCC_L4(float, double, KC32, 1, true);
-      else if (occ == 4) LRCC_L4(float, double, 16, 2, true);
-      else LRCC_L4(float, double, KC32, 1, false);
+      if (occ == 2) LRCC_L4(float, double, 16, 2, false, 4);
+      else if (occ == 3) LRCC_L4(float, double, KC32, 1, true, 4);
+      else if (occ == 4) LRCC_L4(float, double, 16, 2, true, 4);
+      else if (occ == 5) LRCC_L4(float, double, KC32, 1, true, 8);
+      else LRCC_L4(float, double, KC32, 1, false, 4);
     } else {
-      if (occ == 2) LRCC_L4(float, float, 16, 2, false);
-      else if (occ == 3) LRCC_L4(float, float, KC32, 1, true);
-      else if (occ == 4) LRCC_L4(float, float, 16, 2, true);
-      else LRCC_L4(float, float, KC32, 1, false);
+      if (occ == 2) LRCC_L4(float, float, 16, 2, false, 4);
+      else if (occ == 3) LRCC_L4(float, float, KC32, 1, true, 4);
+      else if (occ == 4) LRCC_L4(float, float, 16, 2, true, 4);
+      else if (occ == 5) LRCC_L4(float, float, KC32, 1, true, 8);
+      else LRCC_L4(float, float, KC32, 1, false, 4);
     }
   } else {
     return hipErrorNotSupported;

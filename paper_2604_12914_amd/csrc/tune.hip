@@ -74,7 +74,7 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
       std::istringstream rest(line.substr(key.size()));
       int s = 0, occ = 0;
       double ms = 0;
-      if (rest >> s >> occ >> ms && s > 0 && occ >= 1 && occ <= 4) {
+      if (rest >> s >> occ >> ms && s > 0 && occ >= 1 && occ <= 5) {
         h->order_s = s;
         h->occ[prec] = occ;
         if (out) *out = lrcc_tune_result{s, occ, ms, 0};
@@ -113,7 +113,7 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
   for (int s : {2, 4, 8})
     if (s == 2 || s <= g.nbv) widths.push_back(s);
   std::vector<int> occs;
-  for (int var = 1; var <= 4; ++var)
+  for (int var = 1; var <= 5; ++var)
     if (ppl_has_variant(prec, cmul, var)) occs.push_back(var);
 
   const int saved_s = h->order_s, saved_occ = h->occ[prec];
