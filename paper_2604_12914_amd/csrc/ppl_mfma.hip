@@ -244,16 +244,16 @@ __device__ __forceinline__ void build_v_4m(const T* __restrict__ Ls, const int* 
 }
 
 // Contraction of 16 rows m0 .. m0 + 15 (this lane holds X[m0 + li][16 lk + s]
-// in xr[s], xi[s]) with NN column blocks n0 .. n0 + NN - 1 of the LDS tile V,
-// added to sigma with device-scope atomics (see contract_v for TR).
-template <typename T, typename TA, bool TR, int NN>
+// in xr[s], xi[s]) with NN column blocks n0 .. n0 + NN - 1 of the LDS tile V
+// into the accumulators sr, si (see contract_v for TR).
+template <typename T, bool TR, int NN>
 __device__ __forceinline__ void contract_rows(const T* Vr, const T* Vi, const T (&xr)[16],
-                                              const T (&xi)[16], int n0, int m0, TA* sr_g,
-                                              TA* si_g) {
+                                              const T (&xi)[16], int n0,
+                                              typename Acc<T>::t (&sr)[NN],
+                                              typename Acc<T>::t (&si)[NN]) {
   typedef typename Acc<T>::t acc_t;
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  acc_t sr[NN], si[NN];
 #pragma unroll
   for (int n = 0; n < NN; ++n) {
     sr[n] = acc_t{0, 0, 0, 0};
@@ -287,6 +287,16 @@ __device__ __forceinline__ void contract_rows(const T* Vr, const T* Vi, const T 
     // (that would hold 16 steps of V operands in registers at once)
     if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
   }
+}
+
+// Add the accumulators of rows m0 .. m0 + 15, column blocks n0 .. n0 + NN - 1
+// to sigma with device-scope atomics.
+template <typename T, typename TA, int NN>
+__device__ __forceinline__ void store_rows(const typename Acc<T>::t (&sr)[NN],
+                                           const typename Acc<T>::t (&si)[NN], int n0, int m0,
+                                           TA* sr_g, TA* si_g) {
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int n = 0; n < NN; ++n) {
 #pragma unroll
@@ -346,25 +356,41 @@ __device__ __forceinline__ void contract_v(const T* lds, const T* __restrict__ X
       }
     }
   };
-  // with one wave per SIMD the next rows are prefetched; with two (two
-  // workgroups per CU, or eight waves), the other wave covers the load
-  // latency and the registers are scarce
+  // With one wave per SIMD the next rows are requested before the matrix
+  // work (prefetch).  With two (two workgroups per CU, or eight waves) the
+  // other wave covers the load latency and registers are scarce, so they are
+  // requested after it, but still before this chunk's atomics: the vector-
+  // memory counter retires in order, and a load issued after the atomics
+  // would wait for their round trip too.
   constexpr bool PF = OCC == 1 && NW == 4;
-  if (PF && wave < nfull) fetch_x(wave * 16);
+  typedef typename Acc<T>::t acc_t;
+  const int ntail = (nch - nfull) * 4;  // (chunk, column block) items of the tail
+  auto tail_m0 = [&](int it) { return (nfull + it / 4) * 16; };
+  // rows of this wave's next item after main chunk mc (-1: none)
+  auto next_main = [&](int mc) {
+    return mc + NW < nfull ? (mc + NW) * 16 : (wave < ntail ? tail_m0(wave) : -1);
+  };
+  if (wave < nfull) fetch_x(wave * 16);
+  else if (wave < ntail) fetch_x(tail_m0(wave));
   for (int mc = wave; mc < nfull; mc += NW) {
     const int m0 = mc * 16;
-    if (!PF) fetch_x(m0);
     T xr[16], xi[16];
     unpack(xr, xi);
-    if (PF && mc + NW < nfull) fetch_x(m0 + 16 * NW);
-    contract_rows<T, TA, TR, 4>(Vr, Vi, xr, xi, 0, m0, sr_g, si_g);
+    const int nm = next_main(mc);
+    if (PF && nm >= 0) fetch_x(nm);
+    acc_t sr[4], si[4];
+    contract_rows<T, TR, 4>(Vr, Vi, xr, xi, 0, sr, si);
+    if (!PF && nm >= 0) fetch_x(nm);
+    store_rows<T, TA, 4>(sr, si, 0, m0, sr_g, si_g);
   }
-  for (int it = wave; it < (nch - nfull) * 4; it += NW) {
-    const int m0 = (nfull + it / 4) * 16;
-    fetch_x(m0);
+  for (int it = wave; it < ntail; it += NW) {
+    const int m0 = tail_m0(it);
     T xr[16], xi[16];
     unpack(xr, xi);
-    contract_rows<T, TA, TR, 1>(Vr, Vi, xr, xi, it % 4, m0, sr_g, si_g);
+    acc_t sr[1], si[1];
+    contract_rows<T, TR, 1>(Vr, Vi, xr, xi, it % 4, sr, si);
+    if (it + NW < ntail) fetch_x(tail_m0(it + NW));
+    store_rows<T, TA, 1>(sr, si, it % 4, m0, sr_g, si_g);
   }
 }
 
