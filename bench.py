@@ -259,7 +259,8 @@ def main():
 def dalpha_sweep(lrcc, torch, np, eps, L, mu, omegas, exact, target=1e-5):
     """For each method, the fastest solve whose alpha is within `target` a.u.
     of the exact alpha: tolerances are tried from the loosest down, and the
-    first one that meets the target is timed (after one untimed run)."""
+    first one that meets the target is timed (best of three calls after one
+    untimed run)."""
     methods = {
         "fp64": dict(prec="fp64"),
         "bf16x3_ir_fp64_anchor": dict(prec="bf16x3"),
@@ -279,12 +280,14 @@ def dalpha_sweep(lrcc, torch, np, eps, L, mu, omegas, exact, target=1e-5):
                                      check=False, **kw)
                 err = float(np.abs(a - exact).max())
                 if info["status"] == "LRCC_OK" and err < target:
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    a, info = lrcc.solve(eps, L, mu, omegas, tol=tol, inner_tol=tol * ratio,
-                                         check=False, **kw)
-                    t1 = time.perf_counter()
-                    ms = round((t1 - t0) * 1e3, 3)
+                    ms = 1e300
+                    for _ in range(3):  # best of three timed calls
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        a, info = lrcc.solve(eps, L, mu, omegas, tol=tol,
+                                             inner_tol=tol * ratio, check=False, **kw)
+                        t1 = time.perf_counter()
+                        ms = min(ms, round((t1 - t0) * 1e3, 3))
                     if res is None or ms < res["ms"]:
                         res = {"tol": tol, "inner_tol": tol * ratio, "ms": ms,
                                "max_abs_dalpha_vs_exact": float(np.abs(a - exact).max()),

@@ -136,29 +136,31 @@ void supertile_order(const Geom& g, int ab0, int ab1, int sw, int nx, bool upper
 }
 
 const int* tile_order(lrcc_handle h, const Geom& g, int ab0, int ab1, bool upper,
-                      lrcc_status* st) {
-  const int sw = h->order_s > 0 ? h->order_s : 4;
+                      lrcc_prec prec, lrcc_status* st) {
+  const int sw = h->order_s[prec] > 0 ? h->order_s[prec] : 4;
   const long key[6] = {g.nbv, ab0, ab1, sw, h->ncu, upper};
+  long* okey = h->order_key[prec];
+  Buf& obuf = h->order[prec];
   bool same = true;
-  for (int k = 0; k < 6; ++k) same = same && key[k] == h->order_key[k];
+  for (int k = 0; k < 6; ++k) same = same && key[k] == okey[k];
   if (same) {
     *st = LRCC_OK;
-    return h->order.as<int>();
+    return obuf.as<int>();
   }
   std::vector<int> ord;
   supertile_order(g, ab0, ab1, sw, std::max(1, h->ncu / 32), upper, &ord);
-  hipError_t e = h->order.ensure(ord.size() * sizeof(int));
+  hipError_t e = obuf.ensure(ord.size() * sizeof(int));
   if (e == hipSuccess)
-    e = hipMemcpyAsync(h->order.p, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice,
+    e = hipMemcpyAsync(obuf.p, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice,
                        h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     *st = hip_fail(h, e, "tile order upload");
     return nullptr;
   }
-  for (int k = 0; k < 6; ++k) h->order_key[k] = key[k];
+  for (int k = 0; k < 6; ++k) okey[k] = key[k];
   *st = LRCC_OK;
-  return h->order.as<int>();
+  return obuf.as<int>();
 }
 
 lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
@@ -177,7 +179,7 @@ lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, c
     LRCC_HIP(h, hipEventRecord(e0, h->stream));
   }
   lrcc_status ost;
-  const int* ord = tile_order(h, g, 0, g.nbp, true, &ost);
+  const int* ord = tile_order(h, g, 0, g.nbp, true, prec, &ost);
   if (ost != LRCC_OK) return ost;
   LRCC_HIP(h, ppl_launch(prec, cmul, acc64, g, Ls, Xb, Sb, h->tab.as<int>(), ord, nonherm,
                          h->occ[prec], h->stream));
@@ -360,6 +362,8 @@ lrcc_status lrcc_destroy(lrcc_handle h) {
     h->sb.release();
     h->gb.release();
     h->tab.release();
+    h->hflag.release();
+    for (auto& b : h->order) b.release();
     h->vws.release();
     for (auto& b : h->sv) b.release();
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);

@@ -67,9 +67,10 @@ struct lrcc_handle_s {
   lrcc::Buf xb, sb, gb;   // block-layout doubles: input, accumulator, gradient
   lrcc::Buf tab;          // block-pair table
   lrcc::Buf hflag;        // nonzero when the staged L is not Hermitian (device int)
-  lrcc::Buf order;        // tile order (XCD-aware super-tiles), see tile_order()
-  long order_key[6] = {-1, -1, -1, -1, -1, -1};
-  int order_s = 0;        // super-tile width in virtual blocks (0 = default)
+  lrcc::Buf order[3];     // tile order per precision (XCD-aware super-tiles), see tile_order()
+  long order_key[3][6] = {{-1, -1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1, -1},
+                          {-1, -1, -1, -1, -1, -1}};
+  int order_s[3] = {0, 0, 0};  // super-tile width per precision (0 = default)
   int occ[3] = {0, 0, 0}; // 4M launch variant per precision (1-5, 0 = default)
   lrcc::Buf vws;          // bf16x3: one panel of antisymmetrised integral tiles
   size_t panel_cap = 0;   // bytes allowed for vws (0 = not yet chosen)
@@ -186,7 +187,7 @@ lrcc_status grad_L(lrcc_handle h, const Geom& g, const void* L, const void* X, c
 // each XCD receives a contiguous run of super-tiles (workgroups go to XCDs
 // round-robin).  Returns a device pointer owned by the handle.
 const int* tile_order(lrcc_handle h, const Geom& g, int ab0, int ab1, bool upper,
-                      lrcc_status* st);
+                      lrcc_prec prec, lrcc_status* st);
 
 // Host-side builders of the block-pair table and of the super-tile order
 // (nx = number of XCDs to split the order over; 1 = plain super-tile order).

@@ -529,7 +529,7 @@ hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* 
     if (2 * pt > 0x7fffffffL || (long)nmb * (g.nbp - ab0) > 0x7fffffffL)
       return hipErrorInvalidValue;
     lrcc_status ost;
-    const int* ord = tile_order(h, g, ab0, ab0 + n, true, &ost);
+    const int* ord = tile_order(h, g, ab0, ab0 + n, true, LRCC_BF16X3, &ost);
     if (ost != LRCC_OK) return hipErrorUnknown;
     __bf16* Vdir = static_cast<__bf16*>(Vws);
     __bf16* Vmir = Vdir + (size_t)pt * VT;

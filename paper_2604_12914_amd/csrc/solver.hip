@@ -967,7 +967,7 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
     // block-pair table and tile order of this instance
     std::vector<int> tab, ord;
     block_pair_table(g0.nbv, &tab);
-    supertile_order(g0, 0, g0.nbp, h->order_s > 0 ? h->order_s : 4, 1, true, &ord);
+    supertile_order(g0, 0, g0.nbp, h->order_s[LRCC_FP64] > 0 ? h->order_s[LRCC_FP64] : 4, 1, true, &ord);
     LRCC_HIP(h, own[i][13].ensure(tab.size() * 4));
     LRCC_HIP(h, own[i][14].ensure(ord.size() * 4));
     LRCC_HIP(h, hipMemcpyAsync(own[i][13].p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, cs));

@@ -75,7 +75,7 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
       int s = 0, occ = 0;
       double ms = 0;
       if (rest >> s >> occ >> ms && s > 0 && occ >= 1 && occ <= 5) {
-        h->order_s = s;
+        h->order_s[prec] = s;
         h->occ[prec] = occ;
         if (out) *out = lrcc_tune_result{s, occ, ms, 0};
         return LRCC_OK;
@@ -89,7 +89,7 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
   nchol = std::min(nchol, 512);
   Geom g = make_geom(o, v, nchol, nrhs, 1);
   if (g.M == 0 || g.npv == 0 || nchol == 0) {
-    if (out) *out = lrcc_tune_result{h->order_s > 0 ? h->order_s : 4, 1, 0.0, 0};
+    if (out) *out = lrcc_tune_result{h->order_s[prec] > 0 ? h->order_s[prec] : 4, 1, 0.0, 0};
     return LRCC_OK;
   }
   // synthetic inputs in the packed public layout
@@ -116,13 +116,13 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
   for (int var = 1; var <= 5; ++var)
     if (ppl_has_variant(prec, cmul, var)) occs.push_back(var);
 
-  const int saved_s = h->order_s, saved_occ = h->occ[prec];
+  const int saved_s = h->order_s[prec], saved_occ = h->occ[prec];
   const bool saved_timing = h->timing;
   int best_s = widths[0], best_occ = 1, ncand = 0;
   double best = 1e300;
   for (int s : widths) {
     for (int occ : occs) {
-      h->order_s = s;
+      h->order_s[prec] = s;
       h->occ[prec] = occ;
       double ms_best = 1e300;
       for (int rep = 0; rep < 3; ++rep) {
@@ -131,7 +131,7 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
         lrcc_status st = sigma_packed(h, make_geom(o, v, nchol, nrhs, ppl_chunk(prec, cmul)), L,
                                       false, X, S, LRCC_C128, prec, cmul);
         if (st != LRCC_OK) {
-          h->order_s = saved_s;
+          h->order_s[prec] = saved_s;
           h->occ[prec] = saved_occ;
           h->timing = saved_timing;
           h->tev_used = 0;
@@ -158,7 +158,7 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
   }
   h->timing = saved_timing;
   h->tev_used = 0;  // the tuner reused the timing events: totals restart
-  h->order_s = best_s;
+  h->order_s[prec] = best_s;
   h->occ[prec] = best_occ;
   if (out) *out = lrcc_tune_result{best_s, best_occ, best, ncand};
   if (cache_path) {
