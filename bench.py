@@ -88,6 +88,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the per-precision extras")
+    ap.add_argument("--profile-sigma", choices=("fp64", "fp32", "bf16x3"), default=None,
+                    help="only run --warmup + --steps ladder applications of this precision "
+                         "(for profilers) and print their kernel time")
+    ap.add_argument("--workload", choices=("baseline", "precision"), default="baseline",
+                    help="shape for --profile-sigma")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (a plain copy kernel of known "
                          "size, to scale HBM byte counters)")
@@ -108,6 +113,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     lrcc.lib()  # fails loudly if liblrcc.so is missing
+
+    if args.profile_sigma:
+        profile_sigma(lrcc, torch, np, S, args)
+        return
 
     cfg = S.CONFIGS["baseline"]
     o, v, nchol = cfg.o, cfg.v, cfg.nchol
@@ -254,6 +263,30 @@ def main():
         out["cpu_baseline"] = cpu_baseline(inst.L, o, v, nchol, nrhs, F)
 
     print(json.dumps(out), flush=True)
+
+
+def profile_sigma(lrcc, torch, np, S, args):
+    """Ladder applications only (Hermitian L, packed X of the workload's RHS
+    count), for a profiler run: one JSON line with the mean kernel time."""
+    cfg = S.CONFIGS[args.workload]
+    o, v, nchol, nrhs = cfg.o, cfg.v, cfg.nchol, cfg.nrhs
+    L = torch.from_numpy(S.make_L(np.random.default_rng(4), nchol, v)).cuda()
+    X = torch.from_numpy(S.make_packed(np.random.default_rng(3), nrhs, o, v)).cuda()
+    s = None
+    for _ in range(max(args.warmup, 1)):
+        s = lrcc.ppl_sigma(L, X, prec=args.profile_sigma)
+    torch.cuda.synchronize()
+    lrcc.set_timing(True)
+    for _ in range(args.steps):
+        lrcc.ppl_sigma(L, X, prec=args.profile_sigma, out=s)
+    ms, n = lrcc.get_timing()
+    lrcc.set_timing(False)
+    F = flops_per_sigma(o, v, nchol, nrhs)
+    print(json.dumps({"profile_sigma": args.profile_sigma, "workload": args.workload,
+                      "o": o, "v": v, "nchol": nchol, "nrhs": nrhs,
+                      "ladder_ms": round(ms / max(n, 1), 4), "launches": n,
+                      "tflops_algorithmic": round(F / (ms / max(n, 1) * 1e-3) / 1e12, 2)}),
+          flush=True)
 
 
 def dalpha_sweep(lrcc, torch, np, eps, L, mu, omegas, exact, target=1e-5):
