@@ -212,15 +212,47 @@ def test_baseline_size_sampled_entries(lrcc):
     L = S.make_L(rng, nchol, v)
     X = S.make_packed(rng, nrhs, o, v)
     got = run(lrcc, L, X).reshape(-1, X.shape[-1])
-    pa, pb = ppl.pairs(v)
-    srng = np.random.default_rng(1)
-    ks = np.concatenate([[0, 1, len(pa) - 1], srng.choice(len(pa), 29, replace=False)])
-    rows = np.concatenate([[0, got.shape[0] - 1], srng.choice(got.shape[0], 14, replace=False)])
-    ref = ppl.sigma_entries(L, X, v, rows, [(pa[k], pb[k]) for k in ks])
+    rows, pairs, ks = sample(got.shape[0], v, 1)
+    ref = ppl.sigma_entries(L, X, v, rows, pairs)
     assert rel(got[np.ix_(rows, ks)], ref) < 1e-10
     # invariants at full size: linearity in X and homogeneity in L
     got2 = run(lrcc, 2.0 * L, X).reshape(got.shape)
     assert rel(got2, 4.0 * got) < 1e-13
+
+
+def sample(nrows, v, seed):
+    # first, last and random rows and packed virtual pairs of a full-size run
+    pa, pb = ppl.pairs(v)
+    srng = np.random.default_rng(seed)
+    ks = np.concatenate([[0, 1, len(pa) - 1], srng.choice(len(pa), 29, replace=False)])
+    rows = np.concatenate([[0, nrows - 1], srng.choice(nrows, 14, replace=False)])
+    return rows, [(pa[k], pb[k]) for k in ks], ks
+
+
+# full workload sizes in the default launch configuration of each precision
+# (the one bench.py times), Hermitian and general L, sampled entries
+@pytest.mark.parametrize("workload,prec,herm", [("baseline", "fp64", False),
+                                                ("baseline", "fp32", True),
+                                                ("baseline", "bf16x3", True),
+                                                ("baseline", "bf16x3", False),
+                                                ("precision", "fp64", True),
+                                                ("precision", "bf16x3", True)])
+def test_workload_size_sampled_entries(lrcc, workload, prec, herm):
+    cfg = S.CONFIGS[workload]
+    o, v, nchol, nrhs = cfg.o, cfg.v, cfg.nchol, cfg.nrhs
+    print(f"{prec} sampled parity {workload} herm={herm}", flush=True)
+    rng = np.random.default_rng(2)
+    L = S.make_L(rng, nchol, v, hermitian=herm)
+    X = S.make_packed(rng, nrhs, o, v)
+    got = run(lrcc, L, X, prec=prec).reshape(-1, X.shape[-1])
+    rows, pairs, ks = sample(got.shape[0], v, 3)
+    if prec == "fp32":  # FP32 arithmetic on the inputs rounded to FP32
+        L, X = L.astype(np.complex64).astype(complex), X.astype(np.complex64).astype(complex)
+    ref = ppl.sigma_entries(L, X, v, rows, pairs)
+    tol = {"fp64": 1e-10, "fp32": 2e-6, "bf16x3": 6e-5}[prec]
+    err = rel(got[np.ix_(rows, ks)], ref)
+    print(f"{prec} {workload} sampled relative error {err:.2e}", flush=True)
+    assert err < tol
 
 
 @pytest.mark.parametrize("o,v,nchol,nrhs,herm", [(4, 26, 48, 2, False), (6, 36, 144, 1, True),
