@@ -79,7 +79,12 @@ lrcc_status lrcc_set_stream(lrcc_handle h, void* hip_stream);
  *          accumulation inside a tile) or BF16X3 (split hi/lo bf16 MFMA, FP32
  *          accumulation).  Sums across tiles are kept in FP64 for C128 output.
  * cmul     4M (four real products per complex product) or 3M (three).
- * Limits: v <= 4096, nchol <= 65536, nrhs*o(o-1)/2 <= 2^24. */
+ * Limits: v <= 4096, nchol <= 65536, nrhs*o(o-1)/2 <= 2^24.
+ * When every L^P is Hermitian (L^P_ca == conj L^P_ac, tested exactly on the
+ * device during the call) the ladder operator is Hermitian and each integral
+ * tile is built once for a pair of block pairs and also used as its
+ * conjugate transpose (half the builds); for any other L both tiles are
+ * built.  The two routes agree up to rounding order. */
 lrcc_status lrcc_ppl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs,
                            const void* L, const void* X, void* sigma,
                            lrcc_dtype dt, lrcc_prec prec, lrcc_cmul cmul);

@@ -131,18 +131,25 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
 // One instance of the persistent FP64 ladder (k_ppl_queue): its staged
 // vectors, block-layout doubles and accumulator, geometry, tile order and
 // the first queue item that belongs to it.
+// Items of instance i: local index l < 2 ppl_ntile (tiles, then mirrors).
+// The queue has one counter per XCD; XCD x owns the items l = x (mod nx) of
+// every instance, in instance order, and xstart[x] is the number of them in
+// the instances before this one.
+constexpr int QXMAX = 8;  // XCDs tracked by the queue
 struct BatchInst {
   const double* Ls;
   const double* Xb;
   double* Sb;
   const int* tab;
-  const int* order;    // ppl_ntile tile pairs ab <= cd
+  const int* order;    // ppl_ntile tile pairs ab <= cd (XCD-aware super-tile order)
   const int* nonherm;  // device flag of this instance's L
   int nbv, nbp, ncp, Mp, v;
-  long start;
+  long start;              // first item in a single global list
+  long xstart[QXMAX];      // first item in each XCD's list
 };
-hipError_t ppl_queue_launch(const BatchInst* inst, int ninst, long total, unsigned* counter,
-                            int nwg, hipStream_t st);
+// counter: nx (<= QXMAX) zeroed unsigned counters; xtotal[x]: items of XCD x.
+hipError_t ppl_queue_launch(const BatchInst* inst, int ninst, const long* xtotal, int nx,
+                            unsigned* counter, int nwg, hipStream_t st);
 int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul);   // KC of the staged layout
 bool ppl_has_variant(lrcc_prec prec, lrcc_cmul cmul, int variant);  // 4M launch variants 1-5
 int ppl_planes(lrcc_prec prec, lrcc_cmul cmul);  // planes of the staged L

@@ -443,36 +443,50 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_ppl_4m(const T* __restrict__ L
       Xb, Sb, nbp, Mp, x, y, mirror, lds);
 }
 
-// Persistent ladder over several instances: every workgroup takes the next
-// item of one shared queue (items ordered longest tile first) until the
-// queue is exhausted, so uneven instances share one launch without a tail.
-__global__ __launch_bounds__(WG, 1) void k_ppl_queue(const BatchInst* __restrict__ inst,
-                                                     int ninst, long total,
-                                                     unsigned* __restrict__ counter) {
-  __shared__ __attribute__((aligned(16))) double lds[Smem<double, 16>::elems];
-  __shared__ long item;
-  for (;;) {
+// Persistent ladder over several instances (eight waves, chunks loaded
+// straight into a two-chunk LDS ring: the fastest FP64 launch variant).  A
+// workgroup on XCD x takes the next item of x's queue (the instances' items
+// l = x mod nx, instances ordered longest tile first): with each instance's
+// tile order split into per-XCD super-tile shares, the workgroups of one XCD
+// work on tiles that share Cholesky blocks in its L2.  When x's queue is
+// empty the workgroup takes items from the next XCDs' queues, so uneven
+// instances share one launch without a tail.  Every workgroup leaves once it
+// has found all nx queues empty.
+constexpr int QNW = 8;
+__global__ __launch_bounds__(64 * QNW, 1) void k_ppl_queue(const BatchInst* __restrict__ inst,
+                                                          int ninst,
+                                                          const long* __restrict__ xtotal,
+                                                          int nx,
+                                                          unsigned* __restrict__ counter) {
+  __shared__ __attribute__((aligned(16))) double lds[2 * Smem<double, 16>::build];
+  __shared__ unsigned item;
+  const int x0 = blockIdx.x % nx;
+  for (int xi = 0; xi < nx;) {
+    const int x = (x0 + xi) % nx;
     __syncthreads();  // every wave is done with the previous item and its LDS
-    if (threadIdx.x == 0) item = (long)atomicAdd(counter, 1u);
+    if (threadIdx.x == 0) item = atomicAdd(counter + x, 1u);
     __syncthreads();
     // the item is the same for every lane: keep it (and what is derived from
     // it) in scalar registers
-    const long t = ((long)__builtin_amdgcn_readfirstlane((int)(item >> 32)) << 32) |
-                   (unsigned)__builtin_amdgcn_readfirstlane((int)item);
-    if (t >= total) break;
-    int i = 0;
-    while (i + 1 < ninst && t >= inst[i + 1].start) ++i;
-    const BatchInst& I = inst[i];
-    int x, y;
-    bool mirror;
-    if (!decode_item(I.order, (long)I.nbp * (I.nbp + 1) / 2, I.nbp, t - I.start,
-                     *I.nonherm != 0, &x, &y, &mirror))
+    const long c = (unsigned)__builtin_amdgcn_readfirstlane((int)item);
+    if (c >= xtotal[x]) {  // this XCD's queue is empty: move on to the next
+      ++xi;
       continue;
-    tile_item<double, double, 1, 4>(
-        [&](int p, int q) {
-          build_v_4m<double, 16, 1, false, 4>(I.Ls, I.tab, I.nbv, I.ncp, I.v, p, q, lds);
+    }
+    int i = 0;
+    while (i + 1 < ninst && c >= inst[i + 1].xstart[x]) ++i;
+    const BatchInst& I = inst[i];
+    const long l = (c - I.xstart[x]) * nx + x;
+    int p, q;
+    bool mirror;
+    if (!decode_item(I.order, (long)I.nbp * (I.nbp + 1) / 2, I.nbp, l, *I.nonherm != 0, &p, &q,
+                     &mirror))
+      continue;
+    tile_item<double, double, 1, QNW>(
+        [&](int a, int b) {
+          build_v_4m<double, 16, 1, true, QNW>(I.Ls, I.tab, I.nbv, I.ncp, I.v, a, b, lds);
         },
-        I.Xb, I.Sb, I.nbp, I.Mp, x, y, mirror, lds);
+        I.Xb, I.Sb, I.nbp, I.Mp, p, q, mirror, lds);
   }
 }
 
@@ -700,10 +714,12 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
   return hipGetLastError();
 }
 
-hipError_t ppl_queue_launch(const BatchInst* inst, int ninst, long total, unsigned* counter,
-                            int nwg, hipStream_t st) {
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ppl_queue, dim3(nwg), dim3(WG), 0, st, inst, ninst, total, counter);
+hipError_t ppl_queue_launch(const BatchInst* inst, int ninst, const long* xtotal, int nx,
+                            unsigned* counter, int nwg, hipStream_t st) {
+  if (ninst == 0 || nx < 1 || nx > QXMAX) return nx < 1 || nx > QXMAX ? hipErrorInvalidValue
+                                                                       : hipSuccess;
+  hipLaunchKernelGGL(k_ppl_queue, dim3(nwg), dim3(64 * QNW), 0, st, inst, ninst, xtotal, nx,
+                     counter);
   return hipGetLastError();
 }
 

@@ -952,7 +952,7 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
       if (s) (void)hipStreamDestroy(s);
     }
   } sfree{cs};
-  const int nx = std::max(1, h->ncu / 32);
+  const int nx = std::min(QXMAX, std::max(1, h->ncu / 32));  // XCDs
   for (int i = 0; i < ninst; ++i) {
     const lrcc_instance& I = inst[i];
     S[i].reset(new Solver());
@@ -967,7 +967,8 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
     // block-pair table and tile order of this instance
     std::vector<int> tab, ord;
     block_pair_table(g0.nbv, &tab);
-    supertile_order(g0, 0, g0.nbp, h->order_s[LRCC_FP64] > 0 ? h->order_s[LRCC_FP64] : 4, 1, true, &ord);
+    supertile_order(g0, 0, g0.nbp, h->order_s[LRCC_FP64] > 0 ? h->order_s[LRCC_FP64] : 4, nx,
+                    true, &ord);
     LRCC_HIP(h, own[i][13].ensure(tab.size() * 4));
     LRCC_HIP(h, own[i][14].ensure(ord.size() * 4));
     LRCC_HIP(h, hipMemcpyAsync(own[i][13].p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, cs));
@@ -988,8 +989,8 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
     LRCC_HIP(h, hipStreamSynchronize(cs));  // `one` goes out of scope
     live.push_back(i);
   }
-  (void)nx;
-  // queue descriptors, longest tile first (tile cost ~ 2 ncp + Mp)
+  // queue descriptors, longest tile first (tile cost ~ 2 ncp + Mp), then
+  // the per-XCD item totals
   Buf desc, counter;
   struct DescFree {
     Buf* a;
@@ -999,8 +1000,9 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
       b->release();
     }
   } dfree{&desc, &counter};
-  LRCC_HIP(h, desc.ensure(sizeof(BatchInst) * std::max(1, ninst)));
-  LRCC_HIP(h, counter.ensure(16));
+  const size_t desc_bytes = roundup((long)sizeof(BatchInst) * std::max(1, ninst), 256);
+  LRCC_HIP(h, desc.ensure(desc_bytes + sizeof(long) * QXMAX));
+  LRCC_HIP(h, counter.ensure(64));
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   struct GraphFree {
@@ -1030,15 +1032,23 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
       });
       std::vector<BatchInst> d(now.size());
       long total = 0;
+      std::vector<long> xtotal(QXMAX, 0);
       for (size_t k = 0; k < now.size(); ++k) {
         const Solver& Si = *S[now[k]];
         d[k] = BatchInst{own[now[k]][12].as<double>(), Si.x, Si.s, Si.tab,
                          own[now[k]][14].as<int>(), Si.nonherm, Si.g.nbv, Si.g.nbp,
-                         (int)roundup(Si.g.nchol, KC), (int)Si.g.Mp, Si.g.v, total};
-        total += Si.g.nchol > 0 ? 2 * ppl_ntile(Si.g) : 0;  // tiles, then mirrors
+                         (int)roundup(Si.g.nchol, KC), (int)Si.g.Mp, Si.g.v, total, {}};
+        const long items = Si.g.nchol > 0 ? 2 * ppl_ntile(Si.g) : 0;  // tiles, then mirrors
+        for (int x = 0; x < nx; ++x) {
+          d[k].xstart[x] = xtotal[x];
+          xtotal[x] += items > x ? (items - x + nx - 1) / nx : 0;  // items l = x mod nx
+        }
+        total += items;
       }
       LRCC_HIP(h, hipMemcpyAsync(desc.p, d.data(), d.size() * sizeof(BatchInst),
                                  hipMemcpyHostToDevice, cs));
+      LRCC_HIP(h, hipMemcpyAsync(desc.as<char>() + desc_bytes, xtotal.data(),
+                                 sizeof(long) * QXMAX, hipMemcpyHostToDevice, cs));
       LRCC_HIP(h, hipStreamSynchronize(cs));
       if (exec) {
         LRCC_HIP(h, hipGraphExecDestroy(exec));
@@ -1050,11 +1060,12 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
       }
       LRCC_HIP(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       lrcc_status cst = LRCC_OK;
-      hipError_t ce = fill_zero(counter.p, 16, cs);
+      hipError_t ce = fill_zero(counter.p, 64, cs);
       for (int i : now)
         if (ce == hipSuccess) ce = fill_zero(S[i]->s, (size_t)2 * S[i]->d.plane * 8, cs);
       if (ce == hipSuccess)
-        ce = ppl_queue_launch(desc.as<BatchInst>(), (int)now.size(), total,
+        ce = ppl_queue_launch(desc.as<BatchInst>(), (int)now.size(),
+                              reinterpret_cast<const long*>(desc.as<char>() + desc_bytes), nx,
                               counter.as<unsigned>(), h->ncu, cs);
       for (int i : now)
         if (ce == hipSuccess && cst == LRCC_OK)
