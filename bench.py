@@ -58,7 +58,11 @@ def issued_flops(o, v, nchol, nrhs, prec="fp64", cmul="4m"):
     return build + 8.0 * 4096 * mp * nbp * nbp
 
 
-TRAFFIC_PROFILE = "profiles/k_ppl_4m_fp64_o16_v160_nchol640_hbm_traffic.md"
+# complex-multiply form of the FP64 ladder in the timed solves: the 3M form
+# (three real products per complex product in the integral build; same
+# result up to rounding) is the faster one on MI355X
+SOLVE_CMUL = "3m"
+TRAFFIC_PROFILE = "profiles/k_ppl_3m_fp64_o16_v160_nchol640_hbm_traffic.md"
 TRAFFIC_SOURCES = ("paper_2604_12914_amd/csrc/ppl_mfma.hip", "paper_2604_12914_amd/csrc/internal.hpp")
 
 
@@ -139,13 +143,13 @@ def main():
 
     # ---- timed region: K full FP64 solves ---------------------------------
     for _ in range(args.warmup):
-        alpha64, info = lrcc.solve(eps, L, mu, omegas, tol=1e-8)
+        alpha64, info = lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL)
     torch.cuda.synchronize()
     lrcc.set_timing(True)
     n_sigma = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        alpha64, info = lrcc.solve(eps, L, mu, omegas, tol=1e-8)
+        alpha64, info = lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL)
         n_sigma += info["n_sigma_fp64"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -155,7 +159,7 @@ def main():
     value = n_sigma * F / (t1 - t0) / 1e12
     k_avg = kms / max(nlaunch, 1)
     achieved = F / (k_avg * 1e-3) / 1e12
-    issued = issued_flops(o, v, nchol, nrhs) / (k_avg * 1e-3) / 1e12
+    issued = issued_flops(o, v, nchol, nrhs, "fp64", SOLVE_CMUL) / (k_avg * 1e-3) / 1e12
 
     out = {
         "metric": "PPL A*X TFLOP/s FP64 vs split-prec; LR solve time at |d alpha|<1e-5 a.u.",
@@ -172,7 +176,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "FP64 LR solve, o=16 v=160 Nchol=640, 3 dipole components x "
-                        "omega {0, 0.0656} = 6 RHS, Jacobi+DIIS to relative residual 1e-8",
+                        "omega {0, 0.0656} = 6 RHS, Jacobi+DIIS to relative residual 1e-8, "
+                        f"{SOLVE_CMUL.upper()} complex products in the FP64 ladder",
             "o": o, "v": v, "nchol": nchol, "nrhs": nrhs,
             "sigma_per_step": n_sigma / args.steps,
             "flop_per_sigma": F,
@@ -183,7 +188,8 @@ def main():
             "traffic": measured_traffic(),
             "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
                             "null when the kernel changed since the counters were taken)",
-            "kernel": "k_ppl_4m<double> (fused build + antisymmetrise + contract)",
+            "kernel": f"k_ppl_{SOLVE_CMUL}<double> (fused build + antisymmetrise + contract, "
+                      "eight waves)",
             "kernel_ms_avg": round(k_avg, 4), "launches": nlaunch,
             "issued_tflops": round(issued, 3), "issued_frac": round(issued / PEAK["fp64"], 4),
             "note": "achieved counts the algorithmic 4M flops without symmetry savings; the "
@@ -293,7 +299,8 @@ def dalpha_sweep(lrcc, torch, np, eps, L, mu, omegas, exact, target=1e-5):
     """For each method, the fastest solve whose alpha is within `target` a.u.
     of the exact alpha: tolerances are tried from the loosest down, and the
     first one that meets the target is timed (best of three calls after one
-    untimed run)."""
+    untimed run).  Each method runs with both complex-multiply forms of its
+    FP64 / FP32 ladders (bf16x3 is always 4M) and keeps the faster."""
     methods = {
         "fp64": dict(prec="fp64"),
         "bf16x3_ir_fp64_anchor": dict(prec="bf16x3"),
@@ -307,10 +314,11 @@ def dalpha_sweep(lrcc, torch, np, eps, L, mu, omegas, exact, target=1e-5):
         # below it (fewer inner iterations against fewer outer sweeps); each
         # choice is timed at its loosest tolerance that meets the target
         refine = kw.get("prec", "fp64") != "fp64"
-        for ratio in ((1.0, 1.0 / 3.0) if refine else (1.0,)):
+        for cmul, ratio in [(c, r) for c in ("4m", "3m")
+                            for r in ((1.0, 1.0 / 3.0) if refine else (1.0,))]:
             for tol in (1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 1e-7, 1e-8):
                 a, info = lrcc.solve(eps, L, mu, omegas, tol=tol, inner_tol=tol * ratio,
-                                     check=False, **kw)
+                                     check=False, cmul=cmul, **kw)
                 err = float(np.abs(a - exact).max())
                 if info["status"] == "LRCC_OK" and err < target:
                     ms = 1e300
@@ -318,11 +326,12 @@ def dalpha_sweep(lrcc, torch, np, eps, L, mu, omegas, exact, target=1e-5):
                         torch.cuda.synchronize()
                         t0 = time.perf_counter()
                         a, info = lrcc.solve(eps, L, mu, omegas, tol=tol,
-                                             inner_tol=tol * ratio, check=False, **kw)
+                                             inner_tol=tol * ratio, check=False, cmul=cmul,
+                                             **kw)
                         t1 = time.perf_counter()
                         ms = min(ms, round((t1 - t0) * 1e3, 3))
                     if res is None or ms < res["ms"]:
-                        res = {"tol": tol, "inner_tol": tol * ratio, "ms": ms,
+                        res = {"tol": tol, "inner_tol": tol * ratio, "cmul": cmul, "ms": ms,
                                "max_abs_dalpha_vs_exact": float(np.abs(a - exact).max()),
                                "n_sigma_fp64": info["n_sigma_fp64"],
                                "n_sigma_lowp": info["n_sigma_lowp"]}

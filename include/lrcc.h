@@ -108,7 +108,9 @@ typedef struct {
                         sweep for reduced precision (default 100)            */
   int diis_dim;      /* DIIS subspace size, 1 = plain Jacobi (default 8)     */
   lrcc_prec prec;    /* ladder arithmetic of the inner iterations            */
-  lrcc_cmul cmul;
+  lrcc_cmul cmul;    /* complex form of the FP64 and FP32 ladders (the FP64
+                        solve, the refinement's anchor and an FP32 inner
+                        ladder); bf16x3 ladders always use 4M                */
   double inner_tol;  /* reduced precision: inner relative tolerance (1e-5)   */
   int max_outer;     /* reduced precision: refinement sweeps (default 6)     */
   int deterministic; /* reserved; must be 0                                  */

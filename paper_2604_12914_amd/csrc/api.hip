@@ -182,7 +182,7 @@ lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, c
   const int* ord = tile_order(h, g, 0, g.nbp, true, prec, &ost);
   if (ost != LRCC_OK) return ost;
   LRCC_HIP(h, ppl_launch(prec, cmul, acc64, g, Ls, Xb, Sb, h->tab.as<int>(), ord, nonherm,
-                         h->occ[prec], h->stream));
+                         h->occ[prec][cmul], h->stream));
   if (h->timing) {
     LRCC_HIP(h, hipEventRecord(e1, h->stream));
     ++h->tev_used;

@@ -71,7 +71,7 @@ struct lrcc_handle_s {
   long order_key[3][6] = {{-1, -1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1, -1},
                           {-1, -1, -1, -1, -1, -1}};
   int order_s[3] = {0, 0, 0};  // super-tile width per precision (0 = default)
-  int occ[3] = {0, 0, 0}; // 4M launch variant per precision (1-5, 0 = default)
+  int occ[3][2] = {};     // launch variant per precision and complex form (0 = default)
   lrcc::Buf vws;          // bf16x3: one panel of antisymmetrised integral tiles
   size_t panel_cap = 0;   // bytes allowed for vws (0 = not yet chosen)
   int tab_nbv = -1;

@@ -500,53 +500,86 @@ struct Smem3 {
   static constexpr int elems = 4 * chunk > 2 * NS * VS ? 4 * chunk : 2 * NS * VS;
 };
 
-template <typename T, int KC>
+template <typename T, int KC, bool DL, int NW>
 __device__ __forceinline__ void build_v_3m(const T* __restrict__ Ls, const int* __restrict__ tab,
                                            int nbv, int ncp, int v, int ab, int cd, T* lds) {
   typedef typename Acc<T>::t acc_t;
   typedef typename Vec16<T>::t vec_t;
   constexpr int VN = Vec16<T>::n;
   constexpr int CH = Smem3<T, KC>::chunk;
+  static_assert(NW == 4 || (NW == 8 && DL), "eight waves load chunks straight into LDS");
+  constexpr int NJ = 16 / NW;  // 16-column blocks per wave
   const int pAB = tab[ab], pCD = tab[cd];
   const int A = pAB >> 16, B = pAB & 0xffff, C = pCD >> 16, D = pCD & 0xffff;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  const int rw = wave & 3, j0 = (wave >> 2) * NJ;
 
   const size_t bstride = (size_t)ncp * 3 * NS;
-  const T* const gblk[4] = {Ls + (size_t)(A * nbv + C) * bstride,
-                            Ls + (size_t)(B * nbv + D) * bstride,
-                            Ls + (size_t)(A * nbv + D) * bstride,
-                            Ls + (size_t)(B * nbv + C) * bstride};
-  acc_t t1[2][4], t2[2][4], t3[2][4];  // [W1 / W2][column block]
+  const T* const g0 = Ls + (size_t)(A * nbv + C) * bstride;
+  const T* const g1 = Ls + (size_t)(B * nbv + D) * bstride;
+  const T* const g2 = Ls + (size_t)(A * nbv + D) * bstride;
+  const T* const g3 = Ls + (size_t)(B * nbv + C) * bstride;
+  acc_t t1[2][NJ], t2[2][NJ], t3[2][NJ];  // [W1 / W2][column block]
 #pragma unroll
   for (int w = 0; w < 2; ++w)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       t1[w][j] = acc_t{0, 0, 0, 0};
       t2[w][j] = t1[w][j];
       t3[w][j] = t1[w][j];
     }
-  constexpr int KPB = CH / VN / WG;
-  static_assert(KPB * VN * WG == CH, "chunk must split evenly over the workgroup");
+  // DL = false: chunks prefetched through registers one ahead; DL = true:
+  // loaded straight into a two-chunk LDS ring (1 KB per wave instruction)
+  constexpr int KPB = DL ? 1 : CH / VN / WG;
+  static_assert(DL || KPB * VN * WG == CH, "chunk must split evenly over the workgroup");
+  constexpr int PPB = CH * (int)sizeof(T) / 1024;  // 1 KB pieces per block chunk
+  static_assert(!DL || (CH * (int)sizeof(T)) % 1024 == 0, "whole pieces per block");
+  static_assert(!DL || (4 * PPB) % NW == 0, "whole pieces per wave");
   vec_t pf[4 * KPB];
   auto fetch = [&](int p0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const vec_t* src = reinterpret_cast<const vec_t*>(gblk[q] + (size_t)p0 * 3 * NS);
+      const T* gq = q == 0 ? g0 : q == 1 ? g1 : q == 2 ? g2 : g3;
+      const vec_t* src = reinterpret_cast<const vec_t*>(gq + (size_t)p0 * 3 * NS);
 #pragma unroll
       for (int k = 0; k < KPB; ++k) pf[q * KPB + k] = src[k * WG + threadIdx.x];
     }
   };
-  fetch(0);
-  for (int p0 = 0; p0 < ncp; p0 += KC) {
-    __syncthreads();  // previous chunk (or a previous V tile) no longer read
+  auto issue = [&](int p0, T* buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int k = 0; k < 4 * PPB / NW; ++k) {
+      const int gp = k * NW + wave, q = gp / PPB, pb = gp - q * PPB;
+      const T* gq = q == 0 ? g0 : q == 1 ? g1 : q == 2 ? g2 : g3;
+      __builtin_amdgcn_global_load_lds(
+          reinterpret_cast<const char*>(gq + (size_t)p0 * 3 * NS) + pb * 1024 + lane * 16,
+          (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(buf + q * CH) +
+                                                    pb * 1024),
+          16, 0, 0);
+    }
+  };
+  T* const ring0 = lds;
+  T* const ring1 = lds + (DL ? 4 * CH : 0);
+  __syncthreads();  // LDS may still hold the V tile of a previous contraction
+  if (DL) issue(0, ring0);
+  else fetch(0);
+  for (int p0 = 0, c = 0; p0 < ncp; p0 += KC, ++c) {
+    T* cur = lds;
+    if (DL) {
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this chunk has landed
+      __syncthreads();                     // every wave: loads landed, previous chunk done
+      cur = (c & 1) ? ring1 : ring0;
+      issue(min(p0 + KC, ncp - KC), (c & 1) ? ring0 : ring1);  // branch-free: last again
+    } else {
+      __syncthreads();  // previous chunk no longer read
 #pragma unroll
-      for (int k = 0; k < KPB; ++k)
-        reinterpret_cast<vec_t*>(lds + q * CH)[k * WG + threadIdx.x] = pf[q * KPB + k];
-    __syncthreads();
-    if (p0 + KC < ncp) fetch(p0 + KC);
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < KPB; ++k)
+          reinterpret_cast<vec_t*>(lds + q * CH)[k * WG + threadIdx.x] = pf[q * KPB + k];
+      __syncthreads();
+      fetch(min(p0 + KC, ncp - KC));
+    }
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
       const int p = 4 * ks + lk;
@@ -554,11 +587,11 @@ __device__ __forceinline__ void build_v_3m(const T* __restrict__ Ls, const int* 
       for (int w = 0; w < 2; ++w) {
         // W1: rows from L_AC (block 0), columns from L_BD (block 1);
         // W2: rows from L_AD (block 2), columns from L_BC (block 3)
-        const T* la = lds + (2 * w) * CH + p * 3 * NS + 16 * wave + li;
-        const T* lb = lds + (2 * w + 1) * CH + p * 3 * NS + li;
+        const T* la = cur + (2 * w) * CH + p * 3 * NS + 16 * rw + li;
+        const T* lb = cur + (2 * w + 1) * CH + p * 3 * NS + 16 * j0 + li;
         const T a0 = la[0], a1 = la[NS], a2 = la[2 * NS];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NJ; ++j) {
           t1[w][j] = mfma(a0, lb[16 * j], t1[w][j]);
           t2[w][j] = mfma(a1, lb[NS + 16 * j], t2[w][j]);
           t3[w][j] = mfma(a2, lb[2 * NS + 16 * j], t3[w][j]);
@@ -566,26 +599,27 @@ __device__ __forceinline__ void build_v_3m(const T* __restrict__ Ls, const int* 
       }
     }
   }
+  if (DL) __builtin_amdgcn_s_waitcnt(0x0F70);  // the spare load has landed
   __syncthreads();
 
   // antisymmetrise into V[cd][ab] (planar re, im) in LDS
   T* Vr = lds;
   T* Vi = lds + NS * VS;
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
+  for (int j = 0; j < NJ; ++j)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = 16 * wave + out_row<T>(lk, r), jj = 16 * j + li;  // (a,c), (b,d)
+      const int i = 16 * rw + out_row<T>(lk, r), jj = 16 * (j0 + j) + li;  // (a,c), (b,d)
       const int idx = ((i & 7) * TB + (jj & 7)) * VS + (i >> 3) * TB + (jj >> 3);
       Vr[idx] = (T)2 * (t1[0][j][r] - t2[0][j][r]);
       Vi[idx] = (T)2 * (t3[0][j][r] - t1[0][j][r] - t2[0][j][r]);
     }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
+  for (int j = 0; j < NJ; ++j)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = 16 * wave + out_row<T>(lk, r), jj = 16 * j + li;  // (a,d), (b,c)
+      const int i = 16 * rw + out_row<T>(lk, r), jj = 16 * (j0 + j) + li;  // (a,d), (b,c)
       const int al = i >> 3, dl = i & 7, bl = jj >> 3, cl = jj & 7;
       const int idx = (cl * TB + dl) * VS + al * TB + bl;
       const bool live = (A < B || al < bl) && (B * TB + bl < v) && (C < D || cl < dl) &&
@@ -597,23 +631,24 @@ __device__ __forceinline__ void build_v_3m(const T* __restrict__ Ls, const int* 
   __syncthreads();
 }
 
-template <typename T, typename TA, int KC>
-__global__ __launch_bounds__(WG, 1) void k_ppl_3m(const T* __restrict__ Ls,
-                                                  const T* __restrict__ Xb,
-                                                  TA* __restrict__ Sb,
-                                                  const int* __restrict__ tab,
-                                                  const int* __restrict__ order,
-                                                  const int* __restrict__ nonherm, int nbv,
-                                                  int nbp, int ncp, int Mp, int v) {
-  __shared__ __attribute__((aligned(16))) T lds[Smem3<T, KC>::elems];
+template <typename T, typename TA, int KC, bool DL, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void k_ppl_3m(const T* __restrict__ Ls,
+                                                       const T* __restrict__ Xb,
+                                                       TA* __restrict__ Sb,
+                                                       const int* __restrict__ tab,
+                                                       const int* __restrict__ order,
+                                                       const int* __restrict__ nonherm, int nbv,
+                                                       int nbp, int ncp, int Mp, int v) {
+  constexpr int NE = DL ? 8 * Smem3<T, KC>::chunk : Smem3<T, KC>::elems;
+  __shared__ __attribute__((aligned(16))) T lds[NE > Smem3<T, KC>::elems ? NE : Smem3<T, KC>::elems];
   int x, y;
   bool mirror;
   if (!decode_item(order, (long)nbp * (nbp + 1) / 2, nbp, blockIdx.x, *nonherm != 0, &x, &y,
                    &mirror))
     return;
-  tile_item<T, TA, 1, 4>(
-      [&](int p, int q) { build_v_3m<T, KC>(Ls, tab, nbv, ncp, v, p, q, lds); }, Xb, Sb, nbp,
-      Mp, x, y, mirror, lds);
+  tile_item<T, TA, 1, NW>(
+      [&](int p, int q) { build_v_3m<T, KC, DL, NW>(Ls, tab, nbv, ncp, v, p, q, lds); }, Xb,
+      Sb, nbp, Mp, x, y, mirror, lds);
 }
 
 
@@ -631,7 +666,8 @@ constexpr int KC32 = 32;
 // 5 = as 3 with eight waves (two per SIMD, each holding half the tile's
 // accumulators).
 bool ppl_has_variant(lrcc_prec prec, lrcc_cmul cmul, int variant) {
-  if (cmul != LRCC_CMUL_4M) return variant == 1;
+  if (cmul == LRCC_CMUL_3M)  // 3M: register prefetch, or eight waves with the ring
+    return (prec == LRCC_FP64 || prec == LRCC_FP32) && (variant == 1 || variant == 5);
   if (prec == LRCC_FP64) return variant == 1 || variant == 3 || variant == 5;  // 4 would spill
   if (prec == LRCC_FP32) return variant >= 1 && variant <= 5;
   return variant == 1;
@@ -661,16 +697,32 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
   const long ntile = ppl_ntile(g);
   if (ntile == 0 || g.Mp == 0) return hipSuccess;
   if (2 * ntile > 0x7fffffffL) return hipErrorInvalidValue;
-  dim3 grid((unsigned)(2 * ntile)), block(WG);  // tiles, then their mirrors (3M: 4 waves)
+  if (prec != LRCC_FP64 && prec != LRCC_FP32) return hipErrorNotSupported;
+  const dim3 grid((unsigned)(2 * ntile));  // tiles, then their mirrors
+  if (occ == 0) {
+    // untuned default (the fastest measured at the baseline and precision
+    // workloads): FP64 and 3M eight waves with the direct-to-LDS chunk ring;
+    // FP32 4M two workgroups per CU, with direct loads when the sums are FP32
+    const char* e = getenv("LRCC_VARIANT");
+    occ = e ? atoi(e) : cmul != LRCC_CMUL_4M || prec == LRCC_FP64 ? 5 : acc64 ? 2 : 4;
+  }
+  if (!ppl_has_variant(prec, cmul, occ)) occ = 1;
   if (cmul == LRCC_CMUL_3M) {
-#define LRCC_L3(T, TA, KC)                                                                      \
-  hipLaunchKernelGGL((k_ppl_3m<T, TA, KC>), grid, block, 0, st, static_cast<const T*>(Ls),     \
-                     static_cast<const T*>(Xb), static_cast<TA*>(Sb), tab, order, nonherm, g.nbv, \
-                     g.nbp, g.ncp, (int)g.Mp, g.v)
-    if (prec == LRCC_FP64) LRCC_L3(double, double, 8);
-    else if (prec == LRCC_FP32 && acc64) LRCC_L3(float, double, 16);
-    else if (prec == LRCC_FP32) LRCC_L3(float, float, 16);
-    else return hipErrorNotSupported;
+#define LRCC_L3(T, TA, KC, DL, NW)                                                              \
+  hipLaunchKernelGGL((k_ppl_3m<T, TA, KC, DL, NW>), grid, dim3(64 * NW), 0, st,                 \
+                     static_cast<const T*>(Ls), static_cast<const T*>(Xb), static_cast<TA*>(Sb), \
+                     tab, order, nonherm, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v)
+    const bool w8 = occ == 5;
+    if (prec == LRCC_FP64) {
+      if (w8) LRCC_L3(double, double, 8, true, 8);
+      else LRCC_L3(double, double, 8, false, 4);
+    } else if (acc64) {
+      if (w8) LRCC_L3(float, double, 16, true, 8);
+      else LRCC_L3(float, double, 16, false, 4);
+    } else {
+      if (w8) LRCC_L3(float, float, 16, true, 8);
+      else LRCC_L3(float, float, 16, false, 4);
+    }
 #undef LRCC_L3
     return hipGetLastError();
   }
@@ -678,37 +730,22 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
   hipLaunchKernelGGL((k_ppl_4m<T, TA, KC, OCC, DL, NW>), grid, dim3(64 * NW), 0, st,         \
                      static_cast<const T*>(Ls), static_cast<const T*>(Xb), static_cast<TA*>(Sb), \
                      tab, order, nonherm, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v)
-  // variant: 1 = one WG/CU with register prefetch, 2 = two WG/CU (FP32),
-  // 3 = one WG/CU with direct-to-LDS chunk ring, 4 = two WG/CU with direct loads
-  if (occ == 0) {
-    // untuned default (the fastest measured at the baseline and precision
-    // workloads): FP64 eight waves with the direct-to-LDS chunk ring; FP32
-    // two workgroups per CU, with direct loads when the sums are FP32
-    const char* e = getenv("LRCC_VARIANT");
-    occ = e ? atoi(e)
-            : cmul != LRCC_CMUL_4M ? 1 : prec == LRCC_FP64 ? 5 : acc64 ? 2 : 4;
-  }
-  if (!ppl_has_variant(prec, cmul, occ)) occ = 1;
   if (prec == LRCC_FP64) {
     if (occ == 3) LRCC_L4(double, double, KC64, 1, true, 4);
     else if (occ == 5) LRCC_L4(double, double, KC64, 1, true, 8);
     else LRCC_L4(double, double, KC64, 1, false, 4);
-  } else if (prec == LRCC_FP32) {
-    if (acc64) {
-      if (occ == 2) LRCC_L4(float, double, 16, 2, false, 4);
-      else if (occ == 3) LRCC_L4(float, double, KC32, 1, true, 4);
-      else if (occ == 4) LRCC_L4(float, double, 16, 2, true, 4);
-      else if (occ == 5) LRCC_L4(float, double, KC32, 1, true, 8);
-      else LRCC_L4(float, double, KC32, 1, false, 4);
-    } else {
-      if (occ == 2) LRCC_L4(float, float, 16, 2, false, 4);
-      else if (occ == 3) LRCC_L4(float, float, KC32, 1, true, 4);
-      else if (occ == 4) LRCC_L4(float, float, 16, 2, true, 4);
-      else if (occ == 5) LRCC_L4(float, float, KC32, 1, true, 8);
-      else LRCC_L4(float, float, KC32, 1, false, 4);
-    }
+  } else if (acc64) {
+    if (occ == 2) LRCC_L4(float, double, 16, 2, false, 4);
+    else if (occ == 3) LRCC_L4(float, double, KC32, 1, true, 4);
+    else if (occ == 4) LRCC_L4(float, double, 16, 2, true, 4);
+    else if (occ == 5) LRCC_L4(float, double, KC32, 1, true, 8);
+    else LRCC_L4(float, double, KC32, 1, false, 4);
   } else {
-    return hipErrorNotSupported;
+    if (occ == 2) LRCC_L4(float, float, 16, 2, false, 4);
+    else if (occ == 3) LRCC_L4(float, float, KC32, 1, true, 4);
+    else if (occ == 4) LRCC_L4(float, float, 16, 2, true, 4);
+    else if (occ == 5) LRCC_L4(float, float, KC32, 1, true, 8);
+    else LRCC_L4(float, float, KC32, 1, false, 4);
   }
 #undef LRCC_L4
   return hipGetLastError();

@@ -827,7 +827,7 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
   if (anchor != LRCC_FP64 && anchor != LRCC_FP32)
     return fail(h, LRCC_ERR_ARG, "anchor_prec must be FP64 or FP32");
   LRCC_HIP(h, herm_check(L, LRCC_C128, v, nchol, S.nonherm, h->stream));
-  st = stage_for(S, L, anchor, LRCC_CMUL_4M, h->ls);
+  st = stage_for(S, L, anchor, op.cmul, h->ls);
   if (st != LRCC_OK) return st;
   if (ir) {
     st = stage_for(S, L, op.prec, op.cmul, h->ls2);
@@ -839,7 +839,7 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
   lrcc_status result = LRCC_OK;
   double final_rel = 0;
   if (!ir) {
-    result = jacobi_diis(S, S.b, S.x, LRCC_FP64, LRCC_CMUL_4M, h->ls.p, O.tol, O.max_iter,
+    result = jacobi_diis(S, S.b, S.x, LRCC_FP64, op.cmul, h->ls.p, O.tol, O.max_iter,
                          all.data());
     for (int r = 0; r < S.n; ++r) final_rel = std::max(final_rel, S.h_relres[r]);
     if (result == LRCC_ERR_NONFINITE) return fail(h, result, "non-finite residual");
@@ -865,7 +865,7 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
                          S.x2);
       LRCC_HIP(h, hipGetLastError());
       if (outer == 0 || op.resid_fp64_every) {
-        st = apply_sigma(S, S.x2, anchor, LRCC_CMUL_4M, h->ls.p);
+        st = apply_sigma(S, S.x2, anchor, op.cmul, h->ls.p);
         if (st != LRCC_OK) return st;
         LRCC_HIP(h, hipMemcpyAsync(S.sx, S.s, vb, hipMemcpyDeviceToDevice, h->stream));
       } else {

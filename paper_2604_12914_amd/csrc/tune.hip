@@ -76,7 +76,7 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
       double ms = 0;
       if (rest >> s >> occ >> ms && s > 0 && occ >= 1 && occ <= 5) {
         h->order_s[prec] = s;
-        h->occ[prec] = occ;
+        h->occ[prec][cmul] = occ;
         if (out) *out = lrcc_tune_result{s, occ, ms, 0};
         return LRCC_OK;
       }
@@ -116,14 +116,14 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
   for (int var = 1; var <= 5; ++var)
     if (ppl_has_variant(prec, cmul, var)) occs.push_back(var);
 
-  const int saved_s = h->order_s[prec], saved_occ = h->occ[prec];
+  const int saved_s = h->order_s[prec], saved_occ = h->occ[prec][cmul];
   const bool saved_timing = h->timing;
   int best_s = widths[0], best_occ = 1, ncand = 0;
   double best = 1e300;
   for (int s : widths) {
     for (int occ : occs) {
       h->order_s[prec] = s;
-      h->occ[prec] = occ;
+      h->occ[prec][cmul] = occ;
       double ms_best = 1e300;
       for (int rep = 0; rep < 3; ++rep) {
         h->timing = rep > 0;
@@ -132,7 +132,7 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
                                       false, X, S, LRCC_C128, prec, cmul);
         if (st != LRCC_OK) {
           h->order_s[prec] = saved_s;
-          h->occ[prec] = saved_occ;
+          h->occ[prec][cmul] = saved_occ;
           h->timing = saved_timing;
           h->tev_used = 0;
           return st;
@@ -159,7 +159,7 @@ lrcc_status autotune_impl(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc
   h->timing = saved_timing;
   h->tev_used = 0;  // the tuner reused the timing events: totals restart
   h->order_s[prec] = best_s;
-  h->occ[prec] = best_occ;
+  h->occ[prec][cmul] = best_occ;
   if (out) *out = lrcc_tune_result{best_s, best_occ, best, ncand};
   if (cache_path) {
     std::ofstream app(cache_path, std::ios::app);

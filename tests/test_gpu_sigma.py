@@ -324,8 +324,10 @@ def test_autotune_cache_and_parity_after_tuning(lrcc, tmp_path):
 
 
 @pytest.mark.parametrize("herm", [True, False])
-@pytest.mark.parametrize("prec,variants", [("fp32", (2, 3, 4, 5, 1)), ("fp64", (3, 5, 1))])
-def test_launch_variants(lrcc, tmp_path, prec, variants, herm):
+@pytest.mark.parametrize("prec,cmul,variants", [("fp32", "4m", (2, 3, 4, 5, 1)),
+                                                ("fp64", "4m", (3, 5, 1)),
+                                                ("fp64", "3m", (5, 1)), ("fp32", "3m", (5, 1))])
+def test_launch_variants(lrcc, tmp_path, prec, cmul, variants, herm):
     # force each launch variant of the fused kernel through a tuner cache
     # entry and check parity with it; 132 rows = 9 chunks of 16: whole rounds
     # for four and eight waves plus a chunk shared out column-block-wise
@@ -342,12 +344,13 @@ def test_launch_variants(lrcc, tmp_path, prec, variants, herm):
             ("fp64", torch.complex128): (ppl.sigma(L, X, o, v), 1e-10),
             ("fp64", torch.complex64): (ref64, 1e-6)}
     code = {"fp64": 0, "fp32": 1}[prec]
+    ccode = {"4m": 0, "3m": 1}[cmul]
     for var in variants:
-        print(f"{prec} variant {var}", flush=True)
-        cache = tmp_path / f"force{prec}{var}.txt"
-        cache.write_text(f"gfx950 {ncu} {o} {v} {nchol} {nrhs} {code} 0 4 {var} 1.0\n")
-        r = lrcc.autotune(o, v, nchol, nrhs, prec=prec, cache_path=str(cache))
+        print(f"{prec} {cmul} variant {var}", flush=True)
+        cache = tmp_path / f"force{prec}{cmul}{var}.txt"
+        cache.write_text(f"gfx950 {ncu} {o} {v} {nchol} {nrhs} {code} {ccode} 4 {var} 1.0\n")
+        r = lrcc.autotune(o, v, nchol, nrhs, prec=prec, cmul=cmul, cache_path=str(cache))
         assert r["occupancy"] == var and r["candidates"] == 0
         for dtype in (torch.complex128, torch.complex64):
             ref, tol = bars[(prec, dtype)]
-            assert rel(run(lrcc, L, X, prec=prec, dtype=dtype), ref) < tol
+            assert rel(run(lrcc, L, X, prec=prec, cmul=cmul, dtype=dtype), ref) < tol
