@@ -332,8 +332,19 @@ constexpr int QG = 8;
 // The list is split into nsplit parts (outermost): part p of a workgroup's
 // tiles goes to a workgroup of its own, so that short grids still fill whole
 // rounds of resident workgroups; parts add their sums atomically.
+// With several panels the workgroups of block pairs inside the panel run the
+// whole list and the others only the panel's mirror tiles: there (grouped =
+// false) the plain order, q ascending with its m-blocks and parts, dispatches
+// the long workgroups first and spreads them over all XCDs.
 __device__ __forceinline__ void contract_item(int w, int total, int nx, int nmb, int nq,
-                                              int* q, int* mb, int* part) {
+                                              bool grouped, int* q, int* mb, int* part) {
+  if (!grouped) {
+    const int ns = total / (nmb * nq), r = w % (nmb * ns);
+    *q = w / (nmb * ns);
+    *mb = r / ns;
+    *part = r % ns;
+    return;
+  }
   const int x = w % nx, j = w / nx;
   const int share = total / nx, rem = total % nx;
   int L = x * share + (x < rem ? x : rem) + j;
@@ -351,10 +362,10 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
                                                     const __bf16* __restrict__ Vdir,
                                                     const __bf16* __restrict__ Vmir, int nbp,
                                                     int Mp, int nmb, int ab0, int ab1, int nx,
-                                                    TA* __restrict__ Sb) {
+                                                    int grouped, TA* __restrict__ Sb) {
   __shared__ __attribute__((aligned(16))) __bf16 vt[VTP];  // 36 KB
   int mb, ql, part;
-  contract_item(blockIdx.x, (int)gridDim.x, nx, nmb, nbp - ab0, &ql, &mb, &part);
+  contract_item(blockIdx.x, (int)gridDim.x, nx, nmb, nbp - ab0, grouped != 0, &ql, &mb, &part);
   const int nsplit = (int)gridDim.x / (nmb * (nbp - ab0));
   const int q = ab0 + ql;
   const int ndir = q < ab1 ? nbp - q : 0;
@@ -558,11 +569,11 @@ hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* 
     if (acc64)
       hipLaunchKernelGGL(k_contract<double>, grid, dim3(WG), 0, st,
                          static_cast<const __bf16*>(Xb), Vdir, Vmir, g.nbp, (int)g.Mp, nmb, ab0,
-                         ab0 + n, nx, static_cast<double*>(Sb));
+                         ab0 + n, nx, (int)(n == g.nbp), static_cast<double*>(Sb));
     else
       hipLaunchKernelGGL(k_contract<float>, grid, dim3(WG), 0, st,
                          static_cast<const __bf16*>(Xb), Vdir, Vmir, g.nbp, (int)g.Mp, nmb, ab0,
-                         ab0 + n, nx, static_cast<float*>(Sb));
+                         ab0 + n, nx, (int)(n == g.nbp), static_cast<float*>(Sb));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
