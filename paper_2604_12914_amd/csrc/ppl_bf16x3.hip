@@ -110,7 +110,15 @@ __global__ void k_stage_L16(const void* __restrict__ L, lrcc_dtype dt, int v, in
   }
 }
 
-// Packed doubles -> Xb16[plane][bp][m][64] (hi/lo split, zeros in dead slots)
+// The bf16 X planes hold each block pair's 64 slots as two halves of 32
+// (the two k-steps of the contraction), row after row within a half:
+// Xb16[plane][bp][half][m][32].  One contraction load of 16 rows x 32 slots
+// is then 1 KB of whole cache lines.
+__device__ __forceinline__ long x16_index(long bp, long m, int s, long Mp) {
+  return ((bp * 2 + (s >> 5)) * Mp + m) * 32 + (s & 31);
+}
+
+// Packed doubles -> Xb16 (hi/lo split, zeros in dead slots)
 __global__ void k_pack_x16(const void* __restrict__ X, lrcc_dtype dt, int v, long npv, long M,
                            long Mp, int nbp, const int* __restrict__ tab, __bf16* __restrict__ Xb) {
   const long plane = (long)nbp * Mp * NS;
@@ -127,17 +135,20 @@ __global__ void k_pack_x16(const void* __restrict__ X, lrcc_dtype dt, int v, lon
       re = (float)z.x;
       im = (float)z.y;
     }
-    split(re, Xb[e], Xb[e + plane]);
-    split(im, Xb[e + 2 * plane], Xb[e + 3 * plane]);
+    const long d = x16_index(bp, m, s, Mp);
+    split(re, Xb[d], Xb[d + plane]);
+    split(im, Xb[d + 2 * plane], Xb[d + 3 * plane]);
   }
 }
 
-// FP64 block planes -> bf16 hi/lo planes (same layout)
-__global__ void k_split_x16(long plane, const double* __restrict__ x, __bf16* __restrict__ Xb) {
+// FP64 block planes [plane][bp][m][64] -> Xb16 hi/lo planes
+__global__ void k_split_x16(long plane, long Mp, const double* __restrict__ x,
+                            __bf16* __restrict__ Xb) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < plane;
        e += (long)gridDim.x * blockDim.x) {
-    split((float)x[e], Xb[e], Xb[e + plane]);
-    split((float)x[e + plane], Xb[e + 2 * plane], Xb[e + 3 * plane]);
+    const long d = x16_index(e / (NS * Mp), (e / NS) % Mp, (int)(e % NS), Mp);
+    split((float)x[e], Xb[d], Xb[d + plane]);
+    split((float)x[e + plane], Xb[d + 2 * plane], Xb[d + 3 * plane]);
   }
 }
 
@@ -355,15 +366,15 @@ __device__ __forceinline__ void contract_item(int w, int total, int nx, int nmb,
   *mb = r / gq;
   *q = group * QG + r % gq;
 }
-// Two workgroups per CU: while one waits for its tile's X rows (loaded per
-// tile, straight into registers) the other keeps the matrix cores busy.
+// Two workgroups per CU: while one waits for its X rows (loaded straight into
+// registers, half a tile ahead) the other keeps the matrix cores busy.
 template <typename TA>
 __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ Xb,
                                                     const __bf16* __restrict__ Vdir,
                                                     const __bf16* __restrict__ Vmir, int nbp,
                                                     int Mp, int nmb, int ab0, int ab1, int nx,
                                                     int grouped, TA* __restrict__ Sb) {
-  __shared__ __attribute__((aligned(16))) __bf16 vt[VTP];  // 36 KB
+  __shared__ __attribute__((aligned(16))) __bf16 vt[2 * VTP];  // two V tiles, 72 KB
   int mb, ql, part;
   contract_item(blockIdx.x, (int)gridDim.x, nx, nmb, nbp - ab0, grouped != 0, &ql, &mb, &part);
   const int nsplit = (int)gridDim.x / (nmb * (nbp - ab0));
@@ -373,24 +384,27 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
   const int it0 = (int)((long)(ndir + nmir) * part / nsplit);
   const int ntl = (int)((long)(ndir + nmir) * (part + 1) / nsplit);
   // tile it of this workgroup and the block pair whose X rows it contracts
+  // (selects, no branches: the loads that use them stay where they are put)
   auto tile_of = [&](int it, int* xblk) -> const __bf16* {
-    if (it < nmir) {
-      *xblk = ab0 + it;
-      return Vmir + panel_tile(nbp, ab0, it, q) * VT;
-    }
+    const bool mir = it < nmir;
     const int d = it - nmir;
-    *xblk = q + d;
-    return Vdir + panel_tile(nbp, ab0, q - ab0, q + d) * VT;
+    *xblk = mir ? ab0 + it : q + d;
+    const long t = mir ? panel_tile(nbp, ab0, it, q) : panel_tile(nbp, ab0, q - ab0, q + d);
+    return (mir ? Vmir : Vdir) + t * VT;
   };
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const size_t plane = (size_t)nbp * Mp * NS;
-  int mrow[2];
+  // rows of this wave; blocks past Mp (the last m-block of a short Mp) load
+  // row block 0 instead, so every load is unconditional and in bounds, and
+  // their sums are never stored
+  int mrow[2], mld[2];
   bool mok[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     mrow[i] = mb * 128 + 32 * wave + 16 * i;
     mok[i] = mrow[i] < Mp;
+    mld[i] = mok[i] ? mrow[i] : 0;
   }
   f4 sr[2][4], si[2][4];
 #pragma unroll
@@ -400,22 +414,24 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
       sr[i][j] = (f4){0, 0, 0, 0};
       si[i][j] = sr[i][j];
     }
-  // X operands of one CD: [mblk][k-step][plane], 8 consecutive cd per lane
+  // X operands of one CD: [mblk][k-step][plane], 8 consecutive cd per lane.
+  // The two k-steps rotate through the loads: k-step 1 of this tile is
+  // requested while k-step 0 is contracted, k-step 0 of the next tile while
+  // k-step 1 is; the vector-memory counter retires in order, so each wait
+  // covers exactly the loads issued before the ones still in flight.
   bf8 xa[2][2][4];
-  auto fetch_x = [&](int cd, bf8 (&dst)[2][2][4]) {
+  auto fetch_x = [&](int cd, int ks) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          bf8 z = {};
-          if (mok[i])
-            z = *reinterpret_cast<const bf8*>(
-                Xb + p * plane + ((size_t)cd * Mp + mrow[i] + li) * NS + 32 * ks + 8 * lk);
-          dst[i][ks][p] = z;
-        }
+      for (int p = 0; p < 4; ++p)
+        xa[i][ks][p] = *reinterpret_cast<const bf8*>(
+            Xb + p * plane + (((size_t)cd * 2 + ks) * Mp + mld[i] + li) * 32 + 8 * lk);
   };
+  // V tiles: a two-tile LDS ring, filled through registers.  The next tile
+  // is requested at the start of a tile and stored to the free buffer at its
+  // end, so one barrier per tile suffices and its load has a whole tile of
+  // matrix work to land.
   constexpr int VV = VT / 8 / WG;  // 16-byte vectors per thread per V tile (8)
   u4 vp[VV];
   int xnext = 0;
@@ -424,43 +440,64 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
 #pragma unroll
     for (int k = 0; k < VV; ++k) vp[k] = reinterpret_cast<const u4*>(src)[k * WG + threadIdx.x];
   };
-  if (ntl > it0) fetch(it0);
-  for (int it = it0; it < ntl; ++it) {
-    const int xcur = xnext;
-    __syncthreads();
+  auto store_v = [&](__bf16* buf) {
 #pragma unroll
     for (int k = 0; k < VV; ++k) {
       // vector e of the tile: plane-row (e / 8), 8-bf16 part (e % 8)
       const int e = k * WG + threadIdx.x;
-      *reinterpret_cast<u4*>(vt + (e >> 3) * NSP + (e & 7) * 8) = vp[k];
+      *reinterpret_cast<u4*>(buf + (e >> 3) * NSP + (e & 7) * 8) = vp[k];
     }
-    __syncthreads();
-    if (it + 1 < ntl) fetch(it + 1);
-    fetch_x(xcur, xa);
+  };
+  auto contract_ks = [&](const __bf16* vb, int ks) {
+    bf8 nx[2][2];
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      bf8 nx[2][2];
+    for (int i = 0; i < 2; ++i) {
+      nx[i][0] = neg(xa[i][ks][2]);
+      nx[i][1] = neg(xa[i][ks][3]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bf8 b[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        b[p] = *reinterpret_cast<const bf8*>(vb + (p * NS + 16 * j + li) * NSP + 32 * ks +
+                                             8 * lk);
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        nx[i][0] = neg(xa[i][ks][2]);
-        nx[i][1] = neg(xa[i][ks][3]);
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        bf8 b[4];
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-          b[p] = *reinterpret_cast<const bf8*>(vt + (p * NS + 16 * j + li) * NSP + 32 * ks +
-                                               8 * lk);
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          sr[i][j] = mac3(xa[i][ks][0], xa[i][ks][1], b[0], b[1], sr[i][j]);
-          si[i][j] = mac3(xa[i][ks][0], xa[i][ks][1], b[2], b[3], si[i][j]);
-          sr[i][j] = mac3(nx[i][0], nx[i][1], b[2], b[3], sr[i][j]);
-          si[i][j] = mac3(xa[i][ks][2], xa[i][ks][3], b[0], b[1], si[i][j]);
-        }
+        sr[i][j] = mac3(xa[i][ks][0], xa[i][ks][1], b[0], b[1], sr[i][j]);
+        si[i][j] = mac3(xa[i][ks][0], xa[i][ks][1], b[2], b[3], si[i][j]);
+        sr[i][j] = mac3(nx[i][0], nx[i][1], b[2], b[3], sr[i][j]);
+        si[i][j] = mac3(xa[i][ks][2], xa[i][ks][3], b[0], b[1], si[i][j]);
       }
     }
+  };
+  if (ntl > it0) {
+    fetch(it0);
+    __builtin_amdgcn_sched_barrier(0);  // same load order as in the loop
+    fetch_x(xnext, 0);
+    store_v(vt);
+  }
+  for (int it = it0; it < ntl; ++it) {
+    const int xcur = xnext;
+    const int par = (it - it0) & 1;
+    const __bf16* const cur = vt + par * VTP;
+    __bf16* const nxt = vt + (par ^ 1) * VTP;
+    // this tile's V is visible to every wave, and every wave is done with
+    // the other buffer
+    __syncthreads();
+    fetch_x(xcur, 1);
+    // the next tile (this one again on the last pass: branch-free loads)
+    fetch(min(it + 1, ntl - 1));
+    // scheduling barriers keep each load group between the two k-steps
+    // instead of letting the scheduler sink it to the next barrier
+    __builtin_amdgcn_sched_barrier(0);
+    contract_ks(cur, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_x(xnext, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    contract_ks(cur, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    store_v(nxt);
   }
   // add this part's share of sigma[rows, q]: a plain update when the
   // workgroup is the only writer in this launch, atomic across parts
@@ -511,7 +548,7 @@ hipError_t bf16x3_pack_x(const void* X, lrcc_dtype dt, const Geom& g, const int*
 
 hipError_t bf16x3_split_x(const double* x, const Geom& g, void* Xb, hipStream_t st) {
   hipLaunchKernelGGL(k_split_x16, dim3(grid_for(g.xb_plane())), dim3(256), 0, st, g.xb_plane(),
-                     x, static_cast<__bf16*>(Xb));
+                     g.Mp, x, static_cast<__bf16*>(Xb));
   return hipGetLastError();
 }
 
