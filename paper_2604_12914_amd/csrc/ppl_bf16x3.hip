@@ -428,33 +428,31 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
         xa[i][ks][p] = *reinterpret_cast<const bf8*>(
             Xb + p * plane + (((size_t)cd * 2 + ks) * Mp + mld[i] + li) * 32 + 8 * lk);
   };
-  // V tiles: a two-tile LDS ring, filled through registers.  The next tile
-  // is requested at the start of a tile and stored to the free buffer at its
-  // end, so one barrier per tile suffices and its load has a whole tile of
-  // matrix work to land.
-  constexpr int VV = VT / 8 / WG;  // 16-byte vectors per thread per V tile (8)
-  u4 vp[VV];
+  // V tiles: a two-tile LDS ring, filled through registers in two halves.
+  // The first half of the next tile is requested at the start of a tile and
+  // stored to the free buffer after k-step 0, the second half requested then
+  // and stored at the end: one barrier per tile, each load has a k-step of
+  // matrix work to land, and only half a tile is held in registers.
+  constexpr int VH = VT / 8 / WG / 2;  // 16-byte vectors per thread per half tile (4)
+  u4 vp[VH];
   int xnext = 0;
-  auto fetch = [&](int it) {
-    const __bf16* src = tile_of(it, &xnext);
+  const __bf16* vsrc = Vdir;
+  auto fetch_v = [&](int h) {
 #pragma unroll
-    for (int k = 0; k < VV; ++k) vp[k] = reinterpret_cast<const u4*>(src)[k * WG + threadIdx.x];
+    for (int k = 0; k < VH; ++k)
+      vp[k] = reinterpret_cast<const u4*>(vsrc)[(h * VH + k) * WG + threadIdx.x];
   };
-  auto store_v = [&](__bf16* buf) {
+  auto store_v = [&](__bf16* buf, int h) {
 #pragma unroll
-    for (int k = 0; k < VV; ++k) {
+    for (int k = 0; k < VH; ++k) {
       // vector e of the tile: plane-row (e / 8), 8-bf16 part (e % 8)
-      const int e = k * WG + threadIdx.x;
+      const int e = (h * VH + k) * WG + threadIdx.x;
       *reinterpret_cast<u4*>(buf + (e >> 3) * NSP + (e & 7) * 8) = vp[k];
     }
   };
+  // sigma_r += Xr Vr^T - Xi Vi^T, sigma_i += Xr Vi^T + Xi Vr^T (the minus
+  // sign goes on the Vi operand: sign flips of its bf16 halves)
   auto contract_ks = [&](const __bf16* vb, int ks) {
-    bf8 nx[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      nx[i][0] = neg(xa[i][ks][2]);
-      nx[i][1] = neg(xa[i][ks][3]);
-    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       bf8 b[4];
@@ -462,20 +460,24 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
       for (int p = 0; p < 4; ++p)
         b[p] = *reinterpret_cast<const bf8*>(vb + (p * NS + 16 * j + li) * NSP + 32 * ks +
                                              8 * lk);
+      const bf8 nb2 = neg(b[2]), nb3 = neg(b[3]);
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         sr[i][j] = mac3(xa[i][ks][0], xa[i][ks][1], b[0], b[1], sr[i][j]);
+        sr[i][j] = mac3(xa[i][ks][2], xa[i][ks][3], nb2, nb3, sr[i][j]);
         si[i][j] = mac3(xa[i][ks][0], xa[i][ks][1], b[2], b[3], si[i][j]);
-        sr[i][j] = mac3(nx[i][0], nx[i][1], b[2], b[3], sr[i][j]);
         si[i][j] = mac3(xa[i][ks][2], xa[i][ks][3], b[0], b[1], si[i][j]);
       }
     }
   };
   if (ntl > it0) {
-    fetch(it0);
+    vsrc = tile_of(it0, &xnext);
+    fetch_v(0);
     __builtin_amdgcn_sched_barrier(0);  // same load order as in the loop
     fetch_x(xnext, 0);
-    store_v(vt);
+    store_v(vt, 0);
+    fetch_v(1);
+    store_v(vt, 1);
   }
   for (int it = it0; it < ntl; ++it) {
     const int xcur = xnext;
@@ -487,17 +489,20 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
     __syncthreads();
     fetch_x(xcur, 1);
     // the next tile (this one again on the last pass: branch-free loads)
-    fetch(min(it + 1, ntl - 1));
+    vsrc = tile_of(min(it + 1, ntl - 1), &xnext);
+    fetch_v(0);
     // scheduling barriers keep each load group between the two k-steps
     // instead of letting the scheduler sink it to the next barrier
     __builtin_amdgcn_sched_barrier(0);
     contract_ks(cur, 0);
     __builtin_amdgcn_sched_barrier(0);
+    store_v(nxt, 0);
+    fetch_v(1);
     fetch_x(xnext, 0);
     __builtin_amdgcn_sched_barrier(0);
     contract_ks(cur, 1);
     __builtin_amdgcn_sched_barrier(0);
-    store_v(nxt);
+    store_v(nxt, 1);
   }
   // add this part's share of sigma[rows, q]: a plain update when the
   // workgroup is the only writer in this launch, atomic across parts
