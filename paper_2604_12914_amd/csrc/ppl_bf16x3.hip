@@ -170,7 +170,10 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
                                                   int nbp, int ncp, int v, int ab0, long ptiles,
                                                   __bf16* __restrict__ Vdir,
                                                   __bf16* __restrict__ Vmir) {
-  __shared__ __attribute__((aligned(16))) __bf16 lds[2 * CHUNKP];  // 40 KB
+  // chunk buffers during the build, then W1 and W2 (f32, rows padded to VR)
+  constexpr int VR = NS + 1;
+  constexpr int LDSB = 2 * CHUNKP > 2 * 4 * NS * VR ? 2 * CHUNKP : 2 * 4 * NS * VR;
+  __shared__ __attribute__((aligned(16))) __bf16 lds[LDSB];  // 65 KB
   const bool nh = *nonherm != 0;
   const bool second = blockIdx.x >= ptiles;
   if (second && !nh) return;
@@ -259,41 +262,29 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
   }
   __syncthreads();
 
-  // antisymmetrise into V32[plane][ab][cd] (f32, rows padded to VR) in the
-  // chunk space
-  constexpr int VR = NS + 1;
-  float* Vr = reinterpret_cast<float*>(lds);
-  float* Vi = Vr + NS * VR;
-  if (wsel == 0) {
+  // W1 and W2 to LDS, each already at its V position [ab slot][cd slot]
+  // (plain stores by the two wave pairs at once), then the store loop forms
+  // V = 2 (W1 - W2) on the live slots (a < b, c < d, inside v) on the fly
+  float* const W1r = reinterpret_cast<float*>(lds);
+  float* const W1i = W1r + NS * VR;
+  float* const W2r = W1i + NS * VR;
+  float* const W2i = W2r + NS * VR;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int ii = 16 * (rb0 + i) + out_row(lk, r), jj = 16 * j + li;  // (a,c), (b,d)
-          const int idx = ((ii >> 3) * TB + (jj >> 3)) * VR + (ii & 7) * TB + (jj & 7);
-          Vr[idx] = 2.f * wr[i][j][r];
-          Vi[idx] = 2.f * wi[i][j][r];
-        }
-  }
-  __syncthreads();
-  if (wsel == 1) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int ii = 16 * (rb0 + i) + out_row(lk, r), jj = 16 * j + li;  // (a,d), (b,c)
-          const int al = ii >> 3, dl = ii & 7, bl = jj >> 3, cl = jj & 7;
-          const int idx = (al * TB + bl) * VR + cl * TB + dl;
-          const bool live = (A < B || al < bl) && (B * TB + bl < v) && (C < D || cl < dl) &&
-                            (D * TB + dl < v);
-          Vr[idx] = live ? Vr[idx] - 2.f * wr[i][j][r] : 0.f;
-          Vi[idx] = live ? Vi[idx] - 2.f * wi[i][j][r] : 0.f;
-        }
-  }
+      for (int r = 0; r < 4; ++r) {
+        const int ii = 16 * (rb0 + i) + out_row(lk, r), jj = 16 * j + li;
+        // W1: ii = (a,c), jj = (b,d);  W2: ii = (a,d), jj = (b,c)
+        const int idx = wsel == 0
+                            ? ((ii >> 3) * TB + (jj >> 3)) * VR + (ii & 7) * TB + (jj & 7)
+                            : ((ii >> 3) * TB + (jj >> 3)) * VR + (jj & 7) * TB + (ii & 7);
+        float* const wr_ = wsel == 0 ? W1r : W2r;
+        float* const wi_ = wsel == 0 ? W1i : W2i;
+        wr_[idx] = wr[i][j][r];
+        wi_[idx] = wi[i][j][r];
+      }
   __syncthreads();
   // split and write the tile as [plane][row slot][column slot]: the built
   // pair's V (rows ab) to the upper slot t, or, for a mirror workgroup, to
@@ -305,12 +296,19 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
       bf8 rh, rl, ih, il;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int idx = ct ? (q + e) * VR + row : row * VR + q + e;
+        // element V[ab][cd] of the built pair
+        const int ab = ct ? q + e : row, cd = ct ? row : q + e;
+        const int al = ab >> 3, bl = ab & 7, cl = cd >> 3, dl = cd & 7;
+        const bool live = (A < B || al < bl) && (B * TB + bl < v) && (C < D || cl < dl) &&
+                          (D * TB + dl < v);
+        const int idx = ab * VR + cd;
+        const float vr = live ? 2.f * (W1r[idx] - W2r[idx]) : 0.f;
+        const float vi = live ? 2.f * (W1i[idx] - W2i[idx]) : 0.f;
         __bf16 h, l;
-        split(Vr[idx], h, l);
+        split(vr, h, l);
         rh[e] = h;
         rl[e] = l;
-        split(ct ? -Vi[idx] : Vi[idx], h, l);
+        split(ct ? -vi : vi, h, l);
         ih[e] = h;
         il[e] = l;
       }
