@@ -170,10 +170,11 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
                                                   int nbp, int ncp, int v, int ab0, long ptiles,
                                                   __bf16* __restrict__ Vdir,
                                                   __bf16* __restrict__ Vmir) {
-  // chunk buffers during the build, then W1 and W2 (f32, rows padded to VR)
+  // two-chunk ring of column-side buffers during the build, then W1 and W2
+  // (f32, rows padded to VR)
   constexpr int VR = NS + 1;
-  constexpr int LDSB = 2 * CHUNKP > 2 * 4 * NS * VR ? 2 * CHUNKP : 2 * 4 * NS * VR;
-  __shared__ __attribute__((aligned(16))) __bf16 lds[LDSB];  // 65 KB
+  constexpr int LDSB = 4 * CHUNKP > 2 * 4 * NS * VR ? 4 * CHUNKP : 2 * 4 * NS * VR;
+  __shared__ __attribute__((aligned(16))) __bf16 lds[LDSB];  // 80 KB
   const bool nh = *nonherm != 0;
   const bool second = blockIdx.x >= ptiles;
   if (second && !nh) return;
@@ -208,57 +209,90 @@ __global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
   constexpr int V16 = CHUNK / 8;        // 16-byte vectors per block chunk (1024)
   constexpr int KPB = V16 / WG;         // per thread per block (4)
   u4 pf[2 * KPB];
-  bf8 an[2][4];                         // next chunk's row-side fragments
-  auto fetch = [&](int pc) {
+  // row-side fragments of even and odd chunks: [parity][MFMA block i][plane]
+  bf8 ra[2][2][4];
+  auto fetch_col = [&](int pc) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const u4* src = reinterpret_cast<const u4*>(gcol[q] + (size_t)pc * CHUNK);
 #pragma unroll
       for (int k = 0; k < KPB; ++k) pf[q * KPB + k] = src[k * WG + threadIdx.x];
     }
-    // A fragment of MFMA block i, plane p: row 16 (rb0 + i) + li, P = 8 lk .. 8 lk + 7
+  };
+  // A fragment of MFMA block i, plane p: row 16 (rb0 + i) + li, P = 8 lk .. 8 lk + 7
+  auto fetch_row = [&](int pc, int par) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int p = 0; p < 4; ++p)
-        an[i][p] = *reinterpret_cast<const bf8*>(grow + (size_t)pc * CHUNK +
-                                                 (p * NS + 16 * (rb0 + i) + li) * KB + 8 * lk);
+        ra[par][i][p] = *reinterpret_cast<const bf8*>(
+            grow + (size_t)pc * CHUNK + (p * NS + 16 * (rb0 + i) + li) * KB + 8 * lk);
   };
-  fetch(0);
-  for (int pc = 0; pc < nch; ++pc) {
-    __syncthreads();
+  auto store_col = [&](__bf16* buf) {
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int k = 0; k < KPB; ++k) {
         // vector e of the chunk: plane-row (e / 4), 8-bf16 part (e % 4)
         const int e = k * WG + threadIdx.x;
-        *reinterpret_cast<u4*>(lds + q * CHUNKP + (e >> 2) * KBP + (e & 3) * 8) = pf[q * KPB + k];
+        *reinterpret_cast<u4*>(buf + q * CHUNKP + (e >> 2) * KBP + (e & 3) * 8) = pf[q * KPB + k];
       }
-    bf8 a[2][4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int p = 0; p < 4; ++p) a[i][p] = an[i][p];
-    __syncthreads();
-    if (pc + 1 < nch) fetch(pc + 1);
+  };
+  // W += A B over one chunk: re += Ar Br - Ai Bi, im += Ar Bi + Ai Br (the
+  // minus sign on the Bi operand)
+  auto mma = [&](const __bf16* buf, int par) {
     // column operands: [plane][row][32 P], lane reads 8 consecutive P at 8*lk
-    const __bf16* lb = lds + wsel * CHUNKP + 8 * lk;
+    const __bf16* lb = buf + wsel * CHUNKP + 8 * lk;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       bf8 b[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p)
         b[p] = *reinterpret_cast<const bf8*>(lb + (p * NS + 16 * j + li) * KBP);
+      const bf8 nb2 = neg(b[2]), nb3 = neg(b[3]);
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const bf8 nih = neg(a[i][2]), nil = neg(a[i][3]);
-        wr[i][j] = mac3(a[i][0], a[i][1], b[0], b[1], wr[i][j]);  // Ar Br
-        wi[i][j] = mac3(a[i][0], a[i][1], b[2], b[3], wi[i][j]);  // Ar Bi
-        wr[i][j] = mac3(nih, nil, b[2], b[3], wr[i][j]);          // -Ai Bi
-        wi[i][j] = mac3(a[i][2], a[i][3], b[0], b[1], wi[i][j]);  // Ai Br
+        const bf8 (&a)[4] = ra[par][i];
+        wr[i][j] = mac3(a[0], a[1], b[0], b[1], wr[i][j]);  // Ar Br
+        wr[i][j] = mac3(a[2], a[3], nb2, nb3, wr[i][j]);    // -Ai Bi
+        wi[i][j] = mac3(a[0], a[1], b[2], b[3], wi[i][j]);  // Ar Bi
+        wi[i][j] = mac3(a[2], a[3], b[0], b[1], wi[i][j]);  // Ai Br
       }
     }
+  };
+  // Two-chunk ring: chunk pc sits in buffer pc & 1 (row side in registers
+  // ra[pc & 1]).  The next chunk is requested at the start of a chunk and
+  // its column side stored to the free buffer at the end, so one barrier per
+  // chunk suffices.  The loads of the last chunk repeat it (branch-free).
+  // (Scheduling barriers keep each load group where it is issued and the
+  // column loads ahead of the row loads, so that storing the column side
+  // waits for those alone.)
+  __bf16* const ring[2] = {lds, lds + 2 * CHUNKP};
+  fetch_col(0);
+  __builtin_amdgcn_sched_barrier(0);
+  fetch_row(0, 0);
+  store_col(ring[0]);
+  for (int pc = 0; pc + 1 < nch; pc += 2) {
+    __syncthreads();
+    fetch_col(pc + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_row(pc + 1, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(ring[0], 0);
+    __builtin_amdgcn_sched_barrier(0);
+    store_col(ring[1]);
+    __syncthreads();
+    fetch_col(min(pc + 2, nch - 1));
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_row(min(pc + 2, nch - 1), 0);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(ring[1], 1);
+    __builtin_amdgcn_sched_barrier(0);
+    store_col(ring[0]);
+  }
+  if (nch & 1) {  // the last chunk of an odd count
+    __syncthreads();
+    mma(ring[0], 0);
   }
   __syncthreads();
 
