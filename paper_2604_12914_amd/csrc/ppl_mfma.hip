@@ -494,19 +494,13 @@ __global__ __launch_bounds__(64 * QNW, 1) void k_ppl_queue(const BatchInst* __re
 // Cholesky blocks, T1 = sum ar br, T2 = sum ai bi, T3 = sum (ar+ai)(br+bi)
 // give re = T1 - T2 and im = T3 - T1 - T2: three real MFMA products per
 // complex product instead of four.  The contraction keeps the 4M form.
-template <typename T, int KC>
-struct Smem3 {
-  static constexpr int chunk = 3 * NS * KC;  // one block's chunk: KC vectors x 3 planes x 64
-  static constexpr int elems = 4 * chunk > 2 * NS * VS ? 4 * chunk : 2 * NS * VS;
-};
-
 template <typename T, int KC, bool DL, int NW>
 __device__ __forceinline__ void build_v_3m(const T* __restrict__ Ls, const int* __restrict__ tab,
                                            int nbv, int ncp, int v, int ab, int cd, T* lds) {
   typedef typename Acc<T>::t acc_t;
   typedef typename Vec16<T>::t vec_t;
   constexpr int VN = Vec16<T>::n;
-  constexpr int CH = Smem3<T, KC>::chunk;
+  constexpr int CH = Smem<T, KC>::chunk;
   static_assert(NW == 4 || (NW == 8 && DL), "eight waves load chunks straight into LDS");
   constexpr int NJ = 16 / NW;  // 16-column blocks per wave
   const int pAB = tab[ab], pCD = tab[cd];
@@ -515,7 +509,7 @@ __device__ __forceinline__ void build_v_3m(const T* __restrict__ Ls, const int* 
   const int li = lane & 15, lk = lane >> 4;
   const int rw = wave & 3, j0 = (wave >> 2) * NJ;
 
-  const size_t bstride = (size_t)ncp * 3 * NS;
+  const size_t bstride = (size_t)ncp * 2 * NS;
   const T* const g0 = Ls + (size_t)(A * nbv + C) * bstride;
   const T* const g1 = Ls + (size_t)(B * nbv + D) * bstride;
   const T* const g2 = Ls + (size_t)(A * nbv + D) * bstride;
@@ -541,7 +535,7 @@ __device__ __forceinline__ void build_v_3m(const T* __restrict__ Ls, const int* 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const T* gq = q == 0 ? g0 : q == 1 ? g1 : q == 2 ? g2 : g3;
-      const vec_t* src = reinterpret_cast<const vec_t*>(gq + (size_t)p0 * 3 * NS);
+      const vec_t* src = reinterpret_cast<const vec_t*>(gq + (size_t)p0 * 2 * NS);
 #pragma unroll
       for (int k = 0; k < KPB; ++k) pf[q * KPB + k] = src[k * WG + threadIdx.x];
     }
@@ -552,7 +546,7 @@ __device__ __forceinline__ void build_v_3m(const T* __restrict__ Ls, const int* 
       const int gp = k * NW + wave, q = gp / PPB, pb = gp - q * PPB;
       const T* gq = q == 0 ? g0 : q == 1 ? g1 : q == 2 ? g2 : g3;
       __builtin_amdgcn_global_load_lds(
-          reinterpret_cast<const char*>(gq + (size_t)p0 * 3 * NS) + pb * 1024 + lane * 16,
+          reinterpret_cast<const char*>(gq + (size_t)p0 * 2 * NS) + pb * 1024 + lane * 16,
           (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(buf + q * CH) +
                                                     pb * 1024),
           16, 0, 0);
@@ -587,14 +581,16 @@ __device__ __forceinline__ void build_v_3m(const T* __restrict__ Ls, const int* 
       for (int w = 0; w < 2; ++w) {
         // W1: rows from L_AC (block 0), columns from L_BD (block 1);
         // W2: rows from L_AD (block 2), columns from L_BC (block 3)
-        const T* la = cur + (2 * w) * CH + p * 3 * NS + 16 * rw + li;
-        const T* lb = cur + (2 * w + 1) * CH + p * 3 * NS + 16 * j0 + li;
-        const T a0 = la[0], a1 = la[NS], a2 = la[2 * NS];
+        const T* la = cur + (2 * w) * CH + p * 2 * NS + 16 * rw + li;
+        const T* lb = cur + (2 * w + 1) * CH + p * 2 * NS + 16 * j0 + li;
+        // the third operand of each side, re + im, formed in registers
+        const T a0 = la[0], a1 = la[NS], a2 = a0 + a1;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-          t1[w][j] = mfma(a0, lb[16 * j], t1[w][j]);
-          t2[w][j] = mfma(a1, lb[NS + 16 * j], t2[w][j]);
-          t3[w][j] = mfma(a2, lb[2 * NS + 16 * j], t3[w][j]);
+          const T b0 = lb[16 * j], b1 = lb[NS + 16 * j];
+          t1[w][j] = mfma(a0, b0, t1[w][j]);
+          t2[w][j] = mfma(a1, b1, t2[w][j]);
+          t3[w][j] = mfma(a2, b0 + b1, t3[w][j]);
         }
       }
     }
@@ -639,8 +635,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_ppl_3m(const T* __restrict__ Ls,
                                                        const int* __restrict__ order,
                                                        const int* __restrict__ nonherm, int nbv,
                                                        int nbp, int ncp, int Mp, int v) {
-  constexpr int NE = DL ? 8 * Smem3<T, KC>::chunk : Smem3<T, KC>::elems;
-  __shared__ __attribute__((aligned(16))) T lds[NE > Smem3<T, KC>::elems ? NE : Smem3<T, KC>::elems];
+  constexpr int NE = DL ? 8 * Smem<T, KC>::chunk : Smem<T, KC>::elems;
+  __shared__ __attribute__((aligned(16))) T lds[NE > Smem<T, KC>::elems ? NE : Smem<T, KC>::elems];
   int x, y;
   bool mirror;
   if (!decode_item(order, (long)nbp * (nbp + 1) / 2, nbp, blockIdx.x, *nonherm != 0, &x, &y,
@@ -673,13 +669,11 @@ bool ppl_has_variant(lrcc_prec prec, lrcc_cmul cmul, int variant) {
   return variant == 1;
 }
 
-int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul) {
-  if (cmul == LRCC_CMUL_3M) return prec == LRCC_FP64 ? 8 : 16;
-  // the chunk of the occupancy-2 variant divides that of occupancy 1, so one
-  // staged layout (padded to the larger chunk) serves both
-  return prec == LRCC_FP64 ? KC64 : KC32;
-}
-int ppl_planes(lrcc_prec, lrcc_cmul cmul) { return cmul == LRCC_CMUL_3M ? 3 : 2; }
+// Both complex forms read the same staged planes (re, im) in the same chunks;
+// the chunk of the occupancy-2 variant divides that of occupancy 1, so one
+// staged layout (padded to the larger chunk) serves every launch variant.
+int ppl_chunk(lrcc_prec prec, lrcc_cmul) { return prec == LRCC_FP64 ? KC64 : KC32; }
+int ppl_planes(lrcc_prec, lrcc_cmul) { return 2; }
 
 size_t ppl_ls_bytes(lrcc_prec prec, lrcc_cmul cmul, const Geom& g) {
   const size_t es = prec == LRCC_FP64 ? 8 : 4;
@@ -714,14 +708,14 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
                      tab, order, nonherm, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v)
     const bool w8 = occ == 5;
     if (prec == LRCC_FP64) {
-      if (w8) LRCC_L3(double, double, 8, true, 8);
-      else LRCC_L3(double, double, 8, false, 4);
+      if (w8) LRCC_L3(double, double, KC64, true, 8);
+      else LRCC_L3(double, double, KC64, false, 4);
     } else if (acc64) {
-      if (w8) LRCC_L3(float, double, 16, true, 8);
-      else LRCC_L3(float, double, 16, false, 4);
+      if (w8) LRCC_L3(float, double, KC32, true, 8);
+      else LRCC_L3(float, double, KC32, false, 4);
     } else {
-      if (w8) LRCC_L3(float, float, 16, true, 8);
-      else LRCC_L3(float, float, 16, false, 4);
+      if (w8) LRCC_L3(float, float, KC32, true, 8);
+      else LRCC_L3(float, float, KC32, false, 4);
     }
 #undef LRCC_L3
     return hipGetLastError();
