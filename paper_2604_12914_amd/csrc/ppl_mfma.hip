@@ -245,8 +245,11 @@ __device__ __forceinline__ void build_v_4m(const T* __restrict__ Ls, const int* 
 
 // Contraction of 16 rows m0 .. m0 + 15 (this lane holds X[m0 + li][16 lk + s]
 // in xr[s], xi[s]) with NN column blocks n0 .. n0 + NN - 1 of the LDS tile V
-// into the accumulators sr, si (see contract_v for TR).
-template <typename T, bool TR, int NN>
+// into the accumulators sr, si (see contract_v for TR).  CM3: the 3M form,
+// three real products per complex product (t1 = xr vr, t2 = xi vi,
+// t3 = (xr + xi)(vr +- vi), the sums formed in registers), combined into
+// sr, si at the end.
+template <typename T, bool TR, int NN, bool CM3>
 __device__ __forceinline__ void contract_rows(const T* Vr, const T* Vi, const T (&xr)[16],
                                               const T (&xi)[16], int n0,
                                               typename Acc<T>::t (&sr)[NN],
@@ -254,38 +257,76 @@ __device__ __forceinline__ void contract_rows(const T* Vr, const T* Vi, const T 
   typedef typename Acc<T>::t acc_t;
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-#pragma unroll
-  for (int n = 0; n < NN; ++n) {
-    sr[n] = acc_t{0, 0, 0, 0};
-    si[n] = sr[n];
-  }
-#pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    const int k = 16 * lk + s;  // contracted slot fed by this lane at step s
-    T vr[NN], vi[NN];
+  if constexpr (CM3) {
+    acc_t t1[NN], t2[NN], t3[NN];
 #pragma unroll
     for (int n = 0; n < NN; ++n) {
-      const int c = 16 * (n0 + n) + li;
-      const int a = TR ? c * VS + k : k * VS + c;
-      vr[n] = Vr[a];
-      vi[n] = Vi[a];
-    }
-    // (xr + i xi)(vr + i vi), or (xr + i xi)(vr - i vi) for the mirror
-    const T xrs = xr[s], xis = xi[s];
-    const T s_r = TR ? xis : -xis, s_i = TR ? -xrs : xrs;
-#pragma unroll
-    for (int n = 0; n < NN; ++n) {
-      sr[n] = mfma(xrs, vr[n], sr[n]);
-      si[n] = mfma(s_i, vi[n], si[n]);
+      t1[n] = acc_t{0, 0, 0, 0};
+      t2[n] = t1[n];
+      t3[n] = t1[n];
     }
 #pragma unroll
-    for (int n = 0; n < NN; ++n) {
-      sr[n] = mfma(s_r, vi[n], sr[n]);
-      si[n] = mfma(xis, vr[n], si[n]);
+    for (int s = 0; s < 16; ++s) {
+      const int k = 16 * lk + s;  // contracted slot fed by this lane at step s
+      T vr[NN], vi[NN];
+#pragma unroll
+      for (int n = 0; n < NN; ++n) {
+        const int c = 16 * (n0 + n) + li;
+        const int a = TR ? c * VS + k : k * VS + c;
+        vr[n] = Vr[a];
+        vi[n] = Vi[a];
+      }
+      const T xrs = xr[s], xis = xi[s], xs = xrs + xis;
+#pragma unroll
+      for (int n = 0; n < NN; ++n) {
+        t1[n] = mfma(xrs, vr[n], t1[n]);
+        t2[n] = mfma(xis, vi[n], t2[n]);
+        t3[n] = mfma(xs, TR ? vr[n] - vi[n] : vr[n] + vi[n], t3[n]);
+      }
+      // (three accumulator sets: a shorter look-ahead than in the 4M form)
+      if (s & 1) __builtin_amdgcn_sched_barrier(0);
     }
-    // keep the scheduler from hoisting every step's LDS reads to the top
-    // (that would hold 16 steps of V operands in registers at once)
-    if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    // (xr + i xi)(vr + i vi) = (t1 - t2) + i (t3 - t1 - t2); for the mirror
+    // (xr + i xi)(vr - i vi) = (t1 + t2) + i (t3 - t1 + t2)
+#pragma unroll
+    for (int n = 0; n < NN; ++n) {
+      sr[n] = TR ? t1[n] + t2[n] : t1[n] - t2[n];
+      si[n] = TR ? t3[n] - t1[n] + t2[n] : t3[n] - t1[n] - t2[n];
+    }
+  } else {
+#pragma unroll
+    for (int n = 0; n < NN; ++n) {
+      sr[n] = acc_t{0, 0, 0, 0};
+      si[n] = sr[n];
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = 16 * lk + s;  // contracted slot fed by this lane at step s
+      T vr[NN], vi[NN];
+#pragma unroll
+      for (int n = 0; n < NN; ++n) {
+        const int c = 16 * (n0 + n) + li;
+        const int a = TR ? c * VS + k : k * VS + c;
+        vr[n] = Vr[a];
+        vi[n] = Vi[a];
+      }
+      // (xr + i xi)(vr + i vi), or (xr + i xi)(vr - i vi) for the mirror
+      const T xrs = xr[s], xis = xi[s];
+      const T s_r = TR ? xis : -xis, s_i = TR ? -xrs : xrs;
+#pragma unroll
+      for (int n = 0; n < NN; ++n) {
+        sr[n] = mfma(xrs, vr[n], sr[n]);
+        si[n] = mfma(s_i, vi[n], si[n]);
+      }
+#pragma unroll
+      for (int n = 0; n < NN; ++n) {
+        sr[n] = mfma(s_r, vi[n], sr[n]);
+        si[n] = mfma(xis, vr[n], si[n]);
+      }
+      // keep the scheduler from hoisting every step's LDS reads to the top
+      // (that would hold 16 steps of V operands in registers at once)
+      if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
   }
 }
 
@@ -317,7 +358,7 @@ __device__ __forceinline__ void store_rows(const typename Acc<T>::t (&sr)[NN],
 // rows go to the NW waves in turn; the last Mp/16 mod NW chunks are split into
 // (chunk, 16-column block) items dealt out to all waves, so no wave does an
 // extra whole chunk.
-template <typename T, typename TA, int OCC, bool TR, int NW>
+template <typename T, typename TA, int OCC, bool TR, int NW, bool CM3>
 __device__ __forceinline__ void contract_v(const T* lds, const T* __restrict__ Xb,
                                            TA* __restrict__ Sb, int nbp, int Mp, int src,
                                            int dst) {
@@ -378,17 +419,27 @@ __device__ __forceinline__ void contract_v(const T* lds, const T* __restrict__ X
     unpack(xr, xi);
     const int nm = next_main(mc);
     if (PF && nm >= 0) fetch_x(nm);
-    acc_t sr[4], si[4];
-    contract_rows<T, TR, 4>(Vr, Vi, xr, xi, 0, sr, si);
-    if (!PF && nm >= 0) fetch_x(nm);
-    store_rows<T, TA, 4>(sr, si, 0, m0, sr_g, si_g);
+    if constexpr (CM3) {
+      // two passes of two column blocks (three accumulator sets each)
+      acc_t sr[2], si[2];
+      contract_rows<T, TR, 2, true>(Vr, Vi, xr, xi, 0, sr, si);
+      if (!PF && nm >= 0) fetch_x(nm);
+      store_rows<T, TA, 2>(sr, si, 0, m0, sr_g, si_g);
+      contract_rows<T, TR, 2, true>(Vr, Vi, xr, xi, 2, sr, si);
+      store_rows<T, TA, 2>(sr, si, 2, m0, sr_g, si_g);
+    } else {
+      acc_t sr[4], si[4];
+      contract_rows<T, TR, 4, false>(Vr, Vi, xr, xi, 0, sr, si);
+      if (!PF && nm >= 0) fetch_x(nm);
+      store_rows<T, TA, 4>(sr, si, 0, m0, sr_g, si_g);
+    }
   }
   for (int it = wave; it < ntail; it += NW) {
     const int m0 = tail_m0(it);
     T xr[16], xi[16];
     unpack(xr, xi);
     acc_t sr[1], si[1];
-    contract_rows<T, TR, 1>(Vr, Vi, xr, xi, it % 4, sr, si);
+    contract_rows<T, TR, 1, CM3>(Vr, Vi, xr, xi, it % 4, sr, si);
     if (it + NW < ntail) fetch_x(tail_m0(it + NW));
     store_rows<T, TA, 1>(sr, si, it % 4, m0, sr_g, si_g);
   }
@@ -414,13 +465,13 @@ __device__ __forceinline__ bool decode_item(const int* __restrict__ order, long 
   return true;
 }
 
-template <typename T, typename TA, int OCC, int NW, typename Build>
+template <typename T, typename TA, int OCC, int NW, bool CM3, typename Build>
 __device__ __forceinline__ void tile_item(Build build, const T* __restrict__ Xb,
                                           TA* __restrict__ Sb, int nbp, int Mp, int x, int y,
                                           bool mirror, T* lds) {
   build(x, y);
-  contract_v<T, TA, OCC, false, NW>(lds, Xb, Sb, nbp, Mp, y, x);
-  if (mirror) contract_v<T, TA, OCC, true, NW>(lds, Xb, Sb, nbp, Mp, x, y);
+  contract_v<T, TA, OCC, false, NW, CM3>(lds, Xb, Sb, nbp, Mp, y, x);
+  if (mirror) contract_v<T, TA, OCC, true, NW, CM3>(lds, Xb, Sb, nbp, Mp, x, y);
 }
 
 template <typename T, typename TA, int KC, int OCC, bool DL, int NW>
@@ -438,7 +489,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_ppl_4m(const T* __restrict__ L
   if (!decode_item(order, (long)nbp * (nbp + 1) / 2, nbp, blockIdx.x, *nonherm != 0, &x, &y,
                    &mirror))
     return;
-  tile_item<T, TA, OCC, NW>(
+  tile_item<T, TA, OCC, NW, false>(
       [&](int p, int q) { build_v_4m<T, KC, OCC, DL, NW>(Ls, tab, nbv, ncp, v, p, q, lds); },
       Xb, Sb, nbp, Mp, x, y, mirror, lds);
 }
@@ -482,7 +533,7 @@ __global__ __launch_bounds__(64 * QNW, 1) void k_ppl_queue(const BatchInst* __re
     if (!decode_item(I.order, (long)I.nbp * (I.nbp + 1) / 2, I.nbp, l, *I.nonherm != 0, &p, &q,
                      &mirror))
       continue;
-    tile_item<double, double, 1, QNW>(
+    tile_item<double, double, 1, QNW, false>(
         [&](int a, int b) {
           build_v_4m<double, 16, 1, true, QNW>(I.Ls, I.tab, I.nbv, I.ncp, I.v, a, b, lds);
         },
@@ -642,7 +693,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_ppl_3m(const T* __restrict__ Ls,
   if (!decode_item(order, (long)nbp * (nbp + 1) / 2, nbp, blockIdx.x, *nonherm != 0, &x, &y,
                    &mirror))
     return;
-  tile_item<T, TA, 1, NW>(
+  tile_item<T, TA, 1, NW, true>(
       [&](int p, int q) { build_v_3m<T, KC, DL, NW>(Ls, tab, nbv, ncp, v, p, q, lds); }, Xb,
       Sb, nbp, Mp, x, y, mirror, lds);
 }
