@@ -45,22 +45,22 @@ def issued_flops(o, v, nchol, nrhs, prec="fp64", cmul="4m"):
     """Matrix-core flops one Hermitian ladder application issues: one 64 x 64
     complex integral tile per block-pair pair AB <= CD (two products over the
     padded Cholesky index) and the contraction of every (AB, CD) ordered pair
-    over the rows padded to 16; 3M builds take 3 real products per complex
-    product instead of 4 (bf16x3 counted as effective FP32-like products)."""
+    over the rows padded to 16; the 3M form takes 3 real products per complex
+    product instead of 4 in both (bf16x3 counted as effective FP32-like
+    products)."""
     nbv = (v + 7) // 8
     nbp = nbv * (nbv + 1) // 2
     ntile = nbp * (nbp + 1) // 2
-    kc = {("fp64", "4m"): 16, ("fp32", "4m"): 32, ("fp64", "3m"): 8, ("fp32", "3m"): 16,
-          ("bf16x3", "4m"): 32}[(prec, cmul)]
+    kc = {"fp64": 16, "fp32": 32, "bf16x3": 32}[prec]
     ncp = -(-nchol // kc) * kc
     mp = -(-(nrhs * o * (o - 1) // 2) // 16) * 16
-    build = 8.0 * 4096 * 2 * ncp * ntile * (0.75 if cmul == "3m" else 1.0)
-    return build + 8.0 * 4096 * mp * nbp * nbp
+    form = 0.75 if cmul == "3m" else 1.0
+    return form * 8.0 * 4096 * (2 * ncp * ntile + mp * nbp * nbp)
 
 
 # complex-multiply form of the FP64 ladder in the timed solves: the 3M form
-# (three real products per complex product in the integral build; same
-# result up to rounding) is the faster one on MI355X
+# (three real products per complex product in the integral build and the
+# contraction; same result up to rounding) is the faster one on MI355X
 SOLVE_CMUL = "3m"
 TRAFFIC_PROFILE = "profiles/k_ppl_3m_fp64_o16_v160_nchol640_hbm_traffic.md"
 TRAFFIC_SOURCES = ("paper_2604_12914_amd/csrc/ppl_mfma.hip", "paper_2604_12914_amd/csrc/internal.hpp")
