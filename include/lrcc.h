@@ -166,7 +166,9 @@ typedef struct {
 
 /* Solve several uneven instances together: every ladder application of
  * every instance, component and frequency goes into one persistent launch
- * per iteration (a work queue ordered longest tile first). */
+ * per iteration (a work queue ordered longest tile first).  FP64 ladder
+ * only (opts->prec must be LRCC_FP64, else LRCC_ERR_UNSUPPORTED), in the
+ * complex form opts->cmul selects. */
 lrcc_status lrcc_solve_batched(lrcc_handle h, int ninst, const lrcc_instance* inst,
                                const lrcc_solve_opts* opts, lrcc_solve_info* info);
 

@@ -147,9 +147,10 @@ struct BatchInst {
   long start;              // first item in a single global list
   long xstart[QXMAX];      // first item in each XCD's list
 };
-// counter: nx (<= QXMAX) zeroed unsigned counters; xtotal[x]: items of XCD x.
+// counter: nx (<= QXMAX) zeroed unsigned counters; xtotal[x]: items of XCD x;
+// cm3: the 3M complex form (same staged layout as 4M).
 hipError_t ppl_queue_launch(const BatchInst* inst, int ninst, const long* xtotal, int nx,
-                            unsigned* counter, int nwg, hipStream_t st);
+                            unsigned* counter, int nwg, bool cm3, hipStream_t st);
 int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul);   // KC of the staged layout
 bool ppl_has_variant(lrcc_prec prec, lrcc_cmul cmul, int variant);  // 4M launch variants 1-5
 int ppl_planes(lrcc_prec prec, lrcc_cmul cmul);  // planes of the staged L

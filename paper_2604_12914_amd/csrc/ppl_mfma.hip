@@ -494,57 +494,11 @@ __global__ __launch_bounds__(64 * NW, OCC) void k_ppl_4m(const T* __restrict__ L
       Xb, Sb, nbp, Mp, x, y, mirror, lds);
 }
 
-// Persistent ladder over several instances (eight waves, chunks loaded
-// straight into a two-chunk LDS ring: the fastest FP64 launch variant).  A
-// workgroup on XCD x takes the next item of x's queue (the instances' items
-// l = x mod nx, instances ordered longest tile first): with each instance's
-// tile order split into per-XCD super-tile shares, the workgroups of one XCD
-// work on tiles that share Cholesky blocks in its L2.  When x's queue is
-// empty the workgroup takes items from the next XCDs' queues, so uneven
-// instances share one launch without a tail.  Every workgroup leaves once it
-// has found all nx queues empty.
-constexpr int QNW = 8;
-__global__ __launch_bounds__(64 * QNW, 1) void k_ppl_queue(const BatchInst* __restrict__ inst,
-                                                          int ninst,
-                                                          const long* __restrict__ xtotal,
-                                                          int nx,
-                                                          unsigned* __restrict__ counter) {
-  __shared__ __attribute__((aligned(16))) double lds[2 * Smem<double, 16>::build];
-  __shared__ unsigned item;
-  const int x0 = blockIdx.x % nx;
-  for (int xi = 0; xi < nx;) {
-    const int x = (x0 + xi) % nx;
-    __syncthreads();  // every wave is done with the previous item and its LDS
-    if (threadIdx.x == 0) item = atomicAdd(counter + x, 1u);
-    __syncthreads();
-    // the item is the same for every lane: keep it (and what is derived from
-    // it) in scalar registers
-    const long c = (unsigned)__builtin_amdgcn_readfirstlane((int)item);
-    if (c >= xtotal[x]) {  // this XCD's queue is empty: move on to the next
-      ++xi;
-      continue;
-    }
-    int i = 0;
-    while (i + 1 < ninst && c >= inst[i + 1].xstart[x]) ++i;
-    const BatchInst& I = inst[i];
-    const long l = (c - I.xstart[x]) * nx + x;
-    int p, q;
-    bool mirror;
-    if (!decode_item(I.order, (long)I.nbp * (I.nbp + 1) / 2, I.nbp, l, *I.nonherm != 0, &p, &q,
-                     &mirror))
-      continue;
-    tile_item<double, double, 1, QNW, false>(
-        [&](int a, int b) {
-          build_v_4m<double, 16, 1, true, QNW>(I.Ls, I.tab, I.nbv, I.ncp, I.v, a, b, lds);
-        },
-        I.Xb, I.Sb, I.nbp, I.Mp, p, q, mirror, lds);
-  }
-}
-
-// 3M form of the integral build: with planes (re, im, re+im) of the staged
+// 3M form of the integral build: from the staged planes (re, im) of the
 // Cholesky blocks, T1 = sum ar br, T2 = sum ai bi, T3 = sum (ar+ai)(br+bi)
-// give re = T1 - T2 and im = T3 - T1 - T2: three real MFMA products per
-// complex product instead of four.  The contraction keeps the 4M form.
+// (the sums formed in registers) give re = T1 - T2 and im = T3 - T1 - T2:
+// three real MFMA products per complex product instead of four.  The
+// contraction that follows it uses the 3M form as well (contract_rows).
 template <typename T, int KC, bool DL, int NW>
 __device__ __forceinline__ void build_v_3m(const T* __restrict__ Ls, const int* __restrict__ tab,
                                            int nbv, int ncp, int v, int ab, int cd, T* lds) {
@@ -678,6 +632,60 @@ __device__ __forceinline__ void build_v_3m(const T* __restrict__ Ls, const int* 
   __syncthreads();
 }
 
+// Persistent ladder over several instances (eight waves, chunks loaded
+// straight into a two-chunk LDS ring: the fastest FP64 launch variant).  A
+// workgroup on XCD x takes the next item of x's queue (the instances' items
+// l = x mod nx, instances ordered longest tile first): with each instance's
+// tile order split into per-XCD super-tile shares, the workgroups of one XCD
+// work on tiles that share Cholesky blocks in its L2.  When x's queue is
+// empty the workgroup takes items from the next XCDs' queues, so uneven
+// instances share one launch without a tail.  Every workgroup leaves once it
+// has found all nx queues empty.
+// CM3: the 3M form (three real products per complex product) in the build
+// and the contraction; otherwise 4M.
+constexpr int QNW = 8;
+template <bool CM3>
+__global__ __launch_bounds__(64 * QNW, 1) void k_ppl_queue(const BatchInst* __restrict__ inst,
+                                                          int ninst,
+                                                          const long* __restrict__ xtotal,
+                                                          int nx,
+                                                          unsigned* __restrict__ counter) {
+  __shared__ __attribute__((aligned(16))) double lds[2 * Smem<double, 16>::build];
+  __shared__ unsigned item;
+  const int x0 = blockIdx.x % nx;
+  for (int xi = 0; xi < nx;) {
+    const int x = (x0 + xi) % nx;
+    __syncthreads();  // every wave is done with the previous item and its LDS
+    if (threadIdx.x == 0) item = atomicAdd(counter + x, 1u);
+    __syncthreads();
+    // the item is the same for every lane: keep it (and what is derived from
+    // it) in scalar registers
+    const long c = (unsigned)__builtin_amdgcn_readfirstlane((int)item);
+    if (c >= xtotal[x]) {  // this XCD's queue is empty: move on to the next
+      ++xi;
+      continue;
+    }
+    int i = 0;
+    while (i + 1 < ninst && c >= inst[i + 1].xstart[x]) ++i;
+    const BatchInst& I = inst[i];
+    const long l = (c - I.xstart[x]) * nx + x;
+    int p, q;
+    bool mirror;
+    if (!decode_item(I.order, (long)I.nbp * (I.nbp + 1) / 2, I.nbp, l, *I.nonherm != 0, &p, &q,
+                     &mirror))
+      continue;
+    tile_item<double, double, 1, QNW, CM3>(
+        [&](int a, int b) {
+          if constexpr (CM3)
+            build_v_3m<double, 16, true, QNW>(I.Ls, I.tab, I.nbv, I.ncp, I.v, a, b, lds);
+          else
+            build_v_4m<double, 16, 1, true, QNW>(I.Ls, I.tab, I.nbv, I.ncp, I.v, a, b, lds);
+        },
+        I.Xb, I.Sb, I.nbp, I.Mp, p, q, mirror, lds);
+  }
+}
+
+
 template <typename T, typename TA, int KC, bool DL, int NW>
 __global__ __launch_bounds__(64 * NW, 1) void k_ppl_3m(const T* __restrict__ Ls,
                                                        const T* __restrict__ Xb,
@@ -797,11 +805,15 @@ hipError_t ppl_launch(lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
 }
 
 hipError_t ppl_queue_launch(const BatchInst* inst, int ninst, const long* xtotal, int nx,
-                            unsigned* counter, int nwg, hipStream_t st) {
+                            unsigned* counter, int nwg, bool cm3, hipStream_t st) {
   if (ninst == 0 || nx < 1 || nx > QXMAX) return nx < 1 || nx > QXMAX ? hipErrorInvalidValue
                                                                        : hipSuccess;
-  hipLaunchKernelGGL(k_ppl_queue, dim3(nwg), dim3(64 * QNW), 0, st, inst, ninst, xtotal, nx,
-                     counter);
+  if (cm3)
+    hipLaunchKernelGGL(k_ppl_queue<true>, dim3(nwg), dim3(64 * QNW), 0, st, inst, ninst, xtotal,
+                       nx, counter);
+  else
+    hipLaunchKernelGGL(k_ppl_queue<false>, dim3(nwg), dim3(64 * QNW), 0, st, inst, ninst,
+                       xtotal, nx, counter);
   return hipGetLastError();
 }
 

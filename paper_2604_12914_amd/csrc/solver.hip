@@ -929,8 +929,8 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
   Opts O;
   lrcc_status st = read_opts(h, opts_in, &op, &O);
   if (st != LRCC_OK) return st;
-  if (op.prec != LRCC_FP64 || op.cmul != LRCC_CMUL_4M)
-    return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve runs the FP64 4M ladder");
+  if (op.prec != LRCC_FP64)
+    return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve runs the FP64 ladder");
   constexpr int KC = 16;  // chunk of the persistent FP64 ladder
   std::vector<std::unique_ptr<Solver>> S(ninst);
   std::vector<std::unique_ptr<Buf[]>> own(ninst);
@@ -1066,7 +1066,7 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
       if (ce == hipSuccess)
         ce = ppl_queue_launch(desc.as<BatchInst>(), (int)now.size(),
                               reinterpret_cast<const long*>(desc.as<char>() + desc_bytes), nx,
-                              counter.as<unsigned>(), h->ncu, cs);
+                              counter.as<unsigned>(), h->ncu, op.cmul == LRCC_CMUL_3M, cs);
       for (int i : now)
         if (ce == hipSuccess && cst == LRCC_OK)
           cst = iterate_vectors(*S[i], S[i]->b, S[i]->x, O.tol, O.max_iter, cs);

@@ -25,10 +25,12 @@ def dev_inst(inst, omegas):
             "mu": torch.from_numpy(inst.mu).cuda(), "omegas": omegas}
 
 
-def test_uneven_batch_matches_single_solves_and_oracle(lrcc):
+@pytest.mark.parametrize("cmul", ["4m", "3m"])
+def test_uneven_batch_matches_single_solves_and_oracle(lrcc, cmul):
     # uneven instances (v = 10 o, Nchol = 4 v as in the batched workload, scaled
     # down), including one whose frequency list differs and one with general
-    # (non-Hermitian) Cholesky vectors, so the queue mixes both tile paths
+    # (non-Hermitian) Cholesky vectors, so the queue mixes both tile paths;
+    # both complex forms of the ladder
     shapes = [(2, 20, 80, 0), (3, 30, 120, 1), (4, 40, 160, 2), (5, 44, 100, 3)]
     insts, devs = [], []
     for (o, v, nchol, seed) in shapes:
@@ -37,10 +39,11 @@ def test_uneven_batch_matches_single_solves_and_oracle(lrcc):
         om = OMEGAS if seed != 1 else OMEGAS[:2]
         insts.append((inst, om))
         devs.append(dev_inst(inst, om))
-    alphas, info = lrcc.solve_batched(devs, tol=1e-8)
+    print(f"batched solve, {cmul}", flush=True)
+    alphas, info = lrcc.solve_batched(devs, tol=1e-8, cmul=cmul)
     assert info["status"] == "LRCC_OK"
     for (inst, om), a, d in zip(insts, alphas, devs):
-        single, sinfo = lrcc.solve(d["eps"], d["L"], d["mu"], om, tol=1e-8)
+        single, sinfo = lrcc.solve(d["eps"], d["L"], d["mu"], om, tol=1e-8, cmul=cmul)
         # the same arithmetic in the same order per instance
         assert np.abs(a - single).max() <= 1e-12 * np.abs(single).max()
         exact = response.solve_dense(inst.L, inst.eps, inst.mu, om, inst.o, inst.v)["alpha"]
