@@ -302,14 +302,13 @@ lrcc_status sigma_packed(lrcc_handle h, const Geom& g, const void* L, bool conj_
   LRCC_HIP(h, h->sb.ensure(sbytes));
   LRCC_HIP(h, fill_zero(h->sb.p, sbytes, h->stream));
   if (g.nchol > 0) {
-    const int np = ppl_planes(prec, cmul);
     LRCC_HIP(h, h->hflag.ensure(16));
     LRCC_HIP(h, herm_check(L, dt, g.v, g.nchol, h->hflag.as<int>(), h->stream));
     if (prec == LRCC_FP64) {
-      LRCC_HIP(h, stage_L<double>(L, dt, g, np, conj_t, h->ls.as<double>(), h->stream));
+      LRCC_HIP(h, stage_L<double>(L, dt, g, conj_t, h->ls.as<double>(), h->stream));
       LRCC_HIP(h, pack_to_block<double>(X, dt, g, tab, h->xb.as<double>(), h->stream));
     } else {
-      LRCC_HIP(h, stage_L<float>(L, dt, g, np, conj_t, h->ls.as<float>(), h->stream));
+      LRCC_HIP(h, stage_L<float>(L, dt, g, conj_t, h->ls.as<float>(), h->stream));
       LRCC_HIP(h, pack_to_block<float>(X, dt, g, tab, h->xb.as<float>(), h->stream));
     }
     st = ppl_run(h, prec, cmul, acc64, g, h->ls.p, h->xb.p, h->sb.p, h->hflag.as<int>());

@@ -97,11 +97,11 @@ lrcc_status hip_fail(lrcc_handle h, hipError_t e, const char* what);
   } while (0)
 
 // Staging / layout launchers (layout.hip) ----------------------------------
-// Stage L (complex, dtype dt) into planar blocks of type T with nplanes = 2
-// (re, im) or 3 (re, im, re+im).  conj_t: stage (L^P)^H instead of L^P.
+// Stage L (complex, dtype dt) into planar blocks of type T, planes (re, im)
+// (both complex forms read these).  conj_t: stage (L^P)^H instead of L^P.
 template <typename T>
-hipError_t stage_L(const void* L, lrcc_dtype dt, const Geom& g, int nplanes,
-                   bool conj_t, T* Ls, hipStream_t st);
+hipError_t stage_L(const void* L, lrcc_dtype dt, const Geom& g, bool conj_t, T* Ls,
+                   hipStream_t st);
 // Packed doubles -> planar block layout (2 planes of T); dead slots and pad
 // rows are written as zero.
 template <typename T>
@@ -153,7 +153,6 @@ hipError_t ppl_queue_launch(const BatchInst* inst, int ninst, const long* xtotal
                             unsigned* counter, int nwg, bool cm3, hipStream_t st);
 int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul);   // KC of the staged layout
 bool ppl_has_variant(lrcc_prec prec, lrcc_cmul cmul, int variant);  // 4M launch variants 1-5
-int ppl_planes(lrcc_prec prec, lrcc_cmul cmul);  // planes of the staged L
 size_t ppl_ls_bytes(lrcc_prec prec, lrcc_cmul cmul, const Geom& g);
 size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g);
 

@@ -29,7 +29,7 @@ __device__ inline long pidx(long p, long q, long n) { return p * (2 * n - p - 1)
 
 template <typename T>
 __global__ void k_stage_L(const void* __restrict__ L, lrcc_dtype dt, int v, int nchol,
-                          int nbv, int ncp, int nplanes, int conj_t, T* __restrict__ Ls) {
+                          int nbv, int ncp, int conj_t, T* __restrict__ Ls) {
   // one thread per (block A, block C, P, slot)
   const long total = (long)nbv * nbv * ncp * NS;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
@@ -48,10 +48,9 @@ __global__ void k_stage_L(const void* __restrict__ L, lrcc_dtype dt, int v, int 
       re = z.x;
       im = conj_t ? -z.y : z.y;
     }
-    T* dst = Ls + (r * nplanes) * NS + s;
+    T* dst = Ls + (r * 2) * NS + s;
     dst[0] = (T)re;
     dst[NS] = (T)im;
-    if (nplanes == 3) dst[2 * NS] = (T)re + (T)im;
   }
 }
 
@@ -125,11 +124,11 @@ inline int grid_for(long n) {
 }  // namespace
 
 template <typename T>
-hipError_t stage_L(const void* L, lrcc_dtype dt, const Geom& g, int nplanes, bool conj_t,
+hipError_t stage_L(const void* L, lrcc_dtype dt, const Geom& g, bool conj_t,
                    T* Ls, hipStream_t st) {
   const long total = (long)g.nbv * g.nbv * g.ncp * NS;
   hipLaunchKernelGGL(k_stage_L<T>, dim3(grid_for(total)), dim3(256), 0, st, L, dt, g.v,
-                     g.nchol, g.nbv, g.ncp, nplanes, (int)conj_t, Ls);
+                     g.nchol, g.nbv, g.ncp, (int)conj_t, Ls);
   return hipGetLastError();
 }
 
@@ -170,9 +169,9 @@ hipError_t herm_check(const void* L, lrcc_dtype dt, int v, int nchol, int* nonhe
   return hipGetLastError();
 }
 
-template hipError_t stage_L<double>(const void*, lrcc_dtype, const Geom&, int, bool, double*,
+template hipError_t stage_L<double>(const void*, lrcc_dtype, const Geom&, bool, double*,
                                     hipStream_t);
-template hipError_t stage_L<float>(const void*, lrcc_dtype, const Geom&, int, bool, float*,
+template hipError_t stage_L<float>(const void*, lrcc_dtype, const Geom&, bool, float*,
                                    hipStream_t);
 template hipError_t pack_to_block<double>(const void*, lrcc_dtype, const Geom&, const int*,
                                           double*, hipStream_t);

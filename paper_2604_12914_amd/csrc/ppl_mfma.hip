@@ -732,11 +732,10 @@ bool ppl_has_variant(lrcc_prec prec, lrcc_cmul cmul, int variant) {
 // the chunk of the occupancy-2 variant divides that of occupancy 1, so one
 // staged layout (padded to the larger chunk) serves every launch variant.
 int ppl_chunk(lrcc_prec prec, lrcc_cmul) { return prec == LRCC_FP64 ? KC64 : KC32; }
-int ppl_planes(lrcc_prec, lrcc_cmul) { return 2; }
 
-size_t ppl_ls_bytes(lrcc_prec prec, lrcc_cmul cmul, const Geom& g) {
+size_t ppl_ls_bytes(lrcc_prec prec, lrcc_cmul, const Geom& g) {
   const size_t es = prec == LRCC_FP64 ? 8 : 4;
-  return (size_t)g.nbv * g.nbv * g.ncp * ppl_planes(prec, cmul) * NS * es;
+  return (size_t)g.nbv * g.nbv * g.ncp * 2 * NS * es;  // planes re, im
 }
 size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g) {
   return (size_t)2 * g.xb_plane() * (prec == LRCC_FP64 ? 8 : 4);

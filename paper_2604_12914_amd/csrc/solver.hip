@@ -620,11 +620,9 @@ lrcc_status stage_for(Solver& S, const void* L, lrcc_prec prec, lrcc_cmul cmul, 
   LRCC_HIP(h, dst.ensure(ppl_ls_bytes(prec, cmul, g)));
   if (g.nchol > 0) {
     if (prec == LRCC_FP64)
-      LRCC_HIP(h, stage_L<double>(L, LRCC_C128, g, ppl_planes(prec, cmul), false,
-                                  dst.as<double>(), h->stream));
+      LRCC_HIP(h, stage_L<double>(L, LRCC_C128, g, false, dst.as<double>(), h->stream));
     else
-      LRCC_HIP(h, stage_L<float>(L, LRCC_C128, g, ppl_planes(prec, cmul), false,
-                                 dst.as<float>(), h->stream));
+      LRCC_HIP(h, stage_L<float>(L, LRCC_C128, g, false, dst.as<float>(), h->stream));
   }
   return LRCC_OK;
 }
@@ -982,7 +980,7 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
     LRCC_HIP(h, own[i][12].ensure(ppl_ls_bytes(LRCC_FP64, LRCC_CMUL_4M, gs)));
     LRCC_HIP(h, herm_check(I.L, LRCC_C128, I.v, I.nchol, Si.nonherm, cs));
     if (gs.nchol > 0)
-      LRCC_HIP(h, stage_L<double>(I.L, LRCC_C128, gs, 2, false, own[i][12].as<double>(), cs));
+      LRCC_HIP(h, stage_L<double>(I.L, LRCC_C128, gs, false, own[i][12].as<double>(), cs));
     std::vector<int> one(Si.n, 1);
     st = start_iteration(Si, Si.b, Si.x, one.data(), cs);
     if (st != LRCC_OK) return st;
