@@ -438,6 +438,9 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
     mok[i] = mrow[i] < Mp;
     mld[i] = mok[i] ? mrow[i] : 0;
   }
+  // a wave whose rows all lie past Mp (in the last m-block) still loads and
+  // stores its share of every V tile but skips the matrix work
+  const bool busy = mok[0];
   f4 sr[2][4], si[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -526,13 +529,13 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
     // scheduling barriers keep each load group between the two k-steps
     // instead of letting the scheduler sink it to the next barrier
     __builtin_amdgcn_sched_barrier(0);
-    contract_ks(cur, 0);
+    if (busy) contract_ks(cur, 0);
     __builtin_amdgcn_sched_barrier(0);
     store_v(nxt, 0);
     fetch_v(1);
     fetch_x(xnext, 0);
     __builtin_amdgcn_sched_barrier(0);
-    contract_ks(cur, 1);
+    if (busy) contract_ks(cur, 1);
     __builtin_amdgcn_sched_barrier(0);
     store_v(nxt, 1);
   }
