@@ -28,6 +28,18 @@ Three solves:
   solve_sos       -- eigen-decomposition H = U diag(lam) U^H of the ladder
                      plus virtual energies, giving the sum-over-states form
                      of Eq. (sos) exactly (Hermitian L only)
+
+Left-hand amplitudes and the full response function (Sec. 2.2): Y(omega)
+solves Y (A + omega) = -(eta + F X).  In this model (T = 0, Lambda = 0, a
+Hermitian one-body perturbation, doubles only) eta_nu = <Phi_0|V|nu> =
+conj(xi_nu) and F = 0 (it would couple doubles to quadruples), so
+(A + omega)^T Y^T = -eta.  The response function, with the symmetriser P
+taken as f(A, B) + conj f(B, A) and the 1/2 of the paper,
+    <<x; y>> = (f_xy + conj f_yx) / 2,  f_xy = sum Y_y xi_x + sum eta_x X_y,
+and alpha_full = -<<x; y>>.  For Hermitian L, Y(omega) = conj X(-omega)
+and alpha_full(omega) = alpha(omega) + conj alpha(-omega): both terms of
+Eq. (sos).
+  eta, solve_left_dense, response_full_dense, solve_sos_full
 """
 from __future__ import annotations
 
@@ -188,3 +200,67 @@ def solve_sos(L, eps, mu, omegas, o, v):
         den = lam[None, :] - s[:, None] - om              # [ij, k]
         alpha[w] = np.einsum("xpk,ypk,pk->xy", np.conj(proj), proj, 1.0 / den)
     return dict(alpha=alpha, eigenvalues=lam)
+
+
+def eta(mu: np.ndarray, o: int, v: int) -> np.ndarray:
+    """Left-hand right-hand side of this model: eta = conj(xi)."""
+    return np.conj(rhs(mu, o, v))
+
+
+def solve_left_dense(L, eps, mu, omegas, o, v):
+    """Exact left-hand solve: per occupied pair ij, LU of (A_ij + omega)^T.
+
+    A_ij = diag(D_ij) + K on packed pairs (K the packed ladder matrix), so
+    each column y = Y_ij^T solves (A_ij + omega)^T y = -eta_ij.  Returns
+    dict(Y [nomega, ncomp, npo, npv], alpha_left [nomega, ncomp, ncomp]) with
+    alpha_left_xy = -sum xi_x Y_y = -<eta_x | Y_y>.
+    """
+    xi = rhs(mu, o, v)
+    et = np.conj(xi)
+    D = denominators(eps, o, v)
+    K = ppl.ladder_matrix(L, v)
+    ncomp, npo, npv = xi.shape
+    Y = np.zeros((len(omegas), ncomp, npo, npv), dtype=np.complex128)
+    for w, om in enumerate(omegas):
+        for ij in range(npo):
+            Aij = K + np.diag(D[ij] + om)
+            Y[w, :, ij, :] = np.linalg.solve(Aij.T, -et[:, ij, :].T).T
+    alpha_left = -np.einsum("xpq,wypq->wxy", xi, Y)
+    return dict(Y=Y, alpha_left=alpha_left)
+
+
+def combine_full(alpha_right, alpha_left):
+    """alpha_full = (s + s^H) / 2 per frequency, s = alpha_right + alpha_left
+    (minus the response function (f_xy + conj f_yx) / 2, f = -s)."""
+    s_ = alpha_right + alpha_left
+    return 0.5 * (s_ + np.conj(np.transpose(s_, (0, 2, 1))))
+
+
+def response_full_dense(L, eps, mu, omegas, o, v):
+    """Full response function from the exact right- and left-hand solves."""
+    right = solve_dense(L, eps, mu, omegas, o, v)
+    left = solve_left_dense(L, eps, mu, omegas, o, v)
+    return dict(alpha=combine_full(right["alpha"], left["alpha_left"]), X=right["X"],
+                Y=left["Y"])
+
+
+def solve_sos_full(L, eps, mu, omegas, o, v):
+    """Both terms of Eq. (sos) for this model (Hermitian L only):
+    alpha_xy(omega) = sum_ij sum_k [conj(p_x) p_y / (lam_k - s_ij - omega)
+                                    + p_x conj(p_y) / (lam_k - s_ij + omega)]
+    with p = U^H xi (see solve_sos)."""
+    xi = rhs(mu, o, v)
+    pa, pb = ppl.pairs(v)
+    pi, pj = ppl.pairs(o)
+    eo, ev = eps[:o], eps[o:o + v]
+    H = ppl.ladder_matrix(L, v) + np.diag(ev[pa] + ev[pb])
+    lam, U = np.linalg.eigh(H)
+    s = eo[pi] + eo[pj]
+    proj = np.einsum("ka,xpa->xpk", np.conj(U.T), xi)
+    alpha = np.zeros((len(omegas), xi.shape[0], xi.shape[0]), dtype=np.complex128)
+    for w, om in enumerate(omegas):
+        exc = lam[None, :] - s[:, None]                    # [ij, k]
+        alpha[w] = (np.einsum("xpk,ypk,pk->xy", np.conj(proj), proj, 1.0 / (exc - om))
+                    + np.einsum("xpk,ypk,pk->xy", proj, np.conj(proj), 1.0 / (exc + om)))
+    return dict(alpha=alpha)
+

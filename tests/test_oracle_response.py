@@ -118,3 +118,67 @@ def test_diis_singular_subspace_detected():
     assert response._diis_coefficients([e, 2 * e]) is None
     c = response._diis_coefficients([e, S.cn(rng, 50)])
     assert abs(np.sum(c) - 1) < 1e-14
+
+
+# --- left-hand amplitudes and the full response function (Sec. 2.2) -------
+
+@pytest.mark.parametrize("herm", [True, False])
+def test_transposed_vectors_give_the_transposed_ladder(herm):
+    # K(L^T) = K(L)^T: the left-hand solve runs the ladder on transposed
+    # Cholesky vectors; pinned on the explicit packed matrices
+    rng = np.random.default_rng(31)
+    v = 9
+    L = S.make_L(rng, 7, v, hermitian=herm)
+    Lt = np.ascontiguousarray(L.transpose(0, 2, 1))
+    K = ppl.ladder_matrix(L, v)
+    assert np.abs(ppl.ladder_matrix(Lt, v) - K.T).max() < 1e-14 * np.abs(K).max()
+    if herm:  # Hermitian vectors: K^T = conj(K), not K
+        assert np.abs(K.T - np.conj(K)).max() < 1e-14 * np.abs(K).max()
+        assert np.abs(K.T - K).max() > 1e-3 * np.abs(K).max()
+
+
+@pytest.mark.parametrize("herm", [True, False])
+def test_left_solve_routes_agree(herm):
+    # exact per-pair LU of (A + w)^T against Jacobi + DIIS on the transposed
+    # vectors with the conjugate dipoles (eta = conj xi) and -w
+    o, v, P = 3, 12, 24
+    inst = S.make_instance(o, v, P, ncomp=2, seed=4, gamma=S.solve_gamma(v), hermitian=herm)
+    left = response.solve_left_dense(inst.L, inst.eps, inst.mu, OMEGAS, o, v)
+    Lt = np.ascontiguousarray(inst.L.transpose(0, 2, 1))
+    it = response.solve_iterative(Lt, inst.eps, np.conj(inst.mu), [-w for w in OMEGAS], o, v,
+                                  tol=1e-11)
+    assert rel(it["alpha"], left["alpha_left"]) < 1e-9
+    # each Y solves its own equation: Y (A + w) = -eta, row by row
+    et = response.eta(inst.mu, o, v)
+    D = response.denominators(inst.eps, o, v)
+    K = ppl.ladder_matrix(inst.L, v)
+    for w, om in enumerate(OMEGAS):
+        Y = left["Y"][w]                                   # [comp, ij, ab]
+        lhs = np.einsum("xpa,ab->xpb", Y, K) + Y * (D + om)[None]
+        assert np.linalg.norm(lhs + et) < 1e-12 * np.linalg.norm(et)
+
+
+def test_left_amplitudes_of_a_hermitian_operator():
+    # Hermitian K: (A + w)^T = conj(A + w), so Y(w) = conj X(-w)
+    o, v, P = 3, 12, 24
+    inst = S.make_instance(o, v, P, ncomp=2, seed=5, gamma=S.solve_gamma(v))
+    left = response.solve_left_dense(inst.L, inst.eps, inst.mu, OMEGAS, o, v)
+    right_m = response.solve_dense(inst.L, inst.eps, inst.mu, [-w for w in OMEGAS], o, v)
+    assert rel(left["Y"], np.conj(right_m["X"])) < 1e-12
+
+
+def test_full_response_is_both_sum_over_states_terms():
+    # the combined right/left response against the eigen-decomposition form
+    # with the -w and +w denominators of Eq. (sos)
+    o, v, P = 4, 16, 40
+    inst = S.make_instance(o, v, P, ncomp=3, seed=6, gamma=S.solve_gamma(v))
+    full = response.response_full_dense(inst.L, inst.eps, inst.mu, OMEGAS, o, v)
+    sos = response.solve_sos_full(inst.L, inst.eps, inst.mu, OMEGAS, o, v)
+    assert rel(full["alpha"], sos["alpha"]) < 1e-12
+    a = full["alpha"]
+    # Hermitian in the components; the static value is twice the Hermitian
+    # right-hand alpha's real part; the zz component rises with w
+    assert np.abs(a - np.conj(np.transpose(a, (0, 2, 1)))).max() < 1e-13 * np.abs(a).max()
+    a0 = response.solve_dense(inst.L, inst.eps, inst.mu, [0.0], o, v)["alpha"][0]
+    assert rel(a[0], a0 + np.conj(a0)) < 1e-12
+    assert np.all(np.diff(a[:, 2, 2].real) > 0)
