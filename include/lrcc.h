@@ -123,6 +123,18 @@ typedef struct {
                         exact to FP32 ladder accuracy, about 1e-6 relative).
                         Inside the solve an FP32 ladder sums its tile partials
                         in FP32 too                                          */
+  int response;      /* 0 (default): alpha_xy(w) = -<xi_x | X_y(w)> from the
+                        right-hand amplitudes only.  1: the full linear
+                        response function of Sec. 2.2 (last equation): the
+                        left-hand amplitudes Y(w) solve Y (A + w) = -eta,
+                        eta = conj(xi) and F = 0 in this model, i.e.
+                        (A^T + w) Y^T = -eta, a second solve with the
+                        transposed ladder K(L^T) = K(L)^T; then
+                        alpha_xy = (s_xy + conj s_yx) / 2 with
+                        s = -<xi_x|X_y(w)> - sum xi_x Y_y(w).  For Hermitian
+                        L this is alpha_R(w) + conj(alpha_R(-w)), both terms
+                        of the sum-over-states form.  lrcc_solve_batched
+                        supports 0 only                                      */
 } lrcc_solve_opts;
 
 typedef struct {

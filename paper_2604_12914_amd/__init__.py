@@ -45,7 +45,8 @@ class SolveOpts(ctypes.Structure):
                 ("diis_dim", ctypes.c_int), ("prec", ctypes.c_int),
                 ("cmul", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("deterministic", ctypes.c_int),
-                ("resid_fp64_every", ctypes.c_int), ("anchor_prec", ctypes.c_int)]
+                ("resid_fp64_every", ctypes.c_int), ("anchor_prec", ctypes.c_int),
+                ("response", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -282,11 +283,15 @@ def ppl(L, X, prec="fp64", cmul="4m"):
     return PPLSigma().apply(L, X, prec, cmul)
 
 
+RESPONSE = {"right": 0, "full": 1}
+
+
 def solve(eps, L, mu, omegas, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64",
           cmul="4m", inner_tol=1e-5, max_outer=6, check=True, resid_fp64_every=0,
-          anchor_prec="fp64"):
+          anchor_prec="fp64", response="right"):
     """Model response solve; returns (alpha [nomega, ncomp, ncomp] complex128 numpy,
-    info dict)."""
+    info dict).  response="right": alpha from the right-hand amplitudes;
+    "full": the full response function (right- and left-hand solves)."""
     import numpy as np
     import torch
     L, mu, eps = L.contiguous(), mu.contiguous(), eps.contiguous()
@@ -297,7 +302,7 @@ def solve(eps, L, mu, omegas, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64",
     om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
     alpha = np.zeros((len(om), ncomp, ncomp), dtype=np.complex128)
     opts = SolveOpts(tol, max_iter, diis_dim, PREC[prec], CMUL[cmul], inner_tol, max_outer, 0,
-                     resid_fp64_every, PREC[anchor_prec])
+                     resid_fp64_every, PREC[anchor_prec], RESPONSE[response])
     info = SolveInfo()
     h = handle(L.device.index)
     st = lib().lrcc_solve(h, o, v, nchol, _ptr(eps), _ptr(L), ncomp, _ptr(mu), len(om),
@@ -329,7 +334,7 @@ def solve_batched(instances, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64", cm
         arr[k] = Instance(mu.shape[1], L.shape[1], L.shape[0], eps.data_ptr(), L.data_ptr(),
                           mu.shape[0], mu.data_ptr(), len(om), om.ctypes.data, al.ctypes.data)
     opts = SolveOpts(tol, max_iter, diis_dim, PREC[prec], CMUL[cmul], inner_tol, max_outer, 0,
-                     resid_fp64_every, 0)
+                     resid_fp64_every, 0, 0)
     info = SolveInfo()
     h = handle(dev)
     st = lib().lrcc_solve_batched(h, len(instances), arr, ctypes.byref(opts), ctypes.byref(info))

@@ -283,7 +283,7 @@ lrcc_status sigma_packed(lrcc_handle h, const Geom& g, const void* L, bool conj_
     if (g.nchol > 0) {
       LRCC_HIP(h, h->ls.ensure(bf16x3_ls_bytes(gb)));
       LRCC_HIP(h, h->xb.ensure(bf16x3_xb_bytes(gb)));
-      LRCC_HIP(h, bf16x3_stage_L(L, dt, gb, conj_t, h->ls.p, h->stream));
+      LRCC_HIP(h, bf16x3_stage_L(L, dt, gb, conj_t ? L_ADJ : L_PLAIN, h->ls.p, h->stream));
       LRCC_HIP(h, bf16x3_pack_x(X, dt, gb, tab, h->xb.p, h->stream));
       LRCC_HIP(h, h->hflag.ensure(16));
       LRCC_HIP(h, herm_check(L, dt, g.v, g.nchol, h->hflag.as<int>(), h->stream));
@@ -305,10 +305,12 @@ lrcc_status sigma_packed(lrcc_handle h, const Geom& g, const void* L, bool conj_
     LRCC_HIP(h, h->hflag.ensure(16));
     LRCC_HIP(h, herm_check(L, dt, g.v, g.nchol, h->hflag.as<int>(), h->stream));
     if (prec == LRCC_FP64) {
-      LRCC_HIP(h, stage_L<double>(L, dt, g, conj_t, h->ls.as<double>(), h->stream));
+      LRCC_HIP(h, stage_L<double>(L, dt, g, conj_t ? L_ADJ : L_PLAIN, h->ls.as<double>(),
+                                  h->stream));
       LRCC_HIP(h, pack_to_block<double>(X, dt, g, tab, h->xb.as<double>(), h->stream));
     } else {
-      LRCC_HIP(h, stage_L<float>(L, dt, g, conj_t, h->ls.as<float>(), h->stream));
+      LRCC_HIP(h, stage_L<float>(L, dt, g, conj_t ? L_ADJ : L_PLAIN, h->ls.as<float>(),
+                                 h->stream));
       LRCC_HIP(h, pack_to_block<float>(X, dt, g, tab, h->xb.as<float>(), h->stream));
     }
     st = ppl_run(h, prec, cmul, acc64, g, h->ls.p, h->xb.p, h->sb.p, h->hflag.as<int>());

@@ -97,10 +97,14 @@ lrcc_status hip_fail(lrcc_handle h, hipError_t e, const char* what);
   } while (0)
 
 // Staging / layout launchers (layout.hip) ----------------------------------
+// Which matrix of each L^P the staging writes: L^P itself, its conjugate
+// transpose (the adjoint ladder) or its transpose (the ladder's transpose,
+// for the left-hand response: K(L^T) = K(L)^T).
+enum LForm { L_PLAIN = 0, L_ADJ = 1, L_TRANS = 2 };
 // Stage L (complex, dtype dt) into planar blocks of type T, planes (re, im)
-// (both complex forms read these).  conj_t: stage (L^P)^H instead of L^P.
+// (both complex forms read these), in the form `form`.
 template <typename T>
-hipError_t stage_L(const void* L, lrcc_dtype dt, const Geom& g, bool conj_t, T* Ls,
+hipError_t stage_L(const void* L, lrcc_dtype dt, const Geom& g, LForm form, T* Ls,
                    hipStream_t st);
 // Packed doubles -> planar block layout (2 planes of T); dead slots and pad
 // rows are written as zero.
@@ -168,7 +172,7 @@ size_t bf16x3_xb_bytes(const Geom& g);
 // Panel rows [ab0, ab0 + n): upper tiles, and bytes with their mirrors.
 long bf16x3_panel_tiles(const Geom& g, int ab0, int n);
 size_t bf16x3_panel_bytes(const Geom& g, int ab0, int n);
-hipError_t bf16x3_stage_L(const void* L, lrcc_dtype dt, const Geom& g, bool conj_t, void* Ls,
+hipError_t bf16x3_stage_L(const void* L, lrcc_dtype dt, const Geom& g, LForm form, void* Ls,
                           hipStream_t st);
 hipError_t bf16x3_pack_x(const void* X, lrcc_dtype dt, const Geom& g, const int* tab, void* Xb,
                          hipStream_t st);

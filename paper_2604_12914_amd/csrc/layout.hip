@@ -29,7 +29,7 @@ __device__ inline long pidx(long p, long q, long n) { return p * (2 * n - p - 1)
 
 template <typename T>
 __global__ void k_stage_L(const void* __restrict__ L, lrcc_dtype dt, int v, int nchol,
-                          int nbv, int ncp, int conj_t, T* __restrict__ Ls) {
+                          int nbv, int ncp, int form, T* __restrict__ Ls) {
   // one thread per (block A, block C, P, slot)
   const long total = (long)nbv * nbv * ncp * NS;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
@@ -43,10 +43,10 @@ __global__ void k_stage_L(const void* __restrict__ L, lrcc_dtype dt, int v, int 
     double re = 0.0, im = 0.0;
     if (a < v && c < v && P < nchol) {
       // (L^H)^P_ac = conj(L^P_ca)
-      const size_t src = conj_t ? ((size_t)P * v + c) * v + a : ((size_t)P * v + a) * v + c;
+      const size_t src = form != L_PLAIN ? ((size_t)P * v + c) * v + a : ((size_t)P * v + a) * v + c;
       double2 z = load_c(L, dt, src);
       re = z.x;
-      im = conj_t ? -z.y : z.y;
+      im = form == L_ADJ ? -z.y : z.y;
     }
     T* dst = Ls + (r * 2) * NS + s;
     dst[0] = (T)re;
@@ -124,11 +124,11 @@ inline int grid_for(long n) {
 }  // namespace
 
 template <typename T>
-hipError_t stage_L(const void* L, lrcc_dtype dt, const Geom& g, bool conj_t,
+hipError_t stage_L(const void* L, lrcc_dtype dt, const Geom& g, LForm form,
                    T* Ls, hipStream_t st) {
   const long total = (long)g.nbv * g.nbv * g.ncp * NS;
   hipLaunchKernelGGL(k_stage_L<T>, dim3(grid_for(total)), dim3(256), 0, st, L, dt, g.v,
-                     g.nchol, g.nbv, g.ncp, (int)conj_t, Ls);
+                     g.nchol, g.nbv, g.ncp, (int)form, Ls);
   return hipGetLastError();
 }
 
@@ -169,9 +169,9 @@ hipError_t herm_check(const void* L, lrcc_dtype dt, int v, int nchol, int* nonhe
   return hipGetLastError();
 }
 
-template hipError_t stage_L<double>(const void*, lrcc_dtype, const Geom&, bool, double*,
+template hipError_t stage_L<double>(const void*, lrcc_dtype, const Geom&, LForm, double*,
                                     hipStream_t);
-template hipError_t stage_L<float>(const void*, lrcc_dtype, const Geom&, bool, float*,
+template hipError_t stage_L<float>(const void*, lrcc_dtype, const Geom&, LForm, float*,
                                    hipStream_t);
 template hipError_t pack_to_block<double>(const void*, lrcc_dtype, const Geom&, const int*,
                                           double*, hipStream_t);

@@ -86,7 +86,7 @@ __device__ inline long pidx(long p, long q, long n) { return p * (2 * n - p - 1)
 
 // L -> Ls16[A][C][chunk][plane][64 (a,c)][32 P]
 __global__ void k_stage_L16(const void* __restrict__ L, lrcc_dtype dt, int v, int nchol, int nbv,
-                            int ncp, int conj_t, __bf16* __restrict__ Ls) {
+                            int ncp, int form, __bf16* __restrict__ Ls) {
   const long total = (long)nbv * nbv * ncp * NS;  // (block, P, slot)
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
        e += (long)gridDim.x * blockDim.x) {
@@ -99,10 +99,10 @@ __global__ void k_stage_L16(const void* __restrict__ L, lrcc_dtype dt, int v, in
     const int a = A * TB + s / TB, c = C * TB + s % TB, P = pc * KB + p;
     float re = 0.f, im = 0.f;
     if (a < v && c < v && P < nchol) {
-      const size_t src = conj_t ? ((size_t)P * v + c) * v + a : ((size_t)P * v + a) * v + c;
+      const size_t src = form != L_PLAIN ? ((size_t)P * v + c) * v + a : ((size_t)P * v + a) * v + c;
       double2 z = load_c(L, dt, src);
       re = (float)z.x;
-      im = (float)(conj_t ? -z.y : z.y);
+      im = (float)(form == L_ADJ ? -z.y : z.y);
     }
     __bf16* dst = Ls + (size_t)rest * CHUNK + s * KB + p;
     split(re, dst[0], dst[NS * KB]);
@@ -571,11 +571,11 @@ int bf16x3_chunk() { return KB; }
 size_t bf16x3_ls_bytes(const Geom& g) { return (size_t)g.nbv * g.nbv * g.ncp * NS * NPL * 2; }
 size_t bf16x3_xb_bytes(const Geom& g) { return (size_t)NPL * g.xb_plane() * 2; }
 
-hipError_t bf16x3_stage_L(const void* L, lrcc_dtype dt, const Geom& g, bool conj_t, void* Ls,
+hipError_t bf16x3_stage_L(const void* L, lrcc_dtype dt, const Geom& g, LForm form, void* Ls,
                           hipStream_t st) {
   const long total = (long)g.nbv * g.nbv * g.ncp * NS;
   hipLaunchKernelGGL(k_stage_L16, dim3(grid_for(total)), dim3(256), 0, st, L, dt, g.v, g.nchol,
-                     g.nbv, g.ncp, (int)conj_t, static_cast<__bf16*>(Ls));
+                     g.nbv, g.ncp, (int)form, static_cast<__bf16*>(Ls));
   return hipGetLastError();
 }
 

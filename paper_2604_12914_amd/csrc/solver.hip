@@ -80,9 +80,10 @@ __device__ __forceinline__ double2 block_sum(double2 x, double2* sh) {
   return r;
 }
 
-// xi in block layout for every RHS r = w * ncomp + x.
+// xi in block layout for every RHS r = w * ncomp + x (conj: its complex
+// conjugate, the left-hand right-hand side eta).
 __global__ void k_xi(Dims d, int ncomp, const double2* __restrict__ mu, const int* tab,
-                     const int* otab, double* __restrict__ xi) {
+                     const int* otab, int conj, double* __restrict__ xi) {
   const int r = blockIdx.y;
   const double2* m = mu + (size_t)(r % ncomp) * d.o * d.v;
   for (long f = blockIdx.x * (long)RB + threadIdx.x; f < d.per_rhs; f += (long)gridDim.x * RB) {
@@ -95,7 +96,7 @@ __global__ void k_xi(Dims d, int ncomp, const double2* __restrict__ mu, const in
       im = (ia.x * jb.y + ia.y * jb.x) - (ib.x * ja.y + ib.y * ja.x);
     }
     xi[e.g] = re;
-    xi[e.g + d.plane] = im;
+    xi[e.g + d.plane] = conj ? -im : im;
   }
 }
 
@@ -523,7 +524,7 @@ dim3 grid_rhs(const Solver& S, int nr) { return dim3(S.nchunk, nr); }
 // tab: the block-pair table for this nbv (device).  `ir`: reduced precision.
 lrcc_status setup(Solver& S, lrcc_handle h, int o, int v, int nchol, const double* eps,
                   int ncomp, const void* mu, int nomega, const double* omegas, int mdim,
-                  bool ir, const int* tab, hipStream_t st) {
+                  bool ir, const int* tab, bool conj_rhs, hipStream_t st) {
   S.h = h;
   S.n = nomega * ncomp;
   S.ncomp = ncomp;
@@ -593,7 +594,7 @@ lrcc_status setup(Solver& S, lrcc_handle h, int o, int v, int nchol, const doubl
   LRCC_HIP(h, hipStreamSynchronize(st));  // host vectors go out of scope below
 
   hipLaunchKernelGGL(k_xi, grid_rhs(S, S.n), dim3(RB), 0, st, S.d, ncomp,
-                     static_cast<const double2*>(mu), tab, S.otab, S.xi);
+                     static_cast<const double2*>(mu), tab, S.otab, (int)conj_rhs, S.xi);
   LRCC_HIP(h, hipGetLastError());
   // zero the iterates and the DIIS ring once so dead slots and pad rows hold
   // zeros (the ladder kernel reads whole block-pair rows)
@@ -606,23 +607,24 @@ lrcc_status setup(Solver& S, lrcc_handle h, int o, int v, int nchol, const doubl
   return LRCC_OK;
 }
 
-// Stage L for a ladder of precision `prec` into dst.
-lrcc_status stage_for(Solver& S, const void* L, lrcc_prec prec, lrcc_cmul cmul, Buf& dst) {
+// Stage L (in the form `form`) for a ladder of precision `prec` into dst.
+lrcc_status stage_for(Solver& S, const void* L, lrcc_prec prec, lrcc_cmul cmul, Buf& dst,
+                      LForm form) {
   lrcc_handle h = S.h;
   Geom g = S.g;
   if (prec == LRCC_BF16X3) {
     g.ncp = (int)roundup(g.nchol, bf16x3_chunk());
     LRCC_HIP(h, dst.ensure(bf16x3_ls_bytes(g)));
-    if (g.nchol > 0) LRCC_HIP(h, bf16x3_stage_L(L, LRCC_C128, g, false, dst.p, h->stream));
+    if (g.nchol > 0) LRCC_HIP(h, bf16x3_stage_L(L, LRCC_C128, g, form, dst.p, h->stream));
     return LRCC_OK;
   }
   g.ncp = (int)roundup(g.nchol, ppl_chunk(prec, cmul));
   LRCC_HIP(h, dst.ensure(ppl_ls_bytes(prec, cmul, g)));
   if (g.nchol > 0) {
     if (prec == LRCC_FP64)
-      LRCC_HIP(h, stage_L<double>(L, LRCC_C128, g, false, dst.as<double>(), h->stream));
+      LRCC_HIP(h, stage_L<double>(L, LRCC_C128, g, form, dst.as<double>(), h->stream));
     else
-      LRCC_HIP(h, stage_L<float>(L, LRCC_C128, g, false, dst.as<float>(), h->stream));
+      LRCC_HIP(h, stage_L<float>(L, LRCC_C128, g, form, dst.as<float>(), h->stream));
   }
   return LRCC_OK;
 }
@@ -795,29 +797,22 @@ lrcc_status read_opts(lrcc_handle h, const lrcc_solve_opts* in, lrcc_solve_opts*
 
 }  // namespace
 
-lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps, const void* L,
+namespace {
+
+// One response solve: (A' - w) X = -b for every (w, component), with
+// A' X = D o X + K(L') X, L' = L or L^T (form) and b = xi or its conjugate
+// (conj_rhs); alpha receives -<b_x | X_y> per w.  Counts go into *tally.
+// Returns LRCC_OK, LRCC_ERR_NOT_CONVERGED (alpha filled) or an error.
+lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps, const void* L,
                        int ncomp, const void* mu, int nomega, const double* omegas,
-                       const lrcc_solve_opts* opts_in, double* alpha, lrcc_solve_info* info) {
-  auto t0 = std::chrono::steady_clock::now();
-  lrcc_solve_opts op;
-  Opts O;
-  lrcc_status st = read_opts(h, opts_in, &op, &O);
-  if (st != LRCC_OK) return st;
+                       const lrcc_solve_opts& op, const Opts& O, LForm form, bool conj_rhs,
+                       double* alpha, lrcc_solve_info* tally) {
+  lrcc_status st;
   const bool ir = op.prec != LRCC_FP64;
-  {
-    const Geom g = make_geom(o, v, nchol, nomega * ncomp, 1);
-    if (g.M == 0 || g.npv == 0) {
-      for (int p = 0; p < 2 * nomega * ncomp * ncomp; ++p) alpha[p] = 0;
-      if (info) *info = lrcc_solve_info{0, 0, 0, 0.0, 0.0};
-      return LRCC_OK;
-    }
-    st = ensure_tab(h, g.nbv);
-    if (st != LRCC_OK) return st;
-  }
   Solver S;
   for (int k = 0; k < 12; ++k) S.buf[k] = &h->sv[k];
   st = setup(S, h, o, v, nchol, eps, ncomp, mu, nomega, omegas, O.mdim, ir, h->tab.as<int>(),
-             h->stream);
+             conj_rhs, h->stream);
   if (st != LRCC_OK) return st;
   // staged vectors: h->ls for the FP64 ladder (or the refinement's anchor
   // ladder), h->ls2 for the reduced-precision inner ladder
@@ -825,10 +820,10 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
   if (anchor != LRCC_FP64 && anchor != LRCC_FP32)
     return fail(h, LRCC_ERR_ARG, "anchor_prec must be FP64 or FP32");
   LRCC_HIP(h, herm_check(L, LRCC_C128, v, nchol, S.nonherm, h->stream));
-  st = stage_for(S, L, anchor, op.cmul, h->ls);
+  st = stage_for(S, L, anchor, op.cmul, h->ls, form);
   if (st != LRCC_OK) return st;
   if (ir) {
-    st = stage_for(S, L, op.prec, op.cmul, h->ls2);
+    st = stage_for(S, L, op.prec, op.cmul, h->ls2, form);
     if (st != LRCC_OK) return st;
   }
   const size_t vb = (size_t)2 * S.d.plane * 8;
@@ -901,17 +896,75 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
     st = finish_alpha(S, S.x2, alpha, h->stream);
     if (st != LRCC_OK) return st;
   }
+  tally->iters_max = std::max(tally->iters_max, S.iters_max);
+  tally->n_sigma_fp64 += S.n_sigma64;
+  tally->n_sigma_lowp += S.n_sigma_lp;
+  tally->final_relres = std::max(tally->final_relres, final_rel);
+  return result;
+}
+
+}  // namespace
+
+lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps, const void* L,
+                       int ncomp, const void* mu, int nomega, const double* omegas,
+                       const lrcc_solve_opts* opts_in, double* alpha, lrcc_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  lrcc_solve_opts op;
+  Opts O;
+  lrcc_status st = read_opts(h, opts_in, &op, &O);
+  if (st != LRCC_OK) return st;
+  if (op.response != 0 && op.response != 1) return fail(h, LRCC_ERR_ARG, "unknown response mode");
+  const size_t np = (size_t)nomega * ncomp * ncomp;
+  {
+    const Geom g = make_geom(o, v, nchol, nomega * ncomp, 1);
+    if (g.M == 0 || g.npv == 0) {
+      for (size_t p = 0; p < 2 * np; ++p) alpha[p] = 0;
+      if (info) *info = lrcc_solve_info{0, 0, 0, 0.0, 0.0};
+      return LRCC_OK;
+    }
+    st = ensure_tab(h, g.nbv);
+    if (st != LRCC_OK) return st;
+  }
+  lrcc_solve_info tally{0, 0, 0, 0.0, 0.0};
+  lrcc_status result;
+  if (op.response == 0) {
+    // right-hand amplitudes: alpha_xy = -<xi_x | X_y(w)>
+    result = solve_side(h, o, v, nchol, eps, L, ncomp, mu, nomega, omegas, op, O, L_PLAIN, false,
+                        alpha, &tally);
+  } else {
+    // full linear response function (Sec. 2.2): right-hand X(w) from
+    // (A - w) X = -xi, left-hand Y(w) from Y (A + w) = -eta with eta =
+    // conj(xi) and F = 0 in this model, i.e. (A^T + w) Y^T = -eta: the same
+    // solver with L^T, -w and the conjugate right-hand side.  With
+    // f_xy = sum Y_y xi_x + sum eta_x X_y = -(aL + aR)_xy, the response
+    // function is (f_xy + conj f_yx) / 2 and alpha = -(that).
+    std::vector<double> ar(2 * np), al(2 * np), wneg(nomega);
+    lrcc_status rr = solve_side(h, o, v, nchol, eps, L, ncomp, mu, nomega, omegas, op, O,
+                                L_PLAIN, false, ar.data(), &tally);
+    if (rr != LRCC_OK && rr != LRCC_ERR_NOT_CONVERGED) return rr;
+    for (int w = 0; w < nomega; ++w) wneg[w] = -omegas[w];
+    lrcc_status rl = solve_side(h, o, v, nchol, eps, L, ncomp, mu, nomega, wneg.data(), op, O,
+                                L_TRANS, true, al.data(), &tally);
+    if (rl != LRCC_OK && rl != LRCC_ERR_NOT_CONVERGED) return rl;
+    for (int w = 0; w < nomega; ++w)
+      for (int x = 0; x < ncomp; ++x)
+        for (int y = 0; y < ncomp; ++y) {
+          const size_t pxy = 2 * (((size_t)w * ncomp + x) * ncomp + y);
+          const size_t pyx = 2 * (((size_t)w * ncomp + y) * ncomp + x);
+          alpha[pxy] = 0.5 * ((ar[pxy] + al[pxy]) + (ar[pyx] + al[pyx]));
+          alpha[pxy + 1] = 0.5 * ((ar[pxy + 1] + al[pxy + 1]) - (ar[pyx + 1] + al[pyx + 1]));
+        }
+    result = rr != LRCC_OK ? rr : rl;
+  }
   if (info) {
-    info->iters_max = S.iters_max;
-    info->n_sigma_fp64 = S.n_sigma64;
-    info->n_sigma_lowp = S.n_sigma_lp;
-    info->final_relres = final_rel;
+    *info = tally;
     info->seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   if (result == LRCC_ERR_NOT_CONVERGED) return fail(h, result, "tolerance not reached");
   return result;
 }
+
 
 // ---------------------------------------------------------------------------
 // Batched solve: every instance keeps its own state; per iteration one
@@ -929,6 +982,8 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
   if (st != LRCC_OK) return st;
   if (op.prec != LRCC_FP64)
     return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve runs the FP64 ladder");
+  if (op.response != 0)
+    return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve gives the right-hand response");
   constexpr int KC = 16;  // chunk of the persistent FP64 ladder
   std::vector<std::unique_ptr<Solver>> S(ninst);
   std::vector<std::unique_ptr<Buf[]>> own(ninst);
@@ -973,14 +1028,14 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
     LRCC_HIP(h, hipMemcpyAsync(own[i][14].p, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, cs));
     LRCC_HIP(h, hipStreamSynchronize(cs));
     st = setup(Si, h, I.o, I.v, I.nchol, I.eps, I.ncomp, I.mu, I.nomega, I.omegas, O.mdim, false,
-               own[i][13].as<int>(), cs);
+               own[i][13].as<int>(), false, cs);
     if (st != LRCC_OK) return st;
     Geom gs = Si.g;
     gs.ncp = (int)roundup(gs.nchol, KC);
     LRCC_HIP(h, own[i][12].ensure(ppl_ls_bytes(LRCC_FP64, LRCC_CMUL_4M, gs)));
     LRCC_HIP(h, herm_check(I.L, LRCC_C128, I.v, I.nchol, Si.nonherm, cs));
     if (gs.nchol > 0)
-      LRCC_HIP(h, stage_L<double>(I.L, LRCC_C128, gs, false, own[i][12].as<double>(), cs));
+      LRCC_HIP(h, stage_L<double>(I.L, LRCC_C128, gs, L_PLAIN, own[i][12].as<double>(), cs));
     std::vector<int> one(Si.n, 1);
     st = start_iteration(Si, Si.b, Si.x, one.data(), cs);
     if (st != LRCC_OK) return st;

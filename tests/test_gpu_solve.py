@@ -126,3 +126,59 @@ def test_baseline_workload_matches_exact_alpha(lrcc, prec, cmul, anchor):
     assert np.abs(alpha - exact).max() < 1e-5          # a.u., the accuracy target
     if anchor == "fp64":
         assert rel(alpha, exact) < 1e-7
+
+
+@pytest.mark.parametrize("herm", [True, False])
+@pytest.mark.parametrize("cmul", ["4m", "3m"])
+@pytest.mark.parametrize("o,v,nchol", [(4, 24, 64), (5, 44, 100)])
+def test_full_response_matches_oracle(lrcc, o, v, nchol, cmul, herm):
+    # right- and left-hand solves (the left one on the transposed ladder, the
+    # conjugate right-hand side and -w) combined into the full response
+    # function, against the oracle's exact solves
+    print(f"full response o={o} v={v} nchol={nchol} {cmul} herm={herm}", flush=True)
+    inst = S.make_instance(o, v, nchol, ncomp=3, seed=7, gamma=S.solve_gamma(v),
+                           hermitian=herm)
+    alpha, info = lrcc.solve(*to_dev(inst), OMEGAS, tol=1e-8, cmul=cmul, response="full")
+    ref = response.response_full_dense(inst.L, inst.eps, inst.mu, OMEGAS, o, v)["alpha"]
+    assert info["status"] == "LRCC_OK" and info["final_relres"] < 1e-8
+    assert rel(alpha, ref) < 1e-7
+    # Hermitian in the components by construction
+    herm_err = alpha - np.conj(np.transpose(alpha, (0, 2, 1)))
+    assert np.abs(herm_err).max() < 1e-12 * np.abs(alpha).max()
+    # the right-hand part alone is the default response mode
+    right, _ = lrcc.solve(*to_dev(inst), OMEGAS, tol=1e-8, cmul=cmul)
+    dense = response.solve_dense(inst.L, inst.eps, inst.mu, OMEGAS, o, v)["alpha"]
+    assert rel(right, dense) < 1e-7
+    if herm:  # alpha_full(w) = alpha(w) + conj alpha(-w)
+        minus = response.solve_dense(inst.L, inst.eps, inst.mu, [-w for w in OMEGAS], o, v)
+        assert rel(alpha, dense + np.conj(minus["alpha"])) < 1e-7
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_full_response_reduced_precision(lrcc, prec):
+    o, v, nchol = 5, 44, 100
+    inst = S.make_instance(o, v, nchol, ncomp=2, seed=8, gamma=S.solve_gamma(v), hermitian=False)
+    om = OMEGAS[:2]
+    alpha, info = lrcc.solve(*to_dev(inst), om, prec=prec, tol=1e-8, inner_tol=1e-5,
+                             response="full")
+    ref = response.response_full_dense(inst.L, inst.eps, inst.mu, om, o, v)["alpha"]
+    assert info["status"] == "LRCC_OK"
+    assert rel(alpha, ref) < 1e-7
+    assert info["n_sigma_fp64"] == 2  # one FP64 anchor ladder per side
+
+
+def test_response_mode_errors(lrcc):
+    import ctypes
+    o, v, nchol = 3, 16, 32
+    inst = S.make_instance(o, v, nchol, ncomp=1, seed=5, gamma=S.solve_gamma(v))
+    eps, L, mu = to_dev(inst)
+    with pytest.raises(KeyError):
+        lrcc.solve(eps, L, mu, [0.0], response="left")
+    # an unknown mode through the C-ABI is an argument error
+    opts = lrcc.SolveOpts(1e-8, 100, 8, 0, 0, 1e-5, 6, 0, 0, 0, 7)
+    alpha = np.zeros((1, 1, 1), np.complex128)
+    om = np.zeros(1)
+    st = lrcc.lib().lrcc_solve(lrcc.handle(0), o, v, nchol, lrcc._ptr(eps), lrcc._ptr(L), 1,
+                               lrcc._ptr(mu), 1, om.ctypes.data_as(ctypes.c_void_p),
+                               ctypes.byref(opts), alpha.ctypes.data_as(ctypes.c_void_p), None)
+    assert st == lrcc.ERR_ARG
