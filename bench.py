@@ -257,6 +257,21 @@ def main():
         if exact is not None:
             extra["solve_time_at_dalpha_1e-5"] = dalpha_sweep(lrcc, torch, np, eps, L, mu,
                                                               omegas, exact)
+        # full response function (right- and left-hand solves, Sec. 2.2): for
+        # this Hermitian operator it must equal alpha(w) + conj alpha(-w)
+        try:
+            t0 = time.perf_counter()
+            a_full, inf_full = lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL,
+                                          response="full")
+            t1 = time.perf_counter()
+            a_minus, _ = lrcc.solve(eps, L, mu, [-w for w in omegas], tol=1e-8, cmul=SOLVE_CMUL)
+            extra["solve_fp64_full_response"] = {
+                "ms": round((t1 - t0) * 1e3, 3), "n_sigma_fp64": inf_full["n_sigma_fp64"],
+                "alpha_zz": [float(a_full[w, 2, 2].real) for w in range(len(omegas))],
+                "max_abs_diff_vs_alpha_w_plus_conj_alpha_minus_w":
+                    float(np.abs(a_full - (alpha64 + np.conj(a_minus))).max())}
+        except lrcc.LrccError as err:
+            extra["solve_fp64_full_response"] = {"error": str(err)}
         extra["solve_fp64"] = {"ms": round(ms_step, 3), "iters_max": info["iters_max"],
                                "alpha_zz": [float(alpha64[w, 2, 2].real)
                                             for w in range(len(omegas))]}
