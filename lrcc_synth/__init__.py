@@ -21,6 +21,9 @@ its retained-virtual range of about 50--300 spinors):
 * Draw order from ``numpy.random.default_rng(seed)``: G real part, G
   imaginary part (each ``[nchol, v, v]``), occupied energies, virtual
   energies, then per dipole component its real and imaginary part.
+* Optionally (the hole-hole ladder), occupied-occupied Cholesky vectors
+  ``Loo[P, k, i]`` of the same form over the occupied spinors, drawn last,
+  scaled by ``solve_gamma(o)``.
 
 Packed doubles for sigma-only runs are drawn directly in packed form
 (``[nrhs, o(o-1)/2, v(v-1)/2]``, ``CN(0, 1)``); they stand for an amplitude
@@ -98,18 +101,21 @@ class Instance:
     eps: np.ndarray    # [o + v] float64, occupied first
     mu: np.ndarray     # [ncomp, o, v] complex128
     gamma: float
+    Loo: np.ndarray = None  # [nchol, o, o] complex128 (hole-hole ladder), optional
 
 
 def make_instance(o: int, v: int, nchol: int, ncomp: int = 3, seed: int = 0,
-                  gamma: float = 1.0, hermitian: bool = True) -> Instance:
-    """One synthetic LR instance, drawn in the documented order."""
+                  gamma: float = 1.0, hermitian: bool = True, hh: bool = False) -> Instance:
+    """One synthetic LR instance, drawn in the documented order (``hh``: also
+    the occupied-occupied vectors of the hole-hole ladder, drawn last)."""
     rng = np.random.default_rng(seed)
     L = make_L(rng, nchol, v, gamma, hermitian)
     e_occ = rng.uniform(-2.0, -0.5, size=o)
     e_vir = rng.uniform(0.1, 5.0, size=v)
     mu = np.stack([cn(rng, (o, v), 0.1) for _ in range(ncomp)]) if ncomp else \
         np.zeros((0, o, v), np.complex128)
-    return Instance(o, v, nchol, L, np.concatenate([e_occ, e_vir]), mu, gamma)
+    Loo = make_L(rng, nchol, o, solve_gamma(o), hermitian) if hh else None
+    return Instance(o, v, nchol, L, np.concatenate([e_occ, e_vir]), mu, gamma, Loo)
 
 
 @dataclass

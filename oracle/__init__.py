@@ -13,10 +13,12 @@ Modules:
   response  -- model LR problem: RHS, denominators, Jacobi+DIIS solve, dense
                per-pair solve, sum-over-states solve, alpha.
   grads     -- vector-Jacobian products of sigma with respect to X and L.
+  hhl       -- the hole-hole ladder over occupied-occupied Cholesky vectors
+               (definition, factored identity, brute force, packed matrix).
 
 Every function is pinned by ``tests/test_oracle_*.py`` against brute force,
 closed forms, invariants or finite differences.  Parity with the paper's
 printed numbers is unpinned: the paper's molecular results need integrals
 that are not available, and it prints no worked example of this path.
 """
-from . import ppl, response, grads  # noqa: F401
+from . import ppl, response, grads, hhl  # noqa: F401
