@@ -101,6 +101,17 @@ lrcc_status lrcc_ppl_sigma_adjoint(lrcc_handle h, int o, int v, int nchol, int n
                                    void* dX, void* dL,
                                    lrcc_dtype dt, lrcc_prec prec, lrcc_cmul cmul);
 
+/* Hole-hole ladder alone (a model extension of the Jacobian next to the
+ * particle-particle ladder): sigma_ij^ab = sum_{k,l} <kl||ij> X_kl^ab with
+ * <kl|ij> = sum_P L^P_ki L^P_lj over occupied-occupied Cholesky vectors
+ * Loo[nchol][o][o] (device, dtype dt, Loo[P][k][i] = L^P_ki), the
+ * unrestricted k, l sum as in lrcc_ppl_sigma.  X and sigma: packed doubles as
+ * in lrcc_ppl_sigma (device; sigma overwritten).  FP64 arithmetic.  The
+ * integrals <kl||ij> (no particle index) are formed explicitly, npo x npo.
+ * Asynchronous on the handle's stream. */
+lrcc_status lrcc_hhl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* Loo,
+                           const void* X, void* sigma, lrcc_dtype dt);
+
 /* Options of the response solve.  Zero-initialised fields take defaults. */
 typedef struct {
   double tol;        /* relative residual |R|/|xi| (default 1e-8)            */
@@ -135,6 +146,14 @@ typedef struct {
                         L this is alpha_R(w) + conj(alpha_R(-w)), both terms
                         of the sum-over-states form.  lrcc_solve_batched
                         supports 0 only                                      */
+  const void* L_oo;  /* (device) NULL (default), or occupied-occupied
+                        Cholesky vectors [nchol][o][o] complex128,
+                        L_oo[P][k][i] = L^P_ki: the model Jacobian then also
+                        holds the hole-hole ladder
+                          sum_{k,l} <kl||ij> X_kl^ab, <kl|ij> = sum_P
+                          L^P_ki L^P_lj,
+                        which couples the occupied pairs (applied in FP64
+                        whatever prec is).  lrcc_solve_batched: NULL only    */
 } lrcc_solve_opts;
 
 typedef struct {

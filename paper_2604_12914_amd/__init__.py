@@ -46,7 +46,7 @@ class SolveOpts(ctypes.Structure):
                 ("cmul", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("deterministic", ctypes.c_int),
                 ("resid_fp64_every", ctypes.c_int), ("anchor_prec", ctypes.c_int),
-                ("response", ctypes.c_int)]
+                ("response", ctypes.c_int), ("L_oo", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
             "lrcc_set_stream": [vp, vp],
             "lrcc_ppl_sigma": [vp, i, i, i, i, vp, vp, vp, i, i, i],
             "lrcc_ppl_sigma_adjoint": [vp, i, i, i, i, vp, vp, vp, vp, vp, i, i, i],
+            "lrcc_hhl_sigma": [vp, i, i, i, i, vp, vp, vp, i],
             "lrcc_solve": [vp, i, i, i, vp, vp, i, vp, i, vp,
                            ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)],
             "lrcc_solve_batched": [vp, i, ctypes.POINTER(Instance),
@@ -196,6 +197,30 @@ def ppl_sigma(L, X, o=None, prec="fp64", cmul="4m", out=None):
     return out
 
 
+def hhl_sigma(Loo, X, v=None, out=None):
+    """Hole-hole ladder sigma_ij^ab = sum_kl <kl||ij> X_kl^ab on the GPU (FP64
+    arithmetic); Loo [nchol, o, o], X packed [nrhs, o(o-1)/2, v(v-1)/2]."""
+    import torch
+    Loo, X = Loo.contiguous(), X.contiguous()
+    if Loo.dim() != 3 or Loo.shape[1] != Loo.shape[2] or X.dim() != 3:
+        raise ValueError("Loo must be [nchol, o, o] and X [nrhs, npo, npv]")
+    if Loo.dtype != X.dtype or X.dtype not in (torch.complex128, torch.complex64):
+        raise TypeError("Loo and X must share a complex dtype")
+    nchol, o = Loo.shape[0], Loo.shape[1]
+    nrhs, npo, npv = X.shape
+    if npo != o * (o - 1) // 2:
+        raise ValueError("X's occupied-pair count does not match Loo")
+    if v is None:
+        v = int(round((1 + (1 + 8 * npv) ** 0.5) / 2))
+    if npv != v * (v - 1) // 2:
+        raise ValueError("X's virtual-pair count does not match v")
+    out = torch.empty_like(X) if out is None else out
+    h = handle(X.device.index)
+    _check(lib().lrcc_hhl_sigma(h, o, v, nchol, nrhs, _ptr(Loo), _ptr(X), _ptr(out),
+                                _dtype_code(X)), h)
+    return out
+
+
 def ppl_sigma_adjoint(L, X, G, o=None, want_dX=True, want_dL=True, prec="fp64", cmul="4m"):
     """(dX, dL) for upstream gradient G of sigma = PPL(L, X)."""
     import torch
@@ -288,10 +313,12 @@ RESPONSE = {"right": 0, "full": 1}
 
 def solve(eps, L, mu, omegas, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64",
           cmul="4m", inner_tol=1e-5, max_outer=6, check=True, resid_fp64_every=0,
-          anchor_prec="fp64", response="right"):
+          anchor_prec="fp64", response="right", Loo=None):
     """Model response solve; returns (alpha [nomega, ncomp, ncomp] complex128 numpy,
     info dict).  response="right": alpha from the right-hand amplitudes;
-    "full": the full response function (right- and left-hand solves)."""
+    "full": the full response function (right- and left-hand solves).
+    Loo: occupied-occupied Cholesky vectors [nchol, o, o] (complex128) to
+    include the hole-hole ladder in the model Jacobian."""
     import numpy as np
     import torch
     L, mu, eps = L.contiguous(), mu.contiguous(), eps.contiguous()
@@ -301,8 +328,13 @@ def solve(eps, L, mu, omegas, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64",
     ncomp, o = mu.shape[0], mu.shape[1]
     om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
     alpha = np.zeros((len(om), ncomp, ncomp), dtype=np.complex128)
+    if Loo is not None:
+        Loo = Loo.contiguous()
+        if Loo.dtype != torch.complex128 or tuple(Loo.shape) != (nchol, o, o):
+            raise ValueError("Loo must be complex128 [nchol, o, o]")
     opts = SolveOpts(tol, max_iter, diis_dim, PREC[prec], CMUL[cmul], inner_tol, max_outer, 0,
-                     resid_fp64_every, PREC[anchor_prec], RESPONSE[response])
+                     resid_fp64_every, PREC[anchor_prec], RESPONSE[response],
+                     Loo.data_ptr() if Loo is not None else None)
     info = SolveInfo()
     h = handle(L.device.index)
     st = lib().lrcc_solve(h, o, v, nchol, _ptr(eps), _ptr(L), ncomp, _ptr(mu), len(om),

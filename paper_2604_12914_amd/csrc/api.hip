@@ -366,6 +366,7 @@ lrcc_status lrcc_destroy(lrcc_handle h) {
     h->hflag.release();
     for (auto& b : h->order) b.release();
     h->vws.release();
+    h->hw.release();
     for (auto& b : h->sv) b.release();
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
     if (h->rb) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(h->rb));
@@ -437,6 +438,53 @@ lrcc_status lrcc_ppl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, con
   h->err.clear();
   Geom g = make_geom(o, v, nchol, nrhs, ppl_chunk(prec, cmul));
   return sigma_packed(h, g, L, false, X, sigma, dt, prec, cmul);
+}
+
+lrcc_status lrcc_hhl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* Loo,
+                           const void* X, void* sigma, lrcc_dtype dt) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  if (o < 0 || v < 0 || nchol < 0 || nrhs < 0)
+    return fail(h, LRCC_ERR_ARG, "o, v, nchol and nrhs must be non-negative");
+  if (dt != LRCC_C128 && dt != LRCC_C64) return fail(h, LRCC_ERR_ARG, "unknown dtype");
+  if (v > 4096) return fail(h, LRCC_ERR_SHAPE, "v exceeds 4096");
+  if (o > 4096) return fail(h, LRCC_ERR_SHAPE, "o exceeds 4096");
+  if (nchol > 65536) return fail(h, LRCC_ERR_SHAPE, "nchol exceeds 65536");
+  const long M = (long)nrhs * npair(o);
+  if (M > (1L << 24)) return fail(h, LRCC_ERR_SHAPE, "nrhs*o(o-1)/2 exceeds 2^24");
+  if (nrhs > 65535) return fail(h, LRCC_ERR_SHAPE, "nrhs exceeds 65535");
+  const size_t es = dt == LRCC_C128 ? 16 : 8;
+  const size_t nx = (size_t)M * npair(v) * es;
+  const size_t nl = (size_t)nchol * o * o * es;
+  if (nx == 0) return LRCC_OK;
+  if (!X || !sigma) return fail(h, LRCC_ERR_ARG, "X or sigma is NULL");
+  if ((uintptr_t)X % es || (uintptr_t)sigma % es)
+    return fail(h, LRCC_ERR_ARG, "X/sigma not aligned to the element size");
+  if (overlaps(X, nx, sigma, nx)) return fail(h, LRCC_ERR_ARG, "sigma overlaps X");
+  if (nl > 0) {
+    if (!Loo) return fail(h, LRCC_ERR_ARG, "Loo is NULL");
+    if ((uintptr_t)Loo % es) return fail(h, LRCC_ERR_ARG, "Loo not aligned to the element size");
+    if (overlaps(Loo, nl, sigma, nx)) return fail(h, LRCC_ERR_ARG, "sigma overlaps Loo");
+  }
+  DeviceGuard dg(h->device);
+  h->err.clear();
+  const Geom g = make_geom(o, v, nchol, nrhs, 1);
+  lrcc_status st = ensure_tab(h, g.nbv);
+  if (st != LRCC_OK) return st;
+  const int* tab = h->tab.as<int>();
+  const size_t vb = (size_t)2 * g.xb_plane() * 8;
+  LRCC_HIP(h, h->xb.ensure(vb));
+  LRCC_HIP(h, h->sb.ensure(vb));
+  const size_t wbytes = roundup((size_t)g.npo * g.npo * 16, 256);
+  LRCC_HIP(h, h->hw.ensure(wbytes + (size_t)g.npo * 4));
+  double2* W = h->hw.as<double2>();
+  int* otab = reinterpret_cast<int*>(h->hw.as<char>() + wbytes);
+  LRCC_HIP(h, pack_to_block<double>(X, dt, g, tab, h->xb.as<double>(), h->stream));
+  LRCC_HIP(h, fill_zero(h->sb.p, vb, h->stream));
+  LRCC_HIP(h, hh_pair_table(o, otab, h->stream));
+  LRCC_HIP(h, hh_build_w(Loo, dt, o, nchol, otab, L_PLAIN, W, h->stream));
+  LRCC_HIP(h, hh_apply(W, g, h->xb.as<double>(), h->sb.as<double>(), h->stream));
+  LRCC_HIP(h, block_to_pack<double>(h->sb.as<double>(), g, tab, sigma, dt, h->stream));
+  return LRCC_OK;
 }
 
 lrcc_status lrcc_ppl_sigma_adjoint(lrcc_handle h, int o, int v, int nchol, int nrhs,

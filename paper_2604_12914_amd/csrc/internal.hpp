@@ -77,6 +77,7 @@ struct lrcc_handle_s {
   int tab_nbv = -1;
   // solver workspace
   lrcc::Buf sv[12];
+  lrcc::Buf hw;           // hole-hole ladder: W matrix and occupied pair table
   void* rb = nullptr;     // rocBLAS handle (gradient GEMMs), created on first use
   // ladder-kernel timing (lrcc_set_timing)
   bool timing = false;
@@ -164,6 +165,19 @@ size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g);
 // handle has timing enabled.
 lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
                     const void* Ls, const void* Xb, void* Sb, const int* nonherm);
+
+// Hole-hole ladder (hhl.hip) ------------------------------------------------
+// W[(ij),(kl)] = 2 <kl||ij> from occupied-occupied vectors Loo [nchol][o][o]
+// (dtype dt; form L_TRANS: from (L^P)^T, which gives W^T); otab[p] = (i<<16)|j
+// of packed occupied pair p (device).  W: npo*npo complex (device).
+hipError_t hh_build_w(const void* Loo, lrcc_dtype dt, int o, int nchol, const int* otab,
+                      LForm form, double2* W, hipStream_t st);
+// otab[p] = (i << 16) | j of the packed occupied pairs (device, npo ints).
+hipError_t hh_pair_table(int o, int* otab, hipStream_t st);
+// Sb += W X per block pair and right-hand side on the block layout (FP64
+// planes re, im); Xb and Sb as the ladder's.
+hipError_t hh_apply(const double2* W, const Geom& g, const double* Xb, double* Sb,
+                    hipStream_t st);
 
 // bf16x3 ladder (ppl_bf16x3.hip): staged layouts and the panel driver.
 int bf16x3_chunk();

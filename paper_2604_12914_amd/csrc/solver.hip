@@ -502,6 +502,7 @@ struct Solver {
   float* s32 = nullptr;  // float sums of the FP32 ladder
   int *otab = nullptr, *active = nullptr, *itp = nullptr;
   int* nonherm = nullptr;  // Hermiticity flag of L (herm_check)
+  const double2* W = nullptr;  // hole-hole ladder matrix (optional)
   unsigned* valid = nullptr;
   double2 *Bm = nullptr, *coef = nullptr, *part = nullptr;
   double* relres = nullptr;
@@ -631,8 +632,8 @@ lrcc_status stage_for(Solver& S, const void* L, lrcc_prec prec, lrcc_cmul cmul, 
 
 // s = ladder(xin) for all rows (block layout, FP64 accumulation), with the
 // Cholesky vectors staged for `prec` in ls.
-lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul cmul,
-                        const void* ls) {
+lrcc_status apply_ppl(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul cmul,
+                      const void* ls) {
   lrcc_handle h = S.h;
   Geom g = S.g;
   g.ncp = (int)roundup(g.nchol, ppl_chunk(prec, cmul));
@@ -665,6 +666,17 @@ lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul 
   hipLaunchKernelGGL(k_to_f64, grid, dim3(RB), 0, h->stream, n, S.s32, S.s);
   LRCC_HIP(h, hipGetLastError());
   ++S.n_sigma_lp;
+  return LRCC_OK;
+}
+
+// s = the Jacobian's ladders applied to xin: the particle-particle ladder in
+// `prec` and, when the model includes it, the hole-hole ladder (FP64; its
+// npo^2 npv cost per right-hand side is small beside the ladder's).
+lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul cmul,
+                        const void* ls) {
+  lrcc_status st = apply_ppl(S, xin, prec, cmul, ls);
+  if (st != LRCC_OK || !S.W || S.g.nchol == 0) return st;
+  LRCC_HIP(S.h, hh_apply(S.W, S.g, xin, S.s, S.h->stream));
   return LRCC_OK;
 }
 
@@ -820,6 +832,13 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
   if (anchor != LRCC_FP64 && anchor != LRCC_FP32)
     return fail(h, LRCC_ERR_ARG, "anchor_prec must be FP64 or FP32");
   LRCC_HIP(h, herm_check(L, LRCC_C128, v, nchol, S.nonherm, h->stream));
+  if (op.L_oo && nchol > 0) {  // the hole-hole ladder: W (or W^T for L^T)
+    const size_t wbytes = (size_t)S.g.npo * S.g.npo * 16;
+    LRCC_HIP(h, h->hw.ensure(wbytes));
+    LRCC_HIP(h, hh_build_w(op.L_oo, LRCC_C128, o, nchol, S.otab, form,
+                           h->hw.as<double2>(), h->stream));
+    S.W = h->hw.as<double2>();
+  }
   st = stage_for(S, L, anchor, op.cmul, h->ls, form);
   if (st != LRCC_OK) return st;
   if (ir) {
@@ -984,6 +1003,8 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
     return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve runs the FP64 ladder");
   if (op.response != 0)
     return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve gives the right-hand response");
+  if (op.L_oo)
+    return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve has no hole-hole ladder");
   constexpr int KC = 16;  // chunk of the persistent FP64 ladder
   std::vector<std::unique_ptr<Solver>> S(ninst);
   std::vector<std::unique_ptr<Buf[]>> own(ninst);
