@@ -43,6 +43,7 @@ __all__ = [
     "make_L",
     "make_instance",
     "make_packed",
+    "make_psd",
     "npair",
     "solve_gamma",
 ]
@@ -154,3 +155,17 @@ CONFIGS = {
     "gradcheck": Config("gradcheck", 6, 36, 144, 1, (0.0,), 0,
                         "o=6 v=36 Nchol=144 (Nchol = 4v)"),
 }
+
+
+def make_psd(rng: np.random.Generator, n: int, rank: int, decay: float = 4.0) -> np.ndarray:
+    """Hermitian positive semi-definite ``[n, n]`` complex128 matrix of the
+    given rank, M = B B^H with ``B[:, k] ~ CN(0, 1) exp(-k / decay)``: a
+    stand-in for a two-electron integral matrix over index pairs (decaying
+    spectrum, low numerical rank) for the pivoted Cholesky decomposition.
+    Made exactly Hermitian (the upper triangle mirrored)."""
+    B = cn(rng, (n, rank)) * np.exp(-np.arange(rank, dtype=np.float64) / decay)[None, :]
+    M = B @ np.conj(B.T)
+    iu = np.triu_indices(n, 1)
+    M[(iu[1], iu[0])] = np.conj(M[iu])
+    M[np.diag_indices(n)] = np.real(np.diag(M))
+    return M
