@@ -112,6 +112,20 @@ lrcc_status lrcc_ppl_sigma_adjoint(lrcc_handle h, int o, int v, int nchol, int n
 lrcc_status lrcc_hhl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* Loo,
                            const void* X, void* sigma, lrcc_dtype dt);
 
+/* Pivoted (single-step) Cholesky decomposition of a two-electron integral
+ * matrix (Sec. 3): M (device, n x n complex128, row-major, Hermitian positive
+ * semi-definite; M[i][p] is read for the pivot column p) is decomposed as
+ * M ~= sum_q L_q L_q^H, one vector at a time at the pivot of the largest
+ * remaining diagonal element (the first index among equal values), until
+ * that element is <= tau or max_vectors (capped at n) vectors exist.
+ * L (device, [max_vectors][n] complex128) receives the vectors, pivots
+ * (device, [max_vectors] int, nullable) their pivots, *nvec (host) the
+ * count.  Synchronous: returns when the decomposition is complete.  Errors:
+ * LRCC_ERR_ARG for NULL/misaligned/overlapping buffers, negative sizes or a
+ * tau that is negative or not finite; LRCC_ERR_SHAPE for n > 2^20. */
+lrcc_status lrcc_cholesky(lrcc_handle h, long n, const void* M, double tau, int max_vectors,
+                          void* L, int* pivots, int* nvec);
+
 /* Options of the response solve.  Zero-initialised fields take defaults. */
 typedef struct {
   double tol;        /* relative residual |R|/|xi| (default 1e-8)            */

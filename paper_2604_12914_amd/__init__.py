@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
             "lrcc_ppl_sigma": [vp, i, i, i, i, vp, vp, vp, i, i, i],
             "lrcc_ppl_sigma_adjoint": [vp, i, i, i, i, vp, vp, vp, vp, vp, i, i, i],
             "lrcc_hhl_sigma": [vp, i, i, i, i, vp, vp, vp, i],
+            "lrcc_cholesky": [vp, ctypes.c_long, vp, d, i, vp, vp, ctypes.POINTER(i)],
             "lrcc_solve": [vp, i, i, i, vp, vp, i, vp, i, vp,
                            ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)],
             "lrcc_solve_batched": [vp, i, ctypes.POINTER(Instance),
@@ -219,6 +220,27 @@ def hhl_sigma(Loo, X, v=None, out=None):
     _check(lib().lrcc_hhl_sigma(h, o, v, nchol, nrhs, _ptr(Loo), _ptr(X), _ptr(out),
                                 _dtype_code(X)), h)
     return out
+
+
+def cholesky(M, tau=1e-5, max_vectors=None):
+    """Pivoted Cholesky decomposition of a Hermitian PSD matrix M [n, n]
+    (complex128, on the GPU): returns (L [k, n] tensor, pivots [k] numpy) with
+    M ~= sum_q L_q L_q^H and every remaining diagonal element <= tau."""
+    import numpy as np
+    import torch
+    M = M.contiguous()
+    if M.dim() != 2 or M.shape[0] != M.shape[1] or M.dtype != torch.complex128:
+        raise ValueError("M must be a square complex128 matrix")
+    n = M.shape[0]
+    kmax = n if max_vectors is None else min(int(max_vectors), n)
+    L = torch.empty((kmax, n), dtype=torch.complex128, device=M.device)
+    piv = torch.empty((kmax,), dtype=torch.int32, device=M.device)
+    cnt = ctypes.c_int(0)
+    h = handle(M.device.index)
+    _check(lib().lrcc_cholesky(h, n, _ptr(M), float(tau), kmax, _ptr(L),
+                               piv.data_ptr() if kmax else None, ctypes.byref(cnt)), h)
+    k = cnt.value
+    return L[:k], piv[:k].cpu().numpy().astype(np.int64)
 
 
 def ppl_sigma_adjoint(L, X, G, o=None, want_dX=True, want_dL=True, prec="fp64", cmul="4m"):

@@ -367,6 +367,7 @@ lrcc_status lrcc_destroy(lrcc_handle h) {
     for (auto& b : h->order) b.release();
     h->vws.release();
     h->hw.release();
+    h->cw.release();
     for (auto& b : h->sv) b.release();
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
     if (h->rb) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(h->rb));
@@ -484,6 +485,31 @@ lrcc_status lrcc_hhl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, con
   LRCC_HIP(h, hh_build_w(Loo, dt, o, nchol, otab, L_PLAIN, W, h->stream));
   LRCC_HIP(h, hh_apply(W, g, h->xb.as<double>(), h->sb.as<double>(), h->stream));
   LRCC_HIP(h, block_to_pack<double>(h->sb.as<double>(), g, tab, sigma, dt, h->stream));
+  return LRCC_OK;
+}
+
+lrcc_status lrcc_cholesky(lrcc_handle h, long n, const void* M, double tau, int max_vectors,
+                          void* L, int* pivots, int* nvec) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  if (!nvec) return fail(h, LRCC_ERR_ARG, "nvec is NULL");
+  *nvec = 0;
+  if (n < 0 || max_vectors < 0) return fail(h, LRCC_ERR_ARG, "n and max_vectors must be >= 0");
+  if (!(tau >= 0) || tau > 1e300) return fail(h, LRCC_ERR_ARG, "tau must be finite and >= 0");
+  if (n > (1L << 20)) return fail(h, LRCC_ERR_SHAPE, "n exceeds 2^20");
+  if (max_vectors > n) max_vectors = (int)n;
+  if (n == 0 || max_vectors == 0) return LRCC_OK;
+  if (!M || !L) return fail(h, LRCC_ERR_ARG, "M or L is NULL");
+  if ((uintptr_t)M % 16 || (uintptr_t)L % 16)
+    return fail(h, LRCC_ERR_ARG, "M/L not aligned to 16 bytes");
+  const size_t nm = (size_t)n * n * 16, nl = (size_t)max_vectors * n * 16;
+  if (overlaps(M, nm, L, nl)) return fail(h, LRCC_ERR_ARG, "L overlaps M");
+  if (pivots && ((uintptr_t)pivots % 4 || overlaps(pivots, (size_t)max_vectors * 4, L, nl) ||
+                 overlaps(pivots, (size_t)max_vectors * 4, M, nm)))
+    return fail(h, LRCC_ERR_ARG, "pivots misaligned or overlapping M/L");
+  DeviceGuard dg(h->device);
+  h->err.clear();
+  LRCC_HIP(h, h->cw.ensure(chol_state_bytes(n)));
+  LRCC_HIP(h, chol_run(n, M, tau, max_vectors, L, pivots, h->cw.p, nvec, h->stream));
   return LRCC_OK;
 }
 

@@ -78,6 +78,7 @@ struct lrcc_handle_s {
   // solver workspace
   lrcc::Buf sv[12];
   lrcc::Buf hw;           // hole-hole ladder: W matrix and occupied pair table
+  lrcc::Buf cw;           // pivoted Cholesky: remaining diagonal and state
   void* rb = nullptr;     // rocBLAS handle (gradient GEMMs), created on first use
   // ladder-kernel timing (lrcc_set_timing)
   bool timing = false;
@@ -165,6 +166,14 @@ size_t ppl_xb_bytes(lrcc_prec prec, const Geom& g);
 // handle has timing enabled.
 lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, const Geom& g,
                     const void* Ls, const void* Xb, void* Sb, const int* nonherm);
+
+// Pivoted Cholesky decomposition (chol.hip) ----------------------------------
+// Workspace bytes for n rows; run the decomposition of M (n x n complex128,
+// device) into L [maxv][n] (device) with optional pivots [maxv] (device);
+// *nvec (host) receives the vector count.  Synchronous on st.
+size_t chol_state_bytes(long n);
+hipError_t chol_run(long n, const void* M, double tau, int maxv, void* L, int* pivots, void* ws,
+                    int* nvec, hipStream_t st);
 
 // Hole-hole ladder (hhl.hip) ------------------------------------------------
 // W[(ij),(kl)] = 2 <kl||ij> from occupied-occupied vectors Loo [nchol][o][o]
