@@ -44,6 +44,8 @@ __all__ = [
     "make_instance",
     "make_packed",
     "make_psd",
+    "make_fns_instance",
+    "FnsInstance",
     "npair",
     "solve_gamma",
 ]
@@ -169,3 +171,54 @@ def make_psd(rng: np.random.Generator, n: int, rank: int, decay: float = 4.0) ->
     M[(iu[1], iu[0])] = np.conj(M[iu])
     M[np.diag_indices(n)] = np.real(np.diag(M))
     return M
+
+
+@dataclass
+class FnsInstance:
+    o: int
+    v: int
+    nchol: int
+    eps: np.ndarray    # [o + v] float64, occupied first (canonical spinor energies)
+    Lov: np.ndarray    # [nchol, o, v] complex128, Lov[P, i, a] = L^P_ia
+    A_oo: np.ndarray   # [ncomp, o, o] complex128, A_oo[x, m, i] = <m|A_x|i>
+    A_vv: np.ndarray   # [ncomp, v, v] complex128, A_vv[x, a, e] = <a|A_x|e>
+    A_ov: np.ndarray   # [ncomp, o, v] complex128, A_ov[x, i, a] = <a|A_x|i>
+
+
+def make_fns_instance(o: int, v: int, nchol: int, ncomp: int = 3, seed: int = 0,
+                      lscale: float = 0.05, ascale: float = 0.1,
+                      emax: float = 200.0) -> FnsInstance:
+    """Inputs of the perturbation-sensitive natural-spinor density.
+
+    Draw order from ``default_rng(seed)``: occupied energies ``U(-2, -0.5)``,
+    virtual energies log-uniform on ``[0.1, emax]`` Eh (a relativistic basis
+    reaches far up in energy), the occupied-virtual Cholesky vectors
+    ``Lov[P, i, a] = CN(0, lscale^2) exp(-P / 16) / (1 + e_a)`` (real part
+    then imaginary part of the whole ``[nchol, o, v]`` array; high virtuals
+    couple weakly, so the occupation numbers decay over several decades and
+    a 1e-5 threshold keeps roughly a third to two fifths of the virtuals),
+    then per perturbation component a
+    Hermitian one-body matrix over all ``o + v`` spinors,
+    ``(G + G^H) / 2`` with ``G ~ CN(0, ascale^2)`` (a dipole-like operator),
+    split into its occupied-occupied, virtual-virtual and virtual-occupied
+    blocks.  The blocks are stored as ``A_oo[m, i] = <m|A|i>``,
+    ``A_vv[a, e] = <a|A|e>`` and ``A_ov[i, a] = <a|A|i>``."""
+    rng = np.random.default_rng(seed)
+    e_occ = rng.uniform(-2.0, -0.5, size=o)
+    e_vir = np.exp(rng.uniform(math.log(0.1), math.log(emax), size=v))
+    decay = np.exp(-np.arange(nchol, dtype=np.float64) / 16.0)
+    Lov = cn(rng, (nchol, o, v), lscale) * decay[:, None, None] / (1.0 + e_vir)[None, None, :]
+    n = o + v
+    A_oo = np.zeros((ncomp, o, o), np.complex128)
+    A_vv = np.zeros((ncomp, v, v), np.complex128)
+    A_ov = np.zeros((ncomp, o, v), np.complex128)
+    for x in range(ncomp):
+        g = cn(rng, (n, n), ascale)
+        a = 0.5 * (g + np.conj(g.T))
+        iu = np.triu_indices(n, 1)
+        a[(iu[1], iu[0])] = np.conj(a[iu])
+        a[np.diag_indices(n)] = np.real(np.diag(a))
+        A_oo[x] = a[:o, :o]
+        A_vv[x] = a[o:, o:]
+        A_ov[x] = a[o:, :o].T
+    return FnsInstance(o, v, nchol, np.concatenate([e_occ, e_vir]), Lov, A_oo, A_vv, A_ov)

@@ -16,10 +16,13 @@ Modules:
   hhl       -- the hole-hole ladder over occupied-occupied Cholesky vectors
                (definition, factored identity, brute force, packed matrix).
   chol      -- the pivoted Cholesky decomposition that produces the vectors.
+  fns       -- perturbation-sensitive natural spinors (FNS++): MP2 and
+               perturbed amplitudes, dressed diagonals, the averaged density,
+               truncation by |occupation| and the semicanonical basis.
 
 Every function is pinned by ``tests/test_oracle_*.py`` against brute force,
 closed forms, invariants or finite differences.  Parity with the paper's
 printed numbers is unpinned: the paper's molecular results need integrals
 that are not available, and it prints no worked example of this path.
 """
-from . import ppl, response, grads, hhl, chol  # noqa: F401
+from . import ppl, response, grads, hhl, chol, fns  # noqa: F401
