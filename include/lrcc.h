@@ -126,6 +126,53 @@ lrcc_status lrcc_hhl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, con
 lrcc_status lrcc_cholesky(lrcc_handle h, long n, const void* M, double tau, int max_vectors,
                           void* L, int* pivots, int* nvec);
 
+/* Hermitian eigen-decomposition A = V diag(w) V^H by two-sided Jacobi
+ * rotations (used for the natural spinors and the semicanonicalisation of
+ * Sec. 2.3; exposed on its own for testing and reuse).  A: device, n x n
+ * complex128, row-major, Hermitian (not checked), not modified.  w: device [n], the
+ * eigenvalues in ascending order.  V: device [n][n] complex128, column k the
+ * eigenvector of w[k] (phases arbitrary); may be NULL.  *sweeps (host, may
+ * be NULL): Jacobi sweeps used.  Synchronous.  Errors: LRCC_ERR_ARG for
+ * NULL/misaligned/overlapping buffers or n < 0; LRCC_ERR_SHAPE for n > 8192. */
+lrcc_status lrcc_heev(lrcc_handle h, int n, const void* A, double* w, void* V, int* sweeps);
+
+typedef struct {
+  int sweeps_density;  /* Jacobi sweeps of the density diagonalisation      */
+  int sweeps_fock;     /* Jacobi sweeps of the truncated Fock block          */
+} lrcc_fns_info;
+
+/* Perturbation-sensitive natural spinors (FNS++) of the virtual space,
+ * Sec. 2.4 with the steps of Sec. 2.3, for a canonical reference:
+ *   t_ij^ab = <ij||ab> / (e_i + e_j - e_a - e_b), <ij|ab> = sum_P L_ia L_jb,
+ *   Hb_ii = e_i + 1/2 sum t_in^ef conj<in||ef>,
+ *   Hb_aa = e_a - 1/2 sum t_mn^fa conj<mn||fa>,
+ *   per component x: Ab_ij^ac = P(a,c) sum_e t_ij^ec A_ae
+ *                               - P(i,j) sum_m t_mj^ac A_mi,
+ *   t_ij^ac(A) = Ab / (Hb_aa + Hb_cc - Hb_ii - Hb_jj + omega),
+ *   t_i^a(A) = A_ia / (Hb_aa - Hb_ii + omega),
+ *   G_ab = mean_x [1/2 sum_ijc t_ij^ac(A) conj t_ij^bc(A)
+ *                  + sum_i t_i^a(A) conj t_i^b(A)],
+ *   G V = V diag(n), |n| descending; keep the |n| > threshold columns Vt;
+ *   Ft = Vt^H diag(e_v) Vt = Z diag(eps_new) Z^H (ascending); B = Vt Z.
+ * Inputs (device): eps [o+v] float64 (occupied first), Lov [nchol][o][v]
+ * complex128 (Lov[P][i][a] = L^P_ia), A_ov [ncomp][o][v]
+ * (A_ov[x][i][a] = <a|A_x|i>), A_vv [ncomp][v][v] (<a|A_x|e> at [x][a][e]),
+ * A_oo [ncomp][o][o] (<m|A_x|i> at [x][m][i]); omega and threshold (>= 0)
+ * are host doubles.  Outputs (device unless noted): occ [v] the occupation
+ * numbers in the order above (nullable); B [v][keep] complex128, written
+ * compactly (row stride keep) into a buffer of v*v elements; eps_new [keep]
+ * in a buffer of v doubles; *keep (host); gamma [v][v] the averaged density
+ * (nullable); hbar [o+v] the dressed diagonals (nullable).  Workspace about
+ * 3.5 (o v)^2 complex numbers, kept in the handle.  Synchronous.  Errors:
+ * LRCC_ERR_ARG for NULL/misaligned/overlapping buffers, negative sizes, a
+ * threshold that is negative or not finite or an omega that is not finite;
+ * LRCC_ERR_SHAPE for o > 255, v > 8192 or o v^2 >= 2^31. */
+lrcc_status lrcc_fns_plus(lrcc_handle h, int o, int v, int nchol, const double* eps,
+                          const void* Lov, int ncomp, const void* A_ov, const void* A_vv,
+                          const void* A_oo, double omega, double threshold, double* occ,
+                          void* B, double* eps_new, int* keep, void* gamma, double* hbar,
+                          lrcc_fns_info* info);
+
 /* Options of the response solve.  Zero-initialised fields take defaults. */
 typedef struct {
   double tol;        /* relative residual |R|/|xi| (default 1e-8)            */

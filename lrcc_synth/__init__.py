@@ -45,6 +45,7 @@ __all__ = [
     "make_packed",
     "make_psd",
     "make_fns_instance",
+    "make_hermitian",
     "FnsInstance",
     "npair",
     "solve_gamma",
@@ -222,3 +223,22 @@ def make_fns_instance(o: int, v: int, nchol: int, ncomp: int = 3, seed: int = 0,
         A_vv[x] = a[o:, o:]
         A_ov[x] = a[o:, :o].T
     return FnsInstance(o, v, nchol, np.concatenate([e_occ, e_vir]), Lov, A_oo, A_vv, A_ov)
+
+
+def make_hermitian(rng: np.random.Generator, n: int, spectrum=None) -> np.ndarray:
+    """Hermitian ``[n, n]`` complex128 matrix: ``(G + G^H) / 2`` with
+    ``G ~ CN(0, 1)``; with ``spectrum`` (n real values) instead
+    ``U diag(spectrum) U^H`` for the unitary factor ``U`` of the QR
+    decomposition of a ``CN(0, 1)`` draw (repeated values give exactly
+    degenerate eigenvalues).  Made exactly Hermitian (upper triangle
+    mirrored, real diagonal)."""
+    g = cn(rng, (n, n))
+    if spectrum is None:
+        a = 0.5 * (g + np.conj(g.T))
+    else:
+        q, _ = np.linalg.qr(g)
+        a = (q * np.asarray(spectrum, dtype=np.float64)[None, :]) @ np.conj(q.T)
+    iu = np.triu_indices(n, 1)
+    a[(iu[1], iu[0])] = np.conj(a[iu])
+    a[np.diag_indices(n)] = np.real(np.diag(a))
+    return a

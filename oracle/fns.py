@@ -89,12 +89,14 @@ def fns_plus(eps, Lov, A_ov, A_vv, A_oo, omega, threshold):
     o = Lov.shape[1]
     t, W = mp2_amplitudes(eps, Lov)
     hi, ha = dressed_diagonals(eps, t, W)
-    ncomp = A_ov.shape[0]
-    G = 0
+    ncomp = A_vv.shape[0]
+    v = len(eps) - o
+    G = np.zeros((v, v), np.complex128)   # no component: a zero density
     for x in range(ncomp):
         t2A, t1A = perturbed_amplitudes(t, A_ov[x], A_vv[x], A_oo[x], hi, ha, omega)
         G = G + density(t2A, t1A)
-    G = G / ncomp
+    if ncomp:
+        G = G / ncomp
     n, V = np.linalg.eigh(G)
     order = np.argsort(-np.abs(n), kind="stable")
     n, V = n[order], V[:, order]
@@ -103,3 +105,9 @@ def fns_plus(eps, Lov, A_ov, A_vv, A_oo, omega, threshold):
     Ft = np.conj(Vt.T) @ np.diag(eps[o:]) @ Vt
     et, Z = np.linalg.eigh(Ft)
     return dict(n=n, keep=keep, eps_new=et, B=Vt @ Z, G=G, hi=hi, ha=ha)
+
+
+def hermitian_eigh(A):
+    """Eigenvalues (ascending) and eigenvectors of a Hermitian matrix: the
+    library routine (LAPACK zheevd through numpy) as the definition."""
+    return np.linalg.eigh(A)

@@ -58,6 +58,10 @@ class SolveInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class FnsInfo(ctypes.Structure):
+    _fields_ = [("sweeps_density", ctypes.c_int), ("sweeps_fock", ctypes.c_int)]
+
+
 class TuneResult(ctypes.Structure):
     _fields_ = [("supertile", ctypes.c_int), ("occupancy", ctypes.c_int),
                 ("ms", ctypes.c_double), ("candidates", ctypes.c_int)]
@@ -102,6 +106,9 @@ def lib() -> ctypes.CDLL:
             "lrcc_ppl_sigma_adjoint": [vp, i, i, i, i, vp, vp, vp, vp, vp, i, i, i],
             "lrcc_hhl_sigma": [vp, i, i, i, i, vp, vp, vp, i],
             "lrcc_cholesky": [vp, ctypes.c_long, vp, d, i, vp, vp, ctypes.POINTER(i)],
+            "lrcc_heev": [vp, i, vp, vp, vp, ctypes.POINTER(i)],
+            "lrcc_fns_plus": [vp, i, i, i, vp, vp, i, vp, vp, vp, d, d, vp, vp, vp,
+                              ctypes.POINTER(i), vp, vp, ctypes.POINTER(FnsInfo)],
             "lrcc_solve": [vp, i, i, i, vp, vp, i, vp, i, vp,
                            ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)],
             "lrcc_solve_batched": [vp, i, ctypes.POINTER(Instance),
@@ -241,6 +248,59 @@ def cholesky(M, tau=1e-5, max_vectors=None):
                                piv.data_ptr() if kmax else None, ctypes.byref(cnt)), h)
     k = cnt.value
     return L[:k], piv[:k].cpu().numpy().astype(np.int64)
+
+
+def heev(A, vectors=True):
+    """Eigen-decomposition of a Hermitian complex128 matrix on the GPU by
+    Jacobi rotations: returns (w ascending, V with eigenvectors as columns or
+    None, sweeps)."""
+    import torch
+    A = A.contiguous()
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.dtype != torch.complex128:
+        raise ValueError("A must be a square complex128 matrix")
+    n = A.shape[0]
+    w = torch.empty((n,), dtype=torch.float64, device=A.device)
+    V = torch.empty((n, n), dtype=torch.complex128, device=A.device) if vectors else None
+    sw = ctypes.c_int(0)
+    h = handle(A.device.index)
+    _check(lib().lrcc_heev(h, n, _ptr(A), _ptr(w), _ptr(V), ctypes.byref(sw)), h)
+    return w, V, sw.value
+
+
+def fns_plus(eps, Lov, A_ov, A_vv, A_oo, omega=0.0, threshold=1e-5):
+    """FNS++ virtual basis on the GPU (all inputs complex128/float64 device
+    tensors; eps [o+v], Lov [nchol, o, v], A_ov [ncomp, o, v],
+    A_vv [ncomp, v, v], A_oo [ncomp, o, o]).  Returns a dict with occ [v]
+    (|n| descending), keep, B [v, keep], eps_new [keep], gamma [v, v],
+    hbar [o+v] and the Jacobi sweep counts."""
+    import torch
+    eps, Lov = eps.contiguous(), Lov.contiguous()
+    A_ov, A_vv, A_oo = A_ov.contiguous(), A_vv.contiguous(), A_oo.contiguous()
+    nchol, o, v = Lov.shape
+    ncomp = A_vv.shape[0]
+    if eps.shape != (o + v,) or eps.dtype != torch.float64:
+        raise ValueError("eps must be float64 [o+v]")
+    for t, shp in ((Lov, (nchol, o, v)), (A_ov, (ncomp, o, v)), (A_vv, (ncomp, v, v)),
+                   (A_oo, (ncomp, o, o))):
+        if tuple(t.shape) != shp or t.dtype != torch.complex128:
+            raise ValueError(f"expected complex128 {shp}, got {t.dtype} {tuple(t.shape)}")
+    dev = Lov.device
+    occ = torch.empty((v,), dtype=torch.float64, device=dev)
+    B = torch.empty((v * v,), dtype=torch.complex128, device=dev)
+    en = torch.empty((v,), dtype=torch.float64, device=dev)
+    gamma = torch.empty((v, v), dtype=torch.complex128, device=dev)
+    hbar = torch.empty((o + v,), dtype=torch.float64, device=dev)
+    keep = ctypes.c_int(0)
+    info = FnsInfo()
+    h = handle(dev.index)
+    _check(lib().lrcc_fns_plus(h, o, v, nchol, _ptr(eps), _ptr(Lov), ncomp, _ptr(A_ov),
+                               _ptr(A_vv), _ptr(A_oo), float(omega), float(threshold),
+                               _ptr(occ), _ptr(B), _ptr(en), ctypes.byref(keep), _ptr(gamma),
+                               _ptr(hbar), ctypes.byref(info)), h)
+    k = keep.value
+    return {"occ": occ, "keep": k, "B": B[:v * k].view(v, k), "eps_new": en[:k],
+            "gamma": gamma, "hbar": hbar, "sweeps_density": info.sweeps_density,
+            "sweeps_fock": info.sweeps_fock}
 
 
 def ppl_sigma_adjoint(L, X, G, o=None, want_dX=True, want_dL=True, prec="fp64", cmul="4m"):

@@ -368,6 +368,7 @@ lrcc_status lrcc_destroy(lrcc_handle h) {
     h->vws.release();
     h->hw.release();
     h->cw.release();
+    h->fw.release();
     for (auto& b : h->sv) b.release();
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
     if (h->rb) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(h->rb));
@@ -511,6 +512,78 @@ lrcc_status lrcc_cholesky(lrcc_handle h, long n, const void* M, double tau, int 
   LRCC_HIP(h, h->cw.ensure(chol_state_bytes(n)));
   LRCC_HIP(h, chol_run(n, M, tau, max_vectors, L, pivots, h->cw.p, nvec, h->stream));
   return LRCC_OK;
+}
+
+lrcc_status lrcc_heev(lrcc_handle h, int n, const void* A, double* w, void* V, int* sweeps) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  if (sweeps) *sweeps = 0;
+  if (n < 0) return fail(h, LRCC_ERR_ARG, "n must be >= 0");
+  if (n > 8192) return fail(h, LRCC_ERR_SHAPE, "n exceeds 8192");
+  if (n == 0) return LRCC_OK;
+  if (!A || !w) return fail(h, LRCC_ERR_ARG, "A or w is NULL");
+  if ((uintptr_t)A % 16 || (uintptr_t)w % 8 || (V && (uintptr_t)V % 16))
+    return fail(h, LRCC_ERR_ARG, "A/V not aligned to 16 bytes or w to 8");
+  const size_t na = (size_t)n * n * 16;
+  if (overlaps(w, (size_t)n * 8, A, na) || (V && (overlaps(V, na, A, na) ||
+                                                  overlaps(V, na, w, (size_t)n * 8))))
+    return fail(h, LRCC_ERR_ARG, "outputs overlap A or each other");
+  DeviceGuard dg(h->device);
+  h->err.clear();
+  LRCC_HIP(h, h->fw.ensure(heev_ws_bytes(n)));
+  LRCC_HIP(h, heev_run(n, A, 0, w, V, V ? n : 0, h->fw.p, nullptr, sweeps, h->stream));
+  LRCC_HIP(h, hipStreamSynchronize(h->stream));
+  return LRCC_OK;
+}
+
+lrcc_status lrcc_fns_plus(lrcc_handle h, int o, int v, int nchol, const double* eps,
+                          const void* Lov, int ncomp, const void* A_ov, const void* A_vv,
+                          const void* A_oo, double omega, double threshold, double* occ,
+                          void* B, double* eps_new, int* keep, void* gamma, double* hbar,
+                          lrcc_fns_info* info) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  if (!keep) return fail(h, LRCC_ERR_ARG, "keep is NULL");
+  *keep = 0;
+  if (info) *info = lrcc_fns_info{};
+  if (o < 0 || v < 0 || nchol < 0 || ncomp < 0)
+    return fail(h, LRCC_ERR_ARG, "sizes must be non-negative");
+  if (!(threshold >= 0) || threshold > 1e300)
+    return fail(h, LRCC_ERR_ARG, "threshold must be finite and >= 0");
+  if (!(std::fabs(omega) <= 1e300)) return fail(h, LRCC_ERR_ARG, "omega must be finite");
+  if (o > 255) return fail(h, LRCC_ERR_SHAPE, "o exceeds 255");
+  if (v > 8192) return fail(h, LRCC_ERR_SHAPE, "v exceeds 8192");
+  if ((long)o * v * v >= (1L << 31)) return fail(h, LRCC_ERR_SHAPE, "o v^2 reaches 2^31");
+  if (v == 0) return LRCC_OK;
+  const size_t ne = (size_t)o + v, nl = (size_t)nchol * o * v * 16;
+  const size_t nov = (size_t)ncomp * o * v * 16, nvv = (size_t)ncomp * v * v * 16,
+               noo = (size_t)ncomp * o * o * 16;
+  if (!eps || !B || !eps_new) return fail(h, LRCC_ERR_ARG, "eps, B or eps_new is NULL");
+  if (nl && o && !Lov) return fail(h, LRCC_ERR_ARG, "Lov is NULL");
+  if (ncomp && (!A_vv || (o && (!A_ov || !A_oo))))
+    return fail(h, LRCC_ERR_ARG, "a perturbation block is NULL");
+  auto mis = [](const void* p, size_t a) { return p && (uintptr_t)p % a != 0; };
+  if (mis(eps, 8) || mis(Lov, 16) || mis(A_ov, 16) || mis(A_vv, 16) || mis(A_oo, 16) ||
+      mis(occ, 8) || mis(B, 16) || mis(eps_new, 8) || mis(gamma, 16) || mis(hbar, 8))
+    return fail(h, LRCC_ERR_ARG, "a buffer is misaligned (complex: 16 bytes, real: 8)");
+  const size_t nvv1 = (size_t)v * v * 16;
+  struct Rg { const void* p; size_t n; };
+  const Rg in[] = {{eps, ne * 8}, {Lov, o ? nl : 0}, {A_ov, o ? nov : 0}, {A_vv, nvv},
+                   {A_oo, o ? noo : 0}};
+  const Rg out[] = {{occ, (size_t)v * 8}, {B, nvv1}, {eps_new, (size_t)v * 8},
+                    {gamma, nvv1}, {hbar, ne * 8}};
+  for (const Rg& a : out) {
+    if (!a.p) continue;
+    for (const Rg& b : in)
+      if (b.p && b.n && overlaps(a.p, a.n, b.p, b.n))
+        return fail(h, LRCC_ERR_ARG, "an output overlaps an input");
+    for (const Rg& b : out)
+      if (&b != &a && b.p && overlaps(a.p, a.n, b.p, b.n))
+        return fail(h, LRCC_ERR_ARG, "outputs overlap each other");
+  }
+  DeviceGuard dg(h->device);
+  h->err.clear();
+  LRCC_HIP(h, h->fw.ensure(fns_ws_bytes(o, v, ncomp)));
+  return fns_run(h, o, v, nchol, eps, Lov, ncomp, A_ov, A_vv, A_oo, omega, threshold, occ, B,
+                 eps_new, keep, gamma, hbar, h->fw.p, info);
 }
 
 lrcc_status lrcc_ppl_sigma_adjoint(lrcc_handle h, int o, int v, int nchol, int nrhs,

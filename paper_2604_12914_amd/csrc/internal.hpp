@@ -79,6 +79,7 @@ struct lrcc_handle_s {
   lrcc::Buf sv[12];
   lrcc::Buf hw;           // hole-hole ladder: W matrix and occupied pair table
   lrcc::Buf cw;           // pivoted Cholesky: remaining diagonal and state
+  lrcc::Buf fw;           // FNS++ and eigensolver workspace
   void* rb = nullptr;     // rocBLAS handle (gradient GEMMs), created on first use
   // ladder-kernel timing (lrcc_set_timing)
   bool timing = false;
@@ -174,6 +175,30 @@ lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, c
 size_t chol_state_bytes(long n);
 hipError_t chol_run(long n, const void* M, double tau, int maxv, void* L, int* pivots, void* ws,
                     int* nvec, hipStream_t st);
+
+// Hermitian eigensolver (heev.hip) -------------------------------------------
+// Workspace bytes for an n x n problem; eigenpairs of A (n x n complex128,
+// row-major, device, not modified): w[n] (device) ordered ascending (mode 0)
+// or by descending magnitude (mode 1), the first ncol_out eigenvectors as
+// columns of Vout [n][ncol_out] (device; may be NULL), the ordering
+// permutation in perm_out (device; may be NULL).  The unordered eigenvectors
+// stay in the workspace (heev_vectors) until its next use.  Synchronises st
+// once per sweep; *sweeps (host, may be NULL) gets the sweep count.
+size_t heev_ws_bytes(int n);
+hipError_t heev_run(int n, const void* A, int mode, double* w, void* Vout, int ncol_out,
+                    void* ws, int* perm_out, int* sweeps, hipStream_t st);
+const void* heev_vectors(const void* ws, int n);
+// Out[r][k] = V[r][perm[k]], k < ncol (row stride ncol); Sout (if not NULL)
+// = diag(scale) Out.
+hipError_t gather_cols(int n, int ncol, const void* V, const int* perm, void* Out,
+                       const double* scale, void* Sout, hipStream_t st);
+
+// FNS++ natural spinors (fns.hip) ---------------------------------------------
+size_t fns_ws_bytes(int o, int v, int ncomp);
+lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, const void* Lov,
+                    int ncomp, const void* Aov, const void* Avv, const void* Aoo, double omega,
+                    double threshold, double* occ, void* B, double* eps_new, int* keep,
+                    void* gamma, double* hbar_out, void* ws, lrcc_fns_info* info);
 
 // Hole-hole ladder (hhl.hip) ------------------------------------------------
 // W[(ij),(kl)] = 2 <kl||ij> from occupied-occupied vectors Loo [nchol][o][o]
