@@ -6,15 +6,17 @@
 // Pipeline on the handle's stream (o occupied, v virtual spinors, npo =
 // o(o-1)/2 occupied pairs; all complex128, row-major):
 //   1. G = L^T L over the occupied-virtual Cholesky vectors, G[(ia)][(jb)] =
-//      <ij|ab> (rocBLAS zgemm, (ov)^2 x nchol)
-//   2. k_fns_t: t_ij^ab = (G[ia][jb] - G[ib][ja]) / (e_i + e_j - e_a - e_b),
-//      zero for i = j or a = b; the transposed read goes through LDS tiles
+//      <ij|ab>, for the blocks i < j only (one zgemm per i, (o-1-i) v x v x
+//      nchol: half of the full product)
+//   2. k_fns_t: t_ij^ab = (G[ia][jb] - G[ib][ja]) / (e_i + e_j - e_a - e_b)
+//      for i < j, t_ji = -t_ij, zero for i = j or a = b; the transposed read
+//      goes through LDS tiles
 //   3. k_fns_hbar: Hb_ii = e_i + 1/2 sum_{jab} |t_ij^ab|^2 D_ij^ab and
 //      Hb_aa = e_a - 1/2 sum_{mnf} |t_mn^af|^2 D_mn^af (t conj<||> = |t|^2 D,
-//      the second sum taken over the antisymmetric partner t_mn^af), one
-//      block per index, fixed summation order
+//      the second sum taken over the antisymmetric partner t_mn^af), each
+//      index's range cut into fixed segments, summed in a fixed order
 //   per perturbation component x:
-//   4. X'[(ijc)][a] = sum_e t_ij^ce A_ae (one zgemm, o^2 v x v x v); by the
+//   4. X'[(ijc)][a] = sum_e t_ij^ce A_ae for i < j (one zgemm per i); by the
 //      antisymmetry of t the vv term of the perturbed doubles,
 //      P(a,c) sum_e t_ij^ec A_ae, is X'[(ija)][c] - X'[(ijc)][a]
 //   5. Y[i][(jac)] = sum_m A_mi t_mj^ac (one zgemm, o v^2 x o x o)
@@ -23,7 +25,8 @@
 //      i < j only, laid out so that the density is one product;
 //      k_fns_t1: T1[a][i] = A_ia / (Hb_aa - Hb_ii + w)
 //   7. G_ab += (1/ncomp) (sum_{i<j,c} Q[a]..Q[b]^* + sum_i T1[a][i] T1[b][i]^*)
-//      (two zgemm calls; the restriction to i < j absorbs the factor 1/2)
+//      (the restriction to i < j absorbs the factor 1/2; the long pair sum
+//      is split into chunks whose partial products are added in order)
 //   then:
 //   8. Jacobi eigensolver on G, occupations ordered by descending magnitude;
 //      keep = number with |n| > threshold (read back to the host)
@@ -34,6 +37,7 @@
 // reductions and the eigensolver are the kernels below and in heev.hip.
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -46,7 +50,9 @@ namespace {
 constexpr int TT = 32;  // transpose tile edge
 constexpr int TR = 8;   // rows per thread pass (block = TT x TR threads)
 
-// Step 2.  Grid: x = tile (a-tile, b-tile), y = i * o + j.
+// Step 2.  Grid: x = tile (a-tile, b-tile), y = i * o + j.  Only the blocks
+// i < j of G are formed; t_ij = -t_ji gives the rest (i > j reads block
+// (j, i)), and t_ii = 0.
 __global__ __launch_bounds__(TT * TR) void k_fns_t(int o, int v, const double2* __restrict__ G,
                                                   const double* __restrict__ eps,
                                                   double2* __restrict__ t) {
@@ -54,13 +60,17 @@ __global__ __launch_bounds__(TT * TR) void k_fns_t(int o, int v, const double2* 
   const int ntb = (v + TT - 1) / TT;
   const int a0 = (blockIdx.x / ntb) * TT, b0 = (blockIdx.x % ntb) * TT;
   const int i = blockIdx.y / o, j = blockIdx.y % o;
+  const int lo = min(i, j), hi = max(i, j);
+  const double sg = i < j ? 1.0 : -1.0;
   const long ov = (long)o * v;
   const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
-  // tr[bl][al] = G[(i, b0+bl)][(j, a0+al)]
-  for (int r = ty; r < TT; r += TR) {
-    const int b = b0 + r, a = a0 + tx;
-    tr[r][tx] = (b < v && a < v) ? G[((long)i * v + b) * ov + (long)j * v + a]
-                                 : make_double2(0.0, 0.0);
+  // tr[bl][al] = G[(lo, b0+bl)][(hi, a0+al)]
+  if (i != j) {
+    for (int r = ty; r < TT; r += TR) {
+      const int b = b0 + r, a = a0 + tx;
+      tr[r][tx] = (b < v && a < v) ? G[((long)lo * v + b) * ov + (long)hi * v + a]
+                                   : make_double2(0.0, 0.0);
+    }
   }
   __syncthreads();
   const double eij = eps[i] + eps[j];
@@ -69,9 +79,9 @@ __global__ __launch_bounds__(TT * TR) void k_fns_t(int o, int v, const double2* 
     if (a >= v || b >= v) continue;
     double2 y = make_double2(0.0, 0.0);
     if (i != j && a != b) {
-      const double2 g1 = G[((long)i * v + a) * ov + (long)j * v + b];
+      const double2 g1 = G[((long)lo * v + a) * ov + (long)hi * v + b];
       const double2 g2 = tr[tx][r];
-      const double inv = 1.0 / (eij - eps[o + a] - eps[o + b]);
+      const double inv = sg / (eij - eps[o + a] - eps[o + b]);
       y = make_double2((g1.x - g2.x) * inv, (g1.y - g2.y) * inv);
     }
     t[(((long)i * o + j) * v + a) * v + b] = y;
@@ -89,35 +99,63 @@ __device__ inline double block_sum(double x, double* sh) {
   return sh[0];
 }
 
-// Step 3.  Blocks 0..o-1: occupied; o..o+v-1: virtual.
+// Step 3.  Grid (o + v, NSEG): blockIdx.x < o sums segment blockIdx.y of the
+// (j, a, b) range of occupied i; otherwise segment blockIdx.y of the
+// (m, n, f) range of virtual a.  part[idx][seg] holds the segment sums,
+// k_fns_hbar_fin adds them in segment order (deterministic).
+constexpr int NSEG = 32;
 __global__ __launch_bounds__(HB) void k_fns_hbar(int o, int v, const double2* __restrict__ t,
                                                  const double* __restrict__ eps,
-                                                 double* __restrict__ hbar) {
+                                                 double* __restrict__ part) {
   __shared__ double sh[HB];
   const long v2 = (long)v * v;
+  const int seg = blockIdx.y;
   double acc = 0.0;
   if ((int)blockIdx.x < o) {
     const int i = blockIdx.x;
-    const double2* ti = t + (long)i * o * v2;
-    for (long e = threadIdx.x; e < (long)o * v2; e += HB) {
+    const long n = (long)o * v2, e0 = n * seg / NSEG, e1 = n * (seg + 1) / NSEG;
+    const double2* ti = t + (long)i * n;
+    for (long e = e0 + threadIdx.x; e < e1; e += HB) {
       const int j = (int)(e / v2), a = (int)(e / v % v), b = (int)(e % v);
       const double2 x = ti[e];
       acc += (x.x * x.x + x.y * x.y) * (eps[i] + eps[j] - eps[o + a] - eps[o + b]);
     }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) hbar[i] = eps[i] + 0.5 * s;
   } else {
     const int a = blockIdx.x - o;
-    const long nf = (long)o * o * v;
-    for (long e = threadIdx.x; e < nf; e += HB) {
+    const long n = (long)o * o * v, e0 = n * seg / NSEG, e1 = n * (seg + 1) / NSEG;
+    for (long e = e0 + threadIdx.x; e < e1; e += HB) {
       const long mn = e / v;
-      const int f = (int)(e % v), m = (int)(mn / o), n = (int)(mn % o);
+      const int f = (int)(e % v), m = (int)(mn / o), nn = (int)(mn % o);
       const double2 x = t[(mn * v + a) * v + f];
-      acc += (x.x * x.x + x.y * x.y) * (eps[m] + eps[n] - eps[o + a] - eps[o + f]);
+      acc += (x.x * x.x + x.y * x.y) * (eps[m] + eps[nn] - eps[o + a] - eps[o + f]);
     }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) hbar[o + a] = eps[o + a] - 0.5 * s;
   }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[(long)blockIdx.x * NSEG + seg] = s;
+}
+
+__global__ void k_fns_hbar_fin(int o, int v, const double* __restrict__ part,
+                               const double* __restrict__ eps, double* __restrict__ hbar) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= o + v) return;
+  double s = 0.0;
+  for (int k = 0; k < NSEG; ++k) s += part[(long)idx * NSEG + k];
+  hbar[idx] = eps[idx] + (idx < o ? 0.5 : -0.5) * s;
+}
+
+// Gm += w * sum_s P[s] (fixed order).
+__global__ void k_sum_parts(long n, int ns, const double2* __restrict__ P, double wgt,
+                            double2* __restrict__ Gm) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int k = 0; k < ns; ++k) {
+    const double2 x = P[(long)k * n + e];
+    acc.x += x.x;
+    acc.y += x.y;
+  }
+  Gm[e].x += wgt * acc.x;
+  Gm[e].y += wgt * acc.y;
 }
 
 // Step 6.  Grid: x = tile (a-tile, c-tile), y = occupied pair p (i < j).
@@ -188,6 +226,27 @@ rocblas_status zgemm(rocblas_handle rb, rocblas_operation ta, rocblas_operation 
                        reinterpret_cast<rocblas_double_complex*>(C), (rocblas_int)ldc);
 }
 
+rocblas_status zgemm_sb(rocblas_handle rb, rocblas_operation ta, rocblas_operation tb, long m,
+                        long n, long k, double2 alpha, const double2* A, long lda, long sa,
+                        const double2* B, long ldb, long sb, double2 beta, double2* C, long ldc,
+                        long sc, long batch) {
+  const rocblas_double_complex al{alpha.x, alpha.y}, be{beta.x, beta.y};
+  return rocblas_zgemm_strided_batched(
+      rb, ta, tb, (rocblas_int)m, (rocblas_int)n, (rocblas_int)k, &al,
+      reinterpret_cast<const rocblas_double_complex*>(A), (rocblas_int)lda, sa,
+      reinterpret_cast<const rocblas_double_complex*>(B), (rocblas_int)ldb, sb, &be,
+      reinterpret_cast<rocblas_double_complex*>(C), (rocblas_int)ldc, sc, (rocblas_int)batch);
+}
+
+// Split of the density product's K = npo v range: enough chunks to fill
+// the chip with 64 x 64 output tiles, each chunk at least 1024 long.
+int density_splits(int v, long K) {
+  const long tiles = ((v + 63) / 64) * (long)((v + 63) / 64);
+  long ns = (1024 + tiles - 1) / tiles;
+  ns = std::min(ns, std::max(1L, K / 1024));
+  return (int)std::min(ns, 64L);
+}
+
 }  // namespace
 
 size_t fns_ws_bytes(int o, int v, int ncomp) {
@@ -204,6 +263,8 @@ size_t fns_ws_bytes(int o, int v, int ncomp) {
   b += al256(npo * 4 + 4);                // pair table
   b += al256((size_t)v * 4);              // eigen permutation
   b += al256((size_t)v * v * 16) * 4;     // Vt, S, Ft, Z
+  b += al256((size_t)(o + v) * NSEG * 8);  // hbar segment sums
+  b += al256((size_t)density_splits(v, (long)npo * v) * v * v * 16);  // density partials
   b += heev_ws_bytes(v);
   return b;
 }
@@ -236,6 +297,10 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
   double2* Ft = reinterpret_cast<double2*>(take((size_t)v2 * 16));
   double2* Z = reinterpret_cast<double2*>(take((size_t)v2 * 16));
   void* hws = take(heev_ws_bytes(v));
+  double* hpart = reinterpret_cast<double*>(take((size_t)(o + v) * NSEG * 8));
+  const long Kd = (long)npo * v;
+  const int nsplit = density_splits(v, Kd);
+  double2* Pd = reinterpret_cast<double2*>(take((size_t)nsplit * v2 * 16));
 
   if (!h->rb) {
     if (rocblas_create_handle(reinterpret_cast<rocblas_handle*>(&h->rb)) !=
@@ -260,10 +325,14 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
   if (o == 0) {
     // no occupied spinors: no amplitudes, hbar = eps, a zero density
   } else if (nchol > 0) {
-    // column-major: G^c = L^c L^c^T with L^c (ov x nchol, ld ov)
-    s = blas(zgemm(rb, N, T, ov, ov, nchol, one, static_cast<const double2*>(Lov), ov,
-                   static_cast<const double2*>(Lov), ov, zero, G, ov));
-    if (s != LRCC_OK) return s;
+    // blocks i < j only: row block i against column blocks j > i, column-major
+    // C^c((jb), a) = sum_P L^c((jb), P) L^c((ia), P) with L^c (ov x nchol, ld ov)
+    const double2* L = static_cast<const double2*>(Lov);
+    for (int i = 0; i + 1 < o; ++i) {
+      s = blas(zgemm(rb, N, T, (long)(o - 1 - i) * v, v, nchol, one, L + (long)(i + 1) * v, ov,
+                     L + (long)i * v, ov, zero, G + (long)i * v * ov + (long)(i + 1) * v, ov));
+      if (s != LRCC_OK) return s;
+    }
   } else {
     LRCC_HIP(h, hipMemsetAsync(G, 0, o2v2 * 16, st));
   }
@@ -271,7 +340,10 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
     hipLaunchKernelGGL(k_fns_t, dim3(ntile * ntile, o * o), tb, 0, st, o, v, G, eps, t);
     LRCC_HIP(h, hipGetLastError());
   }
-  hipLaunchKernelGGL(k_fns_hbar, dim3(o + v), dim3(HB), 0, st, o, v, t, eps, hb);
+  hipLaunchKernelGGL(k_fns_hbar, dim3(o + v, NSEG), dim3(HB), 0, st, o, v, t, eps, hpart);
+  LRCC_HIP(h, hipGetLastError());
+  hipLaunchKernelGGL(k_fns_hbar_fin, dim3((o + v + 255) / 256), dim3(256), 0, st, o, v, hpart,
+                     eps, hb);
   LRCC_HIP(h, hipGetLastError());
   if (npo > 0) {
     hipLaunchKernelGGL(k_fns_pairs, dim3(o), dim3(64), 0, st, o, otab);
@@ -286,9 +358,14 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
     const double2* avv = static_cast<const double2*>(Avv) + (size_t)x * v2;
     const double2* aoo = static_cast<const double2*>(Aoo) + (size_t)x * o * o;
     const double2* aov = static_cast<const double2*>(Aov) + (size_t)x * ov;
-    // column-major X'^c (v x o^2 v): X'^c(a, (ijc)) = sum_e A^c(e, a) t^c(e, (ijc))
-    s = blas(zgemm(rb, T, N, v, (long)o * o * v, v, one, avv, v, t, v, zero, Xp, v));
-    if (s != LRCC_OK) return s;
+    // column-major X'^c (v x o^2 v): X'^c(a, (ijc)) = sum_e A^c(e, a) t^c(e, (ijc)),
+    // for the rows i < j only (per i, the rows (i, j > i, c) are contiguous)
+    for (int i = 0; i + 1 < o; ++i) {
+      const long r0 = ((long)i * o + i + 1) * v;
+      s = blas(zgemm(rb, T, N, v, (long)(o - 1 - i) * v, v, one, avv, v, t + r0 * v, v, zero,
+                     Xp + r0 * v, v));
+      if (s != LRCC_OK) return s;
+    }
     // Y^c (o v^2 x o) = t^c (o v^2 x o) * A_oo (o x o) as (A^c)^T
     s = blas(zgemm(rb, N, T, (long)o * v2, o, o, one, t, (long)o * v2, aoo, o, zero, Y,
                    (long)o * v2));
@@ -297,10 +374,20 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
       hipLaunchKernelGGL(k_fns_pert, dim3(ntile * ntile, (int)npo), tb, 0, st, o, v, otab, Xp, Y,
                          hb, omega, Q);
       LRCC_HIP(h, hipGetLastError());
-      // Gm^c = Q^c^H Q^c with Q^c (npo v x v, ld npo v)
-      const long K = (long)npo * v;
-      s = blas(zgemm(rb, C, N, v, v, K, wgt, Q, K, Q, K, one, Gm, v));
+      // Gm^c += Q^c^H Q^c with Q^c (npo v x v, ld npo v), K split into
+      // nsplit chunks (partials Pd, summed in order)
+      const long Kc = (Kd + nsplit - 1) / nsplit, Kl = Kd - (nsplit - 1) * Kc;
+      if (nsplit > 1) {
+        s = blas(zgemm_sb(rb, C, N, v, v, Kc, one, Q, Kd, Kc, Q, Kd, Kc, zero, Pd, v, v2,
+                          nsplit - 1));
+        if (s != LRCC_OK) return s;
+      }
+      s = blas(zgemm(rb, C, N, v, v, Kl, one, Q + (nsplit - 1) * Kc, Kd, Q + (nsplit - 1) * Kc,
+                     Kd, zero, Pd + (long)(nsplit - 1) * v2, v));
       if (s != LRCC_OK) return s;
+      hipLaunchKernelGGL(k_sum_parts, dim3((int)((v2 + 255) / 256)), dim3(256), 0, st, v2,
+                         nsplit, Pd, wgt.x, Gm);
+      LRCC_HIP(h, hipGetLastError());
     }
     hipLaunchKernelGGL(k_fns_t1, dim3((int)((ov + 255) / 256)), dim3(256), 0, st, o, v, aov, hb,
                        omega, T1);
