@@ -95,8 +95,10 @@ def main():
     ap.add_argument("--profile-sigma", choices=("fp64", "fp32", "bf16x3"), default=None,
                     help="only run --warmup + --steps ladder applications of this precision "
                          "(for profilers) and print their kernel time")
-    ap.add_argument("--workload", choices=("baseline", "precision"), default="baseline",
-                    help="shape for --profile-sigma")
+    ap.add_argument("--profile-fns", action="store_true",
+                    help="only run --warmup + --steps FNS++ basis constructions (for profilers)")
+    ap.add_argument("--workload", choices=("baseline", "precision", "scale"), default="baseline",
+                    help="shape for --profile-sigma / --profile-fns")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (a plain copy kernel of known "
                          "size, to scale HBM byte counters)")
@@ -120,6 +122,11 @@ def main():
 
     if args.profile_sigma:
         profile_sigma(lrcc, torch, np, S, args)
+        return
+    if args.profile_fns:
+        c = S.CONFIGS[args.workload]
+        print(json.dumps(fns_bench(lrcc, torch, np, S, c.o, c.v, c.nchol, args.warmup,
+                                   args.steps)), flush=True)
         return
 
     cfg = S.CONFIGS["baseline"]
@@ -277,6 +284,11 @@ def main():
                                             for w in range(len(omegas))]}
         if exact is not None:
             extra["solve_fp64"]["max_abs_dalpha_vs_exact"] = float(np.abs(alpha64 - exact).max())
+        # FNS++ virtual basis at the workload's shapes (Sec. 2.4)
+        try:
+            extra["fns_plus"] = fns_bench(lrcc, torch, np, S, o, v, nchol, 1, 3)
+        except lrcc.LrccError as err:
+            extra["fns_plus"] = {"error": str(err)}
         out["extra"] = extra
 
     # ---- CPU oracle on a bounded share of one ladder application ----------
@@ -284,6 +296,33 @@ def main():
         out["cpu_baseline"] = cpu_baseline(inst.L, o, v, nchol, nrhs, F)
 
     print(json.dumps(out), flush=True)
+
+
+def fns_bench(lrcc, torch, np, S, o, v, nchol, warmup, reps, thr=1e-5, omega=0.0656):
+    """FNS++ basis construction (lrcc_fns_plus) on the synthetic FNS++ inputs
+    of this shape (three dipole-like components): wall time per call (the
+    call is synchronous), the kept count and the Jacobi sweeps; also the
+    eigensolver alone on the resulting v x v density."""
+    inst = S.make_fns_instance(o, v, nchol, 3, seed=0)
+    a = [torch.from_numpy(x).cuda() for x in (inst.eps, inst.Lov, inst.A_ov, inst.A_vv,
+                                                inst.A_oo)]
+    for _ in range(warmup):
+        r = lrcc.fns_plus(*a, omega, thr)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r = lrcc.fns_plus(*a, omega, thr)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    _, _, sw = lrcc.heev(r["gamma"])
+    torch.cuda.synchronize()
+    th = time.perf_counter() - t0
+    return {"workload": f"o={o} v={v} nchol={nchol} ncomp=3 omega={omega} threshold={thr}",
+            "ms": round(min(ts) * 1e3, 3), "ms_median": round(sorted(ts)[len(ts) // 2] * 1e3, 3),
+            "keep": r["keep"], "of": v, "sweeps": [r["sweeps_density"], r["sweeps_fock"]],
+            "heev_density_ms": round(th * 1e3, 3), "heev_density_sweeps": sw}
 
 
 def profile_sigma(lrcc, torch, np, S, args):

@@ -6,9 +6,10 @@
 // even; the circle method: in round k index m-1 pairs with k and every other
 // r pairs with (2k - r) mod (m-1)).  The pairs of one round are disjoint, so
 // their 2x2 rotations combine into one unitary J and a round is one launch,
-// A <- J^H A J and V <- V J, out of place.  Each thread recomputes the
-// rotations of its own row and column pair from the old A (a handful of
-// flops), so no separate parameter pass is needed.
+// A <- J^H A J and V <- V J, out of place: a thread updates one 2x2 block
+// of A (its row pair by its column pair, every element read once) or one
+// row of V on a column pair, recomputing the two rotations it needs from
+// the old A (a handful of flops), so no separate parameter pass is needed.
 //
 // For the pair p < q with a = A_pp, d = A_qq, b = A_pq = |b| e^{i phi}:
 //   tau = (d - a) / (2|b|),  t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
@@ -32,36 +33,49 @@ namespace lrcc {
 
 namespace {
 
-__device__ inline int rr_partner(int r, int k, int m) {
+// Pair s of round k (0 <= s < m/2), returned ordered lo < hi.
+__device__ inline void rr_pair(int s, int k, int m, int& lo, int& hi) {
   const int mm = m - 1;
-  if (r == mm) return k;
-  if (r == k) return mm;
-  int t = (2 * k - r) % mm;
-  return t < 0 ? t + mm : t;
+  int p, q;
+  if (s == 0) {
+    p = k;
+    q = mm;
+  } else {
+    p = (k + s) % mm;
+    q = (k - s + mm) % mm;
+  }
+  lo = min(p, q);
+  hi = max(p, q);
 }
 
-// Column x of the round's rotation: J_xx = d, J_{px,x} = o.
-__device__ inline void rot_col(const double2* __restrict__ A, int n, int x, int px, double& d,
-                               double2& o) {
-  d = 1.0;
-  o = make_double2(0.0, 0.0);
-  if (px >= n) return;  // paired with the padding index
-  const int p = min(x, px), q = max(x, px);
-  const double a = A[(long)p * n + p].x, dd = A[(long)q * n + q].x;
-  const double2 b = A[(long)p * n + q];
+// The rotation of pair (lo, hi) as a 2x2 block in (lo, hi) coordinates:
+// J = [[c, s e^{i phi}], [-s e^{-i phi}, c]]; the identity when hi is the
+// padding index or the coupling vanishes.
+struct Rot2 {
+  double c;
+  double2 up;  // J_lo,hi
+  double2 dn;  // J_hi,lo
+};
+
+__device__ inline Rot2 rotation(const double2* __restrict__ A, int n, int lo, int hi) {
+  Rot2 r{1.0, make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+  if (hi >= n) return r;
+  const double a = A[(long)lo * n + lo].x, d = A[(long)hi * n + hi].x;
+  const double2 b = A[(long)lo * n + hi];
   const double ab = hypot(b.x, b.y);
-  if (!(ab > 0.0)) return;
-  const double tau = (dd - a) / (2.0 * ab);
+  if (!(ab > 0.0)) return r;
+  const double tau = (d - a) / (2.0 * ab);
   double t;
   if (fabs(tau) > 1e150)
     t = 0.5 / tau;
   else
     t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
   const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-  const double px_ = b.x / ab, py_ = b.y / ab;  // e^{i phi}
-  d = c;
-  o = x == p ? make_double2(-s * px_, s * py_)   // J_qp = -s e^{-i phi}
-             : make_double2(s * px_, s * py_);   // J_pq =  s e^{i phi}
+  const double px = b.x / ab, py = b.y / ab;  // e^{i phi}
+  r.c = c;
+  r.up = make_double2(s * px, s * py);
+  r.dn = make_double2(-s * px, s * py);  // -s e^{-i phi}
+  return r;
 }
 
 __device__ inline double2 cmul(double2 a, double2 b) {
@@ -70,58 +84,63 @@ __device__ inline double2 cmul(double2 a, double2 b) {
 __device__ inline double2 cmulc(double2 a, double2 b) {  // conj(a) b
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 rscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
 
-// One round: A2 = J^H A J (first n*n threads), V2 = V J (next n*n).
+// One round.  Threads [0, P^2): the 2x2 block of A on row pair sr and column
+// pair sc, A2 = J_r^H A J_c (each element of A read once); threads
+// [P^2, P^2 + n P): row r of V on column pair sc, V2 = V J_c.  P = m / 2.
 __global__ __launch_bounds__(256) void k_jac_round(int n, int m, int k,
                                                    const double2* __restrict__ A,
                                                    double2* __restrict__ A2,
                                                    const double2* __restrict__ V,
                                                    double2* __restrict__ V2) {
-  const long nn = (long)n * n;
+  const int P = m / 2;
+  const long na = (long)P * P;
   long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (e >= 2 * nn) return;
-  const bool isv = e >= nn;
-  if (isv) e -= nn;
-  const int r = (int)(e / n), c = (int)(e % n);
-  const int pc = rr_partner(c, k, m);
-  double dc;
-  double2 oc;
-  rot_col(A, n, c, pc, dc, oc);
-  const bool cact = pc < n && (oc.x != 0.0 || oc.y != 0.0);
-  if (isv) {
-    const double2 x = V[e];
-    double2 y = make_double2(dc * x.x, dc * x.y);
-    if (cact) {
-      const double2 z = cmul(oc, V[(long)r * n + pc]);
-      y.x += z.x;
-      y.y += z.y;
-    }
-    V2[e] = y;
+  if (e >= na + (long)n * P) return;
+  int sr, sc, r = -1;
+  if (e < na) {
+    sr = (int)(e / P);
+    sc = (int)(e % P);
+  } else {
+    e -= na;
+    r = (int)(e / P);
+    sc = (int)(e % P);
+    sr = 0;
+  }
+  int lc, hc;
+  rr_pair(sc, k, m, lc, hc);
+  const Rot2 jc = rotation(A, n, lc, hc);
+  const bool hcv = hc < n;
+  if (r >= 0) {  // V2[r][lc, hc] = V[r][lc, hc] J_c
+    const double2 x0 = V[(long)r * n + lc];
+    const double2 x1 = hcv ? V[(long)r * n + hc] : make_double2(0.0, 0.0);
+    V2[(long)r * n + lc] = cadd(rscale(jc.c, x0), cmul(x1, jc.dn));
+    if (hcv) V2[(long)r * n + hc] = cadd(cmul(x0, jc.up), rscale(jc.c, x1));
     return;
   }
-  const int pr = rr_partner(r, k, m);
-  double dr;
-  double2 orr;
-  rot_col(A, n, r, pr, dr, orr);
-  const bool ract = pr < n && (orr.x != 0.0 || orr.y != 0.0);
-  auto right = [&](int row) {  // (A J)_{row, c}
-    const double2 x = A[(long)row * n + c];
-    double2 y = make_double2(dc * x.x, dc * x.y);
-    if (cact) {
-      const double2 z = cmul(oc, A[(long)row * n + pc]);
-      y.x += z.x;
-      y.y += z.y;
-    }
-    return y;
-  };
-  const double2 u = right(r);
-  double2 y = make_double2(dr * u.x, dr * u.y);
-  if (ract) {
-    const double2 z = cmulc(orr, right(pr));
-    y.x += z.x;
-    y.y += z.y;
+  int lr, hr;
+  rr_pair(sr, k, m, lr, hr);
+  const Rot2 jr = rotation(A, n, lr, hr);
+  const bool hrv = hr < n;
+  const double2 zero = make_double2(0.0, 0.0);
+  const double2 a00 = A[(long)lr * n + lc];
+  const double2 a01 = hcv ? A[(long)lr * n + hc] : zero;
+  const double2 a10 = hrv ? A[(long)hr * n + lc] : zero;
+  const double2 a11 = (hrv && hcv) ? A[(long)hr * n + hc] : zero;
+  // B = A_blk J_c
+  const double2 b00 = cadd(rscale(jc.c, a00), cmul(a01, jc.dn));
+  const double2 b01 = cadd(cmul(a00, jc.up), rscale(jc.c, a01));
+  const double2 b10 = cadd(rscale(jc.c, a10), cmul(a11, jc.dn));
+  const double2 b11 = cadd(cmul(a10, jc.up), rscale(jc.c, a11));
+  // A2 = J_r^H B: row lo = c B0 + conj(J_hi,lo) B1, row hi = conj(J_lo,hi) B0 + c B1
+  A2[(long)lr * n + lc] = cadd(rscale(jr.c, b00), cmulc(jr.dn, b10));
+  if (hcv) A2[(long)lr * n + hc] = cadd(rscale(jr.c, b01), cmulc(jr.dn, b11));
+  if (hrv) {
+    A2[(long)hr * n + lc] = cadd(cmulc(jr.up, b00), rscale(jr.c, b10));
+    if (hcv) A2[(long)hr * n + hc] = cadd(cmulc(jr.up, b01), rscale(jr.c, b11));
   }
-  A2[e] = y;
 }
 
 __global__ void k_jac_eye(int n, double2* __restrict__ V) {
@@ -221,7 +240,8 @@ hipError_t heev_run(int n, const void* A, int mode, double* w, void* Vout, int n
   hipLaunchKernelGGL(k_jac_eye, dim3(gb), dim3(256), 0, st, n, v0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int m = n + (n & 1);
-  const int g2 = (int)((2 * nn + 255) / 256);
+  const long nthr = (long)(m / 2) * (m / 2) + (long)n * (m / 2);
+  const int g2 = (int)((nthr + 255) / 256);
   constexpr int MAX_SWEEPS = 60;
   bool last = false;
   int sw = 0;
