@@ -15,6 +15,8 @@ Modules:
   grads     -- vector-Jacobian products of sigma with respect to X and L.
   hhl       -- the hole-hole ladder over occupied-occupied Cholesky vectors
                (definition, factored identity, brute force, packed matrix).
+  ring      -- the particle-hole (ring) term of the doubles-doubles Jacobian
+               (definition, a route that never forms the integrals, matrix).
   chol      -- the pivoted Cholesky decomposition that produces the vectors.
   fns       -- perturbation-sensitive natural spinors (FNS++): MP2 and
                perturbed amplitudes, dressed diagonals, the averaged density,
@@ -25,4 +27,4 @@ closed forms, invariants or finite differences.  Parity with the paper's
 printed numbers is unpinned: the paper's molecular results need integrals
 that are not available, and it prints no worked example of this path.
 """
-from . import ppl, response, grads, hhl, chol, fns  # noqa: F401
+from . import ppl, response, grads, hhl, ring, chol, fns  # noqa: F401

@@ -14,62 +14,8 @@ import numpy as np
 import pytest
 
 import lrcc_synth
+from fock import Fock
 from oracle import fns
-
-
-# ---------------------------------------------------------------------------
-# Fock space of n spinors: basis |m>, m a bit mask, bit p = spinor p occupied.
-
-def annihilator(n, p):
-    dim = 1 << n
-    a = np.zeros((dim, dim))
-    for m in range(dim):
-        if m >> p & 1:
-            sign = (-1) ** bin(m & ((1 << p) - 1)).count("1")
-            a[m ^ (1 << p), m] = sign
-    return a
-
-
-class Fock:
-    def __init__(self, o, v):
-        self.o, self.v, self.n = o, v, o + v
-        self.a = [annihilator(self.n, p) for p in range(self.n)]
-        self.c = [x.T.copy() for x in self.a]
-        ref = np.zeros(1 << self.n)
-        ref[0] = 1.0
-        for p in reversed(range(o)):
-            ref = self.c[p] @ ref
-        self.ref = ref
-
-    def vir(self, a):
-        return self.o + a
-
-    def double(self, i, j, a, b):
-        """|ij->ab> = a+_a a+_b a_j a_i |ref>."""
-        A, B = self.vir(a), self.vir(b)
-        return self.c[A] @ (self.c[B] @ (self.a[j] @ (self.a[i] @ self.ref)))
-
-    def single(self, i, a):
-        return self.c[self.vir(a)] @ (self.a[i] @ self.ref)
-
-    def t2_op(self, t):
-        """T2 = 1/4 sum t_ij^ab a+_a a+_b a_j a_i."""
-        o, v = self.o, self.v
-        T = np.zeros((1 << self.n, 1 << self.n), np.complex128)
-        for i, j, a, b in itertools.product(range(o), range(o), range(v), range(v)):
-            if t[i, j, a, b] != 0:
-                T += 0.25 * t[i, j, a, b] * (self.c[self.vir(a)] @ self.c[self.vir(b)]
-                                             @ self.a[j] @ self.a[i])
-        return T
-
-    def one_body(self, M):
-        """sum_pq M[p, q] a+_p a_q over all spinors."""
-        A = np.zeros((1 << self.n, 1 << self.n), np.complex128)
-        for p in range(self.n):
-            for q in range(self.n):
-                if M[p, q] != 0:
-                    A += M[p, q] * (self.c[p] @ self.a[q])
-        return A
 
 
 def full_operator(inst, x):
