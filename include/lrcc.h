@@ -112,6 +112,25 @@ lrcc_status lrcc_ppl_sigma_adjoint(lrcc_handle h, int o, int v, int nchol, int n
 lrcc_status lrcc_hhl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* Loo,
                            const void* X, void* sigma, lrcc_dtype dt);
 
+/* Ring (particle-hole) term of the doubles-doubles Jacobian at zero
+ * ground-state amplitudes (Sec. 2.2), integrals from the Cholesky vectors of
+ * one decomposition over all spinors (Sec. 3):
+ *   <kb||cj> = sum_P L^P_kc L^P_bj - sum_P L^P_kj L^P_bc,
+ *   sigma_ij^ab = P(ij) P(ab) sum_{k,c} <kb||cj> X_ik^ac
+ * (P(ij) f = f - f with i, j swapped; the k, c sum unrestricted, no factor).
+ * Inputs (device, complex128): L_oo [nchol][o][o], L_ov [nchol][o][v],
+ * L_vo [nchol][v][o], L_vv [nchol][v][v] (L_xx[P][p][q] = L^P_pq; for a
+ * Hermitian decomposition L_vo[P] = L_ov[P]^H), X packed doubles as in
+ * lrcc_ppl_sigma.  sigma (device, packed, overwritten).  FP64 arithmetic;
+ * the particle-hole integral matrix, (o v)^2 entries, is formed explicitly,
+ * and the workspace holds about (3 + 2 nrhs) (o v)^2 complex numbers.
+ * Asynchronous on the handle's stream.  Errors: LRCC_ERR_ARG for NULL,
+ * misaligned or overlapping buffers and negative sizes; LRCC_ERR_SHAPE for
+ * o v > 65535 or nrhs o v >= 2^31. */
+lrcc_status lrcc_ring_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* L_oo,
+                            const void* L_ov, const void* L_vo, const void* L_vv, const void* X,
+                            void* sigma);
+
 /* Pivoted (single-step) Cholesky decomposition of a two-electron integral
  * matrix (Sec. 3): M (device, n x n complex128, row-major, Hermitian positive
  * semi-definite; M[i][p] is read for the pivot column p) is decomposed as

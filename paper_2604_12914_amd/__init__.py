@@ -107,6 +107,7 @@ def lib() -> ctypes.CDLL:
             "lrcc_hhl_sigma": [vp, i, i, i, i, vp, vp, vp, i],
             "lrcc_cholesky": [vp, ctypes.c_long, vp, d, i, vp, vp, ctypes.POINTER(i)],
             "lrcc_heev": [vp, i, vp, vp, vp, ctypes.POINTER(i)],
+            "lrcc_ring_sigma": [vp, i, i, i, i, vp, vp, vp, vp, vp, vp],
             "lrcc_fns_plus": [vp, i, i, i, vp, vp, i, vp, vp, vp, d, d, vp, vp, vp,
                               ctypes.POINTER(i), vp, vp, ctypes.POINTER(FnsInfo)],
             "lrcc_solve": [vp, i, i, i, vp, vp, i, vp, i, vp,
@@ -248,6 +249,27 @@ def cholesky(M, tau=1e-5, max_vectors=None):
                                piv.data_ptr() if kmax else None, ctypes.byref(cnt)), h)
     k = cnt.value
     return L[:k], piv[:k].cpu().numpy().astype(np.int64)
+
+
+def ring_sigma(Loo, Lov, Lvo, Lvv, X, o=None, out=None):
+    """Ring term P(ij)P(ab) sum_kc <kb||cj> X_ik^ac on packed complex128
+    doubles X [nrhs, npo, npv]; the four Cholesky blocks [nchol, ., .]."""
+    import torch
+    Loo, Lov, Lvo, Lvv, X = (t.contiguous() for t in (Loo, Lov, Lvo, Lvv, X))
+    nchol, v = Lvv.shape[0], Lvv.shape[1]
+    o = Lov.shape[1] if o is None else o
+    for t, shp in ((Loo, (nchol, o, o)), (Lov, (nchol, o, v)), (Lvo, (nchol, v, o)),
+                   (Lvv, (nchol, v, v))):
+        if tuple(t.shape) != shp or t.dtype != torch.complex128:
+            raise ValueError(f"expected complex128 {shp}, got {t.dtype} {tuple(t.shape)}")
+    if X.dim() != 3 or X.shape[1:] != (o * (o - 1) // 2, v * (v - 1) // 2) or \
+            X.dtype != torch.complex128:
+        raise ValueError("X must be complex128 [nrhs, o(o-1)/2, v(v-1)/2]")
+    S = torch.empty_like(X) if out is None else out
+    h = handle(X.device.index)
+    _check(lib().lrcc_ring_sigma(h, o, v, nchol, X.shape[0], _ptr(Loo), _ptr(Lov), _ptr(Lvo),
+                                 _ptr(Lvv), _ptr(X), _ptr(S)), h)
+    return S
 
 
 def heev(A, vectors=True):

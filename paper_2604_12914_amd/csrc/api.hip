@@ -369,6 +369,7 @@ lrcc_status lrcc_destroy(lrcc_handle h) {
     h->hw.release();
     h->cw.release();
     h->fw.release();
+    h->rw.release();
     for (auto& b : h->sv) b.release();
     for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
     if (h->rb) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(h->rb));
@@ -512,6 +513,36 @@ lrcc_status lrcc_cholesky(lrcc_handle h, long n, const void* M, double tau, int 
   LRCC_HIP(h, h->cw.ensure(chol_state_bytes(n)));
   LRCC_HIP(h, chol_run(n, M, tau, max_vectors, L, pivots, h->cw.p, nvec, h->stream));
   return LRCC_OK;
+}
+
+lrcc_status lrcc_ring_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* L_oo,
+                            const void* L_ov, const void* L_vo, const void* L_vv, const void* X,
+                            void* sigma) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  if (o < 0 || v < 0 || nchol < 0 || nrhs < 0)
+    return fail(h, LRCC_ERR_ARG, "sizes must be non-negative");
+  const long ov = (long)o * v;
+  if (ov > 65535) return fail(h, LRCC_ERR_SHAPE, "o v exceeds 65535");
+  if ((long)nrhs * ov >= (1L << 31)) return fail(h, LRCC_ERR_SHAPE, "nrhs o v reaches 2^31");
+  const size_t nx = (size_t)nrhs * npair(o) * npair(v) * 16;
+  if (nx == 0) return LRCC_OK;
+  if (!X || !sigma) return fail(h, LRCC_ERR_ARG, "X or sigma is NULL");
+  const size_t no = (size_t)nchol * o * o * 16, nov = (size_t)nchol * ov * 16,
+               nv = (size_t)nchol * v * v * 16;
+  if (nchol > 0 && (!L_oo || !L_ov || !L_vo || !L_vv))
+    return fail(h, LRCC_ERR_ARG, "a Cholesky block is NULL");
+  const void* ptrs[] = {L_oo, L_ov, L_vo, L_vv, X, sigma};
+  for (const void* q : ptrs)
+    if (q && (uintptr_t)q % 16) return fail(h, LRCC_ERR_ARG, "a buffer is not 16-byte aligned");
+  if (overlaps(sigma, nx, X, nx) || (nchol > 0 && (overlaps(sigma, nx, L_oo, no) ||
+                                                   overlaps(sigma, nx, L_ov, nov) ||
+                                                   overlaps(sigma, nx, L_vo, nov) ||
+                                                   overlaps(sigma, nx, L_vv, nv))))
+    return fail(h, LRCC_ERR_ARG, "sigma overlaps an input");
+  DeviceGuard dg(h->device);
+  h->err.clear();
+  LRCC_HIP(h, h->rw.ensure(ring_ws_bytes(o, v, nrhs)));
+  return ring_run(h, o, v, nchol, nrhs, L_oo, L_ov, L_vo, L_vv, X, sigma, false, h->rw.p);
 }
 
 lrcc_status lrcc_heev(lrcc_handle h, int n, const void* A, double* w, void* V, int* sweeps) {

@@ -80,6 +80,7 @@ struct lrcc_handle_s {
   lrcc::Buf hw;           // hole-hole ladder: W matrix and occupied pair table
   lrcc::Buf cw;           // pivoted Cholesky: remaining diagonal and state
   lrcc::Buf fw;           // FNS++ and eigensolver workspace
+  lrcc::Buf rw;           // ring term workspace
   void* rb = nullptr;     // rocBLAS handle (gradient GEMMs), created on first use
   // ladder-kernel timing (lrcc_set_timing)
   bool timing = false;
@@ -199,6 +200,13 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
                     int ncomp, const void* Aov, const void* Avv, const void* Aoo, double omega,
                     double threshold, double* occ, void* B, double* eps_new, int* keep,
                     void* gamma, double* hbar_out, void* ws, lrcc_fns_info* info);
+
+// Ring term (ring.hip) --------------------------------------------------------
+// sigma (+)= P(ij)P(ab) sum_kc <kb||cj> X_ik^ac on packed complex128 doubles.
+size_t ring_ws_bytes(int o, int v, int nrhs);
+lrcc_status ring_run(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* Loo,
+                     const void* Lov, const void* Lvo, const void* Lvv, const void* X, void* S,
+                     bool accumulate, void* ws);
 
 // Hole-hole ladder (hhl.hip) ------------------------------------------------
 // W[(ij),(kl)] = 2 <kl||ij> from occupied-occupied vectors Loo [nchol][o][o]
