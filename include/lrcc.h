@@ -123,7 +123,7 @@ lrcc_status lrcc_hhl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, con
  * Hermitian decomposition L_vo[P] = L_ov[P]^H), X packed doubles as in
  * lrcc_ppl_sigma.  sigma (device, packed, overwritten).  FP64 arithmetic;
  * the particle-hole integral matrix, (o v)^2 entries, is formed explicitly,
- * and the workspace holds about (3 + 2 nrhs) (o v)^2 complex numbers.
+ * and the workspace holds about (1 + 2 max(1, nrhs)) (o v)^2 complex numbers.
  * Asynchronous on the handle's stream.  Errors: LRCC_ERR_ARG for NULL,
  * misaligned or overlapping buffers and negative sizes; LRCC_ERR_SHAPE for
  * o v > 65535 or nrhs o v >= 2^31. */
@@ -234,6 +234,16 @@ typedef struct {
                           L^P_ki L^P_lj,
                         which couples the occupied pairs (applied in FP64
                         whatever prec is).  lrcc_solve_batched: NULL only    */
+  const void* L_ov;  /* (device) NULL (default), or occupied-virtual
+                        Cholesky vectors [nchol][o][v] complex128 (needs
+                        L_oo and L_vo): the model Jacobian then also holds
+                        the ring term of lrcc_ring_sigma, built from L_oo,
+                        L_ov, L_vo and L (its particle-hole integral matrix
+                        formed once per solve side, applied in FP64 whatever
+                        prec is).  lrcc_solve_batched: NULL only            */
+  const void* L_vo;  /* (device) virtual-occupied vectors [nchol][v][o]
+                        complex128 with L_ov; for a Hermitian decomposition
+                        L_vo[P] = L_ov[P]^H                                  */
 } lrcc_solve_opts;
 
 typedef struct {

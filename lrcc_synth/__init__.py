@@ -49,6 +49,7 @@ __all__ = [
     "FnsInstance",
     "npair",
     "solve_gamma",
+    "ring_gamma",
 ]
 
 
@@ -106,20 +107,42 @@ class Instance:
     mu: np.ndarray     # [ncomp, o, v] complex128
     gamma: float
     Loo: np.ndarray = None  # [nchol, o, o] complex128 (hole-hole ladder), optional
+    Lov: np.ndarray = None  # [nchol, o, v] complex128 (ring term), optional
+    Lvo: np.ndarray = None  # [nchol, v, o] complex128 (ring term), optional
+
+
+def ring_gamma(o: int, v: int) -> float:
+    """Scale of the occupied-virtual vectors of the ring term: 1 / (6 sqrt(o v)),
+    which keeps the ring operator's norm a fraction of the smallest gap."""
+    return 1.0 / (6.0 * math.sqrt(max(o * v, 1)))
 
 
 def make_instance(o: int, v: int, nchol: int, ncomp: int = 3, seed: int = 0,
-                  gamma: float = 1.0, hermitian: bool = True, hh: bool = False) -> Instance:
+                  gamma: float = 1.0, hermitian: bool = True, hh: bool = False,
+                  ring: bool = False) -> Instance:
     """One synthetic LR instance, drawn in the documented order (``hh``: also
-    the occupied-occupied vectors of the hole-hole ladder, drawn last)."""
+    the occupied-occupied vectors of the hole-hole ladder, drawn last;
+    ``ring``: then the occupied-virtual vectors ``Lov[P] = CN(0, s^2)
+    exp(-P / 16)``, s = ``ring_gamma(o, v)``, with ``Lvo[P] = Lov[P]^H``
+    (one Hermitian decomposition) or, for ``hermitian=False``, an
+    independent draw of the same form; ``ring`` implies ``hh``)."""
     rng = np.random.default_rng(seed)
     L = make_L(rng, nchol, v, gamma, hermitian)
     e_occ = rng.uniform(-2.0, -0.5, size=o)
     e_vir = rng.uniform(0.1, 5.0, size=v)
     mu = np.stack([cn(rng, (o, v), 0.1) for _ in range(ncomp)]) if ncomp else \
         np.zeros((0, o, v), np.complex128)
+    hh = hh or ring
     Loo = make_L(rng, nchol, o, solve_gamma(o), hermitian) if hh else None
-    return Instance(o, v, nchol, L, np.concatenate([e_occ, e_vir]), mu, gamma, Loo)
+    Lov = Lvo = None
+    if ring:
+        decay = np.exp(-np.arange(nchol, dtype=np.float64) / 16.0)[:, None, None]
+        Lov = cn(rng, (nchol, o, v), ring_gamma(o, v)) * decay
+        if hermitian:
+            Lvo = np.ascontiguousarray(np.conj(np.swapaxes(Lov, 1, 2)))
+        else:
+            Lvo = cn(rng, (nchol, v, o), ring_gamma(o, v)) * decay
+    return Instance(o, v, nchol, L, np.concatenate([e_occ, e_vir]), mu, gamma, Loo, Lov, Lvo)
 
 
 @dataclass

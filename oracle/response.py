@@ -46,6 +46,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import hhl, ppl
+from . import ring as ringterm
 
 
 def rhs(mu: np.ndarray, o: int, v: int) -> np.ndarray:
@@ -68,11 +69,14 @@ def denominators(eps: np.ndarray, o: int, v: int) -> np.ndarray:
     return (ev[pa] + ev[pb])[None, :] - (eo[pi] + eo[pj])[:, None]
 
 
-def apply_jacobian(L, X, eps, o, v, Loo=None):
-    """(A X) = D o X + sigma(X) (+ the hole-hole ladder with ``Loo``)."""
+def apply_jacobian(L, X, eps, o, v, Loo=None, ring=None):
+    """(A X) = D o X + sigma(X) (+ the hole-hole ladder with ``Loo``, + the
+    ring term with ``ring`` = (Lov, Lvo), which needs ``Loo``)."""
     AX = denominators(eps, o, v)[None] * X + ppl.sigma(L, X, o, v)
     if Loo is not None:
         AX = AX + hhl.sigma(Loo, X, o, v)
+    if ring is not None:
+        AX = AX + ringterm.sigma(ring[0], ring[1], Loo, L, X, o, v)
     return AX
 
 
@@ -100,7 +104,7 @@ def _diis_coefficients(errs):
 
 
 def solve_iterative(L, eps, mu, omegas, o, v, tol=1e-8, max_iter=200,
-                    diis_dim=8, sigma_fn=None, Loo=None):
+                    diis_dim=8, sigma_fn=None, Loo=None, ring=None):
     """Jacobi + DIIS for every (omega, component) right-hand side.
 
     X0 = -xi / (D - omega).  Each iteration: R = -xi - (D - omega) X - sigma(X);
@@ -114,7 +118,8 @@ def solve_iterative(L, eps, mu, omegas, o, v, tol=1e-8, max_iter=200,
     """
     if sigma_fn is None:
         sigma_fn = (lambda X: ppl.sigma(L, X, o, v)) if Loo is None else \
-            (lambda X: ppl.sigma(L, X, o, v) + hhl.sigma(Loo, X, o, v))
+            (lambda X: ppl.sigma(L, X, o, v) + hhl.sigma(Loo, X, o, v)
+             + (ringterm.sigma(ring[0], ring[1], Loo, L, X, o, v) if ring is not None else 0))
     xi = rhs(mu, o, v)
     D = denominators(eps, o, v)
     ncomp = xi.shape[0]
@@ -241,15 +246,16 @@ def combine_full(alpha_right, alpha_left):
     return 0.5 * (s_ + np.conj(np.transpose(s_, (0, 2, 1))))
 
 
-def response_full_dense(L, eps, mu, omegas, o, v, Loo=None):
+def response_full_dense(L, eps, mu, omegas, o, v, Loo=None, ring=None):
     """Full response function from the exact right- and left-hand solves
-    (per occupied pair, or on the whole vector with the hole-hole ladder)."""
+    (per occupied pair, or on the whole vector with the hole-hole ladder and
+    the ring term)."""
     if Loo is None:
         right = solve_dense(L, eps, mu, omegas, o, v)
         left = solve_left_dense(L, eps, mu, omegas, o, v)
     else:
-        right = solve_dense_coupled(L, eps, mu, omegas, o, v, Loo)
-        left = solve_left_dense_coupled(L, eps, mu, omegas, o, v, Loo)
+        right = solve_dense_coupled(L, eps, mu, omegas, o, v, Loo, ring)
+        left = solve_left_dense_coupled(L, eps, mu, omegas, o, v, Loo, ring)
     return dict(alpha=combine_full(right["alpha"], left["alpha_left"]), X=right["X"],
                 Y=left["Y"])
 
@@ -278,23 +284,26 @@ def solve_sos_full(L, eps, mu, omegas, o, v):
 
 # --- the hole-hole ladder couples the occupied pairs ----------------------
 
-def full_matrix(L, eps, o, v, Loo=None):
+def full_matrix(L, eps, o, v, Loo=None, ring=None):
     """A on the whole packed vector x[(ij, ab)] (ij major): diag(D) + I (x) K
-    (+ W (x) I with the hole-hole ladder).  Small sizes only."""
+    (+ W (x) I with the hole-hole ladder, + the ring matrix with ``ring`` =
+    (Lov, Lvo)).  Small sizes only."""
     K = ppl.ladder_matrix(L, v)
     npo, npv = o * (o - 1) // 2, K.shape[0]
     A = np.diag(denominators(eps, o, v).reshape(-1)).astype(np.complex128)
     A += np.kron(np.eye(npo), K)
     if Loo is not None:
         A += np.kron(hhl.hh_matrix(Loo, o), np.eye(npv))
+    if ring is not None:
+        A += ringterm.ring_matrix(ring[0], ring[1], Loo, L, o, v)
     return A
 
 
-def solve_dense_coupled(L, eps, mu, omegas, o, v, Loo=None):
+def solve_dense_coupled(L, eps, mu, omegas, o, v, Loo=None, ring=None):
     """Exact right-hand solve on the whole vector: (A - w) x = -xi."""
     xi = rhs(mu, o, v)
     ncomp, npo, npv = xi.shape
-    A = full_matrix(L, eps, o, v, Loo)
+    A = full_matrix(L, eps, o, v, Loo, ring)
     X = np.zeros((len(omegas), ncomp, npo, npv), dtype=np.complex128)
     for w, om in enumerate(omegas):
         sol = np.linalg.solve(A - om * np.eye(A.shape[0]), -xi.reshape(ncomp, -1).T)
@@ -303,12 +312,12 @@ def solve_dense_coupled(L, eps, mu, omegas, o, v, Loo=None):
     return dict(alpha=alpha, X=X)
 
 
-def solve_left_dense_coupled(L, eps, mu, omegas, o, v, Loo=None):
+def solve_left_dense_coupled(L, eps, mu, omegas, o, v, Loo=None, ring=None):
     """Exact left-hand solve on the whole vector: (A + w)^T y = -eta."""
     xi = rhs(mu, o, v)
     et = np.conj(xi)
     ncomp, npo, npv = xi.shape
-    A = full_matrix(L, eps, o, v, Loo)
+    A = full_matrix(L, eps, o, v, Loo, ring)
     Y = np.zeros((len(omegas), ncomp, npo, npv), dtype=np.complex128)
     for w, om in enumerate(omegas):
         sol = np.linalg.solve((A + om * np.eye(A.shape[0])).T, -et.reshape(ncomp, -1).T)
@@ -317,11 +326,11 @@ def solve_left_dense_coupled(L, eps, mu, omegas, o, v, Loo=None):
     return dict(Y=Y, alpha_left=alpha_left)
 
 
-def solve_sos_coupled(L, eps, mu, omegas, o, v, Loo=None):
+def solve_sos_coupled(L, eps, mu, omegas, o, v, Loo=None, ring=None):
     """Sum over states of the whole Hermitian A (Hermitian L and Loo):
     alpha_xy(w) = sum_k conj(p_x,k) p_y,k / (lam_k - w), p = U^H xi."""
     xi = rhs(mu, o, v)
-    lam, U = np.linalg.eigh(full_matrix(L, eps, o, v, Loo))
+    lam, U = np.linalg.eigh(full_matrix(L, eps, o, v, Loo, ring))
     proj = np.conj(U.T) @ xi.reshape(xi.shape[0], -1).T      # [k, comp]
     alpha = np.zeros((len(omegas), xi.shape[0], xi.shape[0]), dtype=np.complex128)
     for w, om in enumerate(omegas):

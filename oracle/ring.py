@@ -69,13 +69,16 @@ def sigma_factored(Lov, Lvo, Loo, Lvv, X, o: int, v: int) -> np.ndarray:
     return pack_doubles(s)
 
 
-def ring_matrix(Lov, Lvo, Loo, Lvv, o: int, v: int) -> np.ndarray:
-    """The operator on packed doubles as an explicit matrix (tiny sizes)."""
+def ring_matrix(Lov, Lvo, Loo, Lvv, o: int, v: int, chunk: int = 256) -> np.ndarray:
+    """The operator on packed doubles as an explicit matrix (small sizes):
+    the definition route applied to the unit vectors, a chunk at a time."""
     npo, npv = o * (o - 1) // 2, v * (v - 1) // 2
     n = npo * npv
     R = np.zeros((n, n), np.complex128)
-    for col in range(n):
-        e = np.zeros((1, npo, npv), np.complex128)
-        e.reshape(-1)[col] = 1.0
-        R[:, col] = sigma(Lov, Lvo, Loo, Lvv, e, o, v).reshape(-1)
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        E = np.zeros((c1 - c0, n), np.complex128)
+        E[np.arange(c1 - c0), np.arange(c0, c1)] = 1.0
+        out = sigma(Lov, Lvo, Loo, Lvv, E.reshape(c1 - c0, npo, npv), o, v)
+        R[:, c0:c1] = out.reshape(c1 - c0, n).T
     return R

@@ -46,7 +46,8 @@ class SolveOpts(ctypes.Structure):
                 ("cmul", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("deterministic", ctypes.c_int),
                 ("resid_fp64_every", ctypes.c_int), ("anchor_prec", ctypes.c_int),
-                ("response", ctypes.c_int), ("L_oo", ctypes.c_void_p)]
+                ("response", ctypes.c_int), ("L_oo", ctypes.c_void_p),
+                ("L_ov", ctypes.c_void_p), ("L_vo", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -417,12 +418,13 @@ RESPONSE = {"right": 0, "full": 1}
 
 def solve(eps, L, mu, omegas, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64",
           cmul="4m", inner_tol=1e-5, max_outer=6, check=True, resid_fp64_every=0,
-          anchor_prec="fp64", response="right", Loo=None):
+          anchor_prec="fp64", response="right", Loo=None, Lov=None, Lvo=None):
     """Model response solve; returns (alpha [nomega, ncomp, ncomp] complex128 numpy,
     info dict).  response="right": alpha from the right-hand amplitudes;
     "full": the full response function (right- and left-hand solves).
     Loo: occupied-occupied Cholesky vectors [nchol, o, o] (complex128) to
-    include the hole-hole ladder in the model Jacobian."""
+    include the hole-hole ladder in the model Jacobian; with it, Lov
+    [nchol, o, v] and Lvo [nchol, v, o] add the ring term."""
     import numpy as np
     import torch
     L, mu, eps = L.contiguous(), mu.contiguous(), eps.contiguous()
@@ -436,9 +438,18 @@ def solve(eps, L, mu, omegas, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64",
         Loo = Loo.contiguous()
         if Loo.dtype != torch.complex128 or tuple(Loo.shape) != (nchol, o, o):
             raise ValueError("Loo must be complex128 [nchol, o, o]")
+    if (Lov is None) != (Lvo is None):
+        raise ValueError("Lov and Lvo come together")
+    if Lov is not None:
+        Lov, Lvo = Lov.contiguous(), Lvo.contiguous()
+        if Lov.dtype != torch.complex128 or tuple(Lov.shape) != (nchol, o, v) or \
+                Lvo.dtype != torch.complex128 or tuple(Lvo.shape) != (nchol, v, o):
+            raise ValueError("Lov must be complex128 [nchol, o, v] and Lvo [nchol, v, o]")
     opts = SolveOpts(tol, max_iter, diis_dim, PREC[prec], CMUL[cmul], inner_tol, max_outer, 0,
                      resid_fp64_every, PREC[anchor_prec], RESPONSE[response],
-                     Loo.data_ptr() if Loo is not None else None)
+                     Loo.data_ptr() if Loo is not None else None,
+                     Lov.data_ptr() if Lov is not None else None,
+                     Lvo.data_ptr() if Lvo is not None else None)
     info = SolveInfo()
     h = handle(L.device.index)
     st = lib().lrcc_solve(h, o, v, nchol, _ptr(eps), _ptr(L), ncomp, _ptr(mu), len(om),

@@ -204,6 +204,18 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
 // Ring term (ring.hip) --------------------------------------------------------
 // sigma (+)= P(ij)P(ab) sum_kc <kb||cj> X_ik^ac on packed complex128 doubles.
 size_t ring_ws_bytes(int o, int v, int nrhs);
+// The particle-hole integral matrix M[(kc)][(jb)] = <kb||cj> ((o v)^2
+// complex), from the blocks of L^P or, with `transposed`, of (L^P)^T (the
+// transposed operator, for the left-hand solve); and its application to
+// packed doubles (workspace sizes below).
+size_t ring_m_bytes(int o, int v);
+size_t ring_build_ws_bytes(int o, int v, int nchol, bool transposed);
+size_t ring_apply_ws_bytes(int o, int v, int nrhs);
+lrcc_status ring_build_m(lrcc_handle h, int o, int v, int nchol, const void* Loo,
+                         const void* Lov, const void* Lvo, const void* Lvv, bool transposed,
+                         double2* M, void* ws);
+lrcc_status ring_apply(lrcc_handle h, int o, int v, int nrhs, const double2* M, const void* X,
+                       void* S, bool accumulate, void* ws);
 lrcc_status ring_run(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* Loo,
                      const void* Lov, const void* Lvo, const void* Lvv, const void* X, void* S,
                      bool accumulate, void* ws);

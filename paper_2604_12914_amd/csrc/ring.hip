@@ -19,6 +19,8 @@
 //   k_ring_out: sigma[r][(i<j)][(a<b)] (+)= R_ij^ab - R_ji^ab - R_ij^ba + R_ji^ba
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace lrcc {
@@ -120,75 +122,144 @@ rocblas_status zgemm(rocblas_handle rb, rocblas_operation ta, rocblas_operation 
                        &zero, reinterpret_cast<rocblas_double_complex*>(C), (rocblas_int)ldc);
 }
 
-}  // namespace
-
-size_t ring_ws_bytes(int o, int v, int nrhs) {
-  const size_t ov2 = (size_t)o * v * o * v;
-  return 3 * al256(ov2 * 16) + 2 * al256((size_t)nrhs * ov2 * 16);
+// out[P][j][i] = in[P][i][j] for [n0][n1][n2] complex arrays.
+__global__ void k_tr3(long n0, int n1, int n2, const double2* __restrict__ in,
+                      double2* __restrict__ out) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= n0 * n1 * n2) return;
+  const long P = e / ((long)n1 * n2);
+  const int r = (int)(e % ((long)n1 * n2));
+  const int i = r / n2, j = r % n2;
+  out[(P * n2 + j) * n1 + i] = in[e];
 }
 
-lrcc_status ring_run(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* Loo,
-                     const void* Lov, const void* Lvo, const void* Lvv, const void* X, void* S,
-                     bool accumulate, void* ws) {
-  hipStream_t st = h->stream;
-  const long ov = (long)o * v, o2 = (long)o * o, v2 = (long)v * v;
-  const size_t ov2 = (size_t)ov * ov;
-  const long npo = o2 > 0 ? (long)o * (o - 1) / 2 : 0, npv = (long)v * (v - 1) / 2;
-  const long nout = (long)nrhs * npo * npv;
-  if (nout == 0) return LRCC_OK;
-  char* p = static_cast<char*>(ws);
-  double2* Ap = reinterpret_cast<double2*>(p);
-  p += al256(ov2 * 16);
-  double2* B2 = reinterpret_cast<double2*>(p);
-  p += al256(ov2 * 16);
-  double2* M = reinterpret_cast<double2*>(p);
-  p += al256(ov2 * 16);
-  double2* Xt = reinterpret_cast<double2*>(p);
-  p += al256((size_t)nrhs * ov2 * 16);
-  double2* R = reinterpret_cast<double2*>(p);
+hipError_t transpose3(long n0, int n1, int n2, const void* in, void* out, hipStream_t st) {
+  const long n = n0 * n1 * n2;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tr3, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n0, n1, n2,
+                     static_cast<const double2*>(in), static_cast<double2*>(out));
+  return hipGetLastError();
+}
 
+lrcc_status get_blas(lrcc_handle h, rocblas_handle* rb) {
   if (!h->rb) {
     if (rocblas_create_handle(reinterpret_cast<rocblas_handle*>(&h->rb)) !=
         rocblas_status_success)
       return fail(h, LRCC_ERR_DEVICE, "rocblas_create_handle failed");
   }
-  rocblas_handle rb = static_cast<rocblas_handle>(h->rb);
-  if (rocblas_set_stream(rb, st) != rocblas_status_success)
+  *rb = static_cast<rocblas_handle>(h->rb);
+  if (rocblas_set_stream(*rb, h->stream) != rocblas_status_success)
     return fail(h, LRCC_ERR_DEVICE, "rocblas_set_stream failed");
-  const rocblas_operation N = rocblas_operation_none, T = rocblas_operation_transpose;
-  auto blas = [&](rocblas_status s) -> lrcc_status {
-    return s == rocblas_status_success ? LRCC_OK
-                                       : fail(h, LRCC_ERR_DEVICE, "rocblas_zgemm failed");
-  };
-  lrcc_status s;
+  return LRCC_OK;
+}
+
+}  // namespace
+
+size_t ring_m_bytes(int o, int v) { return al256((size_t)o * v * o * v * 16); }
+
+size_t ring_build_ws_bytes(int o, int v, int nchol, bool transposed) {
+  const size_t ov2 = (size_t)o * v * o * v;
+  size_t b = 2 * al256(ov2 * 16);
+  if (transposed) b += al256((size_t)nchol * (o + v) * (o + v) * 16);
+  return b;
+}
+
+size_t ring_apply_ws_bytes(int o, int v, int nrhs) {
+  return 2 * al256((size_t)nrhs * o * v * o * v * 16);
+}
+
+size_t ring_ws_bytes(int o, int v, int nrhs) {
+  return ring_m_bytes(o, v) + std::max(ring_build_ws_bytes(o, v, 0, false),
+                                       ring_apply_ws_bytes(o, v, nrhs));
+}
+
+lrcc_status ring_build_m(lrcc_handle h, int o, int v, int nchol, const void* Loo,
+                         const void* Lov, const void* Lvo, const void* Lvv, bool transposed,
+                         double2* M, void* ws) {
+  hipStream_t st = h->stream;
+  const long ov = (long)o * v, o2 = (long)o * o, v2 = (long)v * v;
+  const size_t ov2 = (size_t)ov * ov;
+  if (ov2 == 0) return LRCC_OK;
+  char* p = static_cast<char*>(ws);
+  double2* Ap = reinterpret_cast<double2*>(p);
+  p += al256(ov2 * 16);
+  double2* B2 = reinterpret_cast<double2*>(p);
+  p += al256(ov2 * 16);
   if (nchol > 0) {
+    if (transposed) {
+      // the blocks of (L^P)^T: oo and vv transposed, ov and vo swapped and transposed
+      double2* t = reinterpret_cast<double2*>(p);
+      double2 *too = t, *tov = too + nchol * o2, *tvo = tov + nchol * ov, *tvv = tvo + nchol * ov;
+      LRCC_HIP(h, transpose3(nchol, o, o, Loo, too, st));
+      LRCC_HIP(h, transpose3(nchol, v, o, Lvo, tov, st));
+      LRCC_HIP(h, transpose3(nchol, o, v, Lov, tvo, st));
+      LRCC_HIP(h, transpose3(nchol, v, v, Lvv, tvv, st));
+      Loo = too;
+      Lov = tov;
+      Lvo = tvo;
+      Lvv = tvv;
+    }
+    rocblas_handle rb;
+    lrcc_status s = get_blas(h, &rb);
+    if (s != LRCC_OK) return s;
+    const rocblas_operation N = rocblas_operation_none, T = rocblas_operation_transpose;
     // A'^c((bj), (kc)) = sum_P Lvo^c((bj), P) Lov^c((kc), P)
-    s = blas(zgemm(rb, N, T, ov, ov, nchol, static_cast<const double2*>(Lvo), ov,
-                   static_cast<const double2*>(Lov), ov, Ap, ov));
-    if (s != LRCC_OK) return s;
+    if (zgemm(rb, N, T, ov, ov, nchol, static_cast<const double2*>(Lvo), ov,
+              static_cast<const double2*>(Lov), ov, Ap, ov) != rocblas_status_success)
+      return fail(h, LRCC_ERR_DEVICE, "rocblas_zgemm failed");
     // B2^c((kj), (bc)) = sum_P Loo^c((kj), P) Lvv^c((bc), P)
-    s = blas(zgemm(rb, N, T, o2, v2, nchol, static_cast<const double2*>(Loo), o2,
-                   static_cast<const double2*>(Lvv), v2, B2, o2));
-    if (s != LRCC_OK) return s;
+    if (zgemm(rb, N, T, o2, v2, nchol, static_cast<const double2*>(Loo), o2,
+              static_cast<const double2*>(Lvv), v2, B2, o2) != rocblas_status_success)
+      return fail(h, LRCC_ERR_DEVICE, "rocblas_zgemm failed");
   } else {
-    LRCC_HIP(h, hipMemsetAsync(Ap, 0, ov2 * 16, st));
-    LRCC_HIP(h, hipMemsetAsync(B2, 0, ov2 * 16, st));
+    LRCC_HIP(h, fill_zero(Ap, ov2 * 16, st));
+    LRCC_HIP(h, fill_zero(B2, ov2 * 16, st));
   }
   const int ntb = (v + RT - 1) / RT, ntj = (o + RT - 1) / RT;
   hipLaunchKernelGGL(k_ring_m, dim3(ntb * ntj, (unsigned)ov), dim3(RT * 8), 0, st, o, v, Ap, B2,
                      M);
   LRCC_HIP(h, hipGetLastError());
+  return LRCC_OK;
+}
+
+lrcc_status ring_apply(lrcc_handle h, int o, int v, int nrhs, const double2* M, const void* X,
+                       void* S, bool accumulate, void* ws) {
+  hipStream_t st = h->stream;
+  const long ov = (long)o * v;
+  const size_t ov2 = (size_t)ov * ov;
+  const long npo = (long)o * (o - 1) / 2, npv = (long)v * (v - 1) / 2;
+  const long nout = (long)nrhs * npo * npv;
+  if (nout == 0) return LRCC_OK;
+  double2* Xt = static_cast<double2*>(ws);
+  double2* R = reinterpret_cast<double2*>(static_cast<char*>(ws) +
+                                          al256((size_t)nrhs * ov2 * 16));
   const long nx = (long)nrhs * (long)ov2;
   hipLaunchKernelGGL(k_ring_x, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, st, o, v, nrhs,
                      static_cast<const double2*>(X), Xt);
   LRCC_HIP(h, hipGetLastError());
-  // R^c((jb), (ria)) = sum_(kc) M^c((jb), (kc)) Xt^c((kc), (ria))
-  s = blas(zgemm(rb, N, N, ov, (long)nrhs * ov, ov, M, ov, Xt, ov, R, ov));
+  rocblas_handle rb;
+  lrcc_status s = get_blas(h, &rb);
   if (s != LRCC_OK) return s;
+  // R^c((jb), (ria)) = sum_(kc) M^c((jb), (kc)) Xt^c((kc), (ria))
+  if (zgemm(rb, rocblas_operation_none, rocblas_operation_none, ov, (long)nrhs * ov, ov, M, ov,
+            Xt, ov, R, ov) != rocblas_status_success)
+    return fail(h, LRCC_ERR_DEVICE, "rocblas_zgemm failed");
   hipLaunchKernelGGL(k_ring_out, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, st, o, v,
                      nrhs, R, accumulate ? 1 : 0, static_cast<double2*>(S));
   LRCC_HIP(h, hipGetLastError());
   return LRCC_OK;
+}
+
+lrcc_status ring_run(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* Loo,
+                     const void* Lov, const void* Lvo, const void* Lvv, const void* X, void* S,
+                     bool accumulate, void* ws) {
+  const long npo = (long)o * (o - 1) / 2, npv = (long)v * (v - 1) / 2;
+  if ((long)nrhs * npo * npv == 0) return LRCC_OK;
+  double2* M = static_cast<double2*>(ws);
+  void* rest = static_cast<char*>(ws) + ring_m_bytes(o, v);
+  lrcc_status s = ring_build_m(h, o, v, nchol, Loo, Lov, Lvo, Lvv, false, M, rest);
+  if (s != LRCC_OK) return s;
+  return ring_apply(h, o, v, nrhs, M, X, S, accumulate, rest);
 }
 
 }  // namespace lrcc

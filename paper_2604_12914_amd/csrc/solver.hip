@@ -452,6 +452,12 @@ __global__ void k_acc(Dims d, const int* __restrict__ active, const double* __re
   }
 }
 
+// y += x over n doubles (the ring image added to the ladder's).
+__global__ void k_axpy1(long n, const double* __restrict__ x, double* __restrict__ y) {
+  for (long e = blockIdx.x * (long)RB + threadIdx.x; e < n; e += (long)gridDim.x * RB)
+    y[e] += x[e];
+}
+
 // Advance the device-resident iteration counter (one thread).
 __global__ void k_inc(int* itp) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *itp += 1;
@@ -503,6 +509,10 @@ struct Solver {
   int *otab = nullptr, *active = nullptr, *itp = nullptr;
   int* nonherm = nullptr;  // Hermiticity flag of L (herm_check)
   const double2* W = nullptr;  // hole-hole ladder matrix (optional)
+  const double2* ringM = nullptr;  // particle-hole integral matrix of the ring term (optional)
+  double2 *rx = nullptr, *rs = nullptr;  // packed iterate and ring image
+  double* rb = nullptr;                  // ring image in the block layout
+  void* rws = nullptr;                   // ring application workspace
   unsigned* valid = nullptr;
   double2 *Bm = nullptr, *coef = nullptr, *part = nullptr;
   double* relres = nullptr;
@@ -677,6 +687,18 @@ lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul 
   lrcc_status st = apply_ppl(S, xin, prec, cmul, ls);
   if (st != LRCC_OK || !S.W || S.g.nchol == 0) return st;
   LRCC_HIP(S.h, hh_apply(S.W, S.g, xin, S.s, S.h->stream));
+  if (!S.ringM) return LRCC_OK;
+  // the ring term on packed doubles: block -> packed, ring, packed -> block, add
+  hipStream_t s = S.h->stream;
+  const int nrhs = S.ncomp * S.nomega;
+  LRCC_HIP(S.h, block_to_pack<double>(xin, S.g, S.tab, S.rx, LRCC_C128, s));
+  st = ring_apply(S.h, S.g.o, S.g.v, nrhs, S.ringM, S.rx, S.rs, false, S.rws);
+  if (st != LRCC_OK) return st;
+  LRCC_HIP(S.h, pack_to_block<double>(S.rs, LRCC_C128, S.g, S.tab, S.rb, s));
+  const long n = 2 * S.d.plane;
+  hipLaunchKernelGGL(k_axpy1, dim3((unsigned)std::min<long>((n + RB - 1) / RB, 8192)), dim3(RB),
+                     0, s, n, S.rb, S.s);
+  LRCC_HIP(S.h, hipGetLastError());
   return LRCC_OK;
 }
 
@@ -804,6 +826,13 @@ lrcc_status read_opts(lrcc_handle h, const lrcc_solve_opts* in, lrcc_solve_opts*
   if (op->cmul != LRCC_CMUL_4M && op->cmul != LRCC_CMUL_3M)
     return fail(h, LRCC_ERR_ARG, "unknown complex-multiply form");
   if (op->deterministic) return fail(h, LRCC_ERR_UNSUPPORTED, "deterministic mode is reserved");
+  if ((op->L_ov != nullptr) != (op->L_vo != nullptr))
+    return fail(h, LRCC_ERR_ARG, "L_ov and L_vo come together");
+  if (op->L_ov && !op->L_oo)
+    return fail(h, LRCC_ERR_ARG, "the ring term needs L_oo as well");
+  const void* ps[] = {op->L_oo, op->L_ov, op->L_vo};
+  for (const void* q : ps)
+    if (q && (uintptr_t)q % 16) return fail(h, LRCC_ERR_ARG, "L_oo/L_ov/L_vo not 16-byte aligned");
   return LRCC_OK;
 }
 
@@ -838,6 +867,25 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
     LRCC_HIP(h, hh_build_w(op.L_oo, LRCC_C128, o, nchol, S.otab, form,
                            h->hw.as<double2>(), h->stream));
     S.W = h->hw.as<double2>();
+    if (op.L_ov) {  // the ring term: M from the blocks of L (or of L^T)
+      const int nrhs = S.ncomp * S.nomega;
+      const size_t mb = ring_m_bytes(o, v);
+      const size_t bb = ring_build_ws_bytes(o, v, nchol, form == L_TRANS);
+      const size_t ab = ring_apply_ws_bytes(o, v, nrhs);
+      const size_t pk = ((size_t)nrhs * S.g.npo * S.g.npv * 16 + 255) / 256 * 256;
+      const size_t bl = ((size_t)2 * S.d.plane * 8 + 255) / 256 * 256;
+      LRCC_HIP(h, h->rw.ensure(mb + std::max(bb, ab + 2 * pk + bl)));
+      char* base = h->rw.as<char>();
+      double2* M = reinterpret_cast<double2*>(base);
+      st = ring_build_m(h, o, v, nchol, op.L_oo, op.L_ov, op.L_vo, L, form == L_TRANS, M,
+                        base + mb);
+      if (st != LRCC_OK) return st;
+      S.ringM = M;
+      S.rws = base + mb;
+      S.rx = reinterpret_cast<double2*>(base + mb + ab);
+      S.rs = reinterpret_cast<double2*>(base + mb + ab + pk);
+      S.rb = reinterpret_cast<double*>(base + mb + ab + 2 * pk);
+    }
   }
   st = stage_for(S, L, anchor, op.cmul, h->ls, form);
   if (st != LRCC_OK) return st;
@@ -1003,8 +1051,8 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
     return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve runs the FP64 ladder");
   if (op.response != 0)
     return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve gives the right-hand response");
-  if (op.L_oo)
-    return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve has no hole-hole ladder");
+  if (op.L_oo || op.L_ov)
+    return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve has no hole-hole ladder or ring term");
   constexpr int KC = 16;  // chunk of the persistent FP64 ladder
   std::vector<std::unique_ptr<Solver>> S(ninst);
   std::vector<std::unique_ptr<Buf[]>> own(ninst);

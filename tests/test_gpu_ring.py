@@ -108,3 +108,58 @@ def test_ring_errors(lrcc):
         lrcc._check(lrcc.lib().lrcc_ring_sigma(h, o, v, 1, 1, lrcc._ptr(z), lrcc._ptr(z),
                                                lrcc._ptr(z), lrcc._ptr(z), lrcc._ptr(X),
                                                lrcc._ptr(X)), h)
+
+
+# --- the ring term inside the response solve ---------------------------------
+
+from oracle import response  # noqa: E402
+
+OMEGAS = [0.0, 0.0428, 0.0656]
+
+
+def dev_ring(inst):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    return (t(inst.eps), t(inst.L), t(inst.mu)), dict(Loo=t(inst.Loo), Lov=t(inst.Lov),
+                                                      Lvo=t(inst.Lvo))
+
+
+@pytest.mark.parametrize("herm", [True, False])
+@pytest.mark.parametrize("cmul", ["4m", "3m"])
+@pytest.mark.parametrize("o,v,nchol", [(4, 24, 64), (6, 20, 40)])
+def test_solve_with_ring(lrcc, o, v, nchol, cmul, herm):
+    print(f"solve with ring o={o} v={v} nchol={nchol} {cmul} herm={herm}", flush=True)
+    inst = S.make_instance(o, v, nchol, ncomp=3, seed=11, gamma=S.solve_gamma(v),
+                           hermitian=herm, ring=True)
+    args, kw = dev_ring(inst)
+    rg = (inst.Lov, inst.Lvo)
+    alpha, info = lrcc.solve(*args, OMEGAS, tol=1e-8, cmul=cmul, **kw)
+    ref = response.solve_dense_coupled(inst.L, inst.eps, inst.mu, OMEGAS, o, v, inst.Loo, rg)
+    assert info["status"] == "LRCC_OK" and info["final_relres"] < 1e-8
+    assert rel(alpha, ref["alpha"]) < 1e-7
+    no_ring = response.solve_dense_coupled(inst.L, inst.eps, inst.mu, OMEGAS, o, v, inst.Loo)
+    assert rel(no_ring["alpha"], ref["alpha"]) > 1e-4
+    full, finfo = lrcc.solve(*args, OMEGAS, tol=1e-8, cmul=cmul, response="full", **kw)
+    fref = response.response_full_dense(inst.L, inst.eps, inst.mu, OMEGAS, o, v, inst.Loo, rg)
+    assert finfo["status"] == "LRCC_OK"
+    assert rel(full, fref["alpha"]) < 1e-7
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_refinement_with_ring(lrcc, prec):
+    o, v, nchol = 5, 30, 60
+    inst = S.make_instance(o, v, nchol, ncomp=2, seed=12, gamma=S.solve_gamma(v), ring=True)
+    args, kw = dev_ring(inst)
+    alpha, info = lrcc.solve(*args, OMEGAS[:2], prec=prec, tol=1e-8, inner_tol=1e-5, **kw)
+    ref = response.solve_dense_coupled(inst.L, inst.eps, inst.mu, OMEGAS[:2], o, v, inst.Loo,
+                                       (inst.Lov, inst.Lvo))
+    assert info["status"] == "LRCC_OK"
+    assert rel(alpha, ref["alpha"]) < 1e-7
+
+
+def test_solve_ring_argument_errors(lrcc):
+    inst = S.make_instance(3, 8, 10, ncomp=1, seed=13, gamma=S.solve_gamma(8), ring=True)
+    args, kw = dev_ring(inst)
+    with pytest.raises(ValueError):
+        lrcc.solve(*args, [0.0], Loo=kw["Loo"], Lov=kw["Lov"])
+    with pytest.raises(RuntimeError, match="L_oo"):
+        lrcc.solve(*args, [0.0], Lov=kw["Lov"], Lvo=kw["Lvo"])

@@ -93,3 +93,51 @@ def test_linear_and_zero():
                                2 * ring.sigma(*bl, X, o, v) - 1j * ring.sigma(*bl, Y, o, v),
                                atol=1e-12)
     assert np.abs(ring.sigma(*blocks(0 * Lfull, o), X, o, v)).max() == 0
+
+
+# --- the ring term inside the model Jacobian ---------------------------------
+
+from oracle import response  # noqa: E402
+
+OMEGAS = [0.0, 0.0656]
+
+
+def ring_instance(herm=True, seed=3, o=4, v=8, nchol=12):
+    return S.make_instance(o, v, nchol, ncomp=2, seed=seed, gamma=S.solve_gamma(v),
+                           hermitian=herm, ring=True)
+
+
+def test_jacobian_matrix_and_apply_agree():
+    inst = ring_instance(herm=False)
+    o, v = inst.o, inst.v
+    rg = (inst.Lov, inst.Lvo)
+    A = response.full_matrix(inst.L, inst.eps, o, v, inst.Loo, rg)
+    X = S.make_packed(np.random.default_rng(8), 1, o, v)
+    got = response.apply_jacobian(inst.L, X, inst.eps, o, v, inst.Loo, rg)
+    np.testing.assert_allclose(got.reshape(-1), A @ X.reshape(-1), atol=1e-12)
+
+
+def test_coupled_solves_with_ring():
+    """Dense solve = sum over states (Hermitian A, eigen route); the
+    iterative Jacobi+DIIS solve converges to it; the full response function
+    equals alpha(w) + conj alpha(-w); and the ring term moves alpha."""
+    inst = ring_instance()
+    o, v = inst.o, inst.v
+    rg = (inst.Lov, inst.Lvo)
+    A = response.full_matrix(inst.L, inst.eps, o, v, inst.Loo, rg)
+    np.testing.assert_allclose(A, np.conj(A.T), atol=1e-14)
+    assert np.linalg.eigvalsh(A).min() > 0.3
+    dense = response.solve_dense_coupled(inst.L, inst.eps, inst.mu, OMEGAS, o, v, inst.Loo, rg)
+    sos = response.solve_sos_coupled(inst.L, inst.eps, inst.mu, OMEGAS, o, v, inst.Loo, rg)
+    np.testing.assert_allclose(dense["alpha"], sos["alpha"], atol=1e-12)
+    it = response.solve_iterative(inst.L, inst.eps, inst.mu, OMEGAS, o, v, tol=1e-10,
+                                  Loo=inst.Loo, ring=rg)
+    np.testing.assert_allclose(it["alpha"], dense["alpha"], atol=1e-9)
+    full = response.response_full_dense(inst.L, inst.eps, inst.mu, OMEGAS, o, v, inst.Loo, rg)
+    minus = response.solve_dense_coupled(inst.L, inst.eps, inst.mu, [-w for w in OMEGAS], o, v,
+                                         inst.Loo, rg)
+    np.testing.assert_allclose(full["alpha"], dense["alpha"] + np.conj(minus["alpha"]),
+                               atol=1e-12)
+    no_ring = response.solve_dense_coupled(inst.L, inst.eps, inst.mu, OMEGAS, o, v, inst.Loo)
+    d = np.abs(no_ring["alpha"] - dense["alpha"]).max() / np.abs(dense["alpha"]).max()
+    assert d > 1e-4
