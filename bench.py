@@ -284,6 +284,34 @@ def main():
                                             for w in range(len(omegas))]}
         if exact is not None:
             extra["solve_fp64"]["max_abs_dalpha_vs_exact"] = float(np.abs(alpha64 - exact).max())
+        # the whole doubles-doubles Jacobian of the model: both ladders and the
+        # ring term (FP64), same L, eps and mu, extra vectors drawn after them
+        try:
+            fj = S.make_instance(o, v, nchol, ncomp=cfg.ncomp, seed=cfg.seed,
+                                 gamma=S.solve_gamma(v), ring=True)
+            kw = {k: torch.from_numpy(getattr(fj, a)).cuda()
+                  for k, a in (("Loo", "Loo"), ("Lov", "Lov"), ("Lvo", "Lvo"))}
+            lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            a_fj, i_fj = lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL, **kw)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            Xr = torch.from_numpy(S.make_packed(np.random.default_rng(1), nrhs, o, v)).cuda()
+            Lvv = L
+            lrcc.ring_sigma(kw["Loo"], kw["Lov"], kw["Lvo"], Lvv, Xr)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            lrcc.ring_sigma(kw["Loo"], kw["Lov"], kw["Lvo"], Lvv, Xr)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            extra["solve_fp64_pp_hh_ring"] = {
+                "ms": round((t1 - t0) * 1e3, 3), "iters_max": i_fj["iters_max"],
+                "n_sigma_fp64": i_fj["n_sigma_fp64"],
+                "alpha_zz": [float(a_fj[w, 2, 2].real) for w in range(len(omegas))],
+                "ring_sigma_ms_6rhs": round((t3 - t2) * 1e3, 3)}
+        except lrcc.LrccError as err:
+            extra["solve_fp64_pp_hh_ring"] = {"error": str(err)}
         # FNS++ virtual basis at the workload's shapes (Sec. 2.4)
         try:
             extra["fns_plus"] = fns_bench(lrcc, torch, np, S, o, v, nchol, 1, 3)
