@@ -111,3 +111,15 @@ def hermitian_eigh(A):
     """Eigenvalues (ascending) and eigenvectors of a Hermitian matrix: the
     library routine (LAPACK zheevd through numpy) as the definition."""
     return np.linalg.eigh(A)
+
+
+def transform_vectors(B, L):
+    """Cholesky vectors in the new virtual basis: Lt^P = B^H L^P B (so that
+    <ab|cd> = sum_P L_ac L_bd becomes the integrals over the columns of B)."""
+    return np.einsum("ak,pab,bl->pkl", np.conj(B), L, B, optimize=True)
+
+
+def transform_dipole(mu, B):
+    """Occupied-virtual one-body block in the new basis: mu_t[x, i, l] =
+    sum_a mu[x, i, a] B[a, l]."""
+    return np.einsum("xia,al->xil", mu, B, optimize=True)

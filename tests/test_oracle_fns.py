@@ -216,3 +216,37 @@ def test_truncated_basis_properties():
                                                    inst.A_oo[x], hi, ha, 0.0428))
              for x in range(3)]
     np.testing.assert_allclose(G, sum(parts) / 3, atol=1e-18)
+
+
+def test_transformed_vectors_give_the_transformed_ladder():
+    """With a unitary B (no truncation) the ladder of the transformed
+    vectors on the transformed doubles is the transformed ladder:
+    sigma(B^H L B)[X_t] = B^T-side transform of sigma(L)[X] with
+    X_t^{kl} = sum_ab conj(B_ak) conj(B_bl) X^{ab} (both virtual indices);
+    the spectra of the Hermitian L^P are kept; and a truncated B keeps the
+    integrals of the kept spinors."""
+    from oracle import ppl
+    inst = lrcc_synth.make_fns_instance(4, 9, 12, ncomp=2, seed=4)
+    o, v = 4, 9
+    r = fns.fns_plus(inst.eps, inst.Lov, inst.A_ov, inst.A_vv, inst.A_oo, 0.0, 0.0)
+    B = r["B"]
+    assert B.shape == (v, v)
+    rng = np.random.default_rng(1)
+    L = lrcc_synth.make_L(rng, 6, v, 1.0, True)
+    Lt = fns.transform_vectors(B, L)
+    for P in range(6):
+        np.testing.assert_allclose(np.linalg.eigvalsh(Lt[P]), np.linalg.eigvalsh(L[P]),
+                                   atol=1e-12)
+    X = lrcc_synth.make_packed(rng, 2, o, v)
+    Xf = ppl.unpack(X, v)                                   # [r, ij, a, b]
+    Xt = np.einsum("ak,bl,rpab->rpkl", np.conj(B), np.conj(B), Xf)
+    got = ppl.sigma(Lt, ppl.pack(Xt), o, v)
+    sf = ppl.unpack(ppl.sigma(L, X, o, v), v)
+    want = ppl.pack(np.einsum("ak,bl,rpab->rpkl", np.conj(B), np.conj(B), sf))
+    np.testing.assert_allclose(got, want, atol=1e-12 * np.abs(want).max())
+    # a truncated basis: the first k columns give the sub-block of the above
+    k = 5
+    np.testing.assert_allclose(fns.transform_vectors(B[:, :k], L), Lt[:, :k, :k], atol=1e-14)
+    mu = inst.A_ov
+    np.testing.assert_allclose(fns.transform_dipole(mu, B[:, :k]), (mu @ B)[:, :, :k],
+                               atol=1e-15)
