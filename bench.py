@@ -314,7 +314,7 @@ def main():
             extra["solve_fp64_pp_hh_ring"] = {"error": str(err)}
         # FNS++ virtual basis at the workload's shapes (Sec. 2.4)
         try:
-            extra["fns_plus"] = fns_bench(lrcc, torch, np, S, o, v, nchol, 1, 3)
+            extra["fns_plus"] = fns_bench(lrcc, torch, np, S, o, v, nchol, 1, 3, solve=True)
         except lrcc.LrccError as err:
             extra["fns_plus"] = {"error": str(err)}
         out["extra"] = extra
@@ -326,7 +326,8 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def fns_bench(lrcc, torch, np, S, o, v, nchol, warmup, reps, thr=1e-5, omega=0.0656):
+def fns_bench(lrcc, torch, np, S, o, v, nchol, warmup, reps, thr=1e-5, omega=0.0656,
+              solve=False):
     """FNS++ basis construction (lrcc_fns_plus) on the synthetic FNS++ inputs
     of this shape (three dipole-like components): wall time per call (the
     call is synchronous), the kept count and the Jacobi sweeps; also the
@@ -347,10 +348,35 @@ def fns_bench(lrcc, torch, np, S, o, v, nchol, warmup, reps, thr=1e-5, omega=0.0
     _, _, sw = lrcc.heev(r["gamma"])
     torch.cuda.synchronize()
     th = time.perf_counter() - t0
-    return {"workload": f"o={o} v={v} nchol={nchol} ncomp=3 omega={omega} threshold={thr}",
-            "ms": round(min(ts) * 1e3, 3), "ms_median": round(sorted(ts)[len(ts) // 2] * 1e3, 3),
-            "keep": r["keep"], "of": v, "sweeps": [r["sweeps_density"], r["sweeps_fock"]],
-            "heev_density_ms": round(th * 1e3, 3), "heev_density_sweeps": sw}
+    out = {"workload": f"o={o} v={v} nchol={nchol} ncomp=3 omega={omega} threshold={thr}",
+           "ms": round(min(ts) * 1e3, 3), "ms_median": round(sorted(ts)[len(ts) // 2] * 1e3, 3),
+           "keep": r["keep"], "of": v, "sweeps": [r["sweeps_density"], r["sweeps_fock"]],
+           "heev_density_ms": round(th * 1e3, 3), "heev_density_sweeps": sw}
+    if solve:
+        # the response solve before and after the truncation: particle-particle
+        # vectors over the same virtuals (solve scale), the dipole's ov block
+        Lvv = torch.from_numpy(S.make_L(np.random.default_rng(1), nchol, v,
+                                        S.solve_gamma(v), True)).cuda()
+        eps, mu = a[0], a[2]
+        om = [0.0, 0.0656]
+        lrcc.solve(eps, Lvv, mu, om, tol=1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a_full, _ = lrcc.solve(eps, Lvv, mu, om, tol=1e-8)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Lt, mt = lrcc.fns_transform(r["B"], Lvv, mu)
+        eps_t = torch.cat([eps[:o], r["eps_new"]]).contiguous()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        a_red, _ = lrcc.solve(eps_t, Lt, mt, om, tol=1e-8)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        out["solve_fp64_full_ms"] = round((t1 - t0) * 1e3, 3)
+        out["transform_ms"] = round((t2 - t1) * 1e3, 3)
+        out["solve_fp64_truncated_ms"] = round((t3 - t2) * 1e3, 3)
+        out["alpha_max_rel_change"] = float(np.abs(a_red - a_full).max() / np.abs(a_full).max())
+    return out
 
 
 def profile_sigma(lrcc, torch, np, S, args):

@@ -192,6 +192,21 @@ lrcc_status lrcc_fns_plus(lrcc_handle h, int o, int v, int nchol, const double* 
                           void* B, double* eps_new, int* keep, void* gamma, double* hbar,
                           lrcc_fns_info* info);
 
+/* The Cholesky vectors and the occupied-virtual dipole block in the kept
+ * FNS++ basis (the basis change of Sec. 2.3 applied to the quantities of
+ * the response solve): Lt^P = B^H L^P B and mu_t[x][i][l] = sum_a
+ * mu[x][i][a] conj(B[a][l]) (mu[x][i][a] = <a|mu_x|i> has the virtual in
+ * the bra).
+ * B: device [v][k] complex128 (lrcc_fns_plus's output, row stride k).
+ * L: device [nchol][v][v], Lt: device [nchol][k][k]; mu: device
+ * [ncomp][o][v], mu_t: device [ncomp][o][k]; either pair may be NULL to skip
+ * it.  The new spinor energies are lrcc_fns_plus's eps_new.  Asynchronous on
+ * the handle's stream.  Errors: LRCC_ERR_ARG for NULL B with work to do,
+ * misaligned or overlapping buffers, negative sizes or k > v. */
+lrcc_status lrcc_fns_transform(lrcc_handle h, int v, int k, int nchol, int ncomp, int o,
+                               const void* B, const void* L, const void* mu, void* Lt,
+                               void* mu_t);
+
 /* Options of the response solve.  Zero-initialised fields take defaults. */
 typedef struct {
   double tol;        /* relative residual |R|/|xi| (default 1e-8)            */

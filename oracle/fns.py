@@ -120,6 +120,7 @@ def transform_vectors(B, L):
 
 
 def transform_dipole(mu, B):
-    """Occupied-virtual one-body block in the new basis: mu_t[x, i, l] =
-    sum_a mu[x, i, a] B[a, l]."""
-    return np.einsum("xia,al->xil", mu, B, optimize=True)
+    """Occupied-virtual one-body block in the new basis.  mu[x, i, a] =
+    <a|mu_x|i> carries the virtual in the bra, so with the new spinors
+    phi~_l = sum_a phi_a B[a, l]: mu_t[x, i, l] = sum_a conj(B[a, l]) mu[x, i, a]."""
+    return np.einsum("xia,al->xil", mu, np.conj(B), optimize=True)

@@ -109,6 +109,7 @@ def lib() -> ctypes.CDLL:
             "lrcc_cholesky": [vp, ctypes.c_long, vp, d, i, vp, vp, ctypes.POINTER(i)],
             "lrcc_heev": [vp, i, vp, vp, vp, ctypes.POINTER(i)],
             "lrcc_ring_sigma": [vp, i, i, i, i, vp, vp, vp, vp, vp, vp],
+            "lrcc_fns_transform": [vp, i, i, i, i, i, vp, vp, vp, vp, vp],
             "lrcc_fns_plus": [vp, i, i, i, vp, vp, i, vp, vp, vp, d, d, vp, vp, vp,
                               ctypes.POINTER(i), vp, vp, ctypes.POINTER(FnsInfo)],
             "lrcc_solve": [vp, i, i, i, vp, vp, i, vp, i, vp,
@@ -271,6 +272,33 @@ def ring_sigma(Loo, Lov, Lvo, Lvv, X, o=None, out=None):
     _check(lib().lrcc_ring_sigma(h, o, v, nchol, X.shape[0], _ptr(Loo), _ptr(Lov), _ptr(Lvo),
                                  _ptr(Lvv), _ptr(X), _ptr(S)), h)
     return S
+
+
+def fns_transform(B, L=None, mu=None):
+    """(Lt, mu_t): Cholesky vectors L [nchol, v, v] and dipole block
+    mu [ncomp, o, v] in the kept FNS++ basis B [v, k] (complex128, GPU):
+    Lt^P = B^H L^P B, mu_t = mu conj(B)."""
+    import torch
+    B = B.contiguous()
+    v, k = B.shape
+    Lt = mt = None
+    nchol = ncomp = o = 0
+    if L is not None:
+        L = L.contiguous()
+        nchol = L.shape[0]
+        if tuple(L.shape) != (nchol, v, v) or L.dtype != torch.complex128:
+            raise ValueError("L must be complex128 [nchol, v, v]")
+        Lt = torch.empty((nchol, k, k), dtype=torch.complex128, device=B.device)
+    if mu is not None:
+        mu = mu.contiguous()
+        ncomp, o = mu.shape[0], mu.shape[1]
+        if tuple(mu.shape) != (ncomp, o, v) or mu.dtype != torch.complex128:
+            raise ValueError("mu must be complex128 [ncomp, o, v]")
+        mt = torch.empty((ncomp, o, k), dtype=torch.complex128, device=B.device)
+    h = handle(B.device.index)
+    _check(lib().lrcc_fns_transform(h, v, k, nchol, ncomp, o, _ptr(B), _ptr(L), _ptr(mu),
+                                    _ptr(Lt), _ptr(mt)), h)
+    return Lt, mt
 
 
 def heev(A, vectors=True):

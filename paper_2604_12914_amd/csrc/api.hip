@@ -545,6 +545,36 @@ lrcc_status lrcc_ring_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, co
   return ring_run(h, o, v, nchol, nrhs, L_oo, L_ov, L_vo, L_vv, X, sigma, false, h->rw.p);
 }
 
+lrcc_status lrcc_fns_transform(lrcc_handle h, int v, int k, int nchol, int ncomp, int o,
+                               const void* B, const void* L, const void* mu, void* Lt,
+                               void* mu_t) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  if (v < 0 || k < 0 || nchol < 0 || ncomp < 0 || o < 0)
+    return fail(h, LRCC_ERR_ARG, "sizes must be non-negative");
+  if (k > v) return fail(h, LRCC_ERR_ARG, "k exceeds v");
+  if ((L != nullptr) != (Lt != nullptr) || (mu != nullptr) != (mu_t != nullptr))
+    return fail(h, LRCC_ERR_ARG, "L/Lt and mu/mu_t come in pairs");
+  const size_t nb = (size_t)v * k * 16, nl = (size_t)nchol * v * v * 16,
+               nlt = (size_t)nchol * k * k * 16, nm = (size_t)ncomp * o * v * 16,
+               nmt = (size_t)ncomp * o * k * 16;
+  const bool dol = L && nlt > 0, dom = mu && nmt > 0;
+  if (!dol && !dom) return LRCC_OK;
+  if (!B) return fail(h, LRCC_ERR_ARG, "B is NULL");
+  const void* ps[] = {B, L, mu, Lt, mu_t};
+  for (const void* q : ps)
+    if (q && (uintptr_t)q % 16) return fail(h, LRCC_ERR_ARG, "a buffer is not 16-byte aligned");
+  if ((dol && (overlaps(Lt, nlt, L, nl) || overlaps(Lt, nlt, B, nb) ||
+               (dom && (overlaps(Lt, nlt, mu, nm) || overlaps(Lt, nlt, mu_t, nmt))))) ||
+      (dom && (overlaps(mu_t, nmt, mu, nm) || overlaps(mu_t, nmt, B, nb) ||
+               (dol && overlaps(mu_t, nmt, L, nl)))))
+    return fail(h, LRCC_ERR_ARG, "an output overlaps an input or the other output");
+  DeviceGuard dg(h->device);
+  h->err.clear();
+  LRCC_HIP(h, h->rw.ensure(fns_transform_ws_bytes(v, k, dol ? nchol : 0) + 256));
+  return fns_transform(h, v, k, dol ? nchol : 0, dom ? ncomp * o : 0, B, L, mu, Lt, mu_t,
+                       h->rw.p);
+}
+
 lrcc_status lrcc_heev(lrcc_handle h, int n, const void* A, double* w, void* V, int* sweeps) {
   if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
   if (sweeps) *sweeps = 0;

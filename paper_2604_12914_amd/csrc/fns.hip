@@ -206,6 +206,11 @@ __global__ void k_fns_t1(int o, int v, const double2* __restrict__ Aov,
   T1[e] = make_double2(x.x * inv, x.y * inv);
 }
 
+__global__ void k_conj_copy(long n, const double2* __restrict__ in, double2* __restrict__ out) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e < n) out[e] = make_double2(in[e].x, -in[e].y);
+}
+
 __global__ void k_fns_pairs(int o, int* __restrict__ otab) {
   const int i = blockIdx.x;
   for (int j = i + 1 + threadIdx.x; j < o; j += blockDim.x) {
@@ -426,6 +431,53 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
     info->sweeps_fock = sweeps2;
   }
   LRCC_HIP(h, hipStreamSynchronize(st));
+  return LRCC_OK;
+}
+
+// Vectors and dipole block in the kept basis: Lt^P = B^H L^P B (two
+// strided-batched products over P, through T^P = L^P B) and
+// mu_t = mu conj(B) (the dipole's virtual index is a bra index).
+size_t fns_transform_ws_bytes(int v, int k, int nchol) {
+  return al256((size_t)nchol * v * k * 16) + al256((size_t)v * k * 16);
+}
+
+lrcc_status fns_transform(lrcc_handle h, int v, int k, int nchol, int nrow, const void* B,
+                          const void* L, const void* mu, void* Lt, void* mut, void* ws) {
+  if (v == 0 || k == 0) return LRCC_OK;
+  if (!h->rb) {
+    if (rocblas_create_handle(reinterpret_cast<rocblas_handle*>(&h->rb)) !=
+        rocblas_status_success)
+      return fail(h, LRCC_ERR_DEVICE, "rocblas_create_handle failed");
+  }
+  rocblas_handle rb = static_cast<rocblas_handle>(h->rb);
+  if (rocblas_set_stream(rb, h->stream) != rocblas_status_success)
+    return fail(h, LRCC_ERR_DEVICE, "rocblas_set_stream failed");
+  const rocblas_operation N = rocblas_operation_none, C = rocblas_operation_conjugate_transpose;
+  const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+  const double2* Bp = static_cast<const double2*>(B);
+  if (nchol > 0 && L && Lt) {
+    double2* T = static_cast<double2*>(ws);
+    // T^c (k x v) = B^c (k x v) L^c (v x v), per P
+    if (zgemm_sb(rb, N, N, k, v, v, one, Bp, k, 0, static_cast<const double2*>(L), v,
+                 (long)v * v, zero, T, k, (long)v * k, nchol) != rocblas_status_success)
+      return fail(h, LRCC_ERR_DEVICE, "rocblas_zgemm_strided_batched failed");
+    // Lt^c (k x k) = T^c (k x v) (B^c)^H (v x k), per P
+    if (zgemm_sb(rb, N, C, k, k, v, one, T, k, (long)v * k, Bp, k, 0, zero,
+                 static_cast<double2*>(Lt), k, (long)k * k, nchol) != rocblas_status_success)
+      return fail(h, LRCC_ERR_DEVICE, "rocblas_zgemm_strided_batched failed");
+  }
+  if (nrow > 0 && mu && mut) {
+    double2* Bc = reinterpret_cast<double2*>(static_cast<char*>(ws) +
+                                             al256((size_t)nchol * v * k * 16));
+    const long nb = (long)v * k;
+    hipLaunchKernelGGL(k_conj_copy, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, h->stream,
+                       nb, Bp, Bc);
+    LRCC_HIP(h, hipGetLastError());
+    // mu_t^c (k x nrow) = conj(B)^c (k x v) mu^c (v x nrow)
+    if (zgemm(rb, N, N, k, nrow, v, one, Bc, k, static_cast<const double2*>(mu), v, zero,
+              static_cast<double2*>(mut), k) != rocblas_status_success)
+      return fail(h, LRCC_ERR_DEVICE, "rocblas_zgemm failed");
+  }
   return LRCC_OK;
 }
 

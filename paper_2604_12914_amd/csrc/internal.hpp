@@ -200,6 +200,9 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
                     int ncomp, const void* Aov, const void* Avv, const void* Aoo, double omega,
                     double threshold, double* occ, void* B, double* eps_new, int* keep,
                     void* gamma, double* hbar_out, void* ws, lrcc_fns_info* info);
+size_t fns_transform_ws_bytes(int v, int k, int nchol);
+lrcc_status fns_transform(lrcc_handle h, int v, int k, int nchol, int nrow, const void* B,
+                          const void* L, const void* mu, void* Lt, void* mut, void* ws);
 
 // Ring term (ring.hip) --------------------------------------------------------
 // sigma (+)= P(ij)P(ab) sum_kc <kb||cj> X_ik^ac on packed complex128 doubles.

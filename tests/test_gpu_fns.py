@@ -185,3 +185,56 @@ def test_fns_errors(lrcc):
         lrcc.fns_plus(*args, float("nan"), 1e-5)
     with pytest.raises(ValueError):
         lrcc.fns_plus(args[0][:-1], *args[1:])
+
+
+def test_fns_transform_matches_oracle(lrcc):
+    inst = S.make_fns_instance(5, 40, 20, 3, seed=31)
+    g = lrcc.fns_plus(cuda(inst.eps), cuda(inst.Lov), cuda(inst.A_ov), cuda(inst.A_vv),
+                      cuda(inst.A_oo), 0.0656, 1e-5)
+    B = g["B"]
+    k = B.shape[1]
+    assert 0 < k < 40
+    L = S.make_L(np.random.default_rng(2), 24, 40, 1.0, True)
+    Lt, mt = lrcc.fns_transform(B, cuda(L), cuda(inst.A_ov))
+    Bn = B.cpu().numpy()
+    Lr, mr = fns.transform_vectors(Bn, L), fns.transform_dipole(inst.A_ov, Bn)
+    assert np.abs(Lt.cpu().numpy() - Lr).max() < 1e-12 * np.abs(Lr).max()
+    assert np.abs(mt.cpu().numpy() - mr).max() < 1e-12 * np.abs(mr).max()
+    Lt2, none = lrcc.fns_transform(B, cuda(L))
+    assert none is None and torch.equal(Lt2, Lt)
+
+
+def joint(o, v, nchol, seed):
+    """FNS++ inputs plus particle-particle vectors over the same virtuals
+    (solve scale), the dipole's virtual-occupied block as the response
+    operator."""
+    inst = S.make_fns_instance(o, v, nchol, 3, seed=seed)
+    L = S.make_L(np.random.default_rng(seed + 1), nchol, v, S.solve_gamma(v), True)
+    return inst, L
+
+
+def test_solve_in_the_truncated_basis(lrcc):
+    """alpha in the FNS++ basis: identical to the canonical one when every
+    spinor is kept (a unitary change of the virtual basis that keeps the
+    Fock block diagonal); after truncation it moves away gradually (this
+    synthetic model's right-hand side spreads over all virtuals, so the
+    error is larger than the paper's molecules show)."""
+    o, v, nchol = 6, 48, 96
+    inst, L = joint(o, v, nchol, 41)
+    omegas = [0.0, 0.0656]
+    eps, Lg, mu = cuda(inst.eps), cuda(L), cuda(inst.A_ov)
+    a_full, _ = lrcc.solve(eps, Lg, mu, omegas, tol=1e-10)
+    errs, keeps = [], []
+    for thr in (0.0, 1e-7, 1e-5):
+        print(f"solve in the FNS++ basis thr={thr}", flush=True)
+        g = lrcc.fns_plus(eps, cuda(inst.Lov), mu, cuda(inst.A_vv), cuda(inst.A_oo), 0.0656,
+                          thr)
+        Lt, mt = lrcc.fns_transform(g["B"], Lg, mu)
+        eps_t = torch.cat([eps[:o], g["eps_new"]]).contiguous()
+        a_red, info = lrcc.solve(eps_t, Lt, mt, omegas, tol=1e-10)
+        assert info["status"] == "LRCC_OK"
+        errs.append(np.abs(a_red - a_full).max() / np.abs(a_full).max())
+        keeps.append(g["keep"])
+    assert keeps[0] == v and errs[0] < 1e-8
+    assert v > keeps[1] > keeps[2] > 0
+    assert errs[1] < errs[2] < 0.2

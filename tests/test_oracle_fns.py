@@ -248,5 +248,24 @@ def test_transformed_vectors_give_the_transformed_ladder():
     k = 5
     np.testing.assert_allclose(fns.transform_vectors(B[:, :k], L), Lt[:, :k, :k], atol=1e-14)
     mu = inst.A_ov
-    np.testing.assert_allclose(fns.transform_dipole(mu, B[:, :k]), (mu @ B)[:, :, :k],
+    np.testing.assert_allclose(fns.transform_dipole(mu, B[:, :k]), (mu @ np.conj(B))[:, :, :k],
                                atol=1e-15)
+
+
+def test_response_is_invariant_under_the_full_basis_change():
+    """Keeping every natural spinor is a unitary change of the virtual basis
+    that keeps the Fock block diagonal: the model's alpha (dense solve) is
+    the same in both bases, which fixes how each input transforms (vectors
+    B^H L B, dipole with conj(B), energies eps_new)."""
+    from oracle import response
+    o, v, nchol = 4, 14, 20
+    inst = lrcc_synth.make_fns_instance(o, v, nchol, ncomp=3, seed=12)
+    L = lrcc_synth.make_L(np.random.default_rng(13), nchol, v, lrcc_synth.solve_gamma(v), True)
+    om = [0.0, 0.0656]
+    full = response.solve_dense(L, inst.eps, inst.A_ov, om, o, v)["alpha"]
+    r = fns.fns_plus(inst.eps, inst.Lov, inst.A_ov, inst.A_vv, inst.A_oo, 0.0656, 0.0)
+    assert r["keep"] == v
+    eps_t = np.concatenate([inst.eps[:o], r["eps_new"]])
+    red = response.solve_dense(fns.transform_vectors(r["B"], L), eps_t,
+                               fns.transform_dipole(inst.A_ov, r["B"]), om, o, v)["alpha"]
+    np.testing.assert_allclose(red, full, atol=1e-10 * np.abs(full).max())
