@@ -97,6 +97,10 @@ def main():
                          "(for profilers) and print their kernel time")
     ap.add_argument("--profile-fns", action="store_true",
                     help="only run --warmup + --steps FNS++ basis constructions (for profilers)")
+    ap.add_argument("--profile-jacobian", action="store_true",
+                    help="only run an FP64 solve with both ladders and the ring term, "
+                         "--warmup + --steps ring applications and one pivoted Cholesky "
+                         "decomposition (for profilers)")
     ap.add_argument("--workload", choices=("baseline", "precision", "scale"), default="baseline",
                     help="shape for --profile-sigma / --profile-fns")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -122,6 +126,9 @@ def main():
 
     if args.profile_sigma:
         profile_sigma(lrcc, torch, np, S, args)
+        return
+    if args.profile_jacobian:
+        profile_jacobian(lrcc, torch, np, S, args)
         return
     if args.profile_fns:
         c = S.CONFIGS[args.workload]
@@ -377,6 +384,53 @@ def fns_bench(lrcc, torch, np, S, o, v, nchol, warmup, reps, thr=1e-5, omega=0.0
         out["solve_fp64_truncated_ms"] = round((t3 - t2) * 1e3, 3)
         out["alpha_max_rel_change"] = float(np.abs(a_red - a_full).max() / np.abs(a_full).max())
     return out
+
+
+def profile_jacobian(lrcc, torch, np, S, args):
+    """The other terms of the model Jacobian and the decomposition behind
+    them, at the workload's shapes: one FP64 solve with both ladders and the
+    ring term, ring applications alone (6 RHS), and one pivoted Cholesky
+    decomposition of a rank-640 Hermitian PSD matrix over v^2/4 pair indices
+    (drawn on the GPU from a seeded generator)."""
+    cfg = S.CONFIGS[args.workload]
+    o, v, nchol = cfg.o, cfg.v, cfg.nchol
+    fj = S.make_instance(o, v, nchol, ncomp=cfg.ncomp, seed=cfg.seed, gamma=S.solve_gamma(v),
+                         ring=True)
+    t = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    kw = dict(Loo=t(fj.Loo), Lov=t(fj.Lov), Lvo=t(fj.Lvo))
+    t0 = time.perf_counter()
+    alpha, info = lrcc.solve(t(fj.eps), t(fj.L), t(fj.mu), list(cfg.omegas), tol=1e-8,
+                             cmul=SOLVE_CMUL, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    X = t(S.make_packed(np.random.default_rng(1), cfg.nrhs, o, v))
+    L = t(fj.L)
+    for _ in range(args.warmup):
+        lrcc.ring_sigma(kw["Loo"], kw["Lov"], kw["Lvo"], L, X)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        lrcc.ring_sigma(kw["Loo"], kw["Lov"], kw["Lvo"], L, X)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    n = (v * v) // 4
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    Bm = torch.randn((n, nchol), dtype=torch.complex128, device="cuda", generator=g)
+    Bm = Bm * torch.exp(-torch.arange(nchol, device="cuda", dtype=torch.float64) / 64.0)
+    M = (Bm @ Bm.conj().T).contiguous()
+    M = 0.5 * (M + M.conj().T)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    Lc, piv = lrcc.cholesky(M.contiguous(), 1e-5)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    print(json.dumps({"profile_jacobian": args.workload,
+                      "solve_pp_hh_ring_ms": round((t1 - t0) * 1e3, 3),
+                      "iters_max": info["iters_max"],
+                      "ring_sigma_ms": round((t3 - t2) * 1e3 / max(args.steps, 1), 3),
+                      "cholesky_n": n, "cholesky_vectors": int(Lc.shape[0]),
+                      "cholesky_ms": round((t5 - t4) * 1e3, 3)}), flush=True)
 
 
 def profile_sigma(lrcc, torch, np, S, args):
