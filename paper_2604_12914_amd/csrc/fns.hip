@@ -434,8 +434,8 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
   return LRCC_OK;
 }
 
-// Vectors and dipole block in the kept basis: Lt^P = B^H L^P B (two
-// strided-batched products over P, through T^P = L^P B) and
+// Vectors and dipole block in the kept basis: Lt^P = B^H L^P B (one product
+// T = L B over all P, then a strided-batched B^H T^P) and
 // mu_t = mu conj(B) (the dipole's virtual index is a bra index).
 size_t fns_transform_ws_bytes(int v, int k, int nchol) {
   return al256((size_t)nchol * v * k * 16) + al256((size_t)v * k * 16);
@@ -457,10 +457,11 @@ lrcc_status fns_transform(lrcc_handle h, int v, int k, int nchol, int nrow, cons
   const double2* Bp = static_cast<const double2*>(B);
   if (nchol > 0 && L && Lt) {
     double2* T = static_cast<double2*>(ws);
-    // T^c (k x v) = B^c (k x v) L^c (v x v), per P
-    if (zgemm_sb(rb, N, N, k, v, v, one, Bp, k, 0, static_cast<const double2*>(L), v,
-                 (long)v * v, zero, T, k, (long)v * k, nchol) != rocblas_status_success)
-      return fail(h, LRCC_ERR_DEVICE, "rocblas_zgemm_strided_batched failed");
+    // T = L B for all P at once: rows (P, a) of L times B; column-major
+    // T^c (k x nchol v) = B^c (k x v) L^c (v x nchol v)
+    if (zgemm(rb, N, N, k, (long)nchol * v, v, one, Bp, k, static_cast<const double2*>(L), v,
+              zero, T, k) != rocblas_status_success)
+      return fail(h, LRCC_ERR_DEVICE, "rocblas_zgemm failed");
     // Lt^c (k x k) = T^c (k x v) (B^c)^H (v x k), per P
     if (zgemm_sb(rb, N, C, k, k, v, one, T, k, (long)v * k, Bp, k, 0, zero,
                  static_cast<double2*>(Lt), k, (long)k * k, nchol) != rocblas_status_success)
