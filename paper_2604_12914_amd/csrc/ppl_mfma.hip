@@ -420,13 +420,15 @@ __device__ __forceinline__ void contract_v(const T* lds, const T* __restrict__ X
     const int nm = next_main(mc);
     if (PF && nm >= 0) fetch_x(nm);
     if constexpr (CM3) {
-      // two passes of two column blocks (three accumulator sets each)
-      acc_t sr[2], si[2];
-      contract_rows<T, TR, 2, true>(Vr, Vi, xr, xi, 0, sr, si);
+      // two passes of two column blocks (three accumulator sets each), both
+      // before the next rows are requested, so those rows and this chunk's
+      // X operands are never live together
+      acc_t sr0[2], si0[2], sr1[2], si1[2];
+      contract_rows<T, TR, 2, true>(Vr, Vi, xr, xi, 0, sr0, si0);
+      contract_rows<T, TR, 2, true>(Vr, Vi, xr, xi, 2, sr1, si1);
       if (!PF && nm >= 0) fetch_x(nm);
-      store_rows<T, TA, 2>(sr, si, 0, m0, sr_g, si_g);
-      contract_rows<T, TR, 2, true>(Vr, Vi, xr, xi, 2, sr, si);
-      store_rows<T, TA, 2>(sr, si, 2, m0, sr_g, si_g);
+      store_rows<T, TA, 2>(sr0, si0, 0, m0, sr_g, si_g);
+      store_rows<T, TA, 2>(sr1, si1, 2, m0, sr_g, si_g);
     } else {
       acc_t sr[4], si[4];
       contract_rows<T, TR, 4, false>(Vr, Vi, xr, xi, 0, sr, si);
