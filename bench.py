@@ -95,6 +95,11 @@ def main():
     ap.add_argument("--profile-sigma", choices=("fp64", "fp32", "bf16x3"), default=None,
                     help="only run --warmup + --steps ladder applications of this precision "
                          "(for profilers) and print their kernel time")
+    ap.add_argument("--cmul", choices=("4m", "3m"), default="4m",
+                    help="complex form of --profile-sigma's ladder (FP64 / FP32)")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="only run the batched FP64 solve of the eight uneven instances once "
+                         "(for profilers)")
     ap.add_argument("--profile-fns", action="store_true",
                     help="only run --warmup + --steps FNS++ basis constructions (for profilers)")
     ap.add_argument("--profile-jacobian", action="store_true",
@@ -126,6 +131,9 @@ def main():
 
     if args.profile_sigma:
         profile_sigma(lrcc, torch, np, S, args)
+        return
+    if args.profile_batched:
+        profile_batched(lrcc, torch, np, S, args)
         return
     if args.profile_jacobian:
         profile_jacobian(lrcc, torch, np, S, args)
@@ -447,24 +455,52 @@ def profile_jacobian(lrcc, torch, np, S, args):
                       "cholesky_ms": round((t5 - t4) * 1e3, 3)}), flush=True)
 
 
+def profile_batched(lrcc, torch, np, S, args):
+    """The batched FP64 solve (3M ladder) of the eight uneven instances, o in
+    {8..32}, v = 10 o, Nchol = 4 v, 3 components x 4 frequencies each, to a
+    relative residual of 1e-6, once after tuning: one JSON line."""
+    cfg = S.CONFIGS["batch"]
+    om = list(cfg.omegas)
+    insts, F = [], 0.0
+    for (o, v, nchol, seed) in cfg.instances:
+        inst = S.make_instance(o, v, nchol, ncomp=cfg.ncomp, seed=seed, gamma=S.solve_gamma(v))
+        insts.append({"eps": torch.from_numpy(inst.eps).cuda(), "L": torch.from_numpy(inst.L).cuda(),
+                      "mu": torch.from_numpy(inst.mu).cuda(), "omegas": om})
+        F += flops_per_sigma(o, v, nchol, cfg.ncomp * len(om))
+    o, v, nchol = max(i[0] for i in cfg.instances), max(i[1] for i in cfg.instances), \
+        max(i[2] for i in cfg.instances)
+    lrcc.autotune(o, v, nchol, cfg.ncomp * len(om), prec="fp64", cmul="3m")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = lrcc.solve_batched(insts, tol=1e-6, diis_dim=4, cmul="3m")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print(json.dumps({"profile_batched": "8 instances", "s": round(t1 - t0, 3),
+                      "n_sigma_fp64": info["n_sigma_fp64"], "iters_max": info["iters_max"],
+                      "tflops_algorithmic": round(F * info["n_sigma_fp64"] / (t1 - t0) / 1e12, 2)}),
+          flush=True)
+
+
 def profile_sigma(lrcc, torch, np, S, args):
     """Ladder applications only (Hermitian L, packed X of the workload's RHS
     count), for a profiler run: one JSON line with the mean kernel time."""
     cfg = S.CONFIGS[args.workload]
     o, v, nchol, nrhs = cfg.o, cfg.v, cfg.nchol, cfg.nrhs
+    cmul = args.cmul if args.profile_sigma != "bf16x3" else "4m"
     L = torch.from_numpy(S.make_L(np.random.default_rng(4), nchol, v)).cuda()
     X = torch.from_numpy(S.make_packed(np.random.default_rng(3), nrhs, o, v)).cuda()
     s = None
     for _ in range(max(args.warmup, 1)):
-        s = lrcc.ppl_sigma(L, X, prec=args.profile_sigma)
+        s = lrcc.ppl_sigma(L, X, prec=args.profile_sigma, cmul=cmul)
     torch.cuda.synchronize()
     lrcc.set_timing(True)
     for _ in range(args.steps):
-        lrcc.ppl_sigma(L, X, prec=args.profile_sigma, out=s)
+        lrcc.ppl_sigma(L, X, prec=args.profile_sigma, cmul=cmul, out=s)
     ms, n = lrcc.get_timing()
     lrcc.set_timing(False)
     F = flops_per_sigma(o, v, nchol, nrhs)
-    print(json.dumps({"profile_sigma": args.profile_sigma, "workload": args.workload,
+    print(json.dumps({"profile_sigma": args.profile_sigma, "cmul": cmul,
+                      "workload": args.workload,
                       "o": o, "v": v, "nchol": nchol, "nrhs": nrhs,
                       "ladder_ms": round(ms / max(n, 1), 4), "launches": n,
                       "tflops_algorithmic": round(F / (ms / max(n, 1) * 1e-3) / 1e12, 2)}),
