@@ -211,6 +211,11 @@ __global__ void k_conj_copy(long n, const double2* __restrict__ in, double2* __r
   if (e < n) out[e] = make_double2(in[e].x, -in[e].y);
 }
 
+__global__ void k_tr_small(int o, const double2* __restrict__ in, double2* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < o * o) out[(e % o) * o + e / o] = in[e];
+}
+
 __global__ void k_fns_pairs(int o, int* __restrict__ otab) {
   const int i = blockIdx.x;
   for (int j = i + 1 + threadIdx.x; j < o; j += blockDim.x) {
@@ -269,6 +274,7 @@ size_t fns_ws_bytes(int o, int v, int ncomp) {
   b += al256((size_t)v * 4);              // eigen permutation
   b += al256((size_t)v * v * 16) * 4;     // Vt, S, Ft, Z
   b += al256((size_t)(o + v) * NSEG * 8);  // hbar segment sums
+  b += al256((size_t)o * o * 16);           // transposed A_oo
   b += al256((size_t)density_splits(v, (long)npo * v) * v * v * 16);  // density partials
   b += heev_ws_bytes(v);
   return b;
@@ -306,6 +312,7 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
   const long Kd = (long)npo * v;
   const int nsplit = density_splits(v, Kd);
   double2* Pd = reinterpret_cast<double2*>(take((size_t)nsplit * v2 * 16));
+  double2* Atr = reinterpret_cast<double2*>(take((size_t)o * o * 16));
 
   if (!h->rb) {
     if (rocblas_create_handle(reinterpret_cast<rocblas_handle*>(&h->rb)) !=
@@ -371,8 +378,11 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
                      Xp + r0 * v, v));
       if (s != LRCC_OK) return s;
     }
-    // Y^c (o v^2 x o) = t^c (o v^2 x o) * A_oo (o x o) as (A^c)^T
-    s = blas(zgemm(rb, N, T, (long)o * v2, o, o, one, t, (long)o * v2, aoo, o, zero, Y,
+    // Y^c (o v^2 x o) = t^c (o v^2 x o) * A_oo (o x o), A_oo through a
+    // transposed copy (a plain NN product)
+    hipLaunchKernelGGL(k_tr_small, dim3((o * o + 255) / 256), dim3(256), 0, st, o, aoo, Atr);
+    LRCC_HIP(h, hipGetLastError());
+    s = blas(zgemm(rb, N, N, (long)o * v2, o, o, one, t, (long)o * v2, Atr, o, zero, Y,
                    (long)o * v2));
     if (s != LRCC_OK) return s;
     if (npo > 0) {
