@@ -5,7 +5,8 @@ the ``cpu_baseline`` leg of ``bench.py`` may import or call anything here.
 The GPU library never imports it and shares no code with it: the packed-pair
 indexing, the integrals, the right-hand side, the denominators, the DIIS
 step and the gradients are all written out again here, plainly, from the
-paper's definitions (and the readings recorded in the design notes).
+paper's definitions (and, where the paper is silent, the readings stated in
+each module).
 
 Modules:
   ppl       -- sigma = PPL(X), by definition, by a factored identity, by brute

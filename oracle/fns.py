@@ -24,9 +24,11 @@ A_oo[m, i]) and A_ia = <a|A|i> (the element that couples the reference to
 the single excitation i -> a, stored A_ov[i, a]); P(p, q) f = f(p, q) - f(q, p).
 G is the matrix of the density operator, G_ab = <Psi1| a+_b a_a |Psi1> for
 |Psi1> = 1/4 sum t_ij^ac(A) |ij->ac> + sum t_i^a(A) |i->a>, so its
-eigenvectors are the coefficients of the natural spinors.  The
-readings (conjugation in the density and the dressed diagonals, the
-lowest-order singles numerator, B = Vt Z) are listed in the design notes.
+eigenvectors are the coefficients of the natural spinors.  Where the paper
+leaves it open: one factor of each product of two amplitudes (or of an
+amplitude and an integral) is conjugated, the singles numerator is the bare
+element <a|A|i>, and the basis change is B = Vt Z (v x k; the printed order
+has the wrong dimensions).
 Plain NumPy (einsum, eigh), FP64.
 """
 from __future__ import annotations
