@@ -869,6 +869,8 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
     S.W = h->hw.as<double2>();
     if (op.L_ov) {  // the ring term: M from the blocks of L (or of L^T)
       const int nrhs = S.ncomp * S.nomega;
+      if ((long)o * v > 65535 || (long)nrhs * o * v >= (1L << 31))
+        return fail(h, LRCC_ERR_SHAPE, "ring term: o v exceeds 65535 or nrhs o v reaches 2^31");
       const size_t mb = ring_m_bytes(o, v);
       const size_t bb = ring_build_ws_bytes(o, v, nchol, form == L_TRANS);
       const size_t ab = ring_apply_ws_bytes(o, v, nrhs);
