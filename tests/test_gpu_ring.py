@@ -163,3 +163,23 @@ def test_solve_ring_argument_errors(lrcc):
         lrcc.solve(*args, [0.0], Loo=kw["Loo"], Lov=kw["Lov"])
     with pytest.raises(RuntimeError, match="L_oo"):
         lrcc.solve(*args, [0.0], Lov=kw["Lov"], Lvo=kw["Lvo"])
+
+
+def test_solve_with_ring_full_size(lrcc):
+    """The workload of the benchmark (o=16, v=160, Nchol=640, 3 components x
+    2 frequencies) with both ladders and the ring term: converged by the
+    solver's FP64 residual, and alpha Hermitian (alpha_xy = conj alpha_yx, a
+    property of the Hermitian Jacobian at any size); the extra terms move
+    alpha by more than the solve tolerance."""
+    print("solve with ring o=16 v=160 nchol=640", flush=True)
+    cfg = S.CONFIGS["baseline"]
+    inst = S.make_instance(cfg.o, cfg.v, cfg.nchol, ncomp=cfg.ncomp, seed=cfg.seed,
+                           gamma=S.solve_gamma(cfg.v), ring=True)
+    args, kw = dev_ring(inst)
+    om = list(cfg.omegas)
+    alpha, info = lrcc.solve(*args, om, tol=1e-8, cmul="3m", **kw)
+    assert info["status"] == "LRCC_OK" and info["final_relres"] < 1e-8
+    herm = np.abs(alpha - np.conj(np.transpose(alpha, (0, 2, 1)))).max()
+    assert herm < 1e-9 * np.abs(alpha).max()
+    plain, _ = lrcc.solve(*args, om, tol=1e-8, cmul="3m")
+    assert rel(plain, alpha) > 1e-4
