@@ -320,11 +320,15 @@ def main():
             lrcc.ring_sigma(kw["Loo"], kw["Lov"], kw["Lvo"], Lvv, Xr)
             torch.cuda.synchronize()
             t3 = time.perf_counter()
+            ov = o * v
+            ring_flop = 8.0 * (nrhs * ov ** 3 + 2.0 * ov * ov * nchol)  # X M, and forming M
             extra["solve_fp64_pp_hh_ring"] = {
                 "ms": round((t1 - t0) * 1e3, 3), "iters_max": i_fj["iters_max"],
                 "n_sigma_fp64": i_fj["n_sigma_fp64"],
                 "alpha_zz": [float(a_fj[w, 2, 2].real) for w in range(len(omegas))],
-                "ring_sigma_ms_6rhs": round((t3 - t2) * 1e3, 3)}
+                "ring_sigma_ms_6rhs": round((t3 - t2) * 1e3, 3),
+                "ring_sigma_tflops": round(ring_flop / (t3 - t2) / 1e12, 2),
+                "ring_sigma_frac_fp64_peak": round(ring_flop / (t3 - t2) / 1e12 / PEAK["fp64"], 3)}
         except lrcc.LrccError as err:
             extra["solve_fp64_pp_hh_ring"] = {"error": str(err)}
         # FNS++ virtual basis at the workload's shapes (Sec. 2.4)
@@ -366,7 +370,9 @@ def fns_bench(lrcc, torch, np, S, o, v, nchol, warmup, reps, thr=1e-5, omega=0.0
     out = {"workload": f"o={o} v={v} nchol={nchol} ncomp=3 omega={omega} threshold={thr}",
            "ms": round(min(ts) * 1e3, 3), "ms_median": round(sorted(ts)[len(ts) // 2] * 1e3, 3),
            "keep": r["keep"], "of": v, "sweeps": [r["sweeps_density"], r["sweeps_fock"]],
-           "heev_density_ms": round(th * 1e3, 3), "heev_density_sweeps": sw}
+           "heev_density_ms": round(th * 1e3, 3), "heev_density_sweeps": sw,
+           # latency-bound: one launch per round of the parallel order
+           "heev_density_us_per_round": round(th * 1e6 / max(sw * (v - 1), 1), 2)}
     if solve:
         # the response solve before and after the truncation: particle-particle
         # vectors over the same virtuals (solve scale), the dipole's ov block
