@@ -181,7 +181,9 @@ typedef struct {
  * numbers in the order above (nullable); B [v][keep] complex128, written
  * compactly (row stride keep) into a buffer of v*v elements; eps_new [keep]
  * in a buffer of v doubles; *keep (host); gamma [v][v] the averaged density
- * (nullable); hbar [o+v] the dressed diagonals (nullable).  Workspace about
+ * (nullable); hbar [o+v] the dressed diagonals (nullable).  A direction-
+ * specific basis (the alternative to averaging that Sec. 2.4 mentions) is
+ * a call with that one component.  Workspace about
  * 3.5 (o v)^2 complex numbers, kept in the handle.  Synchronous.  Errors:
  * LRCC_ERR_ARG for NULL/misaligned/overlapping buffers, negative sizes, a
  * threshold that is negative or not finite or an omega that is not finite;
