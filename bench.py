@@ -2,24 +2,34 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Workload: o=16 occupied, v=160 virtual spinors, Nchol=640 complex Cholesky
-vectors, 3 dipole components x 2 frequencies (0, 0.0656 Eh) = 6 right-hand
-sides, FP64 complex (seeded synthetic inputs, see lrcc_synth).
+Headline workload: the scale workload, o=40 occupied, v=480 virtual
+spinors, Nchol=2400 complex Cholesky vectors, one right-hand side, FP64
+complex128 (seeded synthetic inputs drawn on the GPU with the distribution
+of lrcc_synth: Hermitian L^P = (G + G^H)/2 exp(-P/16), G ~ CN(0,1), packed
+X ~ CN(0,1)).
 
-One step = one full FP64 response solve: staging of the Cholesky vectors,
-right-hand sides, every Jacobi + DIIS iteration (fused ladder kernel,
-residual / preconditioner / norms pass, DIIS solve, extrapolation) and alpha.
-value = algorithmic ladder flops of all ladder applications in the step
-(F = 8 (2 npv^2 Nchol + nrhs npo npv^2) per application, 4M form, no
-symmetry savings) / wall time, in TFLOP/s.  The kernels exploit the
-Hermitian symmetry of the ladder operator (one integral tile per pair of
-block pairs), so this rate can exceed what the matrix cores issue; the
-roofline object reports both.
+One step = one FP64 ladder application sigma = PPL(L, X) through the C ABI
+(Hermiticity check, staging of the Cholesky vectors, packing of X, the fused
+build / antisymmetrise / contract kernel in the 3M complex form, unpacking).
+value = algorithmic flops of the method as the kernel evaluates it / wall
+time per step, in TFLOP/s:
+    F_alg = 6 (npv (npv + 1) Nchol + nrhs npo npv^2)
+(3M: three real multiply-adds per complex multiply-accumulate; the Hermitian
+ladder operator needs the integrals <ab||cd> only for packed (ab) <= (cd),
+two Cholesky dot products each; the contraction takes every ordered pair of
+packed virtual pairs for every row).  This count is what the matrix cores
+must issue at the least, so value and roofline.achieved stay below the FP64
+peak.  Also reported: the matrix-core work actually issued (padding
+included) and the survey's 4M count without symmetry savings
+(8 (2 npv^2 Nchol + nrhs npo npv^2)) as effective_tflops.
 
-Also reported: ladder-only rates per precision, the split-precision solve
-(time and |d alpha| against the FP64 solve), the roofline of the fused
-ladder kernel (HIP-event kernel time inside the timed region) and the FP64
-CPU oracle timed on a bounded share of one ladder application.
+Extras: the ladder per precision and complex form at the scale and baseline
+workloads (median / min / max kernel times), the baseline workload's FP64
+and split-precision solves, the time to |d alpha| < 1e-5 a.u. per method at
+the baseline and precision workloads, the precision study (|d alpha| per
+frequency against the oracle's exact alpha), the full response function,
+the solve with both ladders and the ring term, and the FNS++ basis; the
+FP64 CPU oracle timed on a bounded share of one headline step.
 """
 from __future__ import annotations
 
@@ -34,11 +44,27 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.0 / 3.0}   # TFLOP/s, dense MFMA
 HBM_GBS = 8000.0
+METRIC = "PPL A*X TFLOP/s FP64 vs split-prec; LR solve time at |d alpha|<1e-5 a.u."
+
+
+def npairs(n):
+    return n * (n - 1) // 2
 
 
 def flops_per_sigma(o, v, nchol, nrhs):
-    npo, npv = o * (o - 1) // 2, v * (v - 1) // 2
+    """The survey's algorithmic count: 4M, no symmetry savings."""
+    npo, npv = npairs(o), npairs(v)
     return 8.0 * (2.0 * npv * npv * nchol + nrhs * npo * npv * npv)
+
+
+def alg_flops(o, v, nchol, nrhs, cmul="4m"):
+    """Work of the method as the kernels evaluate it: integrals <ab||cd> for
+    packed (ab) <= (cd) only (Hermitian operator), two Cholesky dot products
+    each; contraction over every ordered pair for every row; 6 real flops per
+    complex multiply-accumulate in the 3M form, 8 in the 4M form.  No padding."""
+    npo, npv = npairs(o), npairs(v)
+    per = 6.0 if cmul == "3m" else 8.0
+    return per * (float(npv) * (npv + 1) * nchol + float(nrhs) * npo * npv * npv)
 
 
 def issued_flops(o, v, nchol, nrhs, prec="fp64", cmul="4m"):
@@ -58,16 +84,18 @@ def issued_flops(o, v, nchol, nrhs, prec="fp64", cmul="4m"):
     return form * 8.0 * 4096 * (2 * ncp * ntile + mp * nbp * nbp)
 
 
-# complex-multiply form of the FP64 ladder in the timed solves: the 3M form
-# (three real products per complex product in the integral build and the
-# contraction; same result up to rounding) is the faster one on MI355X
+# complex-multiply form of the FP64 ladder in the headline and the timed
+# solves: the 3M form (three real products per complex product in the
+# integral build and the contraction; same result up to rounding) is the
+# faster one on MI355X
 SOLVE_CMUL = "3m"
-TRAFFIC_PROFILE = "profiles/k_ppl_3m_fp64_o16_v160_nchol640_hbm_traffic.md"
+HEADLINE = "scale"
+TRAFFIC_PROFILE = "profiles/k_ppl_3m_fp64_o40_v480_nchol2400_hbm_traffic.md"
 TRAFFIC_SOURCES = ("paper_2604_12914_amd/csrc/ppl_mfma.hip", "paper_2604_12914_amd/csrc/internal.hpp")
 
 
 def measured_traffic():
-    """HBM bytes per launch of the fused FP64 kernel from the committed
+    """HBM bytes per launch of the headline kernel from the committed
     FETCH_SIZE / WRITE_SIZE counter summary, or None when the kernel sources
     have changed since the counters were taken (their hash differs)."""
     import hashlib
@@ -85,18 +113,77 @@ def measured_traffic():
     return float(fields["traffic_bytes_per_launch"])
 
 
+def stats(xs):
+    xs = sorted(xs)
+    return {"median": round(xs[len(xs) // 2], 4), "min": round(xs[0], 4),
+            "max": round(xs[-1], 4), "n": len(xs)}
+
+
+def gpu_inputs(torch, o, v, nchol, nrhs, seed=0, dtype=None):
+    """Synthetic inputs of lrcc_synth's distribution drawn on the GPU (for
+    timing only; the parity tests use lrcc_synth's NumPy draws): Hermitian
+    L^P = (G + G^H)/2 exp(-P/16), G ~ CN(0, 1); packed X ~ CN(0, 1)."""
+    dtype = dtype or torch.complex128
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    L = torch.randn((nchol, v, v), dtype=torch.complex128, device="cuda", generator=g)
+    L = 0.5 * (L + L.transpose(1, 2).conj())
+    L *= torch.exp(-torch.arange(nchol, device="cuda", dtype=torch.float64) / 16.0)[:, None, None]
+    L = L.to(dtype).contiguous()
+    X = torch.randn((nrhs, npairs(o), npairs(v)), dtype=torch.complex128, device="cuda",
+                    generator=g).to(dtype).contiguous()
+    torch.cuda.synchronize()
+    return L, X
+
+
+def time_sigma(lrcc, torch, L, X, prec, cmul, reps, warmup=1):
+    """Kernel (HIP events on the launch stream, via the library's timer) and
+    call times of `reps` ladder applications after `warmup` untimed ones."""
+    s = None
+    for _ in range(warmup):
+        s = lrcc.ppl_sigma(L, X, prec=prec, cmul=cmul, out=s)
+    torch.cuda.synchronize()
+    kms, cms = [], []
+    for _ in range(reps):
+        lrcc.set_timing(True)
+        t0 = time.perf_counter()
+        s = lrcc.ppl_sigma(L, X, prec=prec, cmul=cmul, out=s)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        km, kn = lrcc.get_timing()
+        lrcc.set_timing(False)
+        kms.append(km / max(kn, 1))
+        cms.append((t1 - t0) * 1e3)
+    return kms, cms
+
+
+def sigma_extra(lrcc, torch, o, v, nchol, nrhs, prec, cmul, L, X, reps):
+    kms, cms = time_sigma(lrcc, torch, L, X, prec, cmul, reps)
+    km = sorted(kms)[len(kms) // 2]
+    A = alg_flops(o, v, nchol, nrhs, cmul)
+    return {
+        "kernel_ms": stats(kms), "call_ms": stats(cms),
+        "tflops_alg_kernel": round(A / (km * 1e-3) / 1e12, 2),
+        "frac_alg": round(A / (km * 1e-3) / 1e12 / PEAK[prec], 4),
+        "issued_frac": round(issued_flops(o, v, nchol, nrhs, prec, cmul)
+                             / (km * 1e-3) / 1e12 / PEAK[prec], 4),
+        "effective_tflops": round(flops_per_sigma(o, v, nchol, nrhs) / (km * 1e-3) / 1e12, 2),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the per-precision extras")
+    ap.add_argument("--no-extra", action="store_true", help="skip the extras")
     ap.add_argument("--profile-sigma", choices=("fp64", "fp32", "bf16x3"), default=None,
                     help="only run --warmup + --steps ladder applications of this precision "
                          "(for profilers) and print their kernel time")
     ap.add_argument("--cmul", choices=("4m", "3m"), default="4m",
                     help="complex form of --profile-sigma's ladder (FP64 / FP32)")
+    ap.add_argument("--c64", action="store_true", help="complex64 storage for --profile-sigma")
     ap.add_argument("--profile-batched", action="store_true",
                     help="only run the batched FP64 solve of the eight uneven instances once "
                          "(for profilers)")
@@ -106,8 +193,11 @@ def main():
                     help="only run an FP64 solve with both ladders and the ring term, "
                          "--warmup + --steps ring applications and one pivoted Cholesky "
                          "decomposition (for profilers)")
+    ap.add_argument("--profile-grad", action="store_true",
+                    help="only run --warmup + --steps gradients with respect to L (for "
+                         "profilers)")
     ap.add_argument("--workload", choices=("baseline", "precision", "scale"), default="baseline",
-                    help="shape for --profile-sigma / --profile-fns")
+                    help="shape for --profile-sigma / --profile-fns / --profile-grad")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (a plain copy kernel of known "
                          "size, to scale HBM byte counters)")
@@ -129,8 +219,18 @@ def main():
         sys.exit(1)
     lrcc.lib()  # fails loudly if liblrcc.so is missing
 
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.profile_sigma:
         profile_sigma(lrcc, torch, np, S, args)
+        return
+    if args.profile_grad:
+        profile_grad(lrcc, torch, np, S, args)
         return
     if args.profile_batched:
         profile_batched(lrcc, torch, np, S, args)
@@ -144,48 +244,35 @@ def main():
                                    args.steps)), flush=True)
         return
 
-    cfg = S.CONFIGS["baseline"]
-    o, v, nchol = cfg.o, cfg.v, cfg.nchol
-    omegas = list(cfg.omegas)
-    nrhs = cfg.nrhs
-    inst = S.make_instance(o, v, nchol, ncomp=cfg.ncomp, seed=cfg.seed,
-                           gamma=S.solve_gamma(v))
-    eps = torch.from_numpy(inst.eps).cuda()
-    L = torch.from_numpy(inst.L).cuda()
-    mu = torch.from_numpy(inst.mu).cuda()
-    F = flops_per_sigma(o, v, nchol, nrhs)
-
-    if args.copy_calibration:
-        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
-        src.fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    # ---- timed region: K full FP64 solves ---------------------------------
+    # ---- timed region: K FP64 ladder applications at the scale workload --
+    cfg = S.CONFIGS[HEADLINE]
+    o, v, nchol, nrhs = cfg.o, cfg.v, cfg.nchol, cfg.nrhs
+    L, X = gpu_inputs(torch, o, v, nchol, nrhs)
+    A = alg_flops(o, v, nchol, nrhs, SOLVE_CMUL)
+    s = None
     for _ in range(args.warmup):
-        alpha64, info = lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL)
+        s = lrcc.ppl_sigma(L, X, prec="fp64", cmul=SOLVE_CMUL, out=s)
     torch.cuda.synchronize()
     lrcc.set_timing(True)
-    n_sigma = 0
+    step_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        alpha64, info = lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL)
-        n_sigma += info["n_sigma_fp64"]
+        ts = time.perf_counter()
+        s = lrcc.ppl_sigma(L, X, prec="fp64", cmul=SOLVE_CMUL, out=s)
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kms, nlaunch = lrcc.get_timing()
     lrcc.set_timing(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
-    value = n_sigma * F / (t1 - t0) / 1e12
     k_avg = kms / max(nlaunch, 1)
-    achieved = F / (k_avg * 1e-3) / 1e12
+    achieved = A / (k_avg * 1e-3) / 1e12
     issued = issued_flops(o, v, nchol, nrhs, "fp64", SOLVE_CMUL) / (k_avg * 1e-3) / 1e12
-
+    effective = flops_per_sigma(o, v, nchol, nrhs) / (k_avg * 1e-3) / 1e12
     out = {
-        "metric": "PPL A*X TFLOP/s FP64 vs split-prec; LR solve time at |d alpha|<1e-5 a.u.",
-        "value": round(value, 3),
+        "metric": METRIC,
+        "value": round(A * args.steps / (t1 - t0) / 1e12, 3),
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -197,12 +284,14 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "FP64 LR solve, o=16 v=160 Nchol=640, 3 dipole components x "
-                        "omega {0, 0.0656} = 6 RHS, Jacobi+DIIS to relative residual 1e-8, "
-                        f"{SOLVE_CMUL.upper()} complex products in the FP64 ladder",
+            "workload": "FP64 PPL ladder sigma = PPL(L, X) at the scale workload o=40 v=480 "
+                        "Nchol=2400, 1 RHS, complex128, Hermitian L, 3M complex products",
             "o": o, "v": v, "nchol": nchol, "nrhs": nrhs,
-            "sigma_per_step": n_sigma / args.steps,
-            "flop_per_sigma": F,
+            "flop_per_step_alg": A,
+            "flop_per_step_4m_unhalved": flops_per_sigma(o, v, nchol, nrhs),
+            "step_ms": stats(step_ms),
+            "effective_tflops": round(flops_per_sigma(o, v, nchol, nrhs) * args.steps
+                                      / (t1 - t0) / 1e12, 3),
         },
         "roofline": {
             "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"],
@@ -214,135 +303,298 @@ def main():
                       "eight waves)",
             "kernel_ms_avg": round(k_avg, 4), "launches": nlaunch,
             "issued_tflops": round(issued, 3), "issued_frac": round(issued / PEAK["fp64"], 4),
-            "note": "achieved counts the algorithmic 4M flops without symmetry savings; the "
-                    "kernel builds one integral tile per Hermitian pair, so achieved can "
-                    "exceed the issued rate; issued_frac is the matrix-core utilisation",
+            "effective_tflops": round(effective, 3),
+            "note": "achieved = the method's 3M work with the Hermitian halving, no padding "
+                    "(6 (npv (npv+1) Nchol + nrhs npo npv^2) flop) per kernel launch / HIP-event "
+                    "kernel time; issued adds the padding the kernel computes (dead slots of "
+                    "diagonal block pairs, rows padded to 16, matching "
+                    "SQ_INSTS_VALU_MFMA_MOPS_F64); effective_tflops is the 4M count without "
+                    "symmetry savings over the same time",
         },
     }
-
-    # ---- extras: ladder-only rates, split-precision solve ------------------
+    del s
     if not args.no_extra:
-        extra = {}
-        X = torch.from_numpy(S.make_packed(np.random.default_rng(3), nrhs, o, v)).cuda()
-        Lraw = torch.from_numpy(S.make_L(np.random.default_rng(4), nchol, v)).cuda()
-        for prec, cmul in (("fp64", "4m"), ("fp64", "3m"), ("fp32", "4m"), ("fp32", "3m"),
-                           ("bf16x3", "4m")):
-            try:
-                tune = lrcc.autotune(o, v, nchol, nrhs, prec=prec, cmul=cmul)
-                s = lrcc.ppl_sigma(Lraw, X, prec=prec, cmul=cmul)
-                torch.cuda.synchronize()
-                lrcc.set_timing(True)
-                ts = []
-                for _ in range(3):
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    e0.record()
-                    lrcc.ppl_sigma(Lraw, X, prec=prec, cmul=cmul, out=s)
-                    e1.record()
-                    torch.cuda.synchronize()
-                    ts.append(e0.elapsed_time(e1))
-                km, kn = lrcc.get_timing()
-                lrcc.set_timing(False)
-                extra[f"sigma_{prec}_{cmul}"] = {
-                    "tuned": {"supertile": tune["supertile"], "occupancy": tune["occupancy"]},
-                    "call_ms": round(min(ts), 3),
-                    "kernel_ms": round(km / kn, 3),
-                    "tflops_call": round(F / (min(ts) * 1e-3) / 1e12, 2),
-                    "tflops_kernel": round(F / (km / kn * 1e-3) / 1e12, 2),
-                    "frac_peak": round(F / (km / kn * 1e-3) / 1e12 / PEAK[prec], 4),
-                    "issued_frac": round(issued_flops(o, v, nchol, nrhs, prec, cmul)
-                                         / (km / kn * 1e-3) / 1e12 / PEAK[prec], 4),
-                }
-            except lrcc.LrccError as e:
-                extra[f"sigma_{prec}_{cmul}"] = {"error": str(e)}
-        exact = golden_alpha()
-        for name, kw in (("fp32_ir", dict(prec="fp32")), ("bf16x3_ir", dict(prec="bf16x3"))):
-            try:
-                lrcc.solve(eps, L, mu, omegas, tol=1e-8, **kw)
+        out["extra"] = extras(lrcc, torch, np, S, L, X, args)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(L, X, o, v, A)
+    print(json.dumps(out), flush=True)
+
+
+def extras(lrcc, torch, np, S, Lscale, Xscale, args):
+    extra = {}
+    c5 = S.CONFIGS["scale"]
+    # ---- the ladder at the scale workload per precision ------------------
+    try:
+        # (the FP64 3M ladder is the headline itself: config.step_ms)
+        sc = {"fp64_4m": sigma_extra(lrcc, torch, c5.o, c5.v, c5.nchol, c5.nrhs, "fp64", "4m",
+                                     Lscale, Xscale, 3)}
+        L64, X64 = Lscale.to(torch.complex64), Xscale.to(torch.complex64)
+        sc["fp32_4m_c64"] = sigma_extra(lrcc, torch, c5.o, c5.v, c5.nchol, c5.nrhs, "fp32",
+                                        "4m", L64, X64, 5)
+        sc["bf16x3_4m_c64"] = sigma_extra(lrcc, torch, c5.o, c5.v, c5.nchol, c5.nrhs,
+                                          "bf16x3", "4m", L64, X64, 5)
+        del L64, X64
+        extra["sigma_scale"] = sc
+    except lrcc.LrccError as e:
+        extra["sigma_scale"] = {"error": str(e)}
+    torch.cuda.empty_cache()
+
+    # ---- baseline workload: ladder per precision, 20 repetitions ---------
+    cfg = S.CONFIGS["baseline"]
+    o, v, nchol, nrhs = cfg.o, cfg.v, cfg.nchol, cfg.nrhs
+    omegas = list(cfg.omegas)
+    X = torch.from_numpy(S.make_packed(np.random.default_rng(3), nrhs, o, v)).cuda()
+    Lraw = torch.from_numpy(S.make_L(np.random.default_rng(4), nchol, v)).cuda()
+    sb = {}
+    for prec, cmul in (("fp64", "4m"), ("fp64", "3m"), ("fp32", "4m"), ("fp32", "3m"),
+                       ("bf16x3", "4m")):
+        try:
+            tune = lrcc.autotune(o, v, nchol, nrhs, prec=prec, cmul=cmul)
+            e = sigma_extra(lrcc, torch, o, v, nchol, nrhs, prec, cmul, Lraw, X, 20)
+            e["tuned"] = {"supertile": tune["supertile"], "occupancy": tune["occupancy"]}
+            sb[f"{prec}_{cmul}"] = e
+        except lrcc.LrccError as err:
+            sb[f"{prec}_{cmul}"] = {"error": str(err)}
+    extra["sigma_baseline"] = sb
+
+    # ---- baseline workload: solves ---------------------------------------
+    inst = S.make_instance(o, v, nchol, ncomp=cfg.ncomp, seed=cfg.seed, gamma=S.solve_gamma(v))
+    eps = torch.from_numpy(inst.eps).cuda()
+    L = torch.from_numpy(inst.L).cuda()
+    mu = torch.from_numpy(inst.mu).cuda()
+    exact = golden_alpha("baseline")
+    lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL)
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        alpha64, info = lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL)
+        ts.append((time.perf_counter() - t0) * 1e3)
+    ms64 = min(ts)
+    e = {"ms": stats(ts), "tol": 1e-8, "iters_max": info["iters_max"],
+         "n_sigma_fp64": info["n_sigma_fp64"], "final_relres": info["final_relres"],
+         "alpha_zz": [float(alpha64[w, 2, 2].real) for w in range(len(omegas))],
+         "tflops_alg": round(info["n_sigma_fp64"] * alg_flops(o, v, nchol, nrhs, SOLVE_CMUL)
+                             / (ms64 * 1e-3) / 1e12, 3)}
+    if exact is not None:
+        e["max_abs_dalpha_vs_exact"] = float(np.abs(alpha64 - exact).max())
+    extra["solve_baseline_fp64"] = e
+    for name, kw in (("fp32_ir", dict(prec="fp32")), ("bf16x3_ir", dict(prec="bf16x3"))):
+        try:
+            lrcc.solve(eps, L, mu, omegas, tol=1e-8, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            a_lp, inf_lp = lrcc.solve(eps, L, mu, omegas, tol=1e-8, **kw)
+            t1 = time.perf_counter()
+            e = {"tol": 1e-8, "ms": round((t1 - t0) * 1e3, 3),
+                 "speedup_vs_fp64": round(ms64 / ((t1 - t0) * 1e3), 3),
+                 "max_abs_dalpha_vs_fp64_solve": float(np.abs(a_lp - alpha64).max()),
+                 "n_sigma_fp64": inf_lp["n_sigma_fp64"], "n_sigma_lowp": inf_lp["n_sigma_lowp"],
+                 "final_relres_fp64": inf_lp["final_relres"]}
+            if exact is not None:
+                e["max_abs_dalpha_vs_exact"] = float(np.abs(a_lp - exact).max())
+            extra[f"solve_baseline_{name}"] = e
+        except lrcc.LrccError as err:
+            extra[f"solve_baseline_{name}"] = {"error": str(err)}
+    if exact is not None:
+        extra["solve_time_at_dalpha_1e-5_baseline"] = dalpha_sweep(
+            lrcc, torch, np, eps, L, mu, omegas, exact, full=True)
+    # full response function (right- and left-hand solves, Sec. 2.2): for
+    # this Hermitian operator it must equal alpha(w) + conj alpha(-w)
+    try:
+        t0 = time.perf_counter()
+        a_full, inf_full = lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL,
+                                      response="full")
+        t1 = time.perf_counter()
+        a_minus, _ = lrcc.solve(eps, L, mu, [-w for w in omegas], tol=1e-8, cmul=SOLVE_CMUL)
+        extra["solve_baseline_fp64_full_response"] = {
+            "ms": round((t1 - t0) * 1e3, 3), "n_sigma_fp64": inf_full["n_sigma_fp64"],
+            "alpha_zz": [float(a_full[w, 2, 2].real) for w in range(len(omegas))],
+            "max_abs_diff_vs_alpha_w_plus_conj_alpha_minus_w":
+                float(np.abs(a_full - (alpha64 + np.conj(a_minus))).max())}
+    except lrcc.LrccError as err:
+        extra["solve_baseline_fp64_full_response"] = {"error": str(err)}
+    # the whole doubles-doubles Jacobian of the model: both ladders and the
+    # ring term (FP64), same L, eps and mu, extra vectors drawn after them
+    try:
+        fj = S.make_instance(o, v, nchol, ncomp=cfg.ncomp, seed=cfg.seed,
+                             gamma=S.solve_gamma(v), ring=True)
+        kw = {k: torch.from_numpy(getattr(fj, a)).cuda()
+              for k, a in (("Loo", "Loo"), ("Lov", "Lov"), ("Lvo", "Lvo"))}
+        lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a_fj, i_fj = lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Xr = torch.from_numpy(S.make_packed(np.random.default_rng(1), nrhs, o, v)).cuda()
+        lrcc.ring_sigma(kw["Loo"], kw["Lov"], kw["Lvo"], L, Xr)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        lrcc.ring_sigma(kw["Loo"], kw["Lov"], kw["Lvo"], L, Xr)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        ov = o * v
+        ring_flop = 8.0 * (nrhs * ov ** 3 + 2.0 * ov * ov * nchol)  # X M, and forming M
+        extra["solve_baseline_fp64_pp_hh_ring"] = {
+            "ms": round((t1 - t0) * 1e3, 3), "iters_max": i_fj["iters_max"],
+            "n_sigma_fp64": i_fj["n_sigma_fp64"],
+            "alpha_zz": [float(a_fj[w, 2, 2].real) for w in range(len(omegas))],
+            "ring_sigma_ms_6rhs": round((t3 - t2) * 1e3, 3),
+            "ring_sigma_tflops": round(ring_flop / (t3 - t2) / 1e12, 2),
+            "ring_sigma_frac_fp64_peak": round(ring_flop / (t3 - t2) / 1e12 / PEAK["fp64"], 3)}
+    except lrcc.LrccError as err:
+        extra["solve_baseline_fp64_pp_hh_ring"] = {"error": str(err)}
+    # FNS++ virtual basis at the workload's shapes (Sec. 2.4)
+    try:
+        extra["fns_plus"] = fns_bench(lrcc, torch, np, S, o, v, nchol, 1, 3, solve=True)
+    except lrcc.LrccError as err:
+        extra["fns_plus"] = {"error": str(err)}
+    del L, Lraw, X
+    torch.cuda.empty_cache()
+
+    # ---- precision workload: alpha error per frequency -------------------
+    try:
+        extra["precision_study"] = precision_study(lrcc, torch, np, S)
+    except lrcc.LrccError as err:
+        extra["precision_study"] = {"error": str(err)}
+    return extra
+
+
+def precision_study(lrcc, torch, np, S):
+    """o=24, v=256, Nchol=1024, z at four frequencies: |d alpha| per
+    frequency against the oracle's exact alpha for the FP64 solve and the
+    refined FP32 / bf16x3 solves to a relative FP64 residual of 1e-8, and
+    each method's time to |d alpha| < 1e-5 a.u."""
+    cfg = S.CONFIGS["precision"]
+    o, v, nchol = cfg.o, cfg.v, cfg.nchol
+    omegas = list(cfg.omegas)
+    exact = golden_alpha("precision")
+    inst = S.make_instance(o, v, nchol, ncomp=cfg.ncomp, seed=cfg.seed, gamma=S.solve_gamma(v))
+    eps = torch.from_numpy(inst.eps).cuda()
+    L = torch.from_numpy(inst.L).cuda()
+    mu = torch.from_numpy(inst.mu).cuda()
+    out = {"workload": f"o={o} v={v} nchol={nchol}, z, omega {omegas}",
+           "exact": "tests/golden/alpha_exact.json 'precision' (FP64 oracle, Jacobi + DIIS "
+                    "to 1e-11)" if exact is not None else None}
+    for name, kw in (("fp64", dict(prec="fp64", cmul=SOLVE_CMUL)),
+                     ("fp32_ir", dict(prec="fp32")), ("bf16x3_ir", dict(prec="bf16x3"))):
+        lrcc.solve(eps, L, mu, omegas, tol=1e-8, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a, info = lrcc.solve(eps, L, mu, omegas, tol=1e-8, **kw)
+        t1 = time.perf_counter()
+        e = {"ms": round((t1 - t0) * 1e3, 3), "n_sigma_fp64": info["n_sigma_fp64"],
+             "n_sigma_lowp": info["n_sigma_lowp"], "final_relres_fp64": info["final_relres"],
+             "alpha": [float(a[w, 0, 0].real) for w in range(len(omegas))]}
+        if exact is not None:
+            err = np.abs(a - exact)[:, 0, 0]
+            e["abs_dalpha_per_omega"] = [float(x) for x in err]
+            e["rel_dalpha_per_omega"] = [float(x) for x in err / np.abs(exact[:, 0, 0])]
+        out[f"solve_{name}_tol1e-8"] = e
+    if exact is not None:
+        out["solve_time_at_dalpha_1e-5"] = dalpha_sweep(lrcc, torch, np, eps, L, mu, omegas,
+                                                        exact, full=False)
+    return out
+
+
+def dalpha_sweep(lrcc, torch, np, eps, L, mu, omegas, exact, target=1e-5, full=True):
+    """For each method, the fastest solve whose alpha is within `target` a.u.
+    of the exact alpha: tolerances are tried from the loosest down; the first
+    one that meets the target is timed (best of three calls, the trial call
+    included).  Refinement runs its inner solve to the outer tolerance or a
+    third of it and keeps the faster; with full=True every method also tries
+    both complex forms of its FP64 / FP32 ladders (bf16x3 is always 4M).
+    Every refined solve reports the FP64 residual of its result, and
+    n_sigma_fp64 counts the FP64 ladders it took."""
+    methods = {
+        "fp64": (dict(prec="fp64"), ("4m", "3m") if full else (SOLVE_CMUL,)),
+        "bf16x3_ir": (dict(prec="bf16x3"), ("4m",)),
+        "fp32_ir": (dict(prec="fp32"), ("4m", "3m") if full else ("4m",)),
+    }
+    if full:
+        methods["bf16x3_ir_fp32_anchor"] = (dict(prec="bf16x3", anchor_prec="fp32"), ("4m",))
+    out = {"target_abs_dalpha": target}
+    for name, (kw, cmuls) in methods.items():
+        res = None
+        refine = kw["prec"] != "fp64"
+        for cmul, ratio in [(c, r) for c in cmuls for r in ((1.0, 1.0 / 3.0) if refine else (1.0,))]:
+            for tol in (1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 1e-7, 1e-8):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                a_lp, inf_lp = lrcc.solve(eps, L, mu, omegas, tol=1e-8, **kw)
-                t1 = time.perf_counter()
-                e = {
-                    "tol": 1e-8,
-                    "ms": round((t1 - t0) * 1e3, 3),
-                    "speedup_vs_fp64": round(ms_step / ((t1 - t0) * 1e3), 3),
-                    "max_abs_dalpha_vs_fp64_solve": float(np.abs(a_lp - alpha64).max()),
-                    "n_sigma_fp64": inf_lp["n_sigma_fp64"],
-                    "n_sigma_lowp": inf_lp["n_sigma_lowp"],
-                }
-                if exact is not None:
-                    e["max_abs_dalpha_vs_exact"] = float(np.abs(a_lp - exact).max())
-                extra[f"solve_{name}"] = e
-            except lrcc.LrccError as err:
-                extra[f"solve_{name}"] = {"error": str(err)}
-        if exact is not None:
-            extra["solve_time_at_dalpha_1e-5"] = dalpha_sweep(lrcc, torch, np, eps, L, mu,
-                                                              omegas, exact)
-        # full response function (right- and left-hand solves, Sec. 2.2): for
-        # this Hermitian operator it must equal alpha(w) + conj alpha(-w)
-        try:
-            t0 = time.perf_counter()
-            a_full, inf_full = lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL,
-                                          response="full")
-            t1 = time.perf_counter()
-            a_minus, _ = lrcc.solve(eps, L, mu, [-w for w in omegas], tol=1e-8, cmul=SOLVE_CMUL)
-            extra["solve_fp64_full_response"] = {
-                "ms": round((t1 - t0) * 1e3, 3), "n_sigma_fp64": inf_full["n_sigma_fp64"],
-                "alpha_zz": [float(a_full[w, 2, 2].real) for w in range(len(omegas))],
-                "max_abs_diff_vs_alpha_w_plus_conj_alpha_minus_w":
-                    float(np.abs(a_full - (alpha64 + np.conj(a_minus))).max())}
-        except lrcc.LrccError as err:
-            extra["solve_fp64_full_response"] = {"error": str(err)}
-        extra["solve_fp64"] = {"ms": round(ms_step, 3), "iters_max": info["iters_max"],
-                               "alpha_zz": [float(alpha64[w, 2, 2].real)
-                                            for w in range(len(omegas))]}
-        if exact is not None:
-            extra["solve_fp64"]["max_abs_dalpha_vs_exact"] = float(np.abs(alpha64 - exact).max())
-        # the whole doubles-doubles Jacobian of the model: both ladders and the
-        # ring term (FP64), same L, eps and mu, extra vectors drawn after them
-        try:
-            fj = S.make_instance(o, v, nchol, ncomp=cfg.ncomp, seed=cfg.seed,
-                                 gamma=S.solve_gamma(v), ring=True)
-            kw = {k: torch.from_numpy(getattr(fj, a)).cuda()
-                  for k, a in (("Loo", "Loo"), ("Lov", "Lov"), ("Lvo", "Lvo"))}
-            lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL, **kw)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            a_fj, i_fj = lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL, **kw)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            Xr = torch.from_numpy(S.make_packed(np.random.default_rng(1), nrhs, o, v)).cuda()
-            Lvv = L
-            lrcc.ring_sigma(kw["Loo"], kw["Lov"], kw["Lvo"], Lvv, Xr)
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            lrcc.ring_sigma(kw["Loo"], kw["Lov"], kw["Lvo"], Lvv, Xr)
-            torch.cuda.synchronize()
-            t3 = time.perf_counter()
-            ov = o * v
-            ring_flop = 8.0 * (nrhs * ov ** 3 + 2.0 * ov * ov * nchol)  # X M, and forming M
-            extra["solve_fp64_pp_hh_ring"] = {
-                "ms": round((t1 - t0) * 1e3, 3), "iters_max": i_fj["iters_max"],
-                "n_sigma_fp64": i_fj["n_sigma_fp64"],
-                "alpha_zz": [float(a_fj[w, 2, 2].real) for w in range(len(omegas))],
-                "ring_sigma_ms_6rhs": round((t3 - t2) * 1e3, 3),
-                "ring_sigma_tflops": round(ring_flop / (t3 - t2) / 1e12, 2),
-                "ring_sigma_frac_fp64_peak": round(ring_flop / (t3 - t2) / 1e12 / PEAK["fp64"], 3)}
-        except lrcc.LrccError as err:
-            extra["solve_fp64_pp_hh_ring"] = {"error": str(err)}
-        # FNS++ virtual basis at the workload's shapes (Sec. 2.4)
-        try:
-            extra["fns_plus"] = fns_bench(lrcc, torch, np, S, o, v, nchol, 1, 3, solve=True)
-        except lrcc.LrccError as err:
-            extra["fns_plus"] = {"error": str(err)}
-        out["extra"] = extra
+                a, info = lrcc.solve(eps, L, mu, omegas, tol=tol, inner_tol=tol * ratio,
+                                     check=False, cmul=cmul, **kw)
+                ms = (time.perf_counter() - t0) * 1e3
+                err = float(np.abs(a - exact).max())
+                if info["status"] == "LRCC_OK" and err < target:
+                    for _ in range(2):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        a, info = lrcc.solve(eps, L, mu, omegas, tol=tol,
+                                             inner_tol=tol * ratio, check=False, cmul=cmul,
+                                             **kw)
+                        ms = min(ms, (time.perf_counter() - t0) * 1e3)
+                    if res is None or ms < res["ms"]:
+                        res = {"tol": tol, "inner_tol": tol * ratio, "cmul": cmul,
+                               "ms": round(ms, 3),
+                               "max_abs_dalpha_vs_exact": float(np.abs(a - exact).max()),
+                               "n_sigma_fp64": info["n_sigma_fp64"],
+                               "n_sigma_lowp": info["n_sigma_lowp"],
+                               "final_relres_fp64": info["final_relres"]}
+                    break
+        out[name] = res
+    if out.get("fp64"):
+        for name in methods:
+            if name != "fp64" and out.get(name):
+                out[name]["speedup_vs_fp64"] = round(out["fp64"]["ms"] / out[name]["ms"], 3)
+    return out
 
-    # ---- CPU oracle on a bounded share of one ladder application ----------
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(inst.L, o, v, nchol, nrhs, F)
 
-    print(json.dumps(out), flush=True)
+def golden_alpha(name):
+    """Exact alpha of a workload from tests/golden (written by the oracle)."""
+    import numpy as np
+    p = os.path.join(ROOT, "tests", "golden", "alpha_exact.json")
+    try:
+        g = json.load(open(p))[name]
+    except (OSError, KeyError, ValueError):
+        return None
+    return np.array(g["alpha_re"]) + 1j * np.array(g["alpha_im"])
+
+
+def cpu_baseline(Ld, Xd, o, v, F, budget_s=12.0):
+    """Time the FP64 oracle's definition-route sigma on the headline inputs,
+    rows a = 0, 1, ... until ~budget_s has passed (at least one row), and
+    scale by the row count: the oracle builds <ab|cd> for all b, c, d and
+    contracts all rows for every a, so each of its v - 1 rows costs the
+    same.  Reported in the headline's unit (its algorithmic flops per
+    second)."""
+    import numpy as np
+
+    from oracle import ppl
+
+    L = Ld.cpu().numpy()
+    X = Xd.cpu().numpy()
+    t0 = time.perf_counter()
+    a = 0
+    while a < v - 1 and (a == 0 or time.perf_counter() - t0 < budget_s):
+        ppl.sigma(L, X, o, v, a_range=(a, a + 1))
+        a += 1
+    dt = time.perf_counter() - t0
+    t_full = dt * (v - 1) / a
+    blas, threads = "unknown", os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        info = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        if info:
+            threads = max(p.get("num_threads", 1) for p in info)
+            blas = ", ".join(f"{p.get('internal_api')} {p.get('version')}" for p in info)
+    except Exception:
+        pass
+    return {"value": round(F / t_full / 1e12, 6), "unit": "TFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "blas": blas, "host_cpus": os.cpu_count(),
+            "sample": f"rows a=0..{a - 1} of {v - 1} of one FP64 ladder application at o={o} "
+                      f"v={v} Nchol={L.shape[0]} nrhs={X.shape[0]} ({dt:.1f} s), scaled by the "
+                      f"row count to {t_full:.0f} s"}
 
 
 def fns_bench(lrcc, torch, np, S, o, v, nchol, warmup, reps, thr=1e-5, omega=0.0656,
@@ -493,8 +745,8 @@ def profile_sigma(lrcc, torch, np, S, args):
     cfg = S.CONFIGS[args.workload]
     o, v, nchol, nrhs = cfg.o, cfg.v, cfg.nchol, cfg.nrhs
     cmul = args.cmul if args.profile_sigma != "bf16x3" else "4m"
-    L = torch.from_numpy(S.make_L(np.random.default_rng(4), nchol, v)).cuda()
-    X = torch.from_numpy(S.make_packed(np.random.default_rng(3), nrhs, o, v)).cuda()
+    L, X = gpu_inputs(torch, o, v, nchol, nrhs,
+                      dtype=torch.complex64 if args.c64 else torch.complex128)
     s = None
     for _ in range(max(args.warmup, 1)):
         s = lrcc.ppl_sigma(L, X, prec=args.profile_sigma, cmul=cmul)
@@ -506,102 +758,39 @@ def profile_sigma(lrcc, torch, np, S, args):
     lrcc.set_timing(False)
     F = flops_per_sigma(o, v, nchol, nrhs)
     print(json.dumps({"profile_sigma": args.profile_sigma, "cmul": cmul,
-                      "workload": args.workload,
+                      "workload": args.workload, "c64": bool(args.c64),
                       "o": o, "v": v, "nchol": nchol, "nrhs": nrhs,
                       "ladder_ms": round(ms / max(n, 1), 4), "launches": n,
                       "tflops_algorithmic": round(F / (ms / max(n, 1) * 1e-3) / 1e12, 2)}),
           flush=True)
 
 
-def dalpha_sweep(lrcc, torch, np, eps, L, mu, omegas, exact, target=1e-5):
-    """For each method, the fastest solve whose alpha is within `target` a.u.
-    of the exact alpha: tolerances are tried from the loosest down, and the
-    first one that meets the target is timed (best of three calls after one
-    untimed run).  Each method runs with both complex-multiply forms of its
-    FP64 / FP32 ladders (bf16x3 is always 4M) and keeps the faster."""
-    methods = {
-        "fp64": dict(prec="fp64"),
-        "bf16x3_ir_fp64_anchor": dict(prec="bf16x3"),
-        "bf16x3_ir_fp32_anchor": dict(prec="bf16x3", anchor_prec="fp32"),
-        "fp32_ir_fp64_anchor": dict(prec="fp32"),
-    }
-    out = {"target_abs_dalpha": target}
-    for name, kw in methods.items():
-        res = None
-        # refinement: the inner solve stops at the outer tolerance or a little
-        # below it (fewer inner iterations against fewer outer sweeps); each
-        # choice is timed at its loosest tolerance that meets the target
-        refine = kw.get("prec", "fp64") != "fp64"
-        for cmul, ratio in [(c, r) for c in ("4m", "3m")
-                            for r in ((1.0, 1.0 / 3.0) if refine else (1.0,))]:
-            for tol in (1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 1e-7, 1e-8):
-                a, info = lrcc.solve(eps, L, mu, omegas, tol=tol, inner_tol=tol * ratio,
-                                     check=False, cmul=cmul, **kw)
-                err = float(np.abs(a - exact).max())
-                if info["status"] == "LRCC_OK" and err < target:
-                    ms = 1e300
-                    for _ in range(3):  # best of three timed calls
-                        torch.cuda.synchronize()
-                        t0 = time.perf_counter()
-                        a, info = lrcc.solve(eps, L, mu, omegas, tol=tol,
-                                             inner_tol=tol * ratio, check=False, cmul=cmul,
-                                             **kw)
-                        t1 = time.perf_counter()
-                        ms = min(ms, round((t1 - t0) * 1e3, 3))
-                    if res is None or ms < res["ms"]:
-                        res = {"tol": tol, "inner_tol": tol * ratio, "cmul": cmul, "ms": ms,
-                               "max_abs_dalpha_vs_exact": float(np.abs(a - exact).max()),
-                               "n_sigma_fp64": info["n_sigma_fp64"],
-                               "n_sigma_lowp": info["n_sigma_lowp"]}
-                    break
-        out[name] = res
-    if out.get("fp64"):
-        for name in methods:
-            if name != "fp64" and out.get(name):
-                out[name]["speedup_vs_fp64"] = round(out["fp64"]["ms"] / out[name]["ms"], 3)
-    return out
 
 
-def golden_alpha():
-    """Exact alpha of this workload from tests/golden (written by the oracle)."""
-    import numpy as np
-    p = os.path.join(ROOT, "tests", "golden", "alpha_exact.json")
-    try:
-        g = json.load(open(p))["baseline"]
-    except (OSError, KeyError, ValueError):
-        return None
-    return np.array(g["alpha_re"]) + 1j * np.array(g["alpha_im"])
-
-
-def cpu_baseline(L, o, v, nchol, nrhs, F, budget_s=12.0):
-    """Time the FP64 oracle's definition-route sigma on rows a = 0, 1, ...
-    until ~budget_s has passed, and scale to the whole ladder application by
-    the work share of those rows (each row a costs in proportion to v-a-1)."""
-    import numpy as np
-
-    import lrcc_synth as S
-    from oracle import ppl
-
-    X = S.make_packed(np.random.default_rng(3), nrhs, o, v)
-    npv = v * (v - 1) // 2
+def profile_grad(lrcc, torch, np, S, args):
+    """Gradients with respect to L only (the dL kernel), for a profiler run:
+    one JSON line with the mean wall time per call."""
+    cfg = S.CONFIGS[args.workload]
+    o, v, nchol, nrhs = cfg.o, cfg.v, cfg.nchol, cfg.nrhs
+    dt = torch.complex64 if args.c64 else torch.complex128
+    L, X = gpu_inputs(torch, o, v, nchol, nrhs, dtype=dt)
+    G = torch.randn(X.shape, dtype=torch.complex128, device="cuda").to(dt)
+    for _ in range(max(args.warmup, 1)):
+        lrcc.ppl_sigma_adjoint(L, X, G, want_dX=False)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    a = 0
-    while a < v - 1 and time.perf_counter() - t0 < budget_s:
-        ppl.sigma(L, X, o, v, a_range=(a, a + 1))
-        a += 1
-    dt = time.perf_counter() - t0
-    share = sum(v - r - 1 for r in range(a)) / npv
-    t_full = dt / share
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count()
-    return {"value": round(F / t_full / 1e12, 5), "unit": "TFLOP/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"rows a=0..{a - 1} of one FP64 ladder application at o={o} v={v} "
-                      f"Nchol={nchol} nrhs={nrhs} ({100 * share:.1f}% of its work, "
-                      f"{dt:.1f} s), scaled by work share to {t_full:.1f} s"}
+    for _ in range(args.steps):
+        lrcc.ppl_sigma_adjoint(L, X, G, want_dX=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    npv = npairs(v)
+    # the gradient's work: every packed (ab), (cd) pair of R = sum_m conj(G) X
+    # (npv^2 M complex products) and its contraction with the Cholesky
+    # vectors (v^4 Nchol), 8 flops per complex multiply-accumulate
+    F = 8.0 * (float(npv) * npv * nrhs * npairs(o) + float(v) ** 4 * nchol)
+    print(json.dumps({"profile_grad": args.workload, "c64": bool(args.c64), "o": o, "v": v,
+                      "nchol": nchol, "nrhs": nrhs, "ms": round(ms, 3),
+                      "tflops_alg": round(F / (ms * 1e-3) / 1e12, 2)}), flush=True)
 
 
 if __name__ == "__main__":

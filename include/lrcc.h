@@ -222,15 +222,19 @@ typedef struct {
   double inner_tol;  /* reduced precision: inner relative tolerance (1e-5)   */
   int max_outer;     /* reduced precision: refinement sweeps (default 6)     */
   int deterministic; /* reserved; must be 0                                  */
-  int resid_fp64_every; /* reduced precision: 0 (default) = FP64 ladder of the
-                        iterate in the first sweep only, later sweeps update it
-                        by the reduced-precision ladder of the correction
-                        (the ladder is linear); 1 = FP64 ladder every sweep   */
+  int resid_fp64_every; /* reduced precision: 0 (default) = the stopping
+                        test's ladder of the iterate is a full FP64 ladder in
+                        the first sweep only, later sweeps update it by the
+                        reduced-precision ladder of the correction (the
+                        ladder is linear); 1 = a full FP64 ladder every sweep.
+                        Either way the reported residual is an FP64 one (see
+                        lrcc_solve_info.final_relres)                         */
   lrcc_prec anchor_prec; /* reduced precision: arithmetic of that full-iterate
-                        ladder: FP64 (default) or FP32 (then the residual is
-                        exact to FP32 ladder accuracy, about 1e-6 relative).
-                        Inside the solve an FP32 ladder sums its tile partials
-                        in FP32 too                                          */
+                        ladder: FP64 (default) or FP32 (a cheaper stopping
+                        test, exact to FP32 ladder accuracy, about 1e-6
+                        relative; the FP64 residual is then evaluated once
+                        more at the end).  Inside the solve an FP32 ladder
+                        sums its tile partials in FP32 too                   */
   int response;      /* 0 (default): alpha_xy(w) = -<xi_x | X_y(w)> from the
                         right-hand amplitudes only.  1: the full linear
                         response function of Sec. 2.2 (last equation): the
@@ -267,7 +271,13 @@ typedef struct {
   int iters_max;        /* most iterations any right-hand side took          */
   int n_sigma_fp64;     /* FP64 ladder applications                          */
   int n_sigma_lowp;     /* reduced-precision ladder applications             */
-  double final_relres;  /* largest final relative residual (FP64 residual)   */
+  double final_relres;  /* largest final relative residual |R|/|xi| of the
+                           returned amplitudes, R = -xi - (A - w) X with the
+                           ladder of X applied in FP64.  The FP64 solve's last
+                           iteration gives it; a refinement whose last stopping
+                           test was not a full FP64 ladder of X applies one
+                           more FP64 ladder at the end for it (counted in
+                           n_sigma_fp64), and its status follows that residual */
   double seconds;       /* wall time of the call                             */
 } lrcc_solve_info;
 

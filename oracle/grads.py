@@ -46,3 +46,21 @@ def vjp_L(L, X, G, o, v):
     for P in range(L.shape[0]):
         out[P] = 2.0 * np.einsum("mab,bd,mdc->ac", Gf, np.conj(L[P]), XH)
     return out
+
+
+def vjp_L_entries(L, X, G, v, ac_pairs):
+    """Lbar^P_ac for every P and the chosen (a, c), one pair at a time from
+    the definition above: Lbar^P_ac = 2 sum_m sum_{b,d} G_m[a,b]
+    conj(L^P_bd) conj(X_m[c,d]).  Row a of every G_m and row c of every X_m
+    are read straight from the packed arrays, so full-size checks need no
+    unpacked copy.  Returns ``[nchol, len(ac_pairs)]``."""
+    npv = X.shape[-1]
+    Gm, Xm = G.reshape(-1, npv), X.reshape(-1, npv)
+    Lc = np.conj(L).reshape(L.shape[0], v * v)
+    out = np.zeros((L.shape[0], len(ac_pairs)), dtype=np.complex128)
+    for k, (a, c) in enumerate(ac_pairs):
+        Ga = ppl.packed_row(Gm, v, a)                 # [M, v]: G_m[a, b]
+        Xc = ppl.packed_row(Xm, v, c)                 # [M, v]: X_m[c, d]
+        Q = Ga.T @ np.conj(Xc)                        # [b, d]: sum_m G_m[a,b] conj X_m[c,d]
+        out[:, k] = 2.0 * (Lc @ Q.reshape(v * v))
+    return out

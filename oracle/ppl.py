@@ -43,6 +43,19 @@ def pack(F: np.ndarray) -> np.ndarray:
     return F[..., p, q]
 
 
+def packed_row(Xp: np.ndarray, n: int, p: int) -> np.ndarray:
+    """Row p of the full antisymmetric matrix of every packed vector:
+    ``[..., n(n-1)/2]`` -> ``[..., n]`` with F[p, q] = X(p, q) for q > p,
+    -X(q, p) for q < p and 0 on the diagonal."""
+    out = np.zeros(Xp.shape[:-1] + (n,), dtype=Xp.dtype)
+    for q in range(n):
+        if q > p:
+            out[..., q] = Xp[..., p * (2 * n - p - 1) // 2 + (q - p - 1)]
+        elif q < p:
+            out[..., q] = -Xp[..., q * (2 * n - q - 1) // 2 + (p - q - 1)]
+    return out
+
+
 def unpack_doubles(X: np.ndarray, o: int, v: int) -> np.ndarray:
     """``[nrhs, npo, npv]`` -> ``[nrhs, o, o, v, v]`` antisymmetric in both."""
     Xv = unpack(X, v)                       # [nrhs, npo, v, v]

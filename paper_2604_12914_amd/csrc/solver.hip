@@ -913,6 +913,30 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
     LRCC_HIP(h, hipMemcpyAsync(S.rk, S.b, vb, hipMemcpyDeviceToDevice, h->stream));
     std::vector<int> act(S.n, 1);
     std::vector<double> rel(S.n, 1.0);
+    // rk = b - (D - w) x2 - sx for the RHS flagged in `flags`; their relative
+    // residual norms into rel
+    auto outer_residual = [&](const std::vector<int>& flags) -> lrcc_status {
+      hipLaunchKernelGGL(k_outer, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.eps, S.omega,
+                         S.tab, S.otab, S.active, S.b, S.x2, S.sx, S.rk, S.part);
+      LRCC_HIP(h, hipGetLastError());
+      LRCC_HIP(h, hipMemcpyAsync(S.h_part, S.part, (size_t)S.n * S.nchunk * sizeof(double2),
+                                 hipMemcpyDeviceToHost, h->stream));
+      LRCC_HIP(h, hipStreamSynchronize(h->stream));
+      for (int r = 0; r < S.n; ++r) {
+        if (!flags[r]) continue;
+        double rr = 0, bb = 0;
+        for (int c = 0; c < S.nchunk; ++c) {
+          rr += S.h_part[(size_t)r * S.nchunk + c].x;
+          bb += S.h_part[(size_t)r * S.nchunk + c].y;
+        }
+        rel[r] = std::sqrt(rr / bb);
+        if (!std::isfinite(rel[r])) return fail(h, LRCC_ERR_NONFINITE, "non-finite residual");
+      }
+      return LRCC_OK;
+    };
+    // whether sx is the FP64 ladder of the whole iterate (then rel is the true
+    // FP64 residual), or an estimate built from reduced-precision ladders
+    bool sx_exact = false;
     result = LRCC_ERR_NOT_CONVERGED;
     for (int outer = 0; outer < O.max_outer; ++outer) {
       lrcc_status is = jacobi_diis(S, S.rk, S.x, op.prec, op.cmul, h->ls2.p, O.inner_tol,
@@ -930,29 +954,20 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
         st = apply_sigma(S, S.x2, anchor, op.cmul, h->ls.p);
         if (st != LRCC_OK) return st;
         LRCC_HIP(h, hipMemcpyAsync(S.sx, S.s, vb, hipMemcpyDeviceToDevice, h->stream));
+        sx_exact = anchor == LRCC_FP64;
       } else {
         st = apply_sigma(S, S.x, op.prec, op.cmul, h->ls2.p);
         if (st != LRCC_OK) return st;
         hipLaunchKernelGGL(k_acc, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.active, S.s,
                            S.sx);
         LRCC_HIP(h, hipGetLastError());
+        sx_exact = false;
       }
-      hipLaunchKernelGGL(k_outer, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.eps, S.omega,
-                         S.tab, S.otab, S.active, S.b, S.x2, S.sx, S.rk, S.part);
-      LRCC_HIP(h, hipGetLastError());
-      LRCC_HIP(h, hipMemcpyAsync(S.h_part, S.part, (size_t)S.n * S.nchunk * sizeof(double2),
-                                 hipMemcpyDeviceToHost, h->stream));
-      LRCC_HIP(h, hipStreamSynchronize(h->stream));
+      st = outer_residual(act);
+      if (st != LRCC_OK) return st;
       int nact = 0;
       for (int r = 0; r < S.n; ++r) {
         if (!act[r]) continue;
-        double rr = 0, bb = 0;
-        for (int c = 0; c < S.nchunk; ++c) {
-          rr += S.h_part[(size_t)r * S.nchunk + c].x;
-          bb += S.h_part[(size_t)r * S.nchunk + c].y;
-        }
-        rel[r] = std::sqrt(rr / bb);
-        if (!std::isfinite(rel[r])) return fail(h, LRCC_ERR_NONFINITE, "non-finite residual");
         if (rel[r] < O.tol) act[r] = 0;
         else ++nact;
       }
@@ -960,6 +975,27 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
         result = LRCC_OK;
         break;
       }
+    }
+    if (!sx_exact) {
+      // The stopping test above used an estimate of the ladder of x2 (an
+      // FP32 anchor, or an FP64 anchor plus reduced-precision ladders of the
+      // later corrections).  The reported residual is the FP64 one of the
+      // returned iterate: one FP64 ladder of every right-hand side's x2.
+      if (anchor != LRCC_FP64) {
+        st = stage_for(S, L, LRCC_FP64, op.cmul, h->ls, form);
+        if (st != LRCC_OK) return st;
+      }
+      std::vector<int> every(S.n, 1);
+      LRCC_HIP(h, hipMemcpyAsync(S.active, every.data(), S.n * sizeof(int),
+                                 hipMemcpyHostToDevice, h->stream));
+      st = apply_sigma(S, S.x2, LRCC_FP64, op.cmul, h->ls.p);
+      if (st != LRCC_OK) return st;
+      LRCC_HIP(h, hipMemcpyAsync(S.sx, S.s, vb, hipMemcpyDeviceToDevice, h->stream));
+      st = outer_residual(every);
+      if (st != LRCC_OK) return st;
+      result = LRCC_OK;
+      for (int r = 0; r < S.n; ++r)
+        if (!(rel[r] < O.tol)) result = LRCC_ERR_NOT_CONVERGED;
     }
     for (int r = 0; r < S.n; ++r) final_rel = std::max(final_rel, rel[r]);
     st = finish_alpha(S, S.x2, alpha, h->stream);

@@ -61,3 +61,34 @@ def test_batch_with_empty_and_single_instance(lrcc):
     assert np.all(alphas[1] == 0)
     with pytest.raises(lrcc.LrccError):
         lrcc.solve_batched([dev_inst(inst, [0.0])], prec="fp32")
+
+
+def test_batched_workload_full_size_matches_single_solves(lrcc):
+    # the batched workload at full size: eight instances o in {8..32},
+    # v = 10 o, Nchol = 4 v, 3 components x 4 frequencies each (96 right-hand
+    # sides), one persistent launch per iteration; each instance's alpha must
+    # equal its own single solve (same ladder, same tile order, sums in
+    # another order across workgroups: rounding only), and the smallest
+    # instance the oracle's exact alpha.  Four DIIS vectors: eight do not fit
+    # the two o = 32 instances' history beside the others.
+    torch.cuda.empty_cache()
+    cfg = S.CONFIGS["batch"]
+    insts, devs = [], []
+    for (o, v, nchol, seed) in cfg.instances:
+        inst = S.make_instance(o, v, nchol, ncomp=cfg.ncomp, seed=seed, gamma=S.solve_gamma(v))
+        insts.append(inst)
+        devs.append(dev_inst(inst, list(cfg.omegas)))
+    print("full batched workload: batched solve", flush=True)
+    alphas, info = lrcc.solve_batched(devs, tol=1e-6, diis_dim=4)
+    assert info["status"] == "LRCC_OK" and info["final_relres"] < 1e-6
+    for k, (inst, a, d) in enumerate(zip(insts, alphas, devs)):
+        print(f"full batched workload: single solve {k} (o={inst.o})", flush=True)
+        single, sinfo = lrcc.solve(d["eps"], d["L"], d["mu"], list(cfg.omegas), tol=1e-6,
+                                   diis_dim=4)
+        assert sinfo["status"] == "LRCC_OK"
+        assert np.abs(a - single).max() <= 1e-10 * np.abs(single).max()
+    inst = insts[0]
+    exact = response.solve_sos(inst.L, inst.eps, inst.mu, list(cfg.omegas), inst.o,
+                               inst.v)["alpha"]
+    # a relative residual below 1e-6 bounds the error in alpha well below 1e-5
+    assert np.abs(alphas[0] - exact).max() < 1e-5 * np.abs(exact).max()

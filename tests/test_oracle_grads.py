@@ -54,3 +54,33 @@ def test_adjoint_routes_agree():
     G = S.make_packed(rng, 2, o, v)
     a, b = grads.vjp_X(L, G, o, v), grads.vjp_X_explicit(L, G, o, v)
     assert np.linalg.norm(a - b) < 1e-13 * np.linalg.norm(b)
+
+
+def test_sampled_L_entries_match_full_gradient_and_fd():
+    # the entry-by-entry gradient used at full sizes: against the whole
+    # gradient and, independently, against finite differences per element
+    rng = np.random.default_rng(4)
+    o, v, P = 4, 9, 3
+    L = S.make_L(rng, P, v, hermitian=False)
+    X, G = S.make_packed(rng, 2, o, v), S.make_packed(rng, 2, o, v)
+    pairs = [(0, 0), (3, 7), (8, 1), (5, 5)]
+    got = grads.vjp_L_entries(L, X, G, v, pairs)
+    full = grads.vjp_L(L, X, G, o, v)
+    for k, (a, c) in enumerate(pairs):
+        assert np.abs(got[:, k] - full[:, a, c]).max() < 1e-13 * np.abs(full).max()
+    loss = lambda LL: np.real(np.vdot(G, ppl.sigma(LL, X, o, v)))
+    for (Pi, a, c) in [(0, 3, 7), (2, 8, 1)]:
+        E = np.zeros_like(L)
+        E[Pi, a, c] = 1.0
+        fd = complex(_fd(loss, L, E), _fd(loss, L, 1j * E))
+        k = pairs.index((a, c))
+        assert abs(fd - got[Pi, k]) < 1e-8 * max(1.0, abs(fd))
+
+
+def test_packed_row_is_the_unpacked_row():
+    rng = np.random.default_rng(5)
+    n = 7
+    Xp = S.cn(rng, (3, n * (n - 1) // 2))
+    full = ppl.unpack(Xp, n)
+    for p in range(n):
+        assert np.array_equal(ppl.packed_row(Xp, n, p), full[:, p, :])
