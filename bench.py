@@ -77,7 +77,7 @@ def issued_flops(o, v, nchol, nrhs, prec="fp64", cmul="4m"):
     nbv = (v + 7) // 8
     nbp = nbv * (nbv + 1) // 2
     ntile = nbp * (nbp + 1) // 2
-    kc = {"fp64": 16, "fp32": 32, "bf16x3": 32}[prec]
+    kc = {"fp64": 16, "fp32": 32, "bf16x3": 16}[prec]
     ncp = -(-nchol // kc) * kc
     mp = -(-(nrhs * o * (o - 1) // 2) // 16) * 16
     form = 0.75 if cmul == "3m" else 1.0

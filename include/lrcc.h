@@ -48,12 +48,27 @@ typedef enum {
   LRCC_ERR_NOMEM = 5,          /* workspace allocation failed                 */
   LRCC_ERR_NOT_CONVERGED = 6,  /* solve hit max_iter; info is still filled    */
   LRCC_ERR_NONFINITE = 7,      /* NaN/Inf met in a residual or norm           */
-  LRCC_ERR_UNSUPPORTED = 8     /* valid request the library does not offer    */
+  LRCC_ERR_UNSUPPORTED = 8,    /* valid request the library does not offer    */
+  /* range markers (not returned): the enum spans every int, so that
+   * lrcc_status_str accepts any value */
+  LRCC_STATUS_RANGE_MIN = -0x7fffffff - 1, LRCC_STATUS_RANGE_MAX = 0x7fffffff
 } lrcc_status;
 
-typedef enum { LRCC_C128 = 0, LRCC_C64 = 1 } lrcc_dtype;  /* storage of L, X, sigma */
-typedef enum { LRCC_FP64 = 0, LRCC_FP32 = 1, LRCC_BF16X3 = 2 } lrcc_prec; /* PPL arithmetic */
-typedef enum { LRCC_CMUL_4M = 0, LRCC_CMUL_3M = 1 } lrcc_cmul;  /* complex product form */
+/* Input enums.  The *_RANGE_MIN / *_RANGE_MAX markers are not values to
+ * pass: they make each enum span every int, so that an out-of-range
+ * argument is a well-defined value the validation rejects (LRCC_ERR_ARG). */
+typedef enum {
+  LRCC_C128 = 0, LRCC_C64 = 1,                                   /* storage of L, X, sigma */
+  LRCC_DTYPE_RANGE_MIN = -0x7fffffff - 1, LRCC_DTYPE_RANGE_MAX = 0x7fffffff
+} lrcc_dtype;
+typedef enum {
+  LRCC_FP64 = 0, LRCC_FP32 = 1, LRCC_BF16X3 = 2,                 /* PPL arithmetic */
+  LRCC_PREC_RANGE_MIN = -0x7fffffff - 1, LRCC_PREC_RANGE_MAX = 0x7fffffff
+} lrcc_prec;
+typedef enum {
+  LRCC_CMUL_4M = 0, LRCC_CMUL_3M = 1,                            /* complex product form */
+  LRCC_CMUL_RANGE_MIN = -0x7fffffff - 1, LRCC_CMUL_RANGE_MAX = 0x7fffffff
+} lrcc_cmul;
 
 typedef struct lrcc_handle_s* lrcc_handle;
 
@@ -91,7 +106,11 @@ lrcc_status lrcc_ppl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs,
 
 /* Vector-Jacobian products of sigma = PPL(L, X) for a real loss with
  * upstream gradient G = dloss/dsigma (PyTorch's complex convention:
- * dloss = Re sum conj(grad) d(input)).
+ * dloss = Re sum conj(grad) d(input)).  dX is the product with the
+ * transposed (adjoint) ladder, the operation the left-hand amplitude
+ * equation of Sec. 2.2 applies (Y (A + w) = -(eta + F X) multiplies by the
+ * Jacobian from the left); dL differentiates the on-the-fly integrals of
+ * Sec. 3 with respect to the Cholesky vectors.
  *   dX = sigma(L^H, G)                  (the adjoint ladder; (L^H)^P = (L^P)^H)
  *   dL^P = 2 sum_m G_m conj(L^P) X_m^H  (G_m, X_m full antisymmetric v x v)
  * Either output may be NULL to skip it.  dX has the shape of X, dL of L; both
@@ -221,7 +240,9 @@ typedef struct {
                         ladder); bf16x3 ladders always use 4M                */
   double inner_tol;  /* reduced precision: inner relative tolerance (1e-5)   */
   int max_outer;     /* reduced precision: refinement sweeps (default 6)     */
-  int deterministic; /* reserved; must be 0                                  */
+  int deterministic; /* 1: deterministic ladders for this solve (see
+                        lrcc_set_deterministic); 0 (default): the handle's
+                        setting.  lrcc_solve_batched: 0 only                  */
   int resid_fp64_every; /* reduced precision: 0 (default) = the stopping
                         test's ladder of the iterate is a full FP64 ladder in
                         the first sweep only, later sweeps update it by the
@@ -251,10 +272,16 @@ typedef struct {
                         Cholesky vectors [nchol][o][o] complex128,
                         L_oo[P][k][i] = L^P_ki: the model Jacobian then also
                         holds the hole-hole ladder
-                          sum_{k,l} <kl||ij> X_kl^ab, <kl|ij> = sum_P
+                          HHL = sum_{k,l} <kl||ij> X_kl^ab, <kl|ij> = sum_P
                           L^P_ki L^P_lj,
                         which couples the occupied pairs (applied in FP64
-                        whatever prec is).  lrcc_solve_batched: NULL only    */
+                        whatever prec is), and its two-electron part becomes
+                        the doubles-doubles block of the two-electron
+                        operator at T = 0 (Sec. 2.2): 1/2 sigma + 1/2 HHL
+                        (+ the ring term with L_ov), sigma and HHL being the
+                        unrestricted sums of lrcc_ppl_sigma and
+                        lrcc_hhl_sigma.  Without it the two-electron part is
+                        sigma alone.  lrcc_solve_batched: NULL only          */
   const void* L_ov;  /* (device) NULL (default), or occupied-virtual
                         Cholesky vectors [nchol][o][v] complex128 (needs
                         L_oo and L_vo): the model Jacobian then also holds
@@ -265,6 +292,27 @@ typedef struct {
   const void* L_vo;  /* (device) virtual-occupied vectors [nchol][v][o]
                         complex128 with L_ov; for a Hermitian decomposition
                         L_vo[P] = L_ov[P]^H                                  */
+  const void* x0;    /* (device) NULL (default: the Jacobi start
+                        X = -xi / (D - w)), or initial right-hand amplitudes
+                        [nomega][ncomp][o(o-1)/2][v(v-1)/2] complex128 (a
+                        warm start, e.g. the converged X of a neighbouring
+                        frequency).  With reduced precision the refinement
+                        starts from it (one full-iterate ladder more).
+                        lrcc_solve_batched: NULL only                        */
+  void* x_out;       /* (device) NULL, or [nomega][ncomp][o(o-1)/2][v(v-1)/2]
+                        complex128 receiving the final right-hand amplitudes
+                        (the iterate alpha is computed from).
+                        lrcc_solve_batched: NULL only                        */
+  const char* metrics_path; /* (host) NULL, or a file that receives one JSON
+                        line per iteration, appended: side ("right" / "left"),
+                        phase ("fp64": the FP64 solve, "inner": a reduced-
+                        precision inner iteration, "outer": a refinement
+                        sweep's residual, "final": the FP64-ladder residual of
+                        the returned amplitudes when the last sweep's was an
+                        estimate), sweep, iter, active
+                        right-hand sides, ms since the call began and every
+                        right-hand side's relative residual.  A file that
+                        cannot be opened gives LRCC_ERR_ARG                   */
 } lrcc_solve_opts;
 
 typedef struct {
@@ -312,9 +360,12 @@ typedef struct {
   double* alpha;       /* host, [nomega][ncomp][ncomp] complex128 */
 } lrcc_instance;
 
-/* Solve several uneven instances together: every ladder application of
- * every instance, component and frequency goes into one persistent launch
- * per iteration (a work queue ordered longest tile first).  FP64 ladder
+/* Solve several uneven instances together: the response equations of
+ * Sec. 2.2, one per perturbation component and frequency of each instance
+ * (each instance a molecule or basis of its own size), iterated side by
+ * side.  Every ladder application of every instance, component and
+ * frequency goes into one persistent launch per iteration (a work queue
+ * ordered longest tile first).  FP64 ladder
  * only (opts->prec must be LRCC_FP64, else LRCC_ERR_UNSUPPORTED), in the
  * complex form opts->cmul selects. */
 lrcc_status lrcc_solve_batched(lrcc_handle h, int ninst, const lrcc_instance* inst,
@@ -329,10 +380,24 @@ lrcc_status lrcc_solve_batched(lrcc_handle h, int ninst, const lrcc_instance* in
 lrcc_status lrcc_set_timing(lrcc_handle h, int enable);
 lrcc_status lrcc_get_timing(lrcc_handle h, double* ms, long* launches);
 
-/* Workspace limit of the bf16x3 ladder.  That path stores antisymmetrised
- * integral tiles (64 KB per tile pair with its mirror) for one panel of
- * block pairs at a time; the panel holds as many rows of the block-pair
- * triangle as fit in `bytes` (at least one row).  0 restores the default:
+/* Deterministic mode (a debugging aid, for separating races from rounding):
+ * while enabled, the FP64 and FP32 ladders run a kernel without atomic
+ * additions (one workgroup per output block pair builds every integral tile
+ * of its row in a fixed order, without the Hermitian halving, 4M complex
+ * form whatever cmul is) and the bf16x3 contraction runs unsplit, so that
+ * repeated calls give bit-identical results.  Several times slower than the
+ * default kernels.  The environment variable LRCC_DETERMINISTIC=1 sets it for
+ * new handles.  Applies to lrcc_ppl_sigma, its adjoint's dX and lrcc_solve;
+ * lrcc_solve_batched then returns LRCC_ERR_UNSUPPORTED. */
+lrcc_status lrcc_set_deterministic(lrcc_handle h, int enable);
+
+/* Workspace limit of the bf16x3 ladder and of the gradient with respect to
+ * L.  The bf16x3 path stores antisymmetrised integral tiles (64 KB per tile
+ * pair with its mirror) for one panel of block pairs at a time; the panel
+ * holds as many rows of the block-pair triangle as fit in `bytes` (at least
+ * one row).  The gradient stores the products sum_m conj(G_m) X_m on packed
+ * virtual pairs (64 KB per block-pair pair in FP64) for panels of whole
+ * block rows the same way.  0 restores the default:
  * min(16 GiB, half the free device memory at first use), overridable by the
  * environment variable LRCC_PANEL_MB.  The workspace itself is allocated on
  * the next bf16x3 ladder and kept by the handle. */

@@ -69,15 +69,30 @@ def denominators(eps: np.ndarray, o: int, v: int) -> np.ndarray:
     return (ev[pa] + ev[pb])[None, :] - (eo[pi] + eo[pj])[:, None]
 
 
-def apply_jacobian(L, X, eps, o, v, Loo=None, ring=None):
-    """(A X) = D o X + sigma(X) (+ the hole-hole ladder with ``Loo``, + the
-    ring term with ``ring`` = (Lov, Lvo), which needs ``Loo``)."""
-    AX = denominators(eps, o, v)[None] * X + ppl.sigma(L, X, o, v)
-    if Loo is not None:
-        AX = AX + hhl.sigma(Loo, X, o, v)
+def two_body(L, X, o, v, Loo=None, ring=None):
+    """The two-electron part of the model Jacobian applied to X.
+
+    Particle-particle ladder alone: sigma(X) as ppl.py defines it (the
+    literal unrestricted c, d sum).  With the hole-hole ladder (``Loo``) and
+    optionally the ring term (``ring`` = (Lov, Lvo), which needs ``Loo``):
+    the doubles-doubles block of the normal-ordered two-electron operator at
+    T = 0 (Sec. 2.2), which in the doubled ladder convention of ppl.py and
+    hhl.py is 1/2 PPL + 1/2 HHL (+ RING) -- pinned by the Fock-space matrix
+    element in the tests.
+    """
+    S = ppl.sigma(L, X, o, v)
+    if Loo is None:
+        return S
+    S = 0.5 * S + 0.5 * hhl.sigma(Loo, X, o, v)
     if ring is not None:
-        AX = AX + ringterm.sigma(ring[0], ring[1], Loo, L, X, o, v)
-    return AX
+        S = S + ringterm.sigma(ring[0], ring[1], Loo, L, X, o, v)
+    return S
+
+
+def apply_jacobian(L, X, eps, o, v, Loo=None, ring=None):
+    """(A X) = D o X + the two-electron part (two_body: the ladder alone, or
+    the T = 0 doubles-doubles block with ``Loo`` and ``ring``)."""
+    return denominators(eps, o, v)[None] * X + two_body(L, X, o, v, Loo, ring)
 
 
 def _diis_coefficients(errs):
@@ -117,9 +132,7 @@ def solve_iterative(L, eps, mu, omegas, o, v, tol=1e-8, max_iter=200,
     iters [nomega, ncomp], relres [nomega, ncomp], n_sigma).
     """
     if sigma_fn is None:
-        sigma_fn = (lambda X: ppl.sigma(L, X, o, v)) if Loo is None else \
-            (lambda X: ppl.sigma(L, X, o, v) + hhl.sigma(Loo, X, o, v)
-             + (ringterm.sigma(ring[0], ring[1], Loo, L, X, o, v) if ring is not None else 0))
+        sigma_fn = lambda X: two_body(L, X, o, v, Loo, ring)  # noqa: E731
     xi = rhs(mu, o, v)
     D = denominators(eps, o, v)
     ncomp = xi.shape[0]
@@ -285,15 +298,16 @@ def solve_sos_full(L, eps, mu, omegas, o, v):
 # --- the hole-hole ladder couples the occupied pairs ----------------------
 
 def full_matrix(L, eps, o, v, Loo=None, ring=None):
-    """A on the whole packed vector x[(ij, ab)] (ij major): diag(D) + I (x) K
-    (+ W (x) I with the hole-hole ladder, + the ring matrix with ``ring`` =
-    (Lov, Lvo)).  Small sizes only."""
+    """A on the whole packed vector x[(ij, ab)] (ij major): diag(D) + I (x) K,
+    or with the hole-hole ladder diag(D) + (I (x) K + W (x) I) / 2 (+ the ring
+    matrix with ``ring`` = (Lov, Lvo)), as two_body.  Small sizes only."""
     K = ppl.ladder_matrix(L, v)
     npo, npv = o * (o - 1) // 2, K.shape[0]
     A = np.diag(denominators(eps, o, v).reshape(-1)).astype(np.complex128)
-    A += np.kron(np.eye(npo), K)
-    if Loo is not None:
-        A += np.kron(hhl.hh_matrix(Loo, o), np.eye(npv))
+    if Loo is None:
+        A += np.kron(np.eye(npo), K)
+    else:
+        A += 0.5 * np.kron(np.eye(npo), K) + 0.5 * np.kron(hhl.hh_matrix(Loo, o), np.eye(npv))
     if ring is not None:
         A += ringterm.ring_matrix(ring[0], ring[1], Loo, L, o, v)
     return A

@@ -47,7 +47,9 @@ class SolveOpts(ctypes.Structure):
                 ("max_outer", ctypes.c_int), ("deterministic", ctypes.c_int),
                 ("resid_fp64_every", ctypes.c_int), ("anchor_prec", ctypes.c_int),
                 ("response", ctypes.c_int), ("L_oo", ctypes.c_void_p),
-                ("L_ov", ctypes.c_void_p), ("L_vo", ctypes.c_void_p)]
+                ("L_ov", ctypes.c_void_p), ("L_vo", ctypes.c_void_p),
+                ("x0", ctypes.c_void_p), ("x_out", ctypes.c_void_p),
+                ("metrics_path", ctypes.c_char_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -118,6 +120,7 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)],
             "lrcc_check_sigma_args": [i, i, i, i, vp, vp, vp, i, i, i],
             "lrcc_set_timing": [vp, i],
+            "lrcc_set_deterministic": [vp, i],
             "lrcc_set_workspace_limit": [vp, ctypes.c_size_t],
             "lrcc_autotune": [vp, i, i, i, i, i, i, ctypes.c_char_p, ctypes.POINTER(TuneResult)],
             "lrcc_get_timing": [vp, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_long)],
@@ -387,6 +390,12 @@ def set_timing(enable: bool, device: int = 0):
     _check(lib().lrcc_set_timing(h, 1 if enable else 0), h)
 
 
+def set_deterministic(enable: bool, device: int = 0):
+    """Deterministic (atomic-free, bit-reproducible) ladders on this device's handle."""
+    h = handle(device)
+    _check(lib().lrcc_set_deterministic(h, int(bool(enable))), h)
+
+
 def set_workspace_limit(nbytes: int, device: int = 0):
     """Cap the bf16x3 ladder's integral-panel workspace (0 = default)."""
     h = handle(device)
@@ -446,13 +455,18 @@ RESPONSE = {"right": 0, "full": 1}
 
 def solve(eps, L, mu, omegas, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64",
           cmul="4m", inner_tol=1e-5, max_outer=6, check=True, resid_fp64_every=0,
-          anchor_prec="fp64", response="right", Loo=None, Lov=None, Lvo=None):
+          anchor_prec="fp64", response="right", Loo=None, Lov=None, Lvo=None,
+          deterministic=False, x0=None, x_out=None, metrics_path=None):
     """Model response solve; returns (alpha [nomega, ncomp, ncomp] complex128 numpy,
     info dict).  response="right": alpha from the right-hand amplitudes;
     "full": the full response function (right- and left-hand solves).
     Loo: occupied-occupied Cholesky vectors [nchol, o, o] (complex128) to
     include the hole-hole ladder in the model Jacobian; with it, Lov
-    [nchol, o, v] and Lvo [nchol, v, o] add the ring term."""
+    [nchol, o, v] and Lvo [nchol, v, o] add the ring term.
+    x0 / x_out: initial / final right-hand amplitudes, complex128 tensors
+    [nomega, ncomp, o(o-1)/2, v(v-1)/2] on the GPU (warm start, checkpoint);
+    metrics_path: a file that receives one JSON line per iteration;
+    deterministic: atomic-free, bit-reproducible ladders."""
     import numpy as np
     import torch
     L, mu, eps = L.contiguous(), mu.contiguous(), eps.contiguous()
@@ -473,11 +487,20 @@ def solve(eps, L, mu, omegas, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64",
         if Lov.dtype != torch.complex128 or tuple(Lov.shape) != (nchol, o, v) or \
                 Lvo.dtype != torch.complex128 or tuple(Lvo.shape) != (nchol, v, o):
             raise ValueError("Lov must be complex128 [nchol, o, v] and Lvo [nchol, v, o]")
-    opts = SolveOpts(tol, max_iter, diis_dim, PREC[prec], CMUL[cmul], inner_tol, max_outer, 0,
-                     resid_fp64_every, PREC[anchor_prec], RESPONSE[response],
+    shape = (len(om), ncomp, o * (o - 1) // 2, v * (v - 1) // 2)
+    for name, t in (("x0", x0), ("x_out", x_out)):
+        if t is not None and (t.dtype != torch.complex128 or tuple(t.shape) != shape
+                              or not t.is_contiguous() or not t.is_cuda):
+            raise ValueError(f"{name} must be a contiguous complex128 GPU tensor {shape}")
+    opts = SolveOpts(tol, max_iter, diis_dim, PREC[prec], CMUL[cmul], inner_tol, max_outer,
+                     int(bool(deterministic)), resid_fp64_every, PREC[anchor_prec],
+                     RESPONSE[response],
                      Loo.data_ptr() if Loo is not None else None,
                      Lov.data_ptr() if Lov is not None else None,
-                     Lvo.data_ptr() if Lvo is not None else None)
+                     Lvo.data_ptr() if Lvo is not None else None,
+                     x0.data_ptr() if x0 is not None and x0.numel() else None,
+                     x_out.data_ptr() if x_out is not None and x_out.numel() else None,
+                     metrics_path.encode() if metrics_path else None)
     info = SolveInfo()
     h = handle(L.device.index)
     st = lib().lrcc_solve(h, o, v, nchol, _ptr(eps), _ptr(L), ncomp, _ptr(mu), len(om),
@@ -489,7 +512,8 @@ def solve(eps, L, mu, omegas, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64",
 
 
 def solve_batched(instances, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64", cmul="4m",
-                  inner_tol=1e-5, max_outer=6, check=True, resid_fp64_every=0):
+                  inner_tol=1e-5, max_outer=6, check=True, resid_fp64_every=0,
+                  deterministic=False):
     """Batched solve of several instances: each a dict(eps, L, mu, omegas)."""
     import numpy as np
     import torch
@@ -508,8 +532,8 @@ def solve_batched(instances, tol=1e-8, max_iter=100, diis_dim=8, prec="fp64", cm
         dev = L.device.index
         arr[k] = Instance(mu.shape[1], L.shape[1], L.shape[0], eps.data_ptr(), L.data_ptr(),
                           mu.shape[0], mu.data_ptr(), len(om), om.ctypes.data, al.ctypes.data)
-    opts = SolveOpts(tol, max_iter, diis_dim, PREC[prec], CMUL[cmul], inner_tol, max_outer, 0,
-                     resid_fp64_every, 0, 0)
+    opts = SolveOpts(tol, max_iter, diis_dim, PREC[prec], CMUL[cmul], inner_tol, max_outer,
+                     int(bool(deterministic)), resid_fp64_every, 0, 0)
     info = SolveInfo()
     h = handle(dev)
     st = lib().lrcc_solve_batched(h, len(instances), arr, ctypes.byref(opts), ctypes.byref(info))

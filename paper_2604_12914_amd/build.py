@@ -28,8 +28,8 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, obj: str) -> None:
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+def _compile(src: str, obj: str, extra=()) -> None:
+    cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -39,23 +39,48 @@ def _compile(src: str, obj: str) -> None:
             print(line, file=sys.stderr)
 
 
-def build(verbose: bool = True) -> str:
-    bdir = os.path.join(CSRC, "_build")
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer for the debug
+# library liblrcc_san.so (the device code is built as usual): the host
+# validation paths of the C ABI run under it in the CPU tests, with the
+# shared sanitizer runtime preloaded (SANITIZER_RUNTIME).
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-O1"]
+SAN_OUT = os.path.join(HERE, "liblrcc_san.so")
+SANITIZER_RUNTIME = "/opt/rocm/llvm/lib/clang/22/lib/linux/libclang_rt.asan-x86_64.so"
+
+
+def _link(objs, out, extra=()):
+    tmp = out + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *extra, "-o", tmp, *objs,
+           "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, out)
+
+
+def _objects(bdir, flags):
     os.makedirs(bdir, exist_ok=True)
     srcs = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
     objs = [os.path.join(bdir, f[:-4] + ".o") for f in srcs]
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
     with cf.ThreadPoolExecutor(max_workers=max(jobs, 1)) as ex:
-        list(ex.map(_compile, [os.path.join(CSRC, s) for s in srcs], objs))
-    tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
-           "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
+        list(ex.map(lambda a: _compile(*a, extra=flags),
+                    [(os.path.join(CSRC, s), o) for s, o in zip(srcs, objs)]))
+    return objs
+
+
+def build(verbose: bool = True, sanitized: bool = True) -> str:
+    _link(_objects(os.path.join(CSRC, "_build"), []), OUT)
     if verbose:
         print(f"built {OUT}")
+    if sanitized:
+        _link(_objects(os.path.join(CSRC, "_build_san"), SAN_FLAGS), SAN_OUT,
+              ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+               "-shared-libsan"])
+        if verbose:
+            print(f"built {SAN_OUT}")
     return OUT
 
 

@@ -178,11 +178,15 @@ lrcc_status ppl_run(lrcc_handle h, lrcc_prec prec, lrcc_cmul cmul, bool acc64, c
     e1 = h->tev[2 * h->tev_used + 1];
     LRCC_HIP(h, hipEventRecord(e0, h->stream));
   }
-  lrcc_status ost;
-  const int* ord = tile_order(h, g, 0, g.nbp, true, prec, &ost);
-  if (ost != LRCC_OK) return ost;
-  LRCC_HIP(h, ppl_launch(prec, cmul, acc64, g, Ls, Xb, Sb, h->tab.as<int>(), ord, nonherm,
-                         h->occ[prec][cmul], h->stream));
+  if (h->deterministic) {
+    LRCC_HIP(h, ppl_det_launch(prec, acc64, g, Ls, Xb, Sb, h->tab.as<int>(), h->stream));
+  } else {
+    lrcc_status ost;
+    const int* ord = tile_order(h, g, 0, g.nbp, true, prec, &ost);
+    if (ost != LRCC_OK) return ost;
+    LRCC_HIP(h, ppl_launch(prec, cmul, acc64, g, Ls, Xb, Sb, h->tab.as<int>(), ord, nonherm,
+                           h->occ[prec][cmul], h->stream));
+  }
   if (h->timing) {
     LRCC_HIP(h, hipEventRecord(e1, h->stream));
     ++h->tev_used;
@@ -242,6 +246,8 @@ static lrcc_status check_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs,
     return fail(h, LRCC_ERR_ARG, "unknown complex-multiply form");
   if (v > 4096) return fail(h, LRCC_ERR_SHAPE, "v exceeds 4096");
   if (nchol > 65536) return fail(h, LRCC_ERR_SHAPE, "nchol exceeds 65536");
+  if (o > 65535 || nrhs > (1 << 24))  // (bounds the products below)
+    return fail(h, LRCC_ERR_SHAPE, "nrhs*o(o-1)/2 exceeds 2^24");
   const long M = (long)nrhs * npair(o);
   if (M > (1L << 24)) return fail(h, LRCC_ERR_SHAPE, "nrhs*o(o-1)/2 exceeds 2^24");
   const size_t es = dt == LRCC_C128 ? 16 : 8;
@@ -348,6 +354,7 @@ lrcc_status lrcc_create(lrcc_handle* out, int device, void* stream) {
   h->device = device;
   h->stream = static_cast<hipStream_t>(stream);
   h->ncu = prop.multiProcessorCount;
+  if (const char* e = getenv("LRCC_DETERMINISTIC")) h->deterministic = atoi(e) != 0;
   *out = h;
   return LRCC_OK;
 }
@@ -366,6 +373,7 @@ lrcc_status lrcc_destroy(lrcc_handle h) {
     h->hflag.release();
     for (auto& b : h->order) b.release();
     h->vws.release();
+    h->bitems.release();
     h->hw.release();
     h->cw.release();
     h->fw.release();
@@ -401,6 +409,12 @@ lrcc_status lrcc_set_timing(lrcc_handle h, int enable) {
   if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
   h->timing = enable != 0;
   h->tev_used = 0;
+  return LRCC_OK;
+}
+
+lrcc_status lrcc_set_deterministic(lrcc_handle h, int enable) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  h->deterministic = enable != 0;
   return LRCC_OK;
 }
 
@@ -484,7 +498,7 @@ lrcc_status lrcc_hhl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, con
   LRCC_HIP(h, pack_to_block<double>(X, dt, g, tab, h->xb.as<double>(), h->stream));
   LRCC_HIP(h, fill_zero(h->sb.p, vb, h->stream));
   LRCC_HIP(h, hh_pair_table(o, otab, h->stream));
-  LRCC_HIP(h, hh_build_w(Loo, dt, o, nchol, otab, L_PLAIN, W, h->stream));
+  LRCC_HIP(h, hh_build_w(Loo, dt, o, nchol, otab, L_PLAIN, 2.0, W, h->stream));
   LRCC_HIP(h, hh_apply(W, g, h->xb.as<double>(), h->sb.as<double>(), h->stream));
   LRCC_HIP(h, block_to_pack<double>(h->sb.as<double>(), g, tab, sigma, dt, h->stream));
   return LRCC_OK;
@@ -685,9 +699,9 @@ lrcc_status lrcc_solve(lrcc_handle h, int o, int v, int nchol, const double* eps
     return fail(h, LRCC_ERR_ARG, "sizes must be non-negative");
   if (v > 4096) return fail(h, LRCC_ERR_SHAPE, "v exceeds 4096");
   if (nchol > 65536) return fail(h, LRCC_ERR_SHAPE, "nchol exceeds 65536");
-  if ((long)nomega * ncomp * npair(o) > (1L << 24))
-    return fail(h, LRCC_ERR_SHAPE, "nomega*ncomp*o(o-1)/2 exceeds 2^24");
   if ((long)nomega * ncomp > 4096) return fail(h, LRCC_ERR_SHAPE, "more than 4096 right-hand sides");
+  if (o > 65535 || (long)nomega * ncomp * npair(o) > (1L << 24))
+    return fail(h, LRCC_ERR_SHAPE, "nomega*ncomp*o(o-1)/2 exceeds 2^24");
   if (nomega * ncomp > 0) {
     if (!alpha) return fail(h, LRCC_ERR_ARG, "alpha is NULL");
     if (!omegas) return fail(h, LRCC_ERR_ARG, "omegas is NULL");
@@ -712,7 +726,8 @@ lrcc_status lrcc_solve_batched(lrcc_handle h, int ninst, const lrcc_instance* in
     if (I.o < 0 || I.v < 0 || I.nchol < 0 || I.ncomp < 0 || I.nomega < 0)
       return fail(h, LRCC_ERR_ARG, w + "sizes must be non-negative");
     if (I.v > 4096 || I.nchol > 65536) return fail(h, LRCC_ERR_SHAPE, w + "v or nchol too large");
-    if ((long)I.nomega * I.ncomp * npair(I.o) > (1L << 24) || (long)I.nomega * I.ncomp > 4096)
+    if ((long)I.nomega * I.ncomp > 4096 || I.o > 65535 ||
+        (long)I.nomega * I.ncomp * npair(I.o) > (1L << 24))
       return fail(h, LRCC_ERR_SHAPE, w + "too many right-hand sides");
     if (I.nomega * I.ncomp > 0) {
       if (!I.alpha || !I.omegas) return fail(h, LRCC_ERR_ARG, w + "alpha or omegas is NULL");
@@ -739,6 +754,7 @@ const char* lrcc_status_str(lrcc_status s) {
     case LRCC_ERR_NOT_CONVERGED: return "not converged";
     case LRCC_ERR_NONFINITE: return "non-finite value";
     case LRCC_ERR_UNSUPPORTED: return "unsupported";
+    default: break;
   }
   return "unknown status";
 }

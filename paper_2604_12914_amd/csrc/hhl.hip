@@ -23,7 +23,8 @@ __device__ inline double2 load_c(const void* p, lrcc_dtype dt, size_t i) {
 // One thread per (ij, kl).  form L_TRANS builds W from the transposed
 // vectors (L^P)^T, which gives W^T (the left-hand solve's operator).
 __global__ void k_hh_w(const void* __restrict__ Loo, lrcc_dtype dt, int o, int nchol, long npo,
-                       const int* __restrict__ otab, int form, double2* __restrict__ W) {
+                       const int* __restrict__ otab, int form, double scale,
+                       double2* __restrict__ W) {
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (e >= npo * npo) return;
   const int ij = (int)(e / npo), kl = (int)(e % npo);
@@ -40,7 +41,7 @@ __global__ void k_hh_w(const void* __restrict__ Loo, lrcc_dtype dt, int o, int n
     re += (ki.x * lj.x - ki.y * lj.y) - (kj.x * li.x - kj.y * li.y);
     im += (ki.x * lj.y + ki.y * lj.x) - (kj.x * li.y + kj.y * li.x);
   }
-  W[e] = make_double2(2.0 * re, 2.0 * im);
+  W[e] = make_double2(scale * re, scale * im);
 }
 
 // Sb += W X on the block layout.  Workgroup: (block pair, right-hand side,
@@ -115,11 +116,11 @@ hipError_t hh_pair_table(int o, int* otab, hipStream_t st) {
 }
 
 hipError_t hh_build_w(const void* Loo, lrcc_dtype dt, int o, int nchol, const int* otab,
-                      LForm form, double2* W, hipStream_t st) {
+                      LForm form, double scale, double2* W, hipStream_t st) {
   const long npo = npair(o), n = npo * npo;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_hh_w, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Loo, dt, o,
-                     nchol, npo, otab, (int)form, W);
+                     nchol, npo, otab, (int)form, scale, W);
   return hipGetLastError();
 }
 

@@ -73,8 +73,11 @@ struct lrcc_handle_s {
   int order_s[3] = {0, 0, 0};  // super-tile width per precision (0 = default)
   int occ[3][2] = {};     // launch variant per precision and complex form (0 = default)
   lrcc::Buf vws;          // bf16x3: one panel of antisymmetrised integral tiles
+  lrcc::Buf bitems;       // bf16x3: build items of every panel (int2), see build_items()
+  std::vector<long> bitems_key, bitems_off;  // their geometry key and per-panel offsets
   size_t panel_cap = 0;   // bytes allowed for vws (0 = not yet chosen)
   int tab_nbv = -1;
+  int deterministic = 0;  // ladders without atomics, reproducible bit for bit (lrcc_set_deterministic)
   // solver workspace
   lrcc::Buf sv[12];
   lrcc::Buf hw;           // hole-hole ladder: W matrix and occupied pair table
@@ -159,6 +162,11 @@ struct BatchInst {
 // cm3: the 3M complex form (same staged layout as 4M).
 hipError_t ppl_queue_launch(const BatchInst* inst, int ninst, const long* xtotal, int nx,
                             unsigned* counter, int nwg, bool cm3, hipStream_t st);
+// Deterministic ladder (no atomics; one workgroup per block pair AB owning
+// sigma[:, AB], every tile built in ascending CD order, 4M form): Sb zeroed
+// by the caller; FP64 or FP32 arithmetic on the ppl_launch staged layouts.
+hipError_t ppl_det_launch(lrcc_prec prec, bool acc64, const Geom& g, const void* Ls,
+                          const void* Xb, void* Sb, const int* tab, hipStream_t st);
 int ppl_chunk(lrcc_prec prec, lrcc_cmul cmul);   // KC of the staged layout
 bool ppl_has_variant(lrcc_prec prec, lrcc_cmul cmul, int variant);  // 4M launch variants 1-5
 size_t ppl_ls_bytes(lrcc_prec prec, lrcc_cmul cmul, const Geom& g);
@@ -224,11 +232,13 @@ lrcc_status ring_run(lrcc_handle h, int o, int v, int nchol, int nrhs, const voi
                      bool accumulate, void* ws);
 
 // Hole-hole ladder (hhl.hip) ------------------------------------------------
-// W[(ij),(kl)] = 2 <kl||ij> from occupied-occupied vectors Loo [nchol][o][o]
+// W[(ij),(kl)] = scale <kl||ij> from occupied-occupied vectors Loo [nchol][o][o]
 // (dtype dt; form L_TRANS: from (L^P)^T, which gives W^T); otab[p] = (i<<16)|j
-// of packed occupied pair p (device).  W: npo*npo complex (device).
+// of packed occupied pair p (device).  W: npo*npo complex (device).  scale 2:
+// the hole-hole ladder with the unrestricted k, l sum; 1: half of it, as the
+// T = 0 doubles-doubles block of the model Jacobian holds it.
 hipError_t hh_build_w(const void* Loo, lrcc_dtype dt, int o, int nchol, const int* otab,
-                      LForm form, double2* W, hipStream_t st);
+                      LForm form, double scale, double2* W, hipStream_t st);
 // otab[p] = (i << 16) | j of the packed occupied pairs (device, npo ints).
 hipError_t hh_pair_table(int o, int* otab, hipStream_t st);
 // Sb += W X per block pair and right-hand side on the block layout (FP64

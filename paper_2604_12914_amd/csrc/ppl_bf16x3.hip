@@ -3,20 +3,26 @@
 // Every real operand x is split as x = hi + lo with hi = bf16(x) and
 // lo = bf16(x - hi) (round to nearest even), and a real product is taken as
 // hi*hi + hi*lo + lo*hi (the lo*lo term is dropped), all on the bf16 matrix
-// cores (16x16x32 MFMA) with FP32 accumulation.  Complex products use the
-// 4M form, so one complex multiply-accumulate costs 12 bf16 MFMA products.
+// cores with FP32 accumulation.  Complex products use the 4M form, so one
+// complex multiply-accumulate costs 12 bf16 MFMA products.
 //
 // The ladder is evaluated in panels of consecutive block pairs AB, each
 // holding the tiles (AB, CD) with CD >= AB (the upper triangle of the block-
 // pair matrix) in both orientations:
-//   k_vbuild   one workgroup per upper tile (AB, CD): W1 = sum_P L_AC (x) L_BD
-//              and W2 = sum_P L_AD (x) L_BC on the matrix cores,
-//              antisymmetrised in LDS to V = 2 <ab||cd>, split to hi/lo and
+//   k_vbuild   one workgroup per (AB, CG, DG), CG <= DG two groups of two
+//              virtual blocks: W1 = sum_P L_(A,CG) (x) L_(B,DG) and
+//              W2 = sum_P L_(A,DG) (x) L_(B,CG), two 128 x 128 complex
+//              products on the 32x32x16 bf16 matrix cores, give the four
+//              tiles V(AB, CD) = 2 <ab||cd>, C in CG, D in DG (each output
+//              element of W1 and W2 is an integral one of the tiles needs, so
+//              each Cholesky byte feeds twice the matrix work of a single
+//              64 x 64 tile pair); antisymmetrised in LDS, split to hi/lo and
 //              written to the panel (32 KB per tile).  The mirror tile
 //              V(CD, AB) goes beside it: for Hermitian L^P it is the conjugate
 //              transpose of the tile just built (one build per pair), otherwise
-//              a second wave of workgroups builds it (a flag set on the device
-//              by the staging pass decides, so no host round trip);
+//              the same workgroup builds it from the transposed block roles (a
+//              flag set on the device by the staging pass decides, so no host
+//              round trip);
 //   k_contract sigma[m, Q] += sum_{CD >= Q} X[m, CD] V(Q, CD)^T
 //                           + sum_{AB < Q, AB in panel} X[m, AB] V(Q, AB)^T,
 //              a bf16x3 GEMM in which each workgroup owns its output tile
@@ -28,6 +34,9 @@
 // bf16 arithmetic; a panel costs one extra write and read of V per apply.
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "internal.hpp"
 
 namespace lrcc {
@@ -38,15 +47,13 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned u4 __attribute__((ext_vector_type(4)));
 
-constexpr int KB = 32;                 // Cholesky vectors per chunk (MFMA k)
+constexpr int KB = 16;                 // Cholesky vectors per chunk (MFMA k of the build)
 constexpr int NPL = 4;                 // planes: re_hi, re_lo, im_hi, im_lo
-constexpr int CHUNK = NPL * NS * KB;   // bf16 per block per chunk (16 KB)
+constexpr int CHUNK = NPL * NS * KB;   // bf16 per block per chunk (8 KB): [plane][64][16]
 constexpr int VT = NPL * NS * NS;      // bf16 per V tile (32 KB)
-// LDS rows are padded so that the 8 lanes of one 16-byte LDS read phase hit
-// distinct banks: operand rows of 32 bf16 (64 B) get a stride of 40 (80 B),
-// V rows of 64 bf16 (128 B) a stride of 72 (144 B).
-constexpr int KBP = KB + 8;
-constexpr int CHUNKP = NPL * NS * KBP;  // padded chunk in LDS
+// LDS rows of the contraction's V tiles are padded so that the 8 lanes of
+// one 16-byte LDS read phase hit distinct banks: rows of 64 bf16 (128 B)
+// get a stride of 72 (144 B).
 constexpr int NSP = NS + 8;
 constexpr int VTP = NPL * NS * NSP;     // padded V tile in LDS
 
@@ -84,7 +91,7 @@ __device__ inline double2 load_c(const void* p, lrcc_dtype dt, size_t i) {
 
 __device__ inline long pidx(long p, long q, long n) { return p * (2 * n - p - 1) / 2 + (q - p - 1); }
 
-// L -> Ls16[A][C][chunk][plane][64 (a,c)][32 P]
+// L -> Ls16[A][C][chunk][plane][64 (a,c)][16 P]
 __global__ void k_stage_L16(const void* __restrict__ L, lrcc_dtype dt, int v, int nchol, int nbv,
                             int ncp, int form, __bf16* __restrict__ Ls) {
   const long total = (long)nbv * nbv * ncp * NS;  // (block, P, slot)
@@ -153,207 +160,266 @@ __global__ void k_split_x16(long plane, long Mp, const double* __restrict__ x,
 }
 
 // ---------------------------------------------------------------------------
-// V panel build.  Waves 0,1 build W1 rows (a,c) 0-31 / 32-63 x all (b,d);
-// waves 2,3 build W2 rows (a,d) likewise x all (b,c).
-// Tile index, within the panel that starts at block pair ab0, of the upper
-// tile (ab0 + abl, cd), cd >= ab0 + abl: rows of the triangle one after another.
+// Integral build.  Tile index, within the panel that starts at block pair
+// ab0, of the upper tile (ab0 + abl, cd), cd >= ab0 + abl: rows of the
+// triangle one after another.
 __device__ __forceinline__ long panel_tile(int nbp, int ab0, int abl, int cd) {
   return (long)abl * nbp - (long)abl * ab0 - (long)abl * (abl - 1) / 2 + (cd - ab0 - abl);
 }
 
-// Workgroup w < ptiles: upper tile order[w]; w >= ptiles: its mirror when L
-// is not Hermitian (otherwise, or on the diagonal, nothing to do).
-__global__ __launch_bounds__(WG, 2) void k_vbuild(const __bf16* __restrict__ Ls,
-                                                  const int* __restrict__ tab,
-                                                  const int* __restrict__ order,
-                                                  const int* __restrict__ nonherm, int nbv,
-                                                  int nbp, int ncp, int v, int ab0, long ptiles,
-                                                  __bf16* __restrict__ Vdir,
-                                                  __bf16* __restrict__ Vmir) {
-  // two-chunk ring of column-side buffers during the build, then W1 and W2
-  // (f32, rows padded to VR)
-  constexpr int VR = NS + 1;
-  constexpr int LDSB = 4 * CHUNKP > 2 * 4 * NS * VR ? 4 * CHUNKP : 2 * 4 * NS * VR;
-  __shared__ __attribute__((aligned(16))) __bf16 lds[LDSB];  // 80 KB
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ f16v mfma32(bf8 a, bf8 b, f16v c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// acc += x * y for real operands given as (hi, lo): hi*hi + hi*lo + lo*hi
+__device__ __forceinline__ f16v mac3_32(bf8 xh, bf8 xl, bf8 yh, bf8 yl, f16v acc) {
+  acc = mfma32(xh, yh, acc);
+  acc = mfma32(xh, yl, acc);
+  acc = mfma32(xl, yh, acc);
+  return acc;
+}
+
+// Block-pair index of the virtual blocks (C, D), C <= D.
+__device__ __forceinline__ int bp_index(int C, int D, int nbv) {
+  return C * nbv - C * (C - 1) / 2 + (D - C);
+}
+
+// Byte offset, inside one [64 rows][16 P] plane (2 KB) of a staged block
+// chunk held in LDS, of the 16-byte half h (P 8h .. 8h + 7) of row r.  The
+// halves of rows 4..7 (mod 8) are swapped, so that the eight rows one phase
+// of a 16-byte LDS read covers fall on eight distinct 16-byte bank groups.
+__device__ __forceinline__ int lds_half(int r, int h) {
+  return r * 32 + ((h ^ ((r >> 2) & 1)) << 4);
+}
+
+// Output row / column of element r of a 32x32 MFMA accumulator in lane l
+// (32x32x16: rows in four groups of eight, lanes 32..63 holding rows 4..7 of
+// each group).
+__device__ __forceinline__ int out_row32(int l, int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
+
+constexpr int BW = 8;                    // waves of a build workgroup (two per SIMD)
+constexpr int BWG = 64 * BW;
+constexpr int CHB = CHUNK * 2;           // bytes per staged block chunk (8 KB)
+constexpr int VR = NS + 1;               // padded row of the W staging areas (floats)
+constexpr int AREA = 2 * NS * VR;        // floats per W staging area (re, im planes)
+constexpr int BLDS = (2 * 8 * CHB > 4 * AREA * 4) ? 2 * 8 * CHB : 4 * AREA * 4;
+
+// One workgroup per item (AB, CG, DG): the panel row ab = ab0 + abl with
+// blocks (A, B), the block groups CG = {2 cg, 2 cg + 1} and DG = {2 dg,
+// 2 dg + 1}, cg <= dg.  Its tiles are (AB, C D) for C in CG, D in DG with
+// C <= D < nbv and cd = bp(C, D) >= ab.
+//
+// Roles.  A tile V(XY, ZW)[(x y), (z w)] = 2 (W1[(x z), (y w)] - W2[(x w),
+// (y z)]) with W1 = sum_P L_XZ (x) L_YW and W2 = sum_P L_XW (x) L_YZ.  In the
+// upper pass X = A, Y = B, Z = C_r, W = D_j: W1 is the 128 x 128 product of
+// the blocks (A, C_0..1) with (B, D_0..1), W2 that of (A, D_0..1) with
+// (B, C_0..1).  In the mirror pass (non-Hermitian L only) X = C_r, Y = D_j,
+// Z = A, W = B, which gives V(CD, AB) itself: W1 from (C_0..1, A) x
+// (D_0..1, B), W2 from (C_0..1, B) x (D_0..1, A).
+//
+// The eight operand blocks of a chunk of 16 Cholesky vectors go straight
+// from global memory into a two-chunk LDS ring (8 KB each, slot s loaded by
+// wave s); wave w < 4 computes the 64 x 64 quadrant (w >> 1, w & 1) of W1
+// from slots (w >> 1) and 2 + (w & 1), wave 4 + q the quadrant (q >> 1, q & 1)
+// of W2 from slots 4 + (q >> 1) and 6 + (q & 1): 2 x 2 MFMAs of 32 x 32 per
+// plane product, 48 per chunk.  Then, two tiles at a time, the quadrants go to
+// LDS at their V positions and every thread forms, splits and stores V.
+__global__ __launch_bounds__(BWG, 1) void k_vbuild(const __bf16* __restrict__ Ls,
+                                                   const int* __restrict__ tab,
+                                                   const int2* __restrict__ items,
+                                                   const int* __restrict__ nonherm, int nbv,
+                                                   int nbp, int nch, int v, int ab0,
+                                                   __bf16* __restrict__ Vdir,
+                                                   __bf16* __restrict__ Vmir) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[BLDS];
   const bool nh = *nonherm != 0;
-  const bool second = blockIdx.x >= ptiles;
-  if (second && !nh) return;
-  const int tile = order[second ? blockIdx.x - ptiles : blockIdx.x];
-  const int abl = tile / nbp, cdu = tile - abl * nbp, abu = ab0 + abl;
-  if (second && abu == cdu) return;
-  const long t = panel_tile(nbp, ab0, abl, cdu);
-  // built pair (ab, cd): the upper tile, or its mirror (cdu, abu)
-  const int ab = second ? cdu : abu, cd = second ? abu : cdu;
-  const int pAB = tab[ab], pCD = tab[cd];
-  const int A = pAB >> 16, B = pAB & 0xffff, C = pCD >> 16, D = pCD & 0xffff;
+  const int2 item = items[blockIdx.x];
+  const int abl = item.x, cg = item.y >> 16, dg = item.y & 0xffff;
+  const int ab = ab0 + abl;
+  const int A = tab[ab] >> 16, B = tab[ab] & 0xffff;
+  const int Cb[2] = {2 * cg, 2 * cg + 1}, Db[2] = {2 * dg, 2 * dg + 1};
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int wsel = wave >> 1, rb0 = (wave & 1) * 2;
-  const int nch = ncp / KB;
-  // row side (per wave, straight from global memory into registers) and
-  // column side (shared by the two waves of one product, staged in LDS):
-  // W1 = L_AC (x) L_BD for waves 0, 1; W2 = L_AD (x) L_BC for waves 2, 3
-  const __bf16* const grow = Ls + (size_t)(wsel ? A * nbv + D : A * nbv + C) * nch * CHUNK;
-  const __bf16* const gcol[2] = {Ls + (size_t)(B * nbv + D) * nch * CHUNK,
-                                 Ls + (size_t)(B * nbv + C) * nch * CHUNK};
+  // operand slots read by this wave, and whether it computes W1 or W2
+  const bool w1 = wave < 4;
+  const int q = w1 ? wave : wave - 4;
+  const int aslot = (w1 ? 0 : 4) + (q >> 1), bslot = (w1 ? 2 : 6) + (q & 1);
 
-  f4 wr[2][4], wi[2][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      wr[i][j] = (f4){0, 0, 0, 0};
-      wi[i][j] = wr[i][j];
+  for (int mode = 0; mode < (nh ? 2 : 1); ++mode) {
+    // staged block loaded by this wave into ring slot `wave` (blocks past the
+    // last virtual block, in a last group of one, are replaced by that last
+    // block: in bounds, and their tiles are never stored)
+    int blk;
+    {
+      const int t = wave & 1;
+      const int Ct = min(Cb[t], nbv - 1), Dt = min(Db[t], nbv - 1);
+      if (mode == 0) {
+        const int rowb[4] = {A * nbv + Ct, B * nbv + Dt, A * nbv + Dt, B * nbv + Ct};
+        blk = rowb[wave >> 1];
+      } else {
+        const int rowb[4] = {Ct * nbv + A, Dt * nbv + B, Ct * nbv + B, Dt * nbv + A};
+        blk = rowb[wave >> 1];
+      }
     }
-
-  constexpr int V16 = CHUNK / 8;        // 16-byte vectors per block chunk (1024)
-  constexpr int KPB = V16 / WG;         // per thread per block (4)
-  u4 pf[2 * KPB];
-  // row-side fragments of even and odd chunks: [parity][MFMA block i][plane]
-  bf8 ra[2][2][4];
-  auto fetch_col = [&](int pc) {
+    const char* const gsrc = reinterpret_cast<const char*>(Ls + (size_t)blk * nch * CHUNK);
+    // piece k (1 KB) of this wave's slot: plane k >> 1, rows 32 (k & 1) ..
+    // + 31; lane l writes LDS bytes 16 l of the piece, which hold row
+    // 32 (k & 1) + l / 2, half (l & 1) as placed by lds_half, so it reads
+    // the global half (l & 1) ^ (bit 2 of its row) (the same for both row
+    // halves of a plane: 32 is a multiple of 8)
+    const int goff = (lane >> 1) * 32 + (((lane & 1) ^ ((lane >> 3) & 1)) << 4);
+    auto issue = [&](int c, unsigned char* buf) {
+      const char* src = gsrc + (size_t)c * CHB + goff;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const u4* src = reinterpret_cast<const u4*>(gcol[q] + (size_t)pc * CHUNK);
-#pragma unroll
-      for (int k = 0; k < KPB; ++k) pf[q * KPB + k] = src[k * WG + threadIdx.x];
-    }
-  };
-  // A fragment of MFMA block i, plane p: row 16 (rb0 + i) + li, P = 8 lk .. 8 lk + 7
-  auto fetch_row = [&](int pc, int par) {
+      for (int k = 0; k < 8; ++k)
+        __builtin_amdgcn_global_load_lds(
+            src + k * 1024,
+            (__attribute__((address_space(3))) void*)(buf + wave * CHB + k * 1024), 16, 0, 0);
+    };
+    f16v wr[2][2], wi[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
-        ra[par][i][p] = *reinterpret_cast<const bf8*>(
-            grow + (size_t)pc * CHUNK + (p * NS + 16 * (rb0 + i) + li) * KB + 8 * lk);
-  };
-  auto store_col = [&](__bf16* buf) {
+      for (int j = 0; j < 2; ++j) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int k = 0; k < KPB; ++k) {
-        // vector e of the chunk: plane-row (e / 4), 8-bf16 part (e % 4)
-        const int e = k * WG + threadIdx.x;
-        *reinterpret_cast<u4*>(buf + q * CHUNKP + (e >> 2) * KBP + (e & 3) * 8) = pf[q * KPB + k];
+        for (int e = 0; e < 16; ++e) wr[i][j][e] = 0.f;
+        wi[i][j] = wr[i][j];
       }
-  };
-  // W += A B over one chunk: re += Ar Br - Ai Bi, im += Ar Bi + Ai Br (the
-  // minus sign on the Bi operand)
-  auto mma = [&](const __bf16* buf, int par) {
-    // column operands: [plane][row][32 P], lane reads 8 consecutive P at 8*lk
-    const __bf16* lb = buf + wsel * CHUNKP + 8 * lk;
+    // W += A B over one chunk: re += Ar Br - Ai Bi, im += Ar Bi + Ai Br (the
+    // minus sign on the Bi operand)
+    // this lane's operand bytes in a plane: row (lane & 31) (+ 32 for the
+    // second MFMA block, which leaves bit 2 of the row unchanged), half lane >> 5
+    const int loff = lds_half(lane & 31, lane >> 5);
+    auto mma = [&](const unsigned char* buf) {
+      const unsigned char* as = buf + aslot * CHB + loff;
+      const unsigned char* bs = buf + bslot * CHB + loff;
+      bf8 a[2][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      bf8 b[4];
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
-        b[p] = *reinterpret_cast<const bf8*>(lb + (p * NS + 16 * j + li) * KBP);
-      const bf8 nb2 = neg(b[2]), nb3 = neg(b[3]);
+        for (int p = 0; p < 4; ++p)
+          a[i][p] = *reinterpret_cast<const bf8*>(as + p * 2048 + i * 1024);
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const bf8 (&a)[4] = ra[par][i];
-        wr[i][j] = mac3(a[0], a[1], b[0], b[1], wr[i][j]);  // Ar Br
-        wr[i][j] = mac3(a[2], a[3], nb2, nb3, wr[i][j]);    // -Ai Bi
-        wi[i][j] = mac3(a[0], a[1], b[2], b[3], wi[i][j]);  // Ar Bi
-        wi[i][j] = mac3(a[2], a[3], b[0], b[1], wi[i][j]);  // Ai Br
+      for (int j = 0; j < 2; ++j) {
+        bf8 b[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          b[p] = *reinterpret_cast<const bf8*>(bs + p * 2048 + j * 1024);
+        const bf8 nb2 = neg(b[2]), nb3 = neg(b[3]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          wr[i][j] = mac3_32(a[i][0], a[i][1], b[0], b[1], wr[i][j]);  // Ar Br
+          wr[i][j] = mac3_32(a[i][2], a[i][3], nb2, nb3, wr[i][j]);    // -Ai Bi
+          wi[i][j] = mac3_32(a[i][0], a[i][1], b[2], b[3], wi[i][j]);  // Ar Bi
+          wi[i][j] = mac3_32(a[i][2], a[i][3], b[0], b[1], wi[i][j]);  // Ai Br
+        }
       }
+    };
+    // Two-chunk ring: chunk c sits in buffer c & 1.  At the top of chunk c
+    // every wave waits for its own loads of c, the barrier makes all of them
+    // visible and shows that chunk c - 1 is no longer read, and chunk c + 1
+    // is requested into the other buffer (the last chunk again on the last
+    // pass: a branch-free loop body).
+    __syncthreads();  // LDS may still hold the previous pass's W areas
+    issue(0, lds);
+    for (int c = 0; c < nch; ++c) {
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads of chunk c landed
+      __syncthreads();
+      issue(min(c + 1, nch - 1), lds + ((c + 1) & 1) * 8 * CHB);
+      mma(lds + (c & 1) * 8 * CHB);
     }
-  };
-  // Two-chunk ring: chunk pc sits in buffer pc & 1 (row side in registers
-  // ra[pc & 1]).  The next chunk is requested at the start of a chunk and
-  // its column side stored to the free buffer at the end, so one barrier per
-  // chunk suffices.  The loads of the last chunk repeat it (branch-free).
-  // (Scheduling barriers keep each load group where it is issued and the
-  // column loads ahead of the row loads, so that storing the column side
-  // waits for those alone.)
-  __bf16* const ring[2] = {lds, lds + 2 * CHUNKP};
-  fetch_col(0);
-  __builtin_amdgcn_sched_barrier(0);
-  fetch_row(0, 0);
-  store_col(ring[0]);
-  for (int pc = 0; pc + 1 < nch; pc += 2) {
-    __syncthreads();
-    fetch_col(pc + 1);
-    __builtin_amdgcn_sched_barrier(0);
-    fetch_row(pc + 1, 1);
-    __builtin_amdgcn_sched_barrier(0);
-    mma(ring[0], 0);
-    __builtin_amdgcn_sched_barrier(0);
-    store_col(ring[1]);
-    __syncthreads();
-    fetch_col(min(pc + 2, nch - 1));
-    __builtin_amdgcn_sched_barrier(0);
-    fetch_row(min(pc + 2, nch - 1), 0);
-    __builtin_amdgcn_sched_barrier(0);
-    mma(ring[1], 1);
-    __builtin_amdgcn_sched_barrier(0);
-    store_col(ring[0]);
-  }
-  if (nch & 1) {  // the last chunk of an odd count
-    __syncthreads();
-    mma(ring[0], 0);
-  }
-  __syncthreads();
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // the spare load has landed
+    __syncthreads();                     // every wave is done with the ring
 
-  // W1 and W2 to LDS, each already at its V position [ab slot][cd slot]
-  // (plain stores by the two wave pairs at once), then the store loop forms
-  // V = 2 (W1 - W2) on the live slots (a < b, c < d, inside v) on the fly
-  float* const W1r = reinterpret_cast<float*>(lds);
-  float* const W1i = W1r + NS * VR;
-  float* const W2r = W1i + NS * VR;
-  float* const W2i = W2r + NS * VR;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int ii = 16 * (rb0 + i) + out_row(lk, r), jj = 16 * j + li;
-        // W1: ii = (a,c), jj = (b,d);  W2: ii = (a,d), jj = (b,c)
-        const int idx = wsel == 0
-                            ? ((ii >> 3) * TB + (jj >> 3)) * VR + (ii & 7) * TB + (jj & 7)
-                            : ((ii >> 3) * TB + (jj >> 3)) * VR + (jj & 7) * TB + (ii & 7);
-        float* const wr_ = wsel == 0 ? W1r : W2r;
-        float* const wi_ = wsel == 0 ? W1i : W2i;
-        wr_[idx] = wr[i][j][r];
-        wi_[idx] = wi[i][j][r];
+    // ---- tiles, two at a time: round t holds tiles (C_0, D_t) and (C_1, D_t).
+    // Tile (r, j) takes W1 quadrant (r, j) (wave 2 r + j) and W2 quadrant
+    // (j, r) in the upper pass (rows X W = A D_j), (r, j) in the mirror pass
+    // (rows X W = C_r B): wave 4 + 2 j + r, or 4 + 2 r + j.
+    float* const area = reinterpret_cast<float*>(lds);
+    for (int t = 0; t < 2; ++t) {
+      int k = -1;  // area of this wave's quadrant in this round (0, 1: W1; 2, 3: W2)
+      if (w1) {
+        if ((q & 1) == t) k = q >> 1;
+      } else if (mode == 0) {
+        if ((q >> 1) == t) k = 2 + (q & 1);
+      } else {
+        if ((q & 1) == t) k = 2 + (q >> 1);
       }
-  __syncthreads();
-  // split and write the tile as [plane][row slot][column slot]: the built
-  // pair's V (rows ab) to the upper slot t, or, for a mirror workgroup, to
-  // the mirror slot; for Hermitian L the conjugate transpose goes to the
-  // mirror slot as well (V(cd, ab) = V(ab, cd)^H)
-  auto store = [&](__bf16* dst, bool ct) {
-    for (int w = threadIdx.x; w < NS * (NS / 8); w += WG) {
-      const int row = w >> 3, q = (w & 7) * 8;
-      bf8 rh, rl, ih, il;
+      if (k >= 0) {
+        float* const ar = area + k * AREA;
+        float* const ai = ar + NS * VR;
+        // (the empty asm makes the lane index opaque here, so the index
+        // arithmetic below is not computed ahead of the chunk loop and kept
+        // live across it)
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        // element V[ab][cd] of the built pair
-        const int ab = ct ? q + e : row, cd = ct ? row : q + e;
-        const int al = ab >> 3, bl = ab & 7, cl = cd >> 3, dl = cd & 7;
-        const bool live = (A < B || al < bl) && (B * TB + bl < v) && (C < D || cl < dl) &&
-                          (D * TB + dl < v);
-        const int idx = ab * VR + cd;
-        const float vr = live ? 2.f * (W1r[idx] - W2r[idx]) : 0.f;
-        const float vi = live ? 2.f * (W1i[idx] - W2i[idx]) : 0.f;
-        __bf16 h, l;
-        split(vr, h, l);
-        rh[e] = h;
-        rl[e] = l;
-        split(ct ? -vi : vi, h, l);
-        ih[e] = h;
-        il[e] = l;
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+              const int ii = 32 * i + out_row32(ln, e), jj = 32 * j + (ln & 31);
+              // W1: ii = (x, z), jj = (y, w);  W2: ii = (x, w), jj = (y, z)
+              const int idx = w1 ? ((ii >> 3) * TB + (jj >> 3)) * VR + (ii & 7) * TB + (jj & 7)
+                                 : ((ii >> 3) * TB + (jj >> 3)) * VR + (jj & 7) * TB + (ii & 7);
+              ar[idx] = wr[i][j][e];
+              ai[idx] = wi[i][j][e];
+            }
       }
-      *reinterpret_cast<bf8*>(dst + 0 * NS * NS + row * NS + q) = rh;
-      *reinterpret_cast<bf8*>(dst + 1 * NS * NS + row * NS + q) = rl;
-      *reinterpret_cast<bf8*>(dst + 2 * NS * NS + row * NS + q) = ih;
-      *reinterpret_cast<bf8*>(dst + 3 * NS * NS + row * NS + q) = il;
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int C = Cb[r], D = Db[t];
+        if (C >= nbv || D >= nbv || C > D) continue;  // uniform
+        const int cd = bp_index(C, D, nbv);
+        if (cd < ab || (mode == 1 && cd == ab)) continue;
+        const long tt = panel_tile(nbp, ab0, abl, cd);
+        const int X = mode == 0 ? A : C, Y = mode == 0 ? B : D;
+        const int Z = mode == 0 ? C : A, W = mode == 0 ? D : B;
+        const float* const w1r = area + r * AREA;
+        const float* const w1i = w1r + NS * VR;
+        const float* const w2r = area + (2 + r) * AREA;
+        const float* const w2i = w2r + NS * VR;
+        // write [plane][row slot][column slot]; ct: the conjugate transpose
+        auto store = [&](__bf16* dst, bool ct) {
+          int row = threadIdx.x >> 3, qc = (threadIdx.x & 7) * 8;
+          asm volatile("" : "+v"(row), "+v"(qc));  // computed here, not ahead of the loop
+          bf8 rh, rl, ih, il;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            // element V[xy][zw] of the tile built here
+            const int xy = ct ? qc + e : row, zw = ct ? row : qc + e;
+            const int xl = xy >> 3, yl = xy & 7, zl = zw >> 3, wl = zw & 7;
+            const bool live = (X < Y || xl < yl) && (Y * TB + yl < v) && (Z < W || zl < wl) &&
+                              (W * TB + wl < v);
+            const int idx = xy * VR + zw;
+            const float vr = live ? 2.f * (w1r[idx] - w2r[idx]) : 0.f;
+            const float vi = live ? 2.f * (w1i[idx] - w2i[idx]) : 0.f;
+            __bf16 hi, lo;
+            split(vr, hi, lo);
+            rh[e] = hi;
+            rl[e] = lo;
+            split(ct ? -vi : vi, hi, lo);
+            ih[e] = hi;
+            il[e] = lo;
+          }
+          *reinterpret_cast<bf8*>(dst + 0 * NS * NS + row * NS + qc) = rh;
+          *reinterpret_cast<bf8*>(dst + 1 * NS * NS + row * NS + qc) = rl;
+          *reinterpret_cast<bf8*>(dst + 2 * NS * NS + row * NS + qc) = ih;
+          *reinterpret_cast<bf8*>(dst + 3 * NS * NS + row * NS + qc) = il;
+        };
+        if (mode == 0) {
+          store(Vdir + tt * VT, false);
+          if (!nh && cd != ab) store(Vmir + tt * VT, true);
+        } else {
+          store(Vmir + tt * VT, false);
+        }
+      }
+      __syncthreads();  // the areas are rewritten in the next round
     }
-  };
-  store((second ? Vmir : Vdir) + t * VT, false);
-  if (!second && !nh && abu != cdu) store(Vmir + t * VT, true);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -601,6 +667,54 @@ size_t bf16x3_panel_bytes(const Geom& g, int ab0, int n) {
   return (size_t)bf16x3_panel_tiles(g, ab0, n) * 2 * VT * sizeof(__bf16);  // tile + mirror
 }
 
+// Build items of the panels starting at starts[k] (rows [starts[k],
+// starts[k + 1])), concatenated panel after panel (off[k] = first item of
+// panel k).  An item (abl, cg << 16 | dg) exists when at least one of its
+// tiles lies in the upper triangle: its last tile (min(C_max, D_max), D_max)
+// has cd >= ab.  Within a panel the items are sorted by super-tile (sw-wide
+// ranges of A and B, sw/2-wide ranges of the block groups), and each XCD
+// receives a contiguous share (workgroup w runs on XCD w mod nx, as the
+// (w / nx)-th of that XCD's workgroups), so the workgroups one XCD runs at a
+// time share Cholesky blocks in its L2.
+void build_items(const Geom& g, const std::vector<int>& starts, int sw, int nx,
+                 std::vector<int2>* items, std::vector<long>* off) {
+  const int nbv = g.nbv, ng = (nbv + 1) / 2, sg = std::max(1, sw / 2);
+  std::vector<int> A(g.nbp), B(g.nbp);
+  for (int a = 0, k = 0; a < nbv; ++a)
+    for (int b = a; b < nbv; ++b, ++k) {
+      A[k] = a;
+      B[k] = b;
+    }
+  auto bp = [&](int C, int D) { return C * nbv - C * (C - 1) / 2 + (D - C); };
+  items->clear();
+  off->assign(1, 0);
+  for (size_t k = 0; k + 1 < starts.size(); ++k) {
+    const int ab0 = starts[k], ab1 = starts[k + 1];
+    struct It {
+      long key;
+      int abl, cgdg;
+    };
+    std::vector<It> all;
+    for (int ab = ab0; ab < ab1; ++ab)
+      for (int cg = 0; cg < ng; ++cg)
+        for (int dg = cg; dg < ng; ++dg) {
+          const int Cmax = std::min(2 * cg + 1, nbv - 1), Dmax = std::min(2 * dg + 1, nbv - 1);
+          if (bp(std::min(Cmax, Dmax), Dmax) < ab) continue;
+          const long key = (((long)(A[ab] / sw) * 4096 + B[ab] / sw) * 4096 + cg / sg) * 4096 +
+                           dg / sg;
+          all.push_back({key, ab - ab0, (cg << 16) | dg});
+        }
+    std::stable_sort(all.begin(), all.end(), [](const It& x, const It& y) { return x.key < y.key; });
+    const long total = (long)all.size(), q = total / nx, r = total % nx;
+    for (long w = 0; w < total; ++w) {
+      const long x = w % nx, j = w / nx;
+      const It& e = all[x * q + std::min<long>(x, r) + j];
+      items->push_back(make_int2(e.abl, e.cgdg));
+    }
+    off->push_back((long)items->size());
+  }
+}
+
 // Panels of consecutive block pairs, each as many rows as fit in `cap` bytes
 // (at least one): build, then contract.  Sb (zeroed by the caller, FP64 or
 // FP32 planes) receives the panels' shares.  *nonherm (device) selects the
@@ -610,20 +724,43 @@ hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* 
                       hipStream_t st) {
   if (g.nbp == 0 || g.Mp == 0) return hipSuccess;
   const int nmb = (int)((g.Mp + 127) / 128);
+  std::vector<int> starts;
   for (int ab0 = 0, n = 1; ab0 < g.nbp; ab0 += n) {
     n = 1;
     while (ab0 + n < g.nbp && bf16x3_panel_bytes(g, ab0, n + 1) <= cap) ++n;
+    starts.push_back(ab0);
+  }
+  starts.push_back(g.nbp);
+  // build items of every panel: computed and uploaded once per geometry
+  const int nx = std::max(1, h->ncu / 32);  // XCDs
+  const int sw = h->order_s[LRCC_BF16X3] > 0 ? h->order_s[LRCC_BF16X3] : 4;
+  std::vector<long> key = {g.nbv, nx, sw};
+  key.insert(key.end(), starts.begin(), starts.end());
+  if (key != h->bitems_key) {
+    std::vector<int2> items;
+    build_items(g, starts, sw, nx, &items, &h->bitems_off);
+    h->bitems_key.clear();
+    hipError_t e = h->bitems.ensure(items.size() * sizeof(int2));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h->bitems.p, items.data(), items.size() * sizeof(int2),
+                         hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // `items` goes out of scope
+    if (e != hipSuccess) return e;
+    h->bitems_key = key;
+  }
+  for (size_t k = 0; k + 1 < starts.size(); ++k) {
+    const int ab0 = starts[k], n = starts[k + 1] - starts[k];
     const long pt = bf16x3_panel_tiles(g, ab0, n);
-    if (2 * pt > 0x7fffffffL || (long)nmb * (g.nbp - ab0) > 0x7fffffffL)
+    const long nit = h->bitems_off[k + 1] - h->bitems_off[k];
+    if (2 * pt > 0x7fffffffL || nit > 0x7fffffffL || (long)nmb * (g.nbp - ab0) > 0x7fffffffL)
       return hipErrorInvalidValue;
-    lrcc_status ost;
-    const int* ord = tile_order(h, g, ab0, ab0 + n, true, LRCC_BF16X3, &ost);
-    if (ost != LRCC_OK) return hipErrorUnknown;
     __bf16* Vdir = static_cast<__bf16*>(Vws);
     __bf16* Vmir = Vdir + (size_t)pt * VT;
-    hipLaunchKernelGGL(k_vbuild, dim3((unsigned)(2 * pt)), dim3(WG), 0, st,
-                       static_cast<const __bf16*>(Ls), tab, ord, nonherm, g.nbv, g.nbp, g.ncp,
-                       g.v, ab0, pt, Vdir, Vmir);
+    if (nit > 0)
+      hipLaunchKernelGGL(k_vbuild, dim3((unsigned)nit), dim3(BWG), 0, st,
+                         static_cast<const __bf16*>(Ls), tab,
+                         h->bitems.as<int2>() + h->bitems_off[k], nonherm, g.nbv, g.nbp,
+                         g.ncp / KB, g.v, ab0, Vdir, Vmir);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // parts per contraction list: the fewest that fill whole rounds of the
@@ -631,7 +768,8 @@ hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* 
     const long items = (long)nmb * (g.nbp - ab0), slots = 2L * std::max(1, h->ncu);
     int nsplit = 1;
     double best = 0;
-    for (int sp = 1; sp <= 8 && (long)sp * 4 <= g.nbp; ++sp) {
+    // (deterministic mode: one part, no atomic additions)
+    for (int sp = 1; sp <= (h->deterministic ? 1 : 8) && (long)sp * 4 <= g.nbp; ++sp) {
       const long tot = sp * items, rounds = (tot + slots - 1) / slots;
       const double eff = (double)tot / (double)(rounds * slots);
       if (eff > best + 1e-9) {
@@ -642,7 +780,6 @@ hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* 
     }
     if ((long)nsplit * items > 0x7fffffffL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(nsplit * items));
-    const int nx = std::max(1, h->ncu / 32);  // XCDs
     if (acc64)
       hipLaunchKernelGGL(k_contract<double>, grid, dim3(WG), 0, st,
                          static_cast<const __bf16*>(Xb), Vdir, Vmir, g.nbp, (int)g.Mp, nmb, ab0,

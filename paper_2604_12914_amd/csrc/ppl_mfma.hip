@@ -709,10 +709,86 @@ __global__ __launch_bounds__(64 * NW, 1) void k_ppl_3m(const T* __restrict__ Ls,
 }
 
 
+// Deterministic ladder (a debugging mode): one workgroup per block pair AB
+// owns sigma[:, AB].  It builds every tile V(AB, CD), CD = 0 .. nbp - 1 in
+// ascending order (no Hermitian halving: each tile is built by the
+// workgroup of its row block pair), and adds X[:, CD] V(AB, CD)^T to its
+// rows with plain read-modify-writes; each wave owns whole 16-row chunks.
+// Every run performs the same additions in the same order, so sigma is
+// reproducible bit for bit, at the cost of twice the builds and nbp
+// workgroups only.
+template <typename T, typename TA, int KC>
+__global__ __launch_bounds__(WG, 1) void k_ppl_det(const T* __restrict__ Ls,
+                                                   const T* __restrict__ Xb,
+                                                   TA* __restrict__ Sb,
+                                                   const int* __restrict__ tab, int nbv, int nbp,
+                                                   int ncp, int Mp, int v) {
+  typedef typename Acc<T>::t acc_t;
+  typedef typename Vec16<T>::t vec_t;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int NX = 16 / VN;
+  __shared__ __attribute__((aligned(16))) T lds[Smem<T, KC>::elems];
+  const int ab = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const size_t plane = (size_t)nbp * Mp * NS;
+  TA* const sr_g = Sb + (size_t)ab * Mp * NS;
+  TA* const si_g = sr_g + plane;
+  const T* const Vr = lds;
+  const T* const Vi = lds + NS * VS;
+  for (int cd = 0; cd < nbp; ++cd) {
+    build_v_4m<T, KC, 1, false, 4>(Ls, tab, nbv, ncp, v, ab, cd, lds);
+    const T* xr_g = Xb + (size_t)cd * Mp * NS;
+    const T* xi_g = xr_g + plane;
+    for (int mc = wave; mc < Mp / 16; mc += 4) {
+      const int m0 = mc * 16;
+      T xr[16], xi[16];
+      const vec_t* pr = reinterpret_cast<const vec_t*>(xr_g + (size_t)(m0 + li) * NS + 16 * lk);
+      const vec_t* pi = reinterpret_cast<const vec_t*>(xi_g + (size_t)(m0 + li) * NS + 16 * lk);
+#pragma unroll
+      for (int k = 0; k < NX; ++k) {
+        const vec_t a = pr[k], b = pi[k];
+#pragma unroll
+        for (int t = 0; t < VN; ++t) {
+          xr[k * VN + t] = a[t];
+          xi[k * VN + t] = b[t];
+        }
+      }
+      acc_t sr[4], si[4];
+      contract_rows<T, false, 4, false>(Vr, Vi, xr, xi, 0, sr, si);
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const size_t o = (size_t)(m0 + out_row<T>(lk, r)) * NS + 16 * n + li;
+          sr_g[o] += (TA)sr[n][r];
+          si_g[o] += (TA)si[n][r];
+        }
+    }
+    // (build_v_4m starts with a barrier: the next tile waits for every wave
+    // to finish reading this one)
+  }
+}
+
 constexpr int KC64 = 16;
 constexpr int KC32 = 32;
 
 }  // namespace
+
+hipError_t ppl_det_launch(lrcc_prec prec, bool acc64, const Geom& g, const void* Ls,
+                          const void* Xb, void* Sb, const int* tab, hipStream_t st) {
+  if (g.nbp == 0 || g.Mp == 0) return hipSuccess;
+#define LRCC_LD(T, TA, KC)                                                                      \
+  hipLaunchKernelGGL((k_ppl_det<T, TA, KC>), dim3(g.nbp), dim3(WG), 0, st,                     \
+                     static_cast<const T*>(Ls), static_cast<const T*>(Xb), static_cast<TA*>(Sb), \
+                     tab, g.nbv, g.nbp, g.ncp, (int)g.Mp, g.v)
+  if (prec == LRCC_FP64) LRCC_LD(double, double, KC64);
+  else if (prec == LRCC_FP32 && acc64) LRCC_LD(float, double, KC32);
+  else if (prec == LRCC_FP32) LRCC_LD(float, float, KC32);
+  else return hipErrorNotSupported;
+#undef LRCC_LD
+  return hipGetLastError();
+}
 
 // Launch variants of the 4M kernel (chosen by the tuner; the environment
 // variable LRCC_VARIANT sets the default): 1 = one workgroup per CU, chunks

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <memory>
 #include <vector>
 
@@ -62,20 +63,31 @@ __device__ __forceinline__ Elem locate(const Dims& d, int r, long f, const int* 
   return e;
 }
 
+// Sum over the 64 lanes of a wavefront by lane exchanges (a fixed butterfly:
+// the same order on every run); every lane receives the sum.
+__device__ __forceinline__ double2 wave_sum(double2 x) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    x.x += __shfl_xor(x.x, m, 64);
+    x.y += __shfl_xor(x.y, m, 64);
+  }
+  return x;
+}
+
+// Sum over the workgroup: wavefront sums, then one combine of the NT / 64
+// wave sums through LDS (sh: at least NT / 64 entries).  Every thread
+// receives the sum.
 template <int NT>
 __device__ __forceinline__ double2 block_sum(double2 x, double2* sh) {
-  const int t = threadIdx.x;
-  sh[t] = x;
+  x = wave_sum(x);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
   __syncthreads();
-#pragma unroll
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      sh[t].x += sh[t + s].x;
-      sh[t].y += sh[t + s].y;
-    }
-    __syncthreads();
-  }
   double2 r = sh[0];
+#pragma unroll
+  for (int k = 1; k < NT / 64; ++k) {
+    r.x += sh[k].x;
+    r.y += sh[k].y;
+  }
   __syncthreads();
   return r;
 }
@@ -174,14 +186,30 @@ __global__ __launch_bounds__(RB) void k_resid(Dims d, const double* __restrict__
       dots[j].y += ur * ei - ui * er;
     }
   }
+  // all 1 + mdim sums at once: wavefront sums by lane exchanges, the wave
+  // sums through LDS, one barrier, then thread q adds up quantity q
   const int nq = mdim + 1;
+  constexpr int NW = RB / 64;
   double2* pr = part + ((size_t)r * nq) * gridDim.x;
-  double2 t = block_sum<RB>(make_double2(rr, bb), sh);
-  if (threadIdx.x == 0) pr[blockIdx.x] = t;
-  for (int j = 0; j < mdim; ++j) {
-    if (!((vmask >> j) & 1u)) continue;
-    t = block_sum<RB>(dots[j], sh);
-    if (threadIdx.x == 0) pr[(size_t)(1 + j) * gridDim.x + blockIdx.x] = t;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double2 t = wave_sum(make_double2(rr, bb));
+  if (lane == 0) sh[wv] = t;
+#pragma unroll
+  for (int j = 0; j < MAXD; ++j) {
+    if (j >= mdim || !((vmask >> j) & 1u)) continue;  // uniform
+    t = wave_sum(dots[j]);
+    if (lane == 0) sh[(1 + j) * NW + wv] = t;
+  }
+  __syncthreads();
+  const int q = threadIdx.x;
+  if (q < nq && (q == 0 || ((vmask >> (q - 1)) & 1u))) {
+    double2 acc = sh[q * NW];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) {
+      acc.x += sh[q * NW + k].x;
+      acc.y += sh[q * NW + k].y;
+    }
+    pr[(size_t)q * gridDim.x + blockIdx.x] = acc;
   }
 }
 
@@ -459,6 +487,11 @@ __global__ void k_axpy1(long n, const double* __restrict__ x, double* __restrict
 }
 
 // Advance the device-resident iteration counter (one thread).
+__global__ void k_scale(long n, double a, double* __restrict__ x) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    x[e] *= a;
+}
+
 __global__ void k_inc(int* itp) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *itp += 1;
 }
@@ -522,6 +555,12 @@ struct Solver {
   double2* h_part = nullptr;
   int n_sigma64 = 0, n_sigma_lp = 0, iters_max = 0;
   std::vector<int> act;  // host view of the active flags
+  // per-iteration metrics (one JSON line per iteration; null: off)
+  FILE* metrics = nullptr;
+  const char* side = "right";
+  const char* phase = "fp64";
+  int sweep = 0;
+  std::chrono::steady_clock::time_point t0;
   ~Solver() {
     if (h_active) (void)hipHostFree(h_active);
     if (h_relres) (void)hipHostFree(h_relres);
@@ -679,13 +718,22 @@ lrcc_status apply_ppl(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul cm
   return LRCC_OK;
 }
 
-// s = the Jacobian's ladders applied to xin: the particle-particle ladder in
-// `prec` and, when the model includes it, the hole-hole ladder (FP64; its
-// npo^2 npv cost per right-hand side is small beside the ladder's).
+// s = the two-electron part of the Jacobian applied to xin: the particle-
+// particle ladder in `prec` alone or, when the model includes the hole-hole
+// ladder (and the ring term), the T = 0 doubles-doubles block of the
+// two-electron operator, 1/2 PPL + 1/2 HHL (+ RING) in the ladders' doubled
+// convention (the hole-hole ladder in FP64: its npo^2 npv cost per
+// right-hand side is small beside the ladder's; S.W holds the half).
 lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul cmul,
                         const void* ls) {
   lrcc_status st = apply_ppl(S, xin, prec, cmul, ls);
   if (st != LRCC_OK || !S.W || S.g.nchol == 0) return st;
+  {
+    const long n = 2 * S.d.plane;
+    hipLaunchKernelGGL(k_scale, dim3((unsigned)std::min<long>((n + RB - 1) / RB, 8192)), dim3(RB),
+                       0, S.h->stream, n, 0.5, S.s);
+    LRCC_HIP(S.h, hipGetLastError());
+  }
   LRCC_HIP(S.h, hh_apply(S.W, S.g, xin, S.s, S.h->stream));
   if (!S.ringM) return LRCC_OK;
   // the ring term on packed doubles: block -> packed, ring, packed -> block, add
@@ -705,14 +753,16 @@ lrcc_status apply_sigma(Solver& S, const double* xin, lrcc_prec prec, lrcc_cmul 
 // Start of a Jacobi + DIIS run: active flags, empty subspace, iteration 0,
 // x = b / (D - w).
 lrcc_status start_iteration(Solver& S, const double* b, double* x, const int* h_active_in,
-                            hipStream_t st) {
+                            hipStream_t st, bool keep_x = false) {
   lrcc_handle h = S.h;
   LRCC_HIP(h, hipMemcpyAsync(S.active, h_active_in, S.n * sizeof(int), hipMemcpyHostToDevice, st));
   LRCC_HIP(h, fill_zero(S.valid, roundup((long)S.n * 4, 16), st));
   LRCC_HIP(h, fill_zero(S.itp, 16, st));
-  hipLaunchKernelGGL(k_start, grid_rhs(S, S.n), dim3(RB), 0, st, S.d, S.eps, S.omega, S.tab,
-                     S.otab, S.active, b, x);
-  LRCC_HIP(h, hipGetLastError());
+  if (!keep_x) {  // else x holds the caller's initial amplitudes
+    hipLaunchKernelGGL(k_start, grid_rhs(S, S.n), dim3(RB), 0, st, S.d, S.eps, S.omega, S.tab,
+                       S.otab, S.active, b, x);
+    LRCC_HIP(h, hipGetLastError());
+  }
   S.act.assign(h_active_in, h_active_in + S.n);
   return LRCC_OK;
 }
@@ -764,13 +814,29 @@ int absorb_flags(Solver& S, int it, double tol, lrcc_status* result) {
   return nact;
 }
 
+// One metrics line: the solve side, the phase (fp64: the FP64 solve;
+// inner: a reduced-precision inner iteration; outer: a refinement sweep's
+// FP64 residual), the sweep, the iteration, the active count, every right-
+// hand side's relative residual and the milliseconds since the call began.
+void write_metrics(Solver& S, int it, int nact, const double* rel) {
+  if (!S.metrics) return;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                              S.t0).count();
+  std::fprintf(S.metrics, "{\"side\": \"%s\", \"phase\": \"%s\", \"sweep\": %d, \"iter\": %d, "
+               "\"active\": %d, \"ms\": %.3f, \"relres\": [", S.side, S.phase, S.sweep, it, nact, ms);
+  for (int r = 0; r < S.n; ++r) std::fprintf(S.metrics, r ? ", %.6e" : "%.6e", rel[r]);
+  std::fprintf(S.metrics, "]}\n");
+  std::fflush(S.metrics);
+}
+
 // Jacobi + DIIS for (A - w) x = b on the RHS whose active flag is set on
 // entry.  x receives the solution.  Returns LRCC_ERR_NOT_CONVERGED if any
 // RHS stopped at max_iter, LRCC_ERR_NONFINITE on NaN/Inf.
 lrcc_status jacobi_diis(Solver& S, const double* b, double* x, lrcc_prec prec, lrcc_cmul cmul,
-                        const void* ls, double tol, int max_iter, const int* h_active_in) {
+                        const void* ls, double tol, int max_iter, const int* h_active_in,
+                        bool keep_x = false) {
   lrcc_handle h = S.h;
-  lrcc_status st = start_iteration(S, b, x, h_active_in, h->stream);
+  lrcc_status st = start_iteration(S, b, x, h_active_in, h->stream, keep_x);
   if (st != LRCC_OK) return st;
   lrcc_status result = LRCC_OK;
   for (int it = 0;; ++it) {
@@ -782,6 +848,7 @@ lrcc_status jacobi_diis(Solver& S, const double* b, double* x, lrcc_prec prec, l
     if (st != LRCC_OK) return st;
     LRCC_HIP(h, hipStreamSynchronize(h->stream));
     const int nact = absorb_flags(S, it, tol, &result);
+    write_metrics(S, it, nact, S.h_relres);
     if (nact == 0 || result == LRCC_ERR_NONFINITE) break;
   }
   return result;
@@ -825,11 +892,13 @@ lrcc_status read_opts(lrcc_handle h, const lrcc_solve_opts* in, lrcc_solve_opts*
     return fail(h, LRCC_ERR_ARG, "unknown precision");
   if (op->cmul != LRCC_CMUL_4M && op->cmul != LRCC_CMUL_3M)
     return fail(h, LRCC_ERR_ARG, "unknown complex-multiply form");
-  if (op->deterministic) return fail(h, LRCC_ERR_UNSUPPORTED, "deterministic mode is reserved");
+
   if ((op->L_ov != nullptr) != (op->L_vo != nullptr))
     return fail(h, LRCC_ERR_ARG, "L_ov and L_vo come together");
   if (op->L_ov && !op->L_oo)
     return fail(h, LRCC_ERR_ARG, "the ring term needs L_oo as well");
+  if ((uintptr_t)op->x0 % 16 || (uintptr_t)op->x_out % 16)
+    return fail(h, LRCC_ERR_ARG, "x0/x_out not 16-byte aligned");
   const void* ps[] = {op->L_oo, op->L_ov, op->L_vo};
   for (const void* q : ps)
     if (q && (uintptr_t)q % 16) return fail(h, LRCC_ERR_ARG, "L_oo/L_ov/L_vo not 16-byte aligned");
@@ -847,7 +916,8 @@ namespace {
 lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps, const void* L,
                        int ncomp, const void* mu, int nomega, const double* omegas,
                        const lrcc_solve_opts& op, const Opts& O, LForm form, bool conj_rhs,
-                       double* alpha, lrcc_solve_info* tally) {
+                       double* alpha, lrcc_solve_info* tally, FILE* metrics,
+                       std::chrono::steady_clock::time_point t0) {
   lrcc_status st;
   const bool ir = op.prec != LRCC_FP64;
   Solver S;
@@ -864,7 +934,7 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
   if (op.L_oo && nchol > 0) {  // the hole-hole ladder: W (or W^T for L^T)
     const size_t wbytes = (size_t)S.g.npo * S.g.npo * 16;
     LRCC_HIP(h, h->hw.ensure(wbytes));
-    LRCC_HIP(h, hh_build_w(op.L_oo, LRCC_C128, o, nchol, S.otab, form,
+    LRCC_HIP(h, hh_build_w(op.L_oo, LRCC_C128, o, nchol, S.otab, form, 1.0,
                            h->hw.as<double2>(), h->stream));
     S.W = h->hw.as<double2>();
     if (op.L_ov) {  // the ring term: M from the blocks of L (or of L^T)
@@ -898,18 +968,30 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
   const size_t vb = (size_t)2 * S.d.plane * 8;
   std::vector<int> all(S.n, 1);
 
+  S.metrics = metrics;
+  S.t0 = t0;
+  S.side = form == L_TRANS ? "left" : "right";
+  // the caller's initial amplitudes and final-amplitude buffer belong to the
+  // right-hand solve
+  const bool warm = op.x0 != nullptr && form == L_PLAIN;
+  void* const x_out = form == L_PLAIN ? op.x_out : nullptr;
+
   lrcc_status result = LRCC_OK;
   double final_rel = 0;
   if (!ir) {
+    if (warm) LRCC_HIP(h, pack_to_block<double>(op.x0, LRCC_C128, S.g, S.tab, S.x, h->stream));
+    S.phase = "fp64";
     result = jacobi_diis(S, S.b, S.x, LRCC_FP64, op.cmul, h->ls.p, O.tol, O.max_iter,
-                         all.data());
+                         all.data(), warm);
     for (int r = 0; r < S.n; ++r) final_rel = std::max(final_rel, S.h_relres[r]);
     if (result == LRCC_ERR_NONFINITE) return fail(h, result, "non-finite residual");
     st = finish_alpha(S, S.x, alpha, h->stream);
     if (st != LRCC_OK) return st;
+    if (x_out) LRCC_HIP(h, block_to_pack<double>(S.x, S.g, S.tab, x_out, LRCC_C128, h->stream));
   } else {
-    // iterative refinement: x2 = 0, rk = b
-    LRCC_HIP(h, fill_zero(S.x2, vb, h->stream));
+    // iterative refinement: x2 = 0 (or the initial amplitudes), rk = b - A x2
+    if (warm) LRCC_HIP(h, pack_to_block<double>(op.x0, LRCC_C128, S.g, S.tab, S.x2, h->stream));
+    else LRCC_HIP(h, fill_zero(S.x2, vb, h->stream));
     LRCC_HIP(h, hipMemcpyAsync(S.rk, S.b, vb, hipMemcpyDeviceToDevice, h->stream));
     std::vector<int> act(S.n, 1);
     std::vector<double> rel(S.n, 1.0);
@@ -938,7 +1020,30 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
     // FP64 residual), or an estimate built from reduced-precision ladders
     bool sx_exact = false;
     result = LRCC_ERR_NOT_CONVERGED;
-    for (int outer = 0; outer < O.max_outer; ++outer) {
+    int nact0 = S.n;
+    if (warm) {
+      // residual of the initial amplitudes, with the full-iterate ladder
+      LRCC_HIP(h, hipMemcpyAsync(S.active, act.data(), S.n * sizeof(int), hipMemcpyHostToDevice,
+                                 h->stream));
+      st = apply_sigma(S, S.x2, anchor, op.cmul, h->ls.p);
+      if (st != LRCC_OK) return st;
+      LRCC_HIP(h, hipMemcpyAsync(S.sx, S.s, vb, hipMemcpyDeviceToDevice, h->stream));
+      sx_exact = anchor == LRCC_FP64;
+      st = outer_residual(act);
+      if (st != LRCC_OK) return st;
+      nact0 = 0;
+      for (int r = 0; r < S.n; ++r) {
+        if (rel[r] < O.tol) act[r] = 0;
+        else ++nact0;
+      }
+      S.phase = "outer";
+      S.sweep = -1;
+      write_metrics(S, 0, nact0, rel.data());
+      if (nact0 == 0) result = LRCC_OK;
+    }
+    for (int outer = 0; outer < O.max_outer && nact0 > 0; ++outer) {
+      S.phase = "inner";
+      S.sweep = outer;
       lrcc_status is = jacobi_diis(S, S.rk, S.x, op.prec, op.cmul, h->ls2.p, O.inner_tol,
                                    O.max_iter, act.data());
       if (is == LRCC_ERR_NONFINITE) return fail(h, is, "non-finite residual");
@@ -971,6 +1076,8 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
         if (rel[r] < O.tol) act[r] = 0;
         else ++nact;
       }
+      S.phase = "outer";
+      write_metrics(S, 0, nact, rel.data());
       if (nact == 0) {
         result = LRCC_OK;
         break;
@@ -993,6 +1100,8 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
       LRCC_HIP(h, hipMemcpyAsync(S.sx, S.s, vb, hipMemcpyDeviceToDevice, h->stream));
       st = outer_residual(every);
       if (st != LRCC_OK) return st;
+      S.phase = "final";
+      write_metrics(S, 0, 0, rel.data());
       result = LRCC_OK;
       for (int r = 0; r < S.n; ++r)
         if (!(rel[r] < O.tol)) result = LRCC_ERR_NOT_CONVERGED;
@@ -1000,6 +1109,7 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
     for (int r = 0; r < S.n; ++r) final_rel = std::max(final_rel, rel[r]);
     st = finish_alpha(S, S.x2, alpha, h->stream);
     if (st != LRCC_OK) return st;
+    if (x_out) LRCC_HIP(h, block_to_pack<double>(S.x2, S.g, S.tab, x_out, LRCC_C128, h->stream));
   }
   tally->iters_max = std::max(tally->iters_max, S.iters_max);
   tally->n_sigma_fp64 += S.n_sigma64;
@@ -1019,6 +1129,24 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
   lrcc_status st = read_opts(h, opts_in, &op, &O);
   if (st != LRCC_OK) return st;
   if (op.response != 0 && op.response != 1) return fail(h, LRCC_ERR_ARG, "unknown response mode");
+  // deterministic ladders for this solve (the handle's setting is restored after)
+  struct DetGuard {
+    lrcc_handle h;
+    int prev;
+    ~DetGuard() { h->deterministic = prev; }
+  } det{h, h->deterministic};
+  if (op.deterministic) h->deterministic = 1;
+  // per-iteration metrics: one JSON line per iteration appended to the file
+  struct MetricsFile {
+    FILE* f = nullptr;
+    ~MetricsFile() {
+      if (f) std::fclose(f);
+    }
+  } mf;
+  if (op.metrics_path) {
+    mf.f = std::fopen(op.metrics_path, "a");
+    if (!mf.f) return fail(h, LRCC_ERR_ARG, std::string("cannot open ") + op.metrics_path);
+  }
   const size_t np = (size_t)nomega * ncomp * ncomp;
   {
     const Geom g = make_geom(o, v, nchol, nomega * ncomp, 1);
@@ -1035,7 +1163,7 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
   if (op.response == 0) {
     // right-hand amplitudes: alpha_xy = -<xi_x | X_y(w)>
     result = solve_side(h, o, v, nchol, eps, L, ncomp, mu, nomega, omegas, op, O, L_PLAIN, false,
-                        alpha, &tally);
+                        alpha, &tally, mf.f, t0);
   } else {
     // full linear response function (Sec. 2.2): right-hand X(w) from
     // (A - w) X = -xi, left-hand Y(w) from Y (A + w) = -eta with eta =
@@ -1045,11 +1173,11 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
     // function is (f_xy + conj f_yx) / 2 and alpha = -(that).
     std::vector<double> ar(2 * np), al(2 * np), wneg(nomega);
     lrcc_status rr = solve_side(h, o, v, nchol, eps, L, ncomp, mu, nomega, omegas, op, O,
-                                L_PLAIN, false, ar.data(), &tally);
+                                L_PLAIN, false, ar.data(), &tally, mf.f, t0);
     if (rr != LRCC_OK && rr != LRCC_ERR_NOT_CONVERGED) return rr;
     for (int w = 0; w < nomega; ++w) wneg[w] = -omegas[w];
     lrcc_status rl = solve_side(h, o, v, nchol, eps, L, ncomp, mu, nomega, wneg.data(), op, O,
-                                L_TRANS, true, al.data(), &tally);
+                                L_TRANS, true, al.data(), &tally, mf.f, t0);
     if (rl != LRCC_OK && rl != LRCC_ERR_NOT_CONVERGED) return rl;
     for (int w = 0; w < nomega; ++w)
       for (int x = 0; x < ncomp; ++x)
@@ -1087,6 +1215,12 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
   if (st != LRCC_OK) return st;
   if (op.prec != LRCC_FP64)
     return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve runs the FP64 ladder");
+  if (op.x0 || op.x_out || op.metrics_path)
+    return fail(h, LRCC_ERR_UNSUPPORTED,
+                "the batched solve takes no initial amplitudes, amplitude output or metrics file");
+  if (op.deterministic || h->deterministic)
+    return fail(h, LRCC_ERR_UNSUPPORTED,
+                "the batched solve's persistent ladder sums with atomics (no deterministic mode)");
   if (op.response != 0)
     return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve gives the right-hand response");
   if (op.L_oo || op.L_ov)

@@ -360,3 +360,27 @@ def test_launch_variants(lrcc, tmp_path, prec, cmul, variants, herm):
         for dtype in (torch.complex128, torch.complex64):
             ref, tol = bars[(prec, dtype)]
             assert rel(run(lrcc, L, X, prec=prec, cmul=cmul, dtype=dtype), ref) < tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-10), (torch.complex64, 1e-5)])
+@pytest.mark.parametrize("limit", [1 << 20, 0])
+def test_dL_panels(lrcc, dtype, tol, limit):
+    # the gradient's R' panels: one block row per panel (a 1 MB limit) or the
+    # whole triangle at once; ragged v, rows not a multiple of 16, general L
+    o, v, nchol, nrhs = 5, 29, 37, 2
+    rng = np.random.default_rng(303)
+    L = S.make_L(rng, nchol, v, hermitian=False)
+    X, G = S.make_packed(rng, nrhs, o, v), S.make_packed(rng, nrhs, o, v)
+    lrcc.set_workspace_limit(limit)
+    try:
+        _, dL = lrcc.ppl_sigma_adjoint(dev(L, dtype), dev(X, dtype), dev(G, dtype),
+                                       want_dX=False)
+        torch.cuda.synchronize()
+    finally:
+        lrcc.set_workspace_limit(0)
+    ref = grads.vjp_L(L, X, G, o, v)
+    if dtype == torch.complex64:
+        ref = grads.vjp_L(L.astype(np.complex64).astype(complex),
+                          X.astype(np.complex64).astype(complex),
+                          G.astype(np.complex64).astype(complex), o, v)
+    assert rel(dL.cpu().numpy().astype(np.complex128), ref) < tol

@@ -8,7 +8,7 @@ import pytest
 
 import lrcc_synth as S
 from fock import Fock
-from oracle import hhl, ppl, ring
+from oracle import hhl, ppl, response, ring
 
 
 def blocks(Lfull, o):
@@ -43,6 +43,12 @@ def test_ring_is_the_two_body_matrix_element():
     want = (0.5 * ppl.sigma(Lvv, X, o, v) + 0.5 * hhl.sigma(Loo, X, o, v)
             + ring.sigma(Lov, Lvo, Loo, Lvv, X, o, v))[0]
     np.testing.assert_allclose(got, want, atol=1e-13)
+    # the model Jacobian with both ladders and the ring term applies exactly
+    # this block (zero orbital energies: no Fock-diagonal part)
+    AX = response.apply_jacobian(Lvv, X, np.zeros(n), o, v, Loo, (Lov, Lvo))[0]
+    np.testing.assert_allclose(AX, got, atol=1e-13)
+    Am = response.full_matrix(Lvv, np.zeros(n), o, v, Loo, (Lov, Lvo))
+    np.testing.assert_allclose(Am @ X[0].reshape(-1), got.reshape(-1), atol=1e-13)
 
 
 @pytest.mark.parametrize("o,v,nchol,nrhs,herm", [(3, 5, 4, 2, True), (5, 9, 7, 1, False),
