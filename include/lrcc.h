@@ -104,6 +104,24 @@ lrcc_status lrcc_ppl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs,
                            const void* L, const void* X, void* sigma,
                            lrcc_dtype dt, lrcc_prec prec, lrcc_cmul cmul);
 
+/* sigma = PPL(L, X) without allocating: for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Arguments, result and errors as lrcc_ppl_sigma,
+ * for prec FP64 or FP32 (BF16X3: LRCC_ERR_UNSUPPORTED).  Every intermediate
+ * (block-pair table, tile order, Hermiticity flag, staged L, block-layout X
+ * and the sigma accumulator) lives in one static device array of 64 MiB per
+ * GPU, held from library load until the process ends; a problem that needs
+ * more (about (v/8)^2 nchol KB of staged FP64 vectors plus three copies of
+ * the padded doubles) returns LRCC_ERR_SHAPE before any launch.  The call
+ * issues kernel launches only (no allocation, host copy or memset), on the
+ * handle's stream.  All calls on one GPU share that array and each clears
+ * what it reads before use: calls that can overlap on one GPU (different
+ * streams or handles without ordering between them) race and must be
+ * serialised by the caller. */
+lrcc_status lrcc_ppl_sigma_noalloc(lrcc_handle h, int o, int v, int nchol, int nrhs,
+                                   const void* L, const void* X, void* sigma,
+                                   lrcc_dtype dt, lrcc_prec prec, lrcc_cmul cmul);
+
 /* Vector-Jacobian products of sigma = PPL(L, X) for a real loss with
  * upstream gradient G = dloss/dsigma (PyTorch's complex convention:
  * dloss = Re sum conj(grad) d(input)).  dX is the product with the

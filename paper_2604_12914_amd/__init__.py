@@ -106,6 +106,7 @@ def lib() -> ctypes.CDLL:
             "lrcc_destroy": [vp],
             "lrcc_set_stream": [vp, vp],
             "lrcc_ppl_sigma": [vp, i, i, i, i, vp, vp, vp, i, i, i],
+            "lrcc_ppl_sigma_noalloc": [vp, i, i, i, i, vp, vp, vp, i, i, i],
             "lrcc_ppl_sigma_adjoint": [vp, i, i, i, i, vp, vp, vp, vp, vp, i, i, i],
             "lrcc_hhl_sigma": [vp, i, i, i, i, vp, vp, vp, i],
             "lrcc_cholesky": [vp, ctypes.c_long, vp, d, i, vp, vp, ctypes.POINTER(i)],
@@ -208,6 +209,19 @@ def ppl_sigma(L, X, o=None, prec="fp64", cmul="4m", out=None):
     h = handle(dev)
     _check(lib().lrcc_ppl_sigma(h, o, v, nchol, nrhs, _ptr(L), _ptr(X), _ptr(out),
                                 _dtype_code(X), PREC[prec], CMUL[cmul]), h)
+    return out
+
+
+def ppl_sigma_noalloc(L, X, out, o=None, prec="fp64", cmul="4m"):
+    """sigma = PPL(L, X) into the caller's ``out`` through the allocation-free
+    entry point (the library allocates nothing; FP64 or FP32 ladder)."""
+    L, X = L.contiguous(), X.contiguous()
+    nchol, v, o, nrhs, dev = _geometry(L, X, o)
+    if out.shape != X.shape or out.dtype != X.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous tensor shaped like X")
+    h = handle(dev)
+    _check(lib().lrcc_ppl_sigma_noalloc(h, o, v, nchol, nrhs, _ptr(L), _ptr(X), _ptr(out),
+                                        _dtype_code(X), PREC[prec], CMUL[cmul]), h)
     return out
 
 

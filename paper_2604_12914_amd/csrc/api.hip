@@ -355,6 +355,10 @@ lrcc_status lrcc_create(lrcc_handle* out, int device, void* stream) {
   h->stream = static_cast<hipStream_t>(stream);
   h->ncu = prop.multiProcessorCount;
   if (const char* e = getenv("LRCC_DETERMINISTIC")) h->deterministic = atoi(e) != 0;
+  {
+    DeviceGuard dg(device);
+    noalloc_init(device);  // scratch address of the allocation-free ladder on this device
+  }
   *out = h;
   return LRCC_OK;
 }
@@ -455,6 +459,18 @@ lrcc_status lrcc_ppl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, con
   h->err.clear();
   Geom g = make_geom(o, v, nchol, nrhs, ppl_chunk(prec, cmul));
   return sigma_packed(h, g, L, false, X, sigma, dt, prec, cmul);
+}
+
+lrcc_status lrcc_ppl_sigma_noalloc(lrcc_handle h, int o, int v, int nchol, int nrhs,
+                                   const void* L, const void* X, void* sigma, lrcc_dtype dt,
+                                   lrcc_prec prec, lrcc_cmul cmul) {
+  if (!h) return fail(nullptr, LRCC_ERR_ARG, "handle is NULL");
+  lrcc_status st = check_sigma(h, o, v, nchol, nrhs, L, X, sigma, dt, prec, cmul, "sigma");
+  if (st != LRCC_OK) return st;
+  DeviceGuard dg(h->device);
+  h->err.clear();
+  const Geom g = make_geom(o, v, nchol, nrhs, ppl_chunk(prec, cmul));
+  return sigma_noalloc(h, g, L, X, sigma, dt, prec, cmul);
 }
 
 lrcc_status lrcc_hhl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs, const void* Loo,

@@ -304,6 +304,14 @@ lrcc_status sigma_packed(lrcc_handle h, const Geom& g, const void* L, bool conj_
                          const void* X, void* S, lrcc_dtype dt, lrcc_prec prec,
                          lrcc_cmul cmul);
 
+// Allocation-free ladder (noalloc.hip): the per-device address of the static
+// scratch array is looked up by noalloc_init (called by lrcc_create with the
+// device current); sigma_noalloc runs the FP64 / FP32 ladder in it.
+void noalloc_init(int device);
+size_t noalloc_scratch_bytes();
+lrcc_status sigma_noalloc(lrcc_handle h, const Geom& g, const void* L, const void* X, void* S,
+                          lrcc_dtype dt, lrcc_prec prec, lrcc_cmul cmul);
+
 // Response solve (solver.hip); arguments already validated.
 lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps, const void* L,
                        int ncomp, const void* mu, int nomega, const double* omegas,
