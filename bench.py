@@ -47,6 +47,14 @@ HBM_GBS = 8000.0
 METRIC = "PPL A*X TFLOP/s FP64 vs split-prec; LR solve time at |d alpha|<1e-5 a.u."
 
 
+_T_START = time.perf_counter()
+
+
+def progress(msg):
+    """A progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench {time.perf_counter() - _T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def npairs(n):
     return n * (n - 1) // 2
 
@@ -185,8 +193,8 @@ def main():
                     help="complex form of --profile-sigma's ladder (FP64 / FP32)")
     ap.add_argument("--c64", action="store_true", help="complex64 storage for --profile-sigma")
     ap.add_argument("--profile-batched", action="store_true",
-                    help="only run the batched FP64 solve of the eight uneven instances once "
-                         "(for profilers)")
+                    help="only run the batched workload (eight uneven instances): FP64 and "
+                         "bf16x3-refinement batched solves against sequential single solves")
     ap.add_argument("--profile-fns", action="store_true",
                     help="only run --warmup + --steps FNS++ basis constructions (for profilers)")
     ap.add_argument("--profile-jacobian", action="store_true",
@@ -249,10 +257,12 @@ def main():
     o, v, nchol, nrhs = cfg.o, cfg.v, cfg.nchol, cfg.nrhs
     L, X = gpu_inputs(torch, o, v, nchol, nrhs)
     A = alg_flops(o, v, nchol, nrhs, SOLVE_CMUL)
+    progress(f"inputs ready (o={o} v={v} nchol={nchol}); {args.warmup} warmup ladders")
     s = None
     for _ in range(args.warmup):
         s = lrcc.ppl_sigma(L, X, prec="fp64", cmul=SOLVE_CMUL, out=s)
     torch.cuda.synchronize()
+    progress(f"timing {args.steps} ladders")
     lrcc.set_timing(True)
     step_ms = []
     t0 = time.perf_counter()
@@ -261,6 +271,7 @@ def main():
         s = lrcc.ppl_sigma(L, X, prec="fp64", cmul=SOLVE_CMUL, out=s)
         torch.cuda.synchronize()
         step_ms.append((time.perf_counter() - ts) * 1e3)
+        progress(f"step {len(step_ms)}: {step_ms[-1]:.1f} ms")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kms, nlaunch = lrcc.get_timing()
@@ -316,19 +327,23 @@ def main():
     if not args.no_extra:
         out["extra"] = extras(lrcc, torch, np, S, L, X, args)
     if not args.no_cpu:
+        progress("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(L, X, o, v, A)
+    progress("done")
     print(json.dumps(out), flush=True)
 
 
 def extras(lrcc, torch, np, S, Lscale, Xscale, args):
     extra = {}
     c5 = S.CONFIGS["scale"]
+    progress("extra: the ladder per precision at the scale workload")
     # ---- the ladder at the scale workload per precision ------------------
     try:
         # (the FP64 3M ladder is the headline itself: config.step_ms)
         sc = {"fp64_4m": sigma_extra(lrcc, torch, c5.o, c5.v, c5.nchol, c5.nrhs, "fp64", "4m",
                                      Lscale, Xscale, 3)}
         L64, X64 = Lscale.to(torch.complex64), Xscale.to(torch.complex64)
+        progress("extra: scale workload FP32 and bf16x3 ladders (complex64)")
         sc["fp32_4m_c64"] = sigma_extra(lrcc, torch, c5.o, c5.v, c5.nchol, c5.nrhs, "fp32",
                                         "4m", L64, X64, 5)
         sc["bf16x3_4m_c64"] = sigma_extra(lrcc, torch, c5.o, c5.v, c5.nchol, c5.nrhs,
@@ -349,6 +364,7 @@ def extras(lrcc, torch, np, S, Lscale, Xscale, args):
     for prec, cmul in (("fp64", "4m"), ("fp64", "3m"), ("fp32", "4m"), ("fp32", "3m"),
                        ("bf16x3", "4m")):
         try:
+            progress(f"extra: baseline ladder {prec} {cmul} (autotune, 20 repetitions)")
             tune = lrcc.autotune(o, v, nchol, nrhs, prec=prec, cmul=cmul)
             e = sigma_extra(lrcc, torch, o, v, nchol, nrhs, prec, cmul, Lraw, X, 20)
             e["tuned"] = {"supertile": tune["supertile"], "occupancy": tune["occupancy"]}
@@ -363,6 +379,7 @@ def extras(lrcc, torch, np, S, Lscale, Xscale, args):
     L = torch.from_numpy(inst.L).cuda()
     mu = torch.from_numpy(inst.mu).cuda()
     exact = golden_alpha("baseline")
+    progress("extra: baseline solves")
     lrcc.solve(eps, L, mu, omegas, tol=1e-8, cmul=SOLVE_CMUL)
     ts = []
     for _ in range(3):
@@ -378,7 +395,8 @@ def extras(lrcc, torch, np, S, Lscale, Xscale, args):
     if exact is not None:
         e["max_abs_dalpha_vs_exact"] = float(np.abs(alpha64 - exact).max())
     extra["solve_baseline_fp64"] = e
-    for name, kw in (("fp32_ir", dict(prec="fp32")), ("bf16x3_ir", dict(prec="bf16x3"))):
+    for name, kw in (("fp32_ir", dict(prec="fp32")),
+                     ("bf16x3_ir", dict(prec="bf16x3", cmul=SOLVE_CMUL))):
         try:
             lrcc.solve(eps, L, mu, omegas, tol=1e-8, **kw)
             torch.cuda.synchronize()
@@ -396,8 +414,10 @@ def extras(lrcc, torch, np, S, Lscale, Xscale, args):
         except lrcc.LrccError as err:
             extra[f"solve_baseline_{name}"] = {"error": str(err)}
     if exact is not None:
+        progress("extra: time to |d alpha| < 1e-5 at the baseline workload")
         extra["solve_time_at_dalpha_1e-5_baseline"] = dalpha_sweep(
             lrcc, torch, np, eps, L, mu, omegas, exact, full=True)
+    progress("extra: full response, composite Jacobian, FNS++")
     # full response function (right- and left-hand solves, Sec. 2.2): for
     # this Hermitian operator it must equal alpha(w) + conj alpha(-w)
     try:
@@ -454,6 +474,7 @@ def extras(lrcc, torch, np, S, Lscale, Xscale, args):
 
     # ---- precision workload: alpha error per frequency -------------------
     try:
+        progress("extra: precision workload study")
         extra["precision_study"] = precision_study(lrcc, torch, np, S)
     except lrcc.LrccError as err:
         extra["precision_study"] = {"error": str(err)}
@@ -477,7 +498,9 @@ def precision_study(lrcc, torch, np, S):
            "exact": "tests/golden/alpha_exact.json 'precision' (FP64 oracle, Jacobi + DIIS "
                     "to 1e-11)" if exact is not None else None}
     for name, kw in (("fp64", dict(prec="fp64", cmul=SOLVE_CMUL)),
-                     ("fp32_ir", dict(prec="fp32")), ("bf16x3_ir", dict(prec="bf16x3"))):
+                     ("fp32_ir", dict(prec="fp32")),
+                     ("bf16x3_ir", dict(prec="bf16x3", cmul=SOLVE_CMUL))):
+        progress(f"  precision workload: {name} solve to 1e-8")
         lrcc.solve(eps, L, mu, omegas, tol=1e-8, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -503,18 +526,21 @@ def dalpha_sweep(lrcc, torch, np, eps, L, mu, omegas, exact, target=1e-5, full=T
     one that meets the target is timed (best of three calls, the trial call
     included).  Refinement runs its inner solve to the outer tolerance or a
     third of it and keeps the faster; with full=True every method also tries
-    both complex forms of its FP64 / FP32 ladders (bf16x3 is always 4M).
+    both complex forms of its FP64 / FP32 ladders (bf16x3 is always 4M; for
+    its refinement the form applies to the FP64 ladders).
     Every refined solve reports the FP64 residual of its result, and
     n_sigma_fp64 counts the FP64 ladders it took."""
     methods = {
         "fp64": (dict(prec="fp64"), ("4m", "3m") if full else (SOLVE_CMUL,)),
-        "bf16x3_ir": (dict(prec="bf16x3"), ("4m",)),
+        # (cmul is the complex form of the refinement's FP64 ladders; bf16x3 is 4M)
+        "bf16x3_ir": (dict(prec="bf16x3"), ("4m", "3m") if full else (SOLVE_CMUL,)),
         "fp32_ir": (dict(prec="fp32"), ("4m", "3m") if full else ("4m",)),
     }
     if full:
-        methods["bf16x3_ir_fp32_anchor"] = (dict(prec="bf16x3", anchor_prec="fp32"), ("4m",))
+        methods["bf16x3_ir_fp32_anchor"] = (dict(prec="bf16x3", anchor_prec="fp32"), ("4m", "3m"))
     out = {"target_abs_dalpha": target}
     for name, (kw, cmuls) in methods.items():
+        progress(f"  sweep {name}")
         res = None
         refine = kw["prec"] != "fp64"
         for cmul, ratio in [(c, r) for c in cmuls for r in ((1.0, 1.0 / 3.0) if refine else (1.0,))]:
@@ -714,9 +740,12 @@ def profile_jacobian(lrcc, torch, np, S, args):
 
 
 def profile_batched(lrcc, torch, np, S, args):
-    """The batched FP64 solve (3M ladder) of the eight uneven instances, o in
-    {8..32}, v = 10 o, Nchol = 4 v, 3 components x 4 frequencies each, to a
-    relative residual of 1e-6, once after tuning: one JSON line."""
+    """The batched workload: eight uneven instances, o in {8..32}, v = 10 o,
+    Nchol = 4 v, 3 components x 4 frequencies each.  Batched against
+    sequential single solves, for the FP64 solve (3M ladder, four DIIS
+    vectors, relative residual 1e-6) and for bf16x3 refinement (eight DIIS
+    vectors, FP64 residual 1e-8, the outer FP64 ladders 3M); the FP64 batch
+    also to 1e-8 for the time to the same tolerance.  One JSON line."""
     cfg = S.CONFIGS["batch"]
     om = list(cfg.omegas)
     insts, F = [], 0.0
@@ -728,15 +757,59 @@ def profile_batched(lrcc, torch, np, S, args):
     o, v, nchol = max(i[0] for i in cfg.instances), max(i[1] for i in cfg.instances), \
         max(i[2] for i in cfg.instances)
     lrcc.autotune(o, v, nchol, cfg.ncomp * len(om), prec="fp64", cmul="3m")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, info = lrcc.solve_batched(insts, tol=1e-6, diis_dim=4, cmul="3m")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    print(json.dumps({"profile_batched": "8 instances", "s": round(t1 - t0, 3),
-                      "n_sigma_fp64": info["n_sigma_fp64"], "iters_max": info["iters_max"],
-                      "tflops_algorithmic": round(F * info["n_sigma_fp64"] / (t1 - t0) / 1e12, 2)}),
-          flush=True)
+    out = {"profile_batched": "8 instances, 96 right-hand sides"}
+
+    def keep(info, t):
+        return {"s": round(t, 3), "status": info["status"], "n_sigma_fp64": info["n_sigma_fp64"],
+                "n_sigma_lowp": info["n_sigma_lowp"], "iters_max": info["iters_max"],
+                "final_relres": info["final_relres"]}
+
+    def batched(name, **kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        al, info = lrcc.solve_batched(insts, check=False, **kw)
+        torch.cuda.synchronize()
+        out[name] = keep(info, time.perf_counter() - t0)
+        print(json.dumps({name: out[name]}), file=sys.stderr, flush=True)
+        return al
+
+    def sequential(name, **kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        als, n64, nlp = [], 0, 0
+        for d in insts:
+            a, info = lrcc.solve(d["eps"], d["L"], d["mu"], om, check=False, **kw)
+            als.append(a)
+            n64 += info["n_sigma_fp64"]
+            nlp += info["n_sigma_lowp"]
+        torch.cuda.synchronize()
+        out[name] = {"s": round(time.perf_counter() - t0, 3), "n_sigma_fp64_sum": n64,
+                     "n_sigma_lowp_sum": nlp}
+        print(json.dumps({name: out[name]}), file=sys.stderr, flush=True)
+        return als
+
+    # the batched calls first: the single solves leave the handle's grow-only
+    # workspace at the largest instance's size, which the batch would not fit beside
+    fp64 = dict(tol=1e-6, diis_dim=4, cmul="3m")
+    ir = dict(tol=1e-8, diis_dim=8, prec="bf16x3", cmul="3m")
+    a64 = batched("fp64_batched_tol1e-6", **fp64)
+    out["fp64_batched_tol1e-6"]["tflops_algorithmic"] = round(
+        F * out["fp64_batched_tol1e-6"]["n_sigma_fp64"] / out["fp64_batched_tol1e-6"]["s"] / 1e12, 2)
+    air = batched("bf16x3_ir_batched_tol1e-8", **ir)
+    a8 = batched("fp64_batched_tol1e-8", tol=1e-8, diis_dim=4, cmul="3m")
+    sequential("fp64_sequential_tol1e-6", **fp64)
+    out["fp64_batching_speedup"] = round(out["fp64_sequential_tol1e-6"]["s"]
+                                         / out["fp64_batched_tol1e-6"]["s"], 3)
+    sequential("bf16x3_ir_sequential_tol1e-8", **ir)
+    out["bf16x3_ir_batching_speedup"] = round(out["bf16x3_ir_sequential_tol1e-8"]["s"]
+                                              / out["bf16x3_ir_batched_tol1e-8"]["s"], 3)
+    out["bf16x3_ir_vs_fp64_batched_speedup_tol1e-8"] = round(
+        out["fp64_batched_tol1e-8"]["s"] / out["bf16x3_ir_batched_tol1e-8"]["s"], 3)
+    out["max_rel_dalpha_ir_vs_fp64_tol1e-8"] = float(max(
+        np.abs(a - b).max() / np.abs(b).max() for a, b in zip(air, a8)))
+    out["max_rel_dalpha_fp64_tol1e-6_vs_tol1e-8"] = float(max(
+        np.abs(a - b).max() / np.abs(b).max() for a, b in zip(a64, a8)))
+    print(json.dumps(out), flush=True)
 
 
 def profile_sigma(lrcc, torch, np, S, args):

@@ -381,11 +381,24 @@ typedef struct {
 /* Solve several uneven instances together: the response equations of
  * Sec. 2.2, one per perturbation component and frequency of each instance
  * (each instance a molecule or basis of its own size), iterated side by
- * side.  Every ladder application of every instance, component and
- * frequency goes into one persistent launch per iteration (a work queue
- * ordered longest tile first).  FP64 ladder
- * only (opts->prec must be LRCC_FP64, else LRCC_ERR_UNSUPPORTED), in the
- * complex form opts->cmul selects. */
+ * side.  With opts->prec = LRCC_FP64 every ladder application of every
+ * instance, component and frequency goes into one persistent launch per
+ * iteration (a work queue ordered longest tile first), each iteration
+ * replayed from a captured HIP graph.  With LRCC_FP32 or LRCC_BF16X3 the
+ * solve refines the response equations of Sec. 2.2 iteratively: in each sweep
+ * the correction equations of the instances with unconverged right-hand
+ * sides are solved to opts->inner_tol with the reduced-precision ladder,
+ * one instance after another (their DIIS history, reduced-precision
+ * doubles and staged vectors are one shared set sized for the largest
+ * instance, so memory grows by a per-instance iterate, residual and ladder
+ * only), then the FP64 ladder of every refined iterate runs in one
+ * persistent launch and gives each right-hand side its FP64 residual, the
+ * stopping test against opts->tol (at most opts->max_outer sweeps).
+ * info->n_sigma_fp64 counts those persistent launches (iterations of the
+ * FP64 solve), info->n_sigma_lowp the reduced-precision ladder applications
+ * summed over instances.  opts->anchor_prec must be LRCC_FP64 and
+ * opts->resid_fp64_every has no effect (every sweep ends on the FP64
+ * ladder).  The complex form of every FP64 / FP32 ladder is opts->cmul. */
 lrcc_status lrcc_solve_batched(lrcc_handle h, int ninst, const lrcc_instance* inst,
                                const lrcc_solve_opts* opts, lrcc_solve_info* info);
 

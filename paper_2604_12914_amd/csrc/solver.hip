@@ -161,7 +161,15 @@ __global__ __launch_bounds__(RB) void k_resid(Dims d, const double* __restrict__
   for (int j = 0; j < MAXD; ++j) dots[j] = make_double2(0, 0);
   for (long f = blockIdx.x * (long)RB + threadIdx.x; f < d.per_rhs; f += (long)gridDim.x * RB) {
     Elem e = locate(d, r, f, tab, otab);
-    if (!e.live) continue;
+    if (!e.live) {
+      // dead slots of the ring stay zero (a ring shared by several
+      // instances may hold another layout's values there)
+      xt[slot * hs + e.g] = 0;
+      xt[slot * hs + e.g + d.plane] = 0;
+      ev[slot * hs + e.g] = 0;
+      ev[slot * hs + e.g + d.plane] = 0;
+      continue;
+    }
     const double D = denom(d, e, eps, w);
     const double br = b[e.g], bi = b[e.g + d.plane];
     const double xr = x[e.g], xi = x[e.g + d.plane];
@@ -486,12 +494,13 @@ __global__ void k_axpy1(long n, const double* __restrict__ x, double* __restrict
     y[e] += x[e];
 }
 
-// Advance the device-resident iteration counter (one thread).
+// x *= a over n doubles.
 __global__ void k_scale(long n, double a, double* __restrict__ x) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
     x[e] *= a;
 }
 
+// Advance the device-resident iteration counter (one thread).
 __global__ void k_inc(int* itp) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *itp += 1;
 }
@@ -879,6 +888,31 @@ struct Opts {
   int max_iter, mdim, max_outer;
 };
 
+// Refinement residual: rk = b - (D - w) x2 - sx for the active right-hand
+// sides (device flags); the relative residual norms of those flagged in
+// `flags` into rel.  Synchronises `st`.
+lrcc_status refine_residual(Solver& S, const std::vector<int>& flags, std::vector<double>& rel,
+                            hipStream_t st) {
+  lrcc_handle h = S.h;
+  hipLaunchKernelGGL(k_outer, grid_rhs(S, S.n), dim3(RB), 0, st, S.d, S.eps, S.omega, S.tab,
+                     S.otab, S.active, S.b, S.x2, S.sx, S.rk, S.part);
+  LRCC_HIP(h, hipGetLastError());
+  LRCC_HIP(h, hipMemcpyAsync(S.h_part, S.part, (size_t)S.n * S.nchunk * sizeof(double2),
+                             hipMemcpyDeviceToHost, st));
+  LRCC_HIP(h, hipStreamSynchronize(st));
+  for (int r = 0; r < S.n; ++r) {
+    if (!flags[r]) continue;
+    double rr = 0, bb = 0;
+    for (int c = 0; c < S.nchunk; ++c) {
+      rr += S.h_part[(size_t)r * S.nchunk + c].x;
+      bb += S.h_part[(size_t)r * S.nchunk + c].y;
+    }
+    rel[r] = std::sqrt(rr / bb);
+    if (!std::isfinite(rel[r])) return fail(h, LRCC_ERR_NONFINITE, "non-finite residual");
+  }
+  return LRCC_OK;
+}
+
 lrcc_status read_opts(lrcc_handle h, const lrcc_solve_opts* in, lrcc_solve_opts* op, Opts* o) {
   *op = lrcc_solve_opts{};
   if (in) *op = *in;
@@ -995,26 +1029,8 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
     LRCC_HIP(h, hipMemcpyAsync(S.rk, S.b, vb, hipMemcpyDeviceToDevice, h->stream));
     std::vector<int> act(S.n, 1);
     std::vector<double> rel(S.n, 1.0);
-    // rk = b - (D - w) x2 - sx for the RHS flagged in `flags`; their relative
-    // residual norms into rel
     auto outer_residual = [&](const std::vector<int>& flags) -> lrcc_status {
-      hipLaunchKernelGGL(k_outer, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.eps, S.omega,
-                         S.tab, S.otab, S.active, S.b, S.x2, S.sx, S.rk, S.part);
-      LRCC_HIP(h, hipGetLastError());
-      LRCC_HIP(h, hipMemcpyAsync(S.h_part, S.part, (size_t)S.n * S.nchunk * sizeof(double2),
-                                 hipMemcpyDeviceToHost, h->stream));
-      LRCC_HIP(h, hipStreamSynchronize(h->stream));
-      for (int r = 0; r < S.n; ++r) {
-        if (!flags[r]) continue;
-        double rr = 0, bb = 0;
-        for (int c = 0; c < S.nchunk; ++c) {
-          rr += S.h_part[(size_t)r * S.nchunk + c].x;
-          bb += S.h_part[(size_t)r * S.nchunk + c].y;
-        }
-        rel[r] = std::sqrt(rr / bb);
-        if (!std::isfinite(rel[r])) return fail(h, LRCC_ERR_NONFINITE, "non-finite residual");
-      }
-      return LRCC_OK;
+      return refine_residual(S, flags, rel, h->stream);
     };
     // whether sx is the FP64 ladder of the whole iterate (then rel is the true
     // FP64 residual), or an estimate built from reduced-precision ladders
@@ -1041,56 +1057,63 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
       write_metrics(S, 0, nact0, rel.data());
       if (nact0 == 0) result = LRCC_OK;
     }
-    for (int outer = 0; outer < O.max_outer && nact0 > 0; ++outer) {
-      S.phase = "inner";
-      S.sweep = outer;
-      lrcc_status is = jacobi_diis(S, S.rk, S.x, op.prec, op.cmul, h->ls2.p, O.inner_tol,
-                                   O.max_iter, act.data());
-      if (is == LRCC_ERR_NONFINITE) return fail(h, is, "non-finite residual");
-      // x2 += d; sx = ladder(x2): FP64 ladder of the whole iterate in the
-      // first sweep (or every sweep), else sx += reduced-precision ladder of
-      // the correction d; then rk = b - (D - w) x2 - sx
-      LRCC_HIP(h, hipMemcpyAsync(S.active, act.data(), S.n * sizeof(int), hipMemcpyHostToDevice,
-                                 h->stream));
-      hipLaunchKernelGGL(k_add, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.active, S.x,
-                         S.x2);
-      LRCC_HIP(h, hipGetLastError());
-      if (outer == 0 || op.resid_fp64_every) {
-        st = apply_sigma(S, S.x2, anchor, op.cmul, h->ls.p);
-        if (st != LRCC_OK) return st;
-        LRCC_HIP(h, hipMemcpyAsync(S.sx, S.s, vb, hipMemcpyDeviceToDevice, h->stream));
-        sx_exact = anchor == LRCC_FP64;
-      } else {
-        st = apply_sigma(S, S.x, op.prec, op.cmul, h->ls2.p);
-        if (st != LRCC_OK) return st;
-        hipLaunchKernelGGL(k_acc, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.active, S.s,
-                           S.sx);
+    // the precision of the full-iterate ladders: the anchor, and FP64 once a
+    // check of the returned iterate has run (its staged vectors replace the
+    // anchor's)
+    lrcc_prec full_prec = anchor;
+    bool exact_sweeps = op.resid_fp64_every != 0;
+    int outer = 0;
+    for (;;) {
+      for (; outer < O.max_outer && nact0 > 0; ++outer) {
+        S.phase = "inner";
+        S.sweep = outer;
+        lrcc_status is = jacobi_diis(S, S.rk, S.x, op.prec, op.cmul, h->ls2.p, O.inner_tol,
+                                     O.max_iter, act.data());
+        if (is == LRCC_ERR_NONFINITE) return fail(h, is, "non-finite residual");
+        // x2 += d; sx = ladder(x2): the full-iterate ladder in the first sweep
+        // (or every sweep), else sx += reduced-precision ladder of the
+        // correction d; then rk = b - (D - w) x2 - sx
+        LRCC_HIP(h, hipMemcpyAsync(S.active, act.data(), S.n * sizeof(int),
+                                   hipMemcpyHostToDevice, h->stream));
+        hipLaunchKernelGGL(k_add, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.active, S.x,
+                           S.x2);
         LRCC_HIP(h, hipGetLastError());
-        sx_exact = false;
+        if (outer == 0 || exact_sweeps) {
+          st = apply_sigma(S, S.x2, full_prec, op.cmul, h->ls.p);
+          if (st != LRCC_OK) return st;
+          LRCC_HIP(h, hipMemcpyAsync(S.sx, S.s, vb, hipMemcpyDeviceToDevice, h->stream));
+          sx_exact = full_prec == LRCC_FP64;
+        } else {
+          st = apply_sigma(S, S.x, op.prec, op.cmul, h->ls2.p);
+          if (st != LRCC_OK) return st;
+          hipLaunchKernelGGL(k_acc, grid_rhs(S, S.n), dim3(RB), 0, h->stream, S.d, S.active,
+                             S.s, S.sx);
+          LRCC_HIP(h, hipGetLastError());
+          sx_exact = false;
+        }
+        st = outer_residual(act);
+        if (st != LRCC_OK) return st;
+        int nact = 0;
+        for (int r = 0; r < S.n; ++r) {
+          if (!act[r]) continue;
+          if (rel[r] < O.tol) act[r] = 0;
+          else ++nact;
+        }
+        S.phase = "outer";
+        write_metrics(S, 0, nact, rel.data());
+        nact0 = nact;
       }
-      st = outer_residual(act);
-      if (st != LRCC_OK) return st;
-      int nact = 0;
-      for (int r = 0; r < S.n; ++r) {
-        if (!act[r]) continue;
-        if (rel[r] < O.tol) act[r] = 0;
-        else ++nact;
-      }
-      S.phase = "outer";
-      write_metrics(S, 0, nact, rel.data());
-      if (nact == 0) {
-        result = LRCC_OK;
-        break;
-      }
-    }
-    if (!sx_exact) {
-      // The stopping test above used an estimate of the ladder of x2 (an
-      // FP32 anchor, or an FP64 anchor plus reduced-precision ladders of the
-      // later corrections).  The reported residual is the FP64 one of the
-      // returned iterate: one FP64 ladder of every right-hand side's x2.
-      if (anchor != LRCC_FP64) {
+      if (nact0 > 0 || sx_exact) break;  // out of sweeps, or converged on the FP64 residual
+      // The stopping test used an estimate of the ladder of x2 (an FP32
+      // anchor, or an FP64 anchor plus reduced-precision ladders of the later
+      // corrections).  The reported residual is the FP64 one of the returned
+      // iterate: one FP64 ladder of every right-hand side's x2.  Where it
+      // misses the tolerance the refinement goes on from that residual, with
+      // an FP64 ladder of the whole iterate in every further sweep.
+      if (full_prec != LRCC_FP64) {
         st = stage_for(S, L, LRCC_FP64, op.cmul, h->ls, form);
         if (st != LRCC_OK) return st;
+        full_prec = LRCC_FP64;
       }
       std::vector<int> every(S.n, 1);
       LRCC_HIP(h, hipMemcpyAsync(S.active, every.data(), S.n * sizeof(int),
@@ -1100,12 +1123,18 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
       LRCC_HIP(h, hipMemcpyAsync(S.sx, S.s, vb, hipMemcpyDeviceToDevice, h->stream));
       st = outer_residual(every);
       if (st != LRCC_OK) return st;
+      sx_exact = true;
+      exact_sweeps = true;
+      nact0 = 0;
+      for (int r = 0; r < S.n; ++r) {
+        act[r] = !(rel[r] < O.tol);
+        nact0 += act[r];
+      }
       S.phase = "final";
-      write_metrics(S, 0, 0, rel.data());
-      result = LRCC_OK;
-      for (int r = 0; r < S.n; ++r)
-        if (!(rel[r] < O.tol)) result = LRCC_ERR_NOT_CONVERGED;
+      write_metrics(S, 0, nact0, rel.data());
+      if (nact0 == 0) break;
     }
+    result = nact0 == 0 ? LRCC_OK : LRCC_ERR_NOT_CONVERGED;
     for (int r = 0; r < S.n; ++r) final_rel = std::max(final_rel, rel[r]);
     st = finish_alpha(S, S.x2, alpha, h->stream);
     if (st != LRCC_OK) return st;
@@ -1206,6 +1235,101 @@ lrcc_status solve_impl(lrcc_handle h, int o, int v, int nchol, const double* eps
 // instance's residual / DIIS / extrapolation / counter kernels) is captured
 // once into a hip graph and replayed until the active set changes.
 
+// Batched iterative refinement (reduced-precision inner solves).  Per sweep:
+// the correction equation (A - w) d = r of every instance with unconverged
+// right-hand sides, one instance after another with the reduced-precision
+// ladder (the DIIS ring, the reduced-precision doubles and staged vectors
+// shared, `ls2` restaged per instance); x2 += d; then the FP64 ladder of
+// every such instance's x2 in ONE persistent launch, and each instance's
+// FP64 residual r = b - (D - w) x2 - ladder(x2).  Every sweep ends on that
+// FP64 residual, which is the stopping test and the reported residual.
+template <class Upload>
+lrcc_status batched_refine(lrcc_handle h, int ninst, const lrcc_instance* inst,
+                           const lrcc_solve_opts& op, const Opts& O,
+                           std::vector<std::unique_ptr<Solver>>& S, const std::vector<int>& live,
+                           Upload& upload_desc, Buf& desc, size_t desc_bytes, Buf& counter, int nx,
+                           Buf& ls2, hipStream_t cs, lrcc_solve_info* info,
+                           std::chrono::steady_clock::time_point t0) {
+  lrcc_status st;
+  hipStream_t hs = h->stream;
+  LRCC_HIP(h, hipStreamSynchronize(cs));  // the set-up ran on cs
+  std::vector<std::vector<int>> act(ninst);
+  std::vector<std::vector<double>> rel(ninst);
+  for (int i : live) {
+    Solver& Si = *S[i];
+    act[i].assign(Si.n, 1);
+    rel[i].assign(Si.n, 1.0);
+    const size_t vb = (size_t)2 * Si.d.plane * 8;
+    LRCC_HIP(h, fill_zero(Si.x2, vb, hs));
+    LRCC_HIP(h, hipMemcpyAsync(Si.rk, Si.b, vb, hipMemcpyDeviceToDevice, hs));
+  }
+  int n_outer = 0;
+  for (int sweep = 0; sweep < O.max_outer; ++sweep) {
+    std::vector<int> now;
+    for (int i : live)
+      if (std::count(act[i].begin(), act[i].end(), 1) > 0) now.push_back(i);
+    if (now.empty()) break;
+    for (int i : now) {
+      Solver& Si = *S[i];
+      // the reduced-precision ladders take the handle's block-pair table
+      st = ensure_tab(h, Si.g.nbv);
+      if (st != LRCC_OK) return st;
+      st = stage_for(Si, inst[i].L, op.prec, op.cmul, ls2, L_PLAIN);
+      if (st != LRCC_OK) return st;
+      Si.phase = "inner";
+      Si.sweep = sweep;
+      lrcc_status is = jacobi_diis(Si, Si.rk, Si.x, op.prec, op.cmul, ls2.p, O.inner_tol,
+                                   O.max_iter, act[i].data());
+      if (is == LRCC_ERR_NONFINITE) return fail(h, is, "non-finite residual");
+      LRCC_HIP(h, hipMemcpyAsync(Si.active, act[i].data(), Si.n * sizeof(int),
+                                 hipMemcpyHostToDevice, hs));
+      hipLaunchKernelGGL(k_add, grid_rhs(Si, Si.n), dim3(RB), 0, hs, Si.d, Si.active, Si.x, Si.x2);
+      LRCC_HIP(h, hipGetLastError());
+      LRCC_HIP(h, fill_zero(Si.s, (size_t)2 * Si.d.plane * 8, hs));
+    }
+    // the FP64 ladder of every refined iterate in one persistent launch
+    st = upload_desc(now, true, hs);
+    if (st != LRCC_OK) return st;
+    LRCC_HIP(h, fill_zero(counter.p, 64, hs));
+    LRCC_HIP(h, ppl_queue_launch(desc.as<BatchInst>(), (int)now.size(),
+                                 reinterpret_cast<const long*>(desc.as<char>() + desc_bytes), nx,
+                                 counter.as<unsigned>(), h->ncu, op.cmul == LRCC_CMUL_3M, hs));
+    ++n_outer;
+    for (int i : now) {
+      Solver& Si = *S[i];
+      LRCC_HIP(h, hipMemcpyAsync(Si.sx, Si.s, (size_t)2 * Si.d.plane * 8,
+                                 hipMemcpyDeviceToDevice, hs));
+      st = refine_residual(Si, act[i], rel[i], hs);
+      if (st != LRCC_OK) return st;
+      for (int r = 0; r < Si.n; ++r)
+        if (act[i][r] && rel[i][r] < O.tol) act[i][r] = 0;
+    }
+  }
+  lrcc_status result = LRCC_OK;
+  double final_rel = 0;
+  int iters_max = 0, n_lowp = 0;
+  for (int i : live) {
+    Solver& Si = *S[i];
+    for (int r = 0; r < Si.n; ++r) {
+      final_rel = std::max(final_rel, rel[i][r]);
+      if (act[i][r]) result = LRCC_ERR_NOT_CONVERGED;
+    }
+    st = finish_alpha(Si, Si.x2, inst[i].alpha, hs);
+    if (st != LRCC_OK) return st;
+    iters_max = std::max(iters_max, Si.iters_max);
+    n_lowp += Si.n_sigma_lp;
+  }
+  if (info) {
+    info->iters_max = iters_max;
+    info->n_sigma_fp64 = n_outer;
+    info->n_sigma_lowp = n_lowp;
+    info->final_relres = final_rel;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (result == LRCC_ERR_NOT_CONVERGED) return fail(h, result, "tolerance not reached");
+  return result;
+}
+
 lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* inst,
                                const lrcc_solve_opts* opts_in, lrcc_solve_info* info) {
   auto t0 = std::chrono::steady_clock::now();
@@ -1213,8 +1337,10 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
   Opts O;
   lrcc_status st = read_opts(h, opts_in, &op, &O);
   if (st != LRCC_OK) return st;
-  if (op.prec != LRCC_FP64)
-    return fail(h, LRCC_ERR_UNSUPPORTED, "the batched solve runs the FP64 ladder");
+  const bool ir = op.prec != LRCC_FP64;
+  if (ir && op.anchor_prec != LRCC_FP64)
+    return fail(h, LRCC_ERR_UNSUPPORTED,
+                "the batched refinement takes its residuals from the FP64 ladder (anchor_prec)");
   if (op.x0 || op.x_out || op.metrics_path)
     return fail(h, LRCC_ERR_UNSUPPORTED,
                 "the batched solve takes no initial amplitudes, amplitude output or metrics file");
@@ -1247,12 +1373,40 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
     }
   } sfree{cs};
   const int nx = std::min(QXMAX, std::max(1, h->ncu / 32));  // XCDs
+  // Refinement: the inner solves run one instance at a time, so the DIIS
+  // ring, the reduced-precision copies of the doubles and the reduced-
+  // precision staged vectors are one set, sized for the largest instance
+  // and shared by all; each instance keeps its own iterate, residual and
+  // ladder of the iterate.
+  Buf shared[4];  // 0 ring X~, 1 ring e, 2 x32/s32, 3 staged reduced-precision vectors
+  struct SharedFree {
+    Buf* b;
+    ~SharedFree() {
+      for (int k = 0; k < 4; ++k) b[k].release();
+    }
+  } shfree{shared};
+  if (ir) {
+    size_t vmax = 0;
+    for (int i = 0; i < ninst; ++i) {
+      const Geom gi = make_geom(inst[i].o, inst[i].v, inst[i].nchol, inst[i].nomega * inst[i].ncomp, 1);
+      if (gi.M == 0 || gi.npv == 0) continue;
+      vmax = std::max(vmax, (size_t)2 * gi.xb_plane() * 8);
+    }
+    LRCC_HIP(h, shared[0].ensure(std::max<size_t>(vmax * O.mdim, 16)));
+    LRCC_HIP(h, shared[1].ensure(std::max<size_t>(vmax * O.mdim, 16)));
+    LRCC_HIP(h, shared[2].ensure(std::max<size_t>(vmax, 16)));
+  }
   for (int i = 0; i < ninst; ++i) {
     const lrcc_instance& I = inst[i];
     S[i].reset(new Solver());
     own[i].reset(new Buf[NBUF]);
     Solver& Si = *S[i];
     for (int k = 0; k < NBUF; ++k) Si.buf[k] = &own[i][k];
+    if (ir) {
+      Si.buf[3] = &shared[0];
+      Si.buf[4] = &shared[1];
+      Si.buf[10] = &shared[2];
+    }
     const Geom g0 = make_geom(I.o, I.v, I.nchol, I.nomega * I.ncomp, 1);
     if (g0.M == 0 || g0.npv == 0) {
       for (int p = 0; p < 2 * I.nomega * I.ncomp * I.ncomp; ++p) I.alpha[p] = 0;
@@ -1268,7 +1422,7 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
     LRCC_HIP(h, hipMemcpyAsync(own[i][13].p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, cs));
     LRCC_HIP(h, hipMemcpyAsync(own[i][14].p, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, cs));
     LRCC_HIP(h, hipStreamSynchronize(cs));
-    st = setup(Si, h, I.o, I.v, I.nchol, I.eps, I.ncomp, I.mu, I.nomega, I.omegas, O.mdim, false,
+    st = setup(Si, h, I.o, I.v, I.nchol, I.eps, I.ncomp, I.mu, I.nomega, I.omegas, O.mdim, ir,
                own[i][13].as<int>(), false, cs);
     if (st != LRCC_OK) return st;
     Geom gs = Si.g;
@@ -1278,8 +1432,10 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
     if (gs.nchol > 0)
       LRCC_HIP(h, stage_L<double>(I.L, LRCC_C128, gs, L_PLAIN, own[i][12].as<double>(), cs));
     std::vector<int> one(Si.n, 1);
-    st = start_iteration(Si, Si.b, Si.x, one.data(), cs);
-    if (st != LRCC_OK) return st;
+    if (!ir) {
+      st = start_iteration(Si, Si.b, Si.x, one.data(), cs);
+      if (st != LRCC_OK) return st;
+    }
     LRCC_HIP(h, hipStreamSynchronize(cs));  // `one` goes out of scope
     live.push_back(i);
   }
@@ -1307,6 +1463,41 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
       if (*g) (void)hipGraphDestroy(*g);
     }
   } gfree{&graph, &exec};
+  // queue descriptors of the instances `now` (longest tile first: tile cost
+  // ~ 2 ncp + Mp), the ladder reading x (or x2, the refined iterate) and
+  // writing s, then the per-XCD item totals; synchronises `q`
+  auto by_cost = [&](std::vector<int>& now) {
+    std::stable_sort(now.begin(), now.end(), [&](int a, int b) {
+      const Solver &A = *S[a], &B = *S[b];
+      return 2 * roundup(A.g.nchol, KC) + A.g.Mp > 2 * roundup(B.g.nchol, KC) + B.g.Mp;
+    });
+  };
+  auto upload_desc = [&](std::vector<int>& now, bool use_x2, hipStream_t q) -> lrcc_status {
+    by_cost(now);
+    std::vector<BatchInst> d(now.size());
+    long total = 0;
+    std::vector<long> xtotal(QXMAX, 0);
+    for (size_t k = 0; k < now.size(); ++k) {
+      const Solver& Si = *S[now[k]];
+      d[k] = BatchInst{own[now[k]][12].as<double>(), use_x2 ? Si.x2 : Si.x, Si.s, Si.tab,
+                       own[now[k]][14].as<int>(), Si.nonherm, Si.g.nbv, Si.g.nbp,
+                       (int)roundup(Si.g.nchol, KC), (int)Si.g.Mp, Si.g.v, total, {}};
+      const long items = Si.g.nchol > 0 ? 2 * ppl_ntile(Si.g) : 0;  // tiles, then mirrors
+      for (int x = 0; x < nx; ++x) {
+        d[k].xstart[x] = xtotal[x];
+        xtotal[x] += items > x ? (items - x + nx - 1) / nx : 0;  // items l = x mod nx
+      }
+      total += items;
+    }
+    LRCC_HIP(h, hipMemcpyAsync(desc.p, d.data(), d.size() * sizeof(BatchInst),
+                               hipMemcpyHostToDevice, q));
+    LRCC_HIP(h, hipMemcpyAsync(desc.as<char>() + desc_bytes, xtotal.data(), sizeof(long) * QXMAX,
+                               hipMemcpyHostToDevice, q));
+    LRCC_HIP(h, hipStreamSynchronize(q));
+    return LRCC_OK;
+  };
+  if (ir) return batched_refine(h, ninst, inst, op, O, S, live, upload_desc, desc, desc_bytes,
+                                counter, nx, shared[3], cs, info, t0);
   std::vector<int> active_set;  // instances in the captured graph
   lrcc_status result = LRCC_OK;
   int n_launch = 0;
@@ -1318,32 +1509,11 @@ lrcc_status solve_batched_impl(lrcc_handle h, int ninst, const lrcc_instance* in
       if (any) now.push_back(i);
     }
     if (now.empty()) break;
+    by_cost(now);  // the order of the captured set, so an unchanged set is not captured again
     if (now != active_set) {
       // (re)build the queue descriptors and capture one iteration
-      std::sort(now.begin(), now.end(), [&](int a, int b) {
-        const Solver &A = *S[a], &B = *S[b];
-        return 2 * roundup(A.g.nchol, KC) + A.g.Mp > 2 * roundup(B.g.nchol, KC) + B.g.Mp;
-      });
-      std::vector<BatchInst> d(now.size());
-      long total = 0;
-      std::vector<long> xtotal(QXMAX, 0);
-      for (size_t k = 0; k < now.size(); ++k) {
-        const Solver& Si = *S[now[k]];
-        d[k] = BatchInst{own[now[k]][12].as<double>(), Si.x, Si.s, Si.tab,
-                         own[now[k]][14].as<int>(), Si.nonherm, Si.g.nbv, Si.g.nbp,
-                         (int)roundup(Si.g.nchol, KC), (int)Si.g.Mp, Si.g.v, total, {}};
-        const long items = Si.g.nchol > 0 ? 2 * ppl_ntile(Si.g) : 0;  // tiles, then mirrors
-        for (int x = 0; x < nx; ++x) {
-          d[k].xstart[x] = xtotal[x];
-          xtotal[x] += items > x ? (items - x + nx - 1) / nx : 0;  // items l = x mod nx
-        }
-        total += items;
-      }
-      LRCC_HIP(h, hipMemcpyAsync(desc.p, d.data(), d.size() * sizeof(BatchInst),
-                                 hipMemcpyHostToDevice, cs));
-      LRCC_HIP(h, hipMemcpyAsync(desc.as<char>() + desc_bytes, xtotal.data(),
-                                 sizeof(long) * QXMAX, hipMemcpyHostToDevice, cs));
-      LRCC_HIP(h, hipStreamSynchronize(cs));
+      st = upload_desc(now, false, cs);
+      if (st != LRCC_OK) return st;
       if (exec) {
         LRCC_HIP(h, hipGraphExecDestroy(exec));
         exec = nullptr;

@@ -1,5 +1,7 @@
 """Batched solve (one persistent ladder launch per iteration over every
-instance, graph-captured) against per-instance eager solves and the oracle."""
+instance, graph-captured; with reduced precision, refinement whose FP64
+residuals come from one persistent launch per sweep) against per-instance
+eager solves and the oracle."""
 import numpy as np
 import pytest
 
@@ -59,8 +61,38 @@ def test_batch_with_empty_and_single_instance(lrcc):
     exact = response.solve_dense(inst.L, inst.eps, inst.mu, [0.0], 3, 16)["alpha"]
     assert np.abs(alphas[0] - exact).max() < 1e-7 * np.abs(exact).max()
     assert np.all(alphas[1] == 0)
-    with pytest.raises(lrcc.LrccError):
-        lrcc.solve_batched([dev_inst(inst, [0.0])], prec="fp32")
+    # refinement with an empty instance in the batch
+    alphas, info = lrcc.solve_batched([dev_inst(inst, [0.0]), dev_inst(empty, [0.0])],
+                                      prec="fp32")
+    assert np.abs(alphas[0] - exact).max() < 1e-7 * np.abs(exact).max()
+    assert np.all(alphas[1] == 0) and info["n_sigma_fp64"] >= 1
+
+
+@pytest.mark.parametrize("prec,cmul", [("fp32", "4m"), ("fp32", "3m"), ("bf16x3", "4m")])
+def test_batched_refinement_matches_oracle(lrcc, prec, cmul):
+    # the uneven batch of the FP64 test with reduced-precision inner solves:
+    # every sweep ends on the FP64 residual of all instances from one
+    # persistent launch, so the tolerance holds for the FP64 residual and
+    # alpha matches the exact solve as the FP64 solve does
+    shapes = [(2, 20, 80, 0), (3, 30, 120, 1), (4, 40, 160, 2), (5, 44, 100, 3)]
+    insts, devs = [], []
+    for (o, v, nchol, seed) in shapes:
+        inst = S.make_instance(o, v, nchol, ncomp=3, seed=seed, gamma=S.solve_gamma(v),
+                               hermitian=seed != 2)
+        om = OMEGAS if seed != 1 else OMEGAS[:2]
+        insts.append((inst, om))
+        devs.append(dev_inst(inst, om))
+    print(f"batched refinement {prec} {cmul}", flush=True)
+    alphas, info = lrcc.solve_batched(devs, tol=1e-8, prec=prec, cmul=cmul, inner_tol=1e-5)
+    assert info["status"] == "LRCC_OK" and info["final_relres"] < 1e-8
+    assert info["n_sigma_fp64"] >= 1 and info["n_sigma_lowp"] > 0
+    for (inst, om), a in zip(insts, alphas):
+        exact = response.solve_dense(inst.L, inst.eps, inst.mu, om, inst.o, inst.v)["alpha"]
+        assert np.abs(a - exact).max() < 1e-7 * np.abs(exact).max()
+    # the FP64 residual ends every sweep: far fewer FP64 ladders than the
+    # FP64 solve's iterations
+    _, info64 = lrcc.solve_batched(devs, tol=1e-8, cmul=cmul)
+    assert info["n_sigma_fp64"] < info64["n_sigma_fp64"]
 
 
 def test_batched_workload_full_size_matches_single_solves(lrcc):
@@ -70,7 +102,11 @@ def test_batched_workload_full_size_matches_single_solves(lrcc):
     # equal its own single solve (same ladder, same tile order, sums in
     # another order across workgroups: rounding only), and the smallest
     # instance the oracle's exact alpha.  Four DIIS vectors: eight do not fit
-    # the two o = 32 instances' history beside the others.
+    # the two o = 32 instances' history beside the others.  Then the same
+    # batch refined with bf16x3 inner solves and eight DIIS vectors (the inner
+    # history is one set shared by the instances) to the FP64 residual 1e-8.
+    # The batches run before the single solves, whose grow-only workspace
+    # stays with the handle.
     torch.cuda.empty_cache()
     cfg = S.CONFIGS["batch"]
     insts, devs = [], []
@@ -81,14 +117,20 @@ def test_batched_workload_full_size_matches_single_solves(lrcc):
     print("full batched workload: batched solve", flush=True)
     alphas, info = lrcc.solve_batched(devs, tol=1e-6, diis_dim=4)
     assert info["status"] == "LRCC_OK" and info["final_relres"] < 1e-6
+    print("full batched workload: bf16x3 refinement", flush=True)
+    ref_alphas, rinfo = lrcc.solve_batched(devs, tol=1e-8, prec="bf16x3", diis_dim=8)
+    assert rinfo["status"] == "LRCC_OK" and rinfo["final_relres"] < 1e-8
     for k, (inst, a, d) in enumerate(zip(insts, alphas, devs)):
         print(f"full batched workload: single solve {k} (o={inst.o})", flush=True)
         single, sinfo = lrcc.solve(d["eps"], d["L"], d["mu"], list(cfg.omegas), tol=1e-6,
                                    diis_dim=4)
         assert sinfo["status"] == "LRCC_OK"
         assert np.abs(a - single).max() <= 1e-10 * np.abs(single).max()
+        # the FP64 batch stopped at 1e-6: its alpha is that close to the refined one
+        assert np.abs(a - ref_alphas[k]).max() < 1e-5 * np.abs(ref_alphas[k]).max()
     inst = insts[0]
     exact = response.solve_sos(inst.L, inst.eps, inst.mu, list(cfg.omegas), inst.o,
                                inst.v)["alpha"]
     # a relative residual below 1e-6 bounds the error in alpha well below 1e-5
     assert np.abs(alphas[0] - exact).max() < 1e-5 * np.abs(exact).max()
+    assert np.abs(ref_alphas[0] - exact).max() < 1e-7 * np.abs(exact).max()

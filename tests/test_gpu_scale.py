@@ -99,7 +99,7 @@ def test_scale_adjoint_dX_sampled_entries(lrcc, inputs):
     dX, _ = lrcc.ppl_sigma_adjoint(Ld, Xd, Gd, want_dL=False)
     got = sampled(dX, inputs)
     del dX
-    LH = np.conj(np.transpose(L, (0, 2, 1)))
+    LH = np.ascontiguousarray(np.conj(np.transpose(L, (0, 2, 1))))  # C order: fast slices
     ref = ppl.sigma_entries(LH, G, V, inputs["rows"], inputs["pairs"])
     err = rel(got, ref)
     print(f"scale adjoint dX: sampled relative error {err:.2e}", flush=True)

@@ -95,7 +95,10 @@ def test_refinement_reaches_fp64_answer(lrcc, prec, every):
     if every:
         assert info["n_sigma_fp64"] <= 3
     else:
-        assert info["n_sigma_fp64"] == 1
+        # the first sweep's full-iterate FP64 ladder, and one more FP64 ladder
+        # of the returned iterate when later sweeps updated it with reduced-
+        # precision ladders of the corrections
+        assert 1 <= info["n_sigma_fp64"] <= 2
 
 
 def _golden(name):
@@ -164,7 +167,9 @@ def test_full_response_reduced_precision(lrcc, prec):
     ref = response.response_full_dense(inst.L, inst.eps, inst.mu, om, o, v)["alpha"]
     assert info["status"] == "LRCC_OK"
     assert rel(alpha, ref) < 1e-7
-    assert info["n_sigma_fp64"] == 2  # one FP64 anchor ladder per side
+    # per side: the first sweep's FP64 anchor ladder, and one FP64 ladder of
+    # the returned iterate if later sweeps used reduced-precision updates
+    assert 2 <= info["n_sigma_fp64"] <= 4
 
 
 def test_response_mode_errors(lrcc):
