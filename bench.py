@@ -361,13 +361,12 @@ def extras(lrcc, torch, np, S, Lscale, Xscale, args):
     X = torch.from_numpy(S.make_packed(np.random.default_rng(3), nrhs, o, v)).cuda()
     Lraw = torch.from_numpy(S.make_L(np.random.default_rng(4), nchol, v)).cuda()
     sb = {}
+    # (default launch variants: the ones every later measurement here uses)
     for prec, cmul in (("fp64", "4m"), ("fp64", "3m"), ("fp32", "4m"), ("fp32", "3m"),
                        ("bf16x3", "4m")):
         try:
-            progress(f"extra: baseline ladder {prec} {cmul} (autotune, 20 repetitions)")
-            tune = lrcc.autotune(o, v, nchol, nrhs, prec=prec, cmul=cmul)
+            progress(f"extra: baseline ladder {prec} {cmul} (20 repetitions)")
             e = sigma_extra(lrcc, torch, o, v, nchol, nrhs, prec, cmul, Lraw, X, 20)
-            e["tuned"] = {"supertile": tune["supertile"], "occupancy": tune["occupancy"]}
             sb[f"{prec}_{cmul}"] = e
         except lrcc.LrccError as err:
             sb[f"{prec}_{cmul}"] = {"error": str(err)}
@@ -756,7 +755,6 @@ def profile_batched(lrcc, torch, np, S, args):
         F += flops_per_sigma(o, v, nchol, cfg.ncomp * len(om))
     o, v, nchol = max(i[0] for i in cfg.instances), max(i[1] for i in cfg.instances), \
         max(i[2] for i in cfg.instances)
-    lrcc.autotune(o, v, nchol, cfg.ncomp * len(om), prec="fp64", cmul="3m")
     out = {"profile_batched": "8 instances, 96 right-hand sides"}
 
     def keep(info, t):

@@ -455,7 +455,9 @@ typedef struct {
  * handle for later calls.  cache_path (host, nullable): a text file of
  * earlier results keyed by (arch, CU count, o, v, nchol, nrhs, prec, cmul);
  * a hit skips the timing, a miss appends the new result.  Tuning restarts
- * the totals of lrcc_get_timing. */
+ * the totals of lrcc_get_timing.  LRCC_BF16X3 has a single launch form and
+ * a fixed work order: nothing is timed (supertile 4, occupancy 1,
+ * candidates 0). */
 lrcc_status lrcc_autotune(lrcc_handle h, int o, int v, int nchol, int nrhs, lrcc_prec prec,
                           lrcc_cmul cmul, const char* cache_path, lrcc_tune_result* out);
 

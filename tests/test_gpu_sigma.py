@@ -320,6 +320,9 @@ def test_autotune_cache_and_parity_after_tuning(lrcc, tmp_path):
         again = lrcc.autotune(o, v, nchol, nrhs, prec=prec, cache_path=cache)
         assert again["candidates"] == 0
         assert (again["supertile"], again["occupancy"]) == (r["supertile"], r["occupancy"])
+    # bf16x3: one launch form, nothing timed
+    r = lrcc.autotune(o, v, nchol, nrhs, prec="bf16x3", cache_path=cache)
+    assert r["candidates"] == 0 and r["supertile"] == 4
     rng = np.random.default_rng(500)
     L = S.make_L(rng, nchol, v, hermitian=False)
     X = S.make_packed(rng, nrhs, o, v)
