@@ -26,8 +26,9 @@
 //   k_contract sigma[m, Q] += sum_{CD >= Q} X[m, CD] V(Q, CD)^T
 //                           + sum_{AB < Q, AB in panel} X[m, AB] V(Q, AB)^T,
 //              a bf16x3 GEMM in which each workgroup owns its output tile
-//              (128 rows x 64 slots of block pair Q) for the whole panel: no
-//              atomics.  With one panel every workgroup runs over nbp tiles.
+//              (an m-block of rows x 64 slots of block pair Q) for the whole
+//              panel: no atomics.  With one panel every workgroup runs over
+//              nbp tiles.
 // The integral panel is transient: at most one panel exists.
 // The reason for the split: the fused kernel's atomic accumulation of sigma
 // across CD tiles runs at the device's atomic throughput, which caps the fast
@@ -35,6 +36,7 @@
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "internal.hpp"
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(BWG, 1) void k_vbuild(const __bf16* __restrict__ Ls
 }
 
 // ---------------------------------------------------------------------------
-// Contraction of one panel [ab0, ab1): workgroup (m-block of 128 rows, block
+// Contraction of one panel [ab0, ab1): workgroup (m-block of rb rows, block
 // pair q >= ab0); wave w owns rows 32w .. 32w+31 of the block and all 64
 // slots of q.  Its tiles, in ascending order of the contracted block pair b:
 // the mirror tiles V(q, b) of the panel rows b < q, then the upper tiles
@@ -464,14 +466,18 @@ __device__ __forceinline__ void contract_item(int w, int total, int nx, int nmb,
   *mb = r / gq;
   *q = group * QG + r % gq;
 }
-// Two workgroups per CU: while one waits for its X rows (loaded straight into
-// registers, half a tile ahead) the other keeps the matrix cores busy.
-template <typename TA>
-__global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ Xb,
-                                                    const __bf16* __restrict__ Vdir,
-                                                    const __bf16* __restrict__ Vmir, int nbp,
-                                                    int Mp, int nmb, int ab0, int ab1, int nx,
-                                                    int grouped, TA* __restrict__ Sb) {
+// NWV waves per workgroup, each owning 32 rows of the m-block (rb rows, a
+// multiple of 16 up to 32 NWV; the host balances rb over the m-blocks).
+// Four waves: two workgroups per CU, so that while one waits for its X rows
+// (loaded straight into registers, half a tile ahead) the other keeps the
+// matrix cores busy.  Eight waves: one workgroup per CU over twice the rows,
+// so every V tile is read from memory half as often.
+template <typename TA, int NWV>
+__global__ __launch_bounds__(64 * NWV, NWV == 4 ? 2 : 1) void k_contract(
+    const __bf16* __restrict__ Xb, const __bf16* __restrict__ Vdir,
+    const __bf16* __restrict__ Vmir, int nbp, int Mp, int nmb, int rb, int ab0, int ab1, int nx,
+    int grouped, TA* __restrict__ Sb) {
+  constexpr int CWG = 64 * NWV;
   __shared__ __attribute__((aligned(16))) __bf16 vt[2 * VTP];  // two V tiles, 72 KB
   int mb, ql, part;
   contract_item(blockIdx.x, (int)gridDim.x, nx, nmb, nbp - ab0, grouped != 0, &ql, &mb, &part);
@@ -493,19 +499,20 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const size_t plane = (size_t)nbp * Mp * NS;
-  // rows of this wave; blocks past Mp (the last m-block of a short Mp) load
-  // row block 0 instead, so every load is unconditional and in bounds, and
-  // their sums are never stored
+  // rows of this wave; 16-row blocks past the m-block's rb rows or past Mp
+  // load row block 0 instead, so every load is unconditional and in bounds,
+  // and their sums are never stored
   int mrow[2], mld[2];
   bool mok[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    mrow[i] = mb * 128 + 32 * wave + 16 * i;
-    mok[i] = mrow[i] < Mp;
+    mrow[i] = mb * rb + 32 * wave + 16 * i;
+    mok[i] = 32 * wave + 16 * i < rb && mrow[i] < Mp;
     mld[i] = mok[i] ? mrow[i] : 0;
   }
-  // a wave whose rows all lie past Mp (in the last m-block) still loads and
-  // stores its share of every V tile but skips the matrix work
+  // a wave whose rows all lie past the m-block still loads and stores its
+  // share of every V tile but skips the matrix work (its second row block
+  // lies past the first)
   const bool busy = mok[0];
   f4 sr[2][4], si[2][4];
 #pragma unroll
@@ -534,20 +541,21 @@ __global__ __launch_bounds__(WG, 2) void k_contract(const __bf16* __restrict__ X
   // stored to the free buffer after k-step 0, the second half requested then
   // and stored at the end: one barrier per tile, each load has a k-step of
   // matrix work to land, and only half a tile is held in registers.
-  constexpr int VH = VT / 8 / WG / 2;  // 16-byte vectors per thread per half tile (4)
+  constexpr int VH = VT / 8 / CWG / 2;  // 16-byte vectors per thread per half tile (4 or 2)
+  static_assert(VH * 8 * CWG * 2 == VT, "half tiles split evenly over the threads");
   u4 vp[VH];
   int xnext = 0;
   const __bf16* vsrc = Vdir;
   auto fetch_v = [&](int h) {
 #pragma unroll
     for (int k = 0; k < VH; ++k)
-      vp[k] = reinterpret_cast<const u4*>(vsrc)[(h * VH + k) * WG + threadIdx.x];
+      vp[k] = reinterpret_cast<const u4*>(vsrc)[(h * VH + k) * CWG + threadIdx.x];
   };
   auto store_v = [&](__bf16* buf, int h) {
 #pragma unroll
     for (int k = 0; k < VH; ++k) {
       // vector e of the tile: plane-row (e / 8), 8-bf16 part (e % 8)
-      const int e = (h * VH + k) * WG + threadIdx.x;
+      const int e = (h * VH + k) * CWG + threadIdx.x;
       *reinterpret_cast<u4*>(buf + (e >> 3) * NSP + (e & 7) * 8) = vp[k];
     }
   };
@@ -723,7 +731,12 @@ hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* 
                       bool acc64, void* Vws, size_t cap, const int* tab, const int* nonherm,
                       hipStream_t st) {
   if (g.nbp == 0 || g.Mp == 0) return hipSuccess;
-  const int nmb = (int)((g.Mp + 127) / 128);
+  // contraction shape: waves per workgroup, m-blocks and their balanced
+  // row count (a multiple of 16)
+  int cw = 8;
+  if (const char* e = getenv("LRCC_CONTRACT_WAVES")) cw = atoi(e) == 4 ? 4 : 8;
+  const int nmb = (int)((g.Mp + 32 * cw - 1) / (32 * cw));
+  const int rb = (int)roundup((g.Mp + nmb - 1) / nmb, 16);
   std::vector<int> starts;
   for (int ab0 = 0, n = 1; ab0 < g.nbp; ab0 += n) {
     n = 1;
@@ -765,7 +778,8 @@ hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* 
     if (e != hipSuccess) return e;
     // parts per contraction list: the fewest that fill whole rounds of the
     // resident workgroups (two per CU) to within 5 %, at most 8
-    const long items = (long)nmb * (g.nbp - ab0), slots = 2L * std::max(1, h->ncu);
+    const long items = (long)nmb * (g.nbp - ab0),
+               slots = (cw == 4 ? 2L : 1L) * std::max(1, h->ncu);
     int nsplit = 1;
     double best = 0;
     // (deterministic mode: one part, no atomic additions)
@@ -780,14 +794,18 @@ hipError_t bf16x3_run(lrcc_handle h, const Geom& g, const void* Ls, const void* 
     }
     if ((long)nsplit * items > 0x7fffffffL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(nsplit * items));
-    if (acc64)
-      hipLaunchKernelGGL(k_contract<double>, grid, dim3(WG), 0, st,
-                         static_cast<const __bf16*>(Xb), Vdir, Vmir, g.nbp, (int)g.Mp, nmb, ab0,
-                         ab0 + n, nx, (int)(n == g.nbp), static_cast<double*>(Sb));
-    else
-      hipLaunchKernelGGL(k_contract<float>, grid, dim3(WG), 0, st,
-                         static_cast<const __bf16*>(Xb), Vdir, Vmir, g.nbp, (int)g.Mp, nmb, ab0,
-                         ab0 + n, nx, (int)(n == g.nbp), static_cast<float*>(Sb));
+#define LRCC_KC(TA, NWV)                                                                       \
+  hipLaunchKernelGGL((k_contract<TA, NWV>), grid, dim3(64 * NWV), 0, st,                        \
+                     static_cast<const __bf16*>(Xb), Vdir, Vmir, g.nbp, (int)g.Mp, nmb, rb, ab0, \
+                     ab0 + n, nx, (int)(n == g.nbp), static_cast<TA*>(Sb))
+    if (acc64) {
+      if (cw == 8) LRCC_KC(double, 8);
+      else LRCC_KC(double, 4);
+    } else {
+      if (cw == 8) LRCC_KC(float, 8);
+      else LRCC_KC(float, 4);
+    }
+#undef LRCC_KC
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
