@@ -28,6 +28,7 @@
 #include <algorithm>
 
 #include "internal.hpp"
+#include "panels.hpp"
 
 namespace lrcc {
 
@@ -257,31 +258,26 @@ lrcc_status grad_run(lrcc_handle h, const Geom& g0, const void* L, const void* X
   LRCC_HIP(h, pack_to_block<T>(X, dt, g, tab, h->xb.as<T>(), st));
   LRCC_HIP(h, pack_to_block<T>(G, dt, g, tab, h->gb.as<T>(), st));
   LRCC_HIP(h, fill_zero(Z, lsz, st));
-  // panels of whole block rows A (all pairs (A, B), B >= A): as many as fit
-  // in the workspace limit of the bf16x3 ladder (min(16 GiB, half the free
-  // memory) unless set), at least one row
+  // panels of whole block rows A (all pairs (A, B), B >= A) within the
+  // workspace limit of the bf16x3 ladder (min(16 GiB, half the free memory)
+  // unless set), at least one row
   if (h->panel_cap == 0) {
     size_t freeb = 0, totalb = 0;
     LRCC_HIP(h, hipMemGetInfo(&freeb, &totalb));
     h->panel_cap = std::max<size_t>(std::min((size_t)16 << 30, freeb / 2), (size_t)64 << 20);
   }
   const size_t tile = (size_t)2 * NS * NS * es;
-  auto rows_of = [&](int A0, int A1) {  // block pairs of the rows A0 .. A1 - 1
-    long n = 0;
-    for (int A = A0; A < A1; ++A) n += nbv - A;
-    return n;
-  };
-  // (the first row is the longest: every panel of rows fits once it does)
-  const size_t cap = std::max(h->panel_cap, (size_t)rows_of(0, 1) * nbp * tile);
-  int maxrows = 1;
-  while (maxrows < nbv && (size_t)rows_of(0, maxrows + 1) * nbp * tile <= cap) ++maxrows;
-  LRCC_HIP(h, h->vws.ensure((size_t)rows_of(0, maxrows) * nbp * tile));
+  // the workspace holds the first (largest) panel and no later panel is
+  // larger than it
+  const PanelPlan plan = plan_row_panels(nbv, (size_t)nbp * tile, h->panel_cap);
+  LRCC_HIP(h, h->vws.ensure(plan.bytes));
   T* Rp = h->vws.as<T>();
-  for (int A0 = 0; A0 < nbv;) {
-    int A1 = A0 + 1;
-    while (A1 < nbv && (size_t)rows_of(A0, A1 + 1) * nbp * tile <= cap) ++A1;
+  for (const auto& pr : plan.rows) {
+    const int A0 = pr.first, A1 = pr.second;
     const int ab0 = bpair(A0, A0, nbv);
-    const long ntile = rows_of(A0, A1) * nbp;
+    const long ntile = panel_pairs(nbv, A0, A1) * nbp;
+    if ((size_t)ntile * tile > h->vws.n)  // (the plan guarantees it; checked before any launch)
+      return fail(h, LRCC_ERR_NOMEM, "gradient panel exceeds its workspace");
     if (ntile > 0x7fffffffL) return fail(h, LRCC_ERR_SHAPE, "gradient panel too large");
     hipLaunchKernelGGL((k_grad_r<T>), dim3((unsigned)ntile), dim3(WG), 0, st, h->gb.as<T>(),
                        h->xb.as<T>(), nbp, (int)g.Mp, ab0, Rp);
@@ -291,7 +287,6 @@ lrcc_status grad_run(lrcc_handle h, const Geom& g0, const void* L, const void* X
     hipLaunchKernelGGL((k_grad_z<T>), dim3((unsigned)nz), dim3(WG), 0, st, Ls, Rp, nbv, nbp,
                        g.ncp, g.v, A0, A1, ab0, Z);
     LRCC_HIP(h, hipGetLastError());
-    A0 = A1;
   }
   hipLaunchKernelGGL((k_grad_out<T>), dim3(grid_for((long)g.nchol * g.v * g.v)), dim3(256), 0, st,
                      Z, g.v, g.nchol, nbv, g.ncp, dt, dL);
