@@ -370,6 +370,16 @@ def extras(lrcc, torch, np, S, Lscale, Xscale, args):
             sb[f"{prec}_{cmul}"] = e
         except lrcc.LrccError as err:
             sb[f"{prec}_{cmul}"] = {"error": str(err)}
+    # FP32 on complex64 storage: the tile partials are summed in FP32 (as in
+    # the solver's FP32 ladders), half the atomic bytes of the FP64 sums above
+    X64, L64 = X.to(torch.complex64), Lraw.to(torch.complex64)
+    for cmul in ("4m", "3m"):
+        try:
+            sb[f"fp32_{cmul}_c64"] = sigma_extra(lrcc, torch, o, v, nchol, nrhs, "fp32", cmul,
+                                                 L64, X64, 20)
+        except lrcc.LrccError as err:
+            sb[f"fp32_{cmul}_c64"] = {"error": str(err)}
+    del X64, L64
     extra["sigma_baseline"] = sb
 
     # ---- baseline workload: solves ---------------------------------------
