@@ -366,9 +366,11 @@ def test_launch_variants(lrcc, tmp_path, prec, cmul, variants, herm):
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-10), (torch.complex64, 1e-5)])
-@pytest.mark.parametrize("limit", [1 << 20, 0])
+@pytest.mark.parametrize("limit", [1 << 20, 4 << 20, 0])
 def test_dL_panels(lrcc, dtype, tol, limit):
-    # the gradient's R' panels: one block row per panel (a 1 MB limit) or the
+    # the gradient's R' panels: one block row per panel (a 1 MB limit), a
+    # limit between one and two rows (4 MB: the workspace holds the first row
+    # and the later panels, of shorter rows, must stay within it), or the
     # whole triangle at once; ragged v, rows not a multiple of 16, general L
     o, v, nchol, nrhs = 5, 29, 37, 2
     rng = np.random.default_rng(303)
