@@ -20,7 +20,7 @@ two Cholesky dot products each; the contraction takes every ordered pair of
 packed virtual pairs for every row).  This count is what the matrix cores
 must issue at the least, so value and roofline.achieved stay below the FP64
 peak.  Also reported: the matrix-core work actually issued (padding
-included) and the survey's 4M count without symmetry savings
+included) and the plain 4M count without symmetry savings
 (8 (2 npv^2 Nchol + nrhs npo npv^2)) as effective_tflops.
 
 Extras: the ladder per precision and complex form at the scale and baseline
@@ -60,7 +60,7 @@ def npairs(n):
 
 
 def flops_per_sigma(o, v, nchol, nrhs):
-    """The survey's algorithmic count: 4M, no symmetry savings."""
+    """The plain algorithmic count: 4M complex products, no symmetry savings."""
     npo, npv = npairs(o), npairs(v)
     return 8.0 * (2.0 * npv * npv * nchol + nrhs * npo * npv * npv)
 
