@@ -117,7 +117,8 @@ lrcc_status lrcc_ppl_sigma(lrcc_handle h, int o, int v, int nchol, int nrhs,
  * handle's stream.  All calls on one GPU share that array and each clears
  * what it reads before use: calls that can overlap on one GPU (different
  * streams or handles without ordering between them) race and must be
- * serialised by the caller. */
+ * serialised by the caller.  The deterministic mode (lrcc_set_deterministic)
+ * does not apply: the call runs the default kernels. */
 lrcc_status lrcc_ppl_sigma_noalloc(lrcc_handle h, int o, int v, int nchol, int nrhs,
                                    const void* L, const void* X, void* sigma,
                                    lrcc_dtype dt, lrcc_prec prec, lrcc_cmul cmul);
