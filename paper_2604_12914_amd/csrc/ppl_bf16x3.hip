@@ -190,11 +190,12 @@ __device__ __forceinline__ int bp_index(int C, int D, int nbv) {
 
 // Byte offset, inside one [64 rows][16 P] plane (2 KB) of a staged block
 // chunk held in LDS, of the 16-byte half h (P 8h .. 8h + 7) of row r.  The
-// halves of rows 4..7 (mod 8) are swapped, so that the eight rows one phase
-// of a 16-byte LDS read covers fall on eight distinct 16-byte bank groups.
-__device__ __forceinline__ int lds_half(int r, int h) {
-  return r * 32 + ((h ^ ((r >> 2) & 1)) << 4);
-}
+// halves are swapped where bits 2 and 3 of the row differ, so that the 16
+// consecutive rows one 16-byte LDS read covers per cycle (64 banks of 4
+// bytes) fall on 16 distinct 16-byte bank groups, and any 8 aligned ones on
+// 8 distinct groups of 128 bytes.
+__device__ __forceinline__ int lds_swz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
+__device__ __forceinline__ int lds_half(int r, int h) { return r * 32 + ((h ^ lds_swz(r)) << 4); }
 
 // Output row / column of element r of a 32x32 MFMA accumulator in lane l
 // (32x32x16: rows in four groups of eight, lanes 32..63 holding rows 4..7 of
@@ -268,9 +269,9 @@ __global__ __launch_bounds__(BWG, 1) void k_vbuild(const __bf16* __restrict__ Ls
     // piece k (1 KB) of this wave's slot: plane k >> 1, rows 32 (k & 1) ..
     // + 31; lane l writes LDS bytes 16 l of the piece, which hold row
     // 32 (k & 1) + l / 2, half (l & 1) as placed by lds_half, so it reads
-    // the global half (l & 1) ^ (bit 2 of its row) (the same for both row
-    // halves of a plane: 32 is a multiple of 8)
-    const int goff = (lane >> 1) * 32 + (((lane & 1) ^ ((lane >> 3) & 1)) << 4);
+    // the global half (l & 1) ^ lds_swz(row) (the same for both row halves
+    // of a plane: 32 is a multiple of 16)
+    const int goff = (lane >> 1) * 32 + (((lane & 1) ^ lds_swz(lane >> 1)) << 4);
     auto issue = [&](int c, unsigned char* buf) {
       const char* src = gsrc + (size_t)c * CHB + goff;
 #pragma unroll
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(BWG, 1) void k_vbuild(const __bf16* __restrict__ Ls
     // W += A B over one chunk: re += Ar Br - Ai Bi, im += Ar Bi + Ai Br (the
     // minus sign on the Bi operand)
     // this lane's operand bytes in a plane: row (lane & 31) (+ 32 for the
-    // second MFMA block, which leaves bit 2 of the row unchanged), half lane >> 5
+    // second MFMA block, which leaves bits 2 and 3 of the row unchanged), half lane >> 5
     const int loff = lds_half(lane & 31, lane >> 5);
     auto mma = [&](const unsigned char* buf) {
       const unsigned char* as = buf + aslot * CHB + loff;
