@@ -1069,7 +1069,10 @@ lrcc_status solve_side(lrcc_handle h, int o, int v, int nchol, const double* eps
         S.sweep = outer;
         lrcc_status is = jacobi_diis(S, S.rk, S.x, op.prec, op.cmul, h->ls2.p, O.inner_tol,
                                      O.max_iter, act.data());
+        // an inner solve that stops short is refined further; any other
+        // failure ends the solve
         if (is == LRCC_ERR_NONFINITE) return fail(h, is, "non-finite residual");
+        if (is != LRCC_OK && is != LRCC_ERR_NOT_CONVERGED) return is;
         // x2 += d; sx = ladder(x2): the full-iterate ladder in the first sweep
         // (or every sweep), else sx += reduced-precision ladder of the
         // correction d; then rk = b - (D - w) x2 - sx
@@ -1281,6 +1284,7 @@ lrcc_status batched_refine(lrcc_handle h, int ninst, const lrcc_instance* inst,
       lrcc_status is = jacobi_diis(Si, Si.rk, Si.x, op.prec, op.cmul, ls2.p, O.inner_tol,
                                    O.max_iter, act[i].data());
       if (is == LRCC_ERR_NONFINITE) return fail(h, is, "non-finite residual");
+      if (is != LRCC_OK && is != LRCC_ERR_NOT_CONVERGED) return is;
       LRCC_HIP(h, hipMemcpyAsync(Si.active, act[i].data(), Si.n * sizeof(int),
                                  hipMemcpyHostToDevice, hs));
       hipLaunchKernelGGL(k_add, grid_rhs(Si, Si.n), dim3(RB), 0, hs, Si.d, Si.active, Si.x, Si.x2);
