@@ -346,7 +346,7 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
       if (s != LRCC_OK) return s;
     }
   } else {
-    LRCC_HIP(h, hipMemsetAsync(G, 0, o2v2 * 16, st));
+    LRCC_HIP(h, fill_zero(G, o2v2 * 16, st));
   }
   if (o > 0) {
     hipLaunchKernelGGL(k_fns_t, dim3(ntile * ntile, o * o), tb, 0, st, o, v, G, eps, t);
@@ -363,7 +363,7 @@ lrcc_status fns_run(lrcc_handle h, int o, int v, int nchol, const double* eps, c
   }
 
   // 4-7: perturbed amplitudes and the averaged density
-  LRCC_HIP(h, hipMemsetAsync(Gm, 0, (size_t)v2 * 16, st));
+  LRCC_HIP(h, fill_zero(Gm, (size_t)v2 * 16, st));
   const double2 wgt = make_double2(1.0 / (ncomp > 0 ? ncomp : 1), 0.0);
   double2* Xp = G;  // G is dead once t is formed
   for (int x = 0; x < (o > 0 ? ncomp : 0); ++x) {

@@ -116,6 +116,12 @@ __global__ void k_zero(uint4* p, size_t n16) {
     p[i] = make_uint4(0, 0, 0, 0);
 }
 
+__global__ void k_zero8(uint2* p, size_t n8) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n8;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = make_uint2(0, 0);
+}
+
 inline int grid_for(long n) {
   long g = (n + 255) / 256;
   return (int)(g < 65536 ? (g < 1 ? 1 : g) : 65536);
@@ -150,11 +156,20 @@ hipError_t block_to_pack(const T* Sb, const Geom& g, const int* tab, void* S, lr
 
 // Zero a device buffer with a fill kernel (a plain kernel node stays valid
 // under graph capture, unlike a memset node).
+// Zeroes with a kernel (no memset node, so a caller may capture it): 16-byte
+// stores where p and bytes allow, else 8-byte ones; hipErrorInvalidValue for
+// other sizes or alignments.
 hipError_t fill_zero(void* p, size_t bytes, hipStream_t st) {
   if (bytes == 0) return hipSuccess;
-  if (bytes % 16 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_zero, dim3(grid_for((long)(bytes / 16))), dim3(256), 0, st,
-                     static_cast<uint4*>(p), bytes / 16);
+  const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+  if (bytes % 16 == 0 && a % 16 == 0)
+    hipLaunchKernelGGL(k_zero, dim3(grid_for((long)(bytes / 16))), dim3(256), 0, st,
+                       static_cast<uint4*>(p), bytes / 16);
+  else if (bytes % 8 == 0 && a % 8 == 0)
+    hipLaunchKernelGGL(k_zero8, dim3(grid_for((long)(bytes / 8))), dim3(256), 0, st,
+                       static_cast<uint2*>(p), bytes / 8);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -302,7 +302,7 @@ lrcc_status grad_L(lrcc_handle h, const Geom& g, const void* L, const void* X, c
   const size_t nl = (size_t)g.nchol * g.v * g.v;
   if (nl == 0) return LRCC_OK;
   if (g.M == 0 || g.npv == 0) {  // sigma does not depend on L: zero gradient
-    LRCC_HIP(h, hipMemsetAsync(dL, 0, nl * es, h->stream));
+    LRCC_HIP(h, fill_zero(dL, nl * es, h->stream));
     return LRCC_OK;
   }
   // complex128: FP64 arithmetic; complex64: FP32
