@@ -180,6 +180,20 @@ def test_empty_and_degenerate(lrcc):
         X = np.zeros((nrhs, o * (o - 1) // 2, v * (v - 1) // 2), np.complex128)
         s = lrcc.ppl_sigma(dev(L), dev(X), o=o)
         assert s.shape == X.shape
+    # sigma does not depend on L without occupied pairs, virtual pairs or
+    # right-hand sides: the gradient is zero (written over a NaN-filled buffer)
+    for cdt in (torch.complex128, torch.complex64):
+        for (o, v, nrhs) in [(1, 12, 2), (4, 1, 2), (4, 12, 0)]:
+            L = dev(S.make_L(rng, 5, v)).to(cdt)
+            X = torch.zeros((nrhs, o * (o - 1) // 2, v * (v - 1) // 2), dtype=cdt,
+                            device=L.device)
+            dL = torch.full_like(L, float("nan"))
+            h = lrcc.handle(0)
+            lrcc._check(lrcc.lib().lrcc_ppl_sigma_adjoint(
+                h, o, v, 5, nrhs, lrcc._ptr(L), lrcc._ptr(X), lrcc._ptr(X), None,
+                lrcc._ptr(dL), lrcc._dtype_code(X), lrcc.PREC["fp64"], lrcc.CMUL["4m"]), h)
+            torch.cuda.synchronize()
+            assert int(torch.count_nonzero(dL)) == 0
     # rank-one Hermitian vectors cancel exactly in <ab||cd>
     v = 20
     L = np.stack([np.outer(u, np.conj(u)) for u in S.cn(rng, (3, v))])
