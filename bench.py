@@ -201,6 +201,10 @@ def main():
                     help="only run an FP64 solve with both ladders and the ring term, "
                          "--warmup + --steps ring applications and one pivoted Cholesky "
                          "decomposition (for profilers)")
+    ap.add_argument("--profile-solve", choices=("fp64", "fp32", "bf16x3"), default=None,
+                    help="only run --warmup + --steps response solves of the baseline "
+                         "workload to an FP64 residual of 1e-8 (FP64, or refinement with "
+                         "FP32 / bf16x3 inner solves; for profilers)")
     ap.add_argument("--profile-grad", action="store_true",
                     help="only run --warmup + --steps gradients with respect to L (for "
                          "profilers)")
@@ -239,6 +243,9 @@ def main():
         return
     if args.profile_grad:
         profile_grad(lrcc, torch, np, S, args)
+        return
+    if args.profile_solve:
+        profile_solve(lrcc, torch, np, S, args)
         return
     if args.profile_batched:
         profile_batched(lrcc, torch, np, S, args)
@@ -846,6 +853,35 @@ def profile_sigma(lrcc, torch, np, S, args):
           flush=True)
 
 
+
+
+def profile_solve(lrcc, torch, np, S, args):
+    """Response solves of the baseline workload (the instance and options of
+    the solve extras), for a profiler run: one JSON line with the mean wall
+    time per solve and the ladders it took."""
+    cfg = S.CONFIGS["baseline"]
+    o, v, nchol = cfg.o, cfg.v, cfg.nchol
+    omegas = list(cfg.omegas)
+    inst = S.make_instance(o, v, nchol, ncomp=cfg.ncomp, seed=cfg.seed, gamma=S.solve_gamma(v))
+    eps = torch.from_numpy(inst.eps).cuda()
+    L = torch.from_numpy(inst.L).cuda()
+    mu = torch.from_numpy(inst.mu).cuda()
+    kw = dict(prec=args.profile_solve, tol=1e-8)
+    if args.profile_solve != "fp32":
+        kw["cmul"] = SOLVE_CMUL
+    for _ in range(max(args.warmup, 1)):
+        lrcc.solve(eps, L, mu, omegas, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, info = lrcc.solve(eps, L, mu, omegas, **kw)
+    ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    print(json.dumps({"profile_solve": args.profile_solve, "workload": "baseline",
+                      "o": o, "v": v, "nchol": nchol, "rhs": cfg.nrhs,
+                      "cmul": kw.get("cmul", "4m"), "tol": 1e-8, "ms_per_solve": round(ms, 3),
+                      "solves": args.steps, "n_sigma_fp64": info["n_sigma_fp64"],
+                      "n_sigma_lowp": info["n_sigma_lowp"],
+                      "final_relres": info["final_relres"]}), flush=True)
 
 
 def profile_grad(lrcc, torch, np, S, args):
