@@ -342,18 +342,18 @@ def main():
 
 def extras(lrcc, torch, np, S, Lscale, Xscale, args):
     extra = {}
-    c5 = S.CONFIGS["scale"]
+    scw = S.CONFIGS["scale"]
     progress("extra: the ladder per precision at the scale workload")
     # ---- the ladder at the scale workload per precision ------------------
     try:
         # (the FP64 3M ladder is the headline itself: config.step_ms)
-        sc = {"fp64_4m": sigma_extra(lrcc, torch, c5.o, c5.v, c5.nchol, c5.nrhs, "fp64", "4m",
+        sc = {"fp64_4m": sigma_extra(lrcc, torch, scw.o, scw.v, scw.nchol, scw.nrhs, "fp64", "4m",
                                      Lscale, Xscale, 3)}
         L64, X64 = Lscale.to(torch.complex64), Xscale.to(torch.complex64)
         progress("extra: scale workload FP32 and bf16x3 ladders (complex64)")
-        sc["fp32_4m_c64"] = sigma_extra(lrcc, torch, c5.o, c5.v, c5.nchol, c5.nrhs, "fp32",
+        sc["fp32_4m_c64"] = sigma_extra(lrcc, torch, scw.o, scw.v, scw.nchol, scw.nrhs, "fp32",
                                         "4m", L64, X64, 5)
-        sc["bf16x3_4m_c64"] = sigma_extra(lrcc, torch, c5.o, c5.v, c5.nchol, c5.nrhs,
+        sc["bf16x3_4m_c64"] = sigma_extra(lrcc, torch, scw.o, scw.v, scw.nchol, scw.nrhs,
                                           "bf16x3", "4m", L64, X64, 5)
         del L64, X64
         extra["sigma_scale"] = sc
