@@ -165,8 +165,8 @@ def time_sigma(lrcc, torch, L, X, prec, cmul, reps, warmup=1):
     return kms, cms
 
 
-def sigma_extra(lrcc, torch, o, v, nchol, nrhs, prec, cmul, L, X, reps):
-    kms, cms = time_sigma(lrcc, torch, L, X, prec, cmul, reps)
+def sigma_extra(lrcc, torch, o, v, nchol, nrhs, prec, cmul, L, X, reps, warmup=5):
+    kms, cms = time_sigma(lrcc, torch, L, X, prec, cmul, reps, warmup)
     km = sorted(kms)[len(kms) // 2]
     A = alg_flops(o, v, nchol, nrhs, cmul)
     return {
@@ -347,14 +347,16 @@ def extras(lrcc, torch, np, S, Lscale, Xscale, args):
     # ---- the ladder at the scale workload per precision ------------------
     try:
         # (the FP64 3M ladder is the headline itself: config.step_ms)
+        # (repetitions at this size: the 4M FP64 ladder takes 5.3 s, so three
+        # after one warm-up; the others twenty after five)
         sc = {"fp64_4m": sigma_extra(lrcc, torch, scw.o, scw.v, scw.nchol, scw.nrhs, "fp64", "4m",
-                                     Lscale, Xscale, 3)}
+                                     Lscale, Xscale, 3, warmup=1)}
         L64, X64 = Lscale.to(torch.complex64), Xscale.to(torch.complex64)
         progress("extra: scale workload FP32 and bf16x3 ladders (complex64)")
         sc["fp32_4m_c64"] = sigma_extra(lrcc, torch, scw.o, scw.v, scw.nchol, scw.nrhs, "fp32",
-                                        "4m", L64, X64, 5)
+                                        "4m", L64, X64, 20)
         sc["bf16x3_4m_c64"] = sigma_extra(lrcc, torch, scw.o, scw.v, scw.nchol, scw.nrhs,
-                                          "bf16x3", "4m", L64, X64, 5)
+                                          "bf16x3", "4m", L64, X64, 20)
         del L64, X64
         extra["sigma_scale"] = sc
     except lrcc.LrccError as e:
