@@ -49,3 +49,11 @@ def test_work_counts_by_brute_force(o, v, nchol, nrhs):
         assert bench.alg_flops(o, v, nchol, nrhs, cmul) == per * (builds + contract)
     # no symmetry savings: every ordered pair built, 4M
     assert bench.flops_per_sigma(o, v, nchol, nrhs) == 8 * (len(pv) ** 2 * 2 * nchol + contract)
+
+
+def test_headline_traffic_summary_describes_the_current_kernel():
+    # bench.py reports roofline.traffic from the committed FETCH_SIZE /
+    # WRITE_SIZE summary only while the kernel sources hash as they did when
+    # the counters were taken; a kernel change must come with new counters
+    t = bench.measured_traffic()
+    assert t is not None and t > 0
